@@ -1,0 +1,115 @@
+"""Seeded synthetic inputs for the indefinite least squares (ILS) solvers.
+
+This module only builds inputs: matrices, right-hand sides, planted solutions.
+It holds none of the solvers' arithmetic and is shared by the CPU oracle's
+tests, the GPU parity tests and the benchmark.
+
+The dense family follows the problem statement of Sec. 1 (A = [A1; A2],
+J = diag(I_p, -I_q)): A1 and A2 get i.i.d. N(0,1) entries, A2 is then
+rescaled so that ||A2||_2 = ratio * sigma_min(A1).  With ratio < 1 this keeps
+A^T J A symmetric positive definite, the standing assumption (Sec12)-(Sec13).
+A planted x* gives b = A x* (+ optional noise), so x_ILS = x* when there is no
+noise.  Arrays come out column-major (Fortran order), float64.
+
+The paper's own experiment family (Sec. 5.2 / 5.3: A1 = U[0,1), A2 = 7 * eye)
+is available as `paper_family`.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class DenseILS:
+    A: np.ndarray          # (m, n) float64, Fortran order
+    b: np.ndarray          # (m,)
+    p: int
+    q: int
+    x_star: np.ndarray     # planted solution (n,), or None
+    ratio: float           # ||A2||_2 / sigma_min(A1) after scaling
+    seed: object
+
+    @property
+    def m(self) -> int:
+        return self.p + self.q
+
+    @property
+    def n(self) -> int:
+        return self.A.shape[1]
+
+
+def _rng(seed):
+    if isinstance(seed, (tuple, list)):
+        return np.random.default_rng(list(seed))
+    return np.random.default_rng(seed)
+
+
+def dense_ils(p: int, q: int, n: int, ratio: float = 0.5, seed=0,
+              noise: float = 0.0, a1: np.ndarray | None = None) -> DenseILS:
+    """Gaussian ILS instance with A2 scaled to ||A2||_2 = ratio * sigma_min(A1).
+
+    Draw order from numpy.random.default_rng(seed): A1 (p x n), A2 (q x n),
+    x* (n), noise (m).  `a1` lets two instances share the same A1 (the
+    ratio-0.5 and ratio-0.9 variants of one problem).
+    """
+    rng = _rng(seed)
+    A1 = rng.standard_normal((p, n)) if a1 is None else np.array(a1, dtype=np.float64)
+    if a1 is not None:
+        rng.standard_normal((p, n))  # keep the stream position identical
+    A2 = rng.standard_normal((q, n))
+    x_star = rng.standard_normal(n)
+    e = rng.standard_normal(p + q)
+    if q > 0:
+        smin = np.linalg.svd(A1, compute_uv=False)[-1]
+        a2n = np.linalg.svd(A2, compute_uv=False)[0]
+        A2 = A2 * (ratio * smin / a2n)
+    A = np.asfortranarray(np.vstack([A1, A2]))
+    b = A @ x_star
+    if noise:
+        b = b + noise * e
+    return DenseILS(A=A, b=np.ascontiguousarray(b), p=p, q=q, x_star=x_star,
+                    ratio=ratio, seed=seed)
+
+
+def tiny(seed=0) -> DenseILS:
+    """A1 500x50, A2 100x50, ratio 0.5, b = A x*, no noise."""
+    return dense_ils(500, 100, 50, ratio=0.5, seed=seed)
+
+
+def large(ratio: float = 0.5, seed=1) -> DenseILS:
+    """A1 18000x1000, A2 2000x1000, b = A x* + 1e-8 N(0,1).
+
+    The ratio-0.5 and ratio-0.9 variants use the same seed and hence share
+    A1, A2 (before scaling) and x*.
+    """
+    return dense_ils(18000, 2000, 1000, ratio=ratio, seed=seed, noise=1e-8)
+
+
+def batched_sizes(count: int = 4096, seed: int = 3, lo: int = 32, hi: int = 256):
+    """Per-instance n ~ U{lo..hi}, p = 4n, q = floor(n/2)."""
+    rng = np.random.default_rng(seed)
+    ns = rng.integers(lo, hi + 1, size=count)
+    return [(4 * int(n), int(n) // 2, int(n)) for n in ns]
+
+
+def batched_instance(i: int, n: int, seed: int = 3) -> DenseILS:
+    p, q = 4 * n, n // 2
+    return dense_ils(p, q, n, ratio=0.5, seed=(seed, i))
+
+
+def paper_family(p: int, q: int, n: int, seed=0) -> DenseILS:
+    """The experiment family of Sec. 5.2 (q = n) and Sec. 5.3 (q = 1).
+
+    A1 = U[0,1) p x n, A2 = 7 * (first q rows of I_n), b1, b2 = U[0,1).
+    There is no planted solution (x_star is None).
+    """
+    rng = _rng(seed)
+    A1 = rng.random((p, n))
+    A2 = np.zeros((q, n))
+    k = min(q, n)
+    A2[np.arange(k), np.arange(k)] = 7.0
+    b = rng.random(p + q)
+    A = np.asfortranarray(np.vstack([A1, A2]))
+    return DenseILS(A=A, b=b, p=p, q=q, x_star=None, ratio=float("nan"), seed=seed)
