@@ -1,0 +1,182 @@
+/* ils.h -- C ABI of the MI355X (gfx950) solver for the indefinite least
+ * squares (ILS) problem by the splitting methods of Zhang & Li,
+ * "Splitting-based randomized iterative methods for solving indefinite least
+ * squares problem" (arXiv 2203.15340).
+ *
+ * Problem (Sec. 1, eq. Sec11):  min_x (b - A x)^T J (b - A x),
+ *   A is m x n with m >= n, J = diag(I_p, -I_q), p + q = m.
+ * Partition (eq. Sec121): A1 = rows [0, p) of A, A2 = rows [p, m); b1, b2 alike.
+ * The problem has a unique solution iff A^T J A = A1^T A1 - A2^T A2 is
+ * symmetric positive definite (eq. Sec13), which needs p >= n.
+ *
+ * Memory and layout.  Every array argument is a DEVICE pointer on the device
+ * of the handle (hipMalloc'd memory or a torch tensor's data_ptr()), except
+ * where marked "host".  A is column-major FP64 with leading dimension
+ * lda >= m; A1 and A2 are row ranges of that one buffer.  b has m entries,
+ * x0, x and x_ref have n.  The caller owns every array it passes; the
+ * library neither frees nor keeps any caller pointer after a call returns.
+ * The handle owns all workspace (Gram matrices, factors, vectors, sampler
+ * tables), grows it on demand and frees it in ils_destroy.
+ *
+ * Streams and blocking.  Work is queued on the handle's stream (the one given
+ * to ils_create, else a stream the handle creates).  The solve calls return
+ * after that work has finished, since the iteration counts and status are
+ * read back into the host ils_info.  A handle must not be used by two host
+ * threads at once.
+ *
+ * Errors.  Calls return ILS_OK (0) or a negative ils_status; info->status
+ * holds the same value.  On ILS_ERR_ARG, ILS_ERR_NONFINITE (non-finite entry
+ * in A or b) and ILS_ERR_NOT_SPD x is left untouched.  On
+ * ILS_ERR_NO_CONVERGENCE x holds the last iterate, which may be passed back
+ * as x0 to resume: each method converges from any start (Thm 2.1, 3.2, 4.1).
+ * ILS_ERR_NONFINITE is also returned when an iterate becomes non-finite; x
+ * then holds that iterate.
+ */
+#ifndef ILS_H
+#define ILS_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ILS_OK = 0,
+  ILS_ERR_ARG = -1,            /* invalid sizes, pointers or options */
+  ILS_ERR_NOT_SPD = -2,        /* A1^T A1 not positive definite (rank(A1) < n) */
+  ILS_ERR_NO_CONVERGENCE = -3, /* max_outer reached before the stop rule held */
+  ILS_ERR_NONFINITE = -4,      /* NaN/Inf in A, b or an iterate */
+  ILS_ERR_HIP = -5,            /* a HIP runtime call failed */
+  ILS_ERR_ALLOC = -6           /* device memory allocation failed */
+} ils_status;
+
+/* Outer stopping rule, checked at x_k before x_{k+1} is formed. */
+enum {
+  ILS_STOP_RR = 0,    /* RR = ||A^T J (A x - b)||^2 / ||A^T J b||^2 < tol (Sec. 5) */
+  ILS_STOP_XREF = 1,  /* ||x - x_ref|| / ||x_ref|| < tol */
+  ILS_STOP_FIXED = 2  /* exactly max_outer outer steps (and max_inner inner steps) */
+};
+
+/* Which right-hand side each outer step solves with A1^T A1. */
+enum {
+  ILS_FORM_PAPER = 0,      /* A1^T A1 x_{k+1} = A2^T A2 x_k + A^T J b (eq. Sec23, Sec3.41) */
+  ILS_FORM_CORRECTION = 1  /* A1^T A1 d = A^T J (b - A x_k), x_{k+1} = x_k + d:
+                              the same iterate in exact arithmetic, since
+                              A^T J A = A1^T A1 - A2^T A2 (Sec. 2) */
+};
+
+enum {
+  ILS_PREC_FP64 = 0,  /* every step in FP64 */
+  ILS_PREC_MIXED = 1  /* A1^T A1 and the inner sweeps in FP32, residual and
+                         update in FP64; needs ILS_FORM_CORRECTION */
+};
+
+/* SP-SCD column choice (Alg. 5 and Remark 4.1). */
+enum {
+  ILS_SAMPLE_UNIFORM = 0, /* uniform alpha_t-subset, largest |residual| in it */
+  ILS_SAMPLE_NORM = 1     /* alpha = 1 with P(j) = ||A1_(j)||^2 / ||A1||_F^2 (SP-RCD) */
+};
+
+typedef struct {
+  double tol;            /* outer threshold; default 1e-6 (Sec. 5) */
+  int32_t stop_rule;     /* ILS_STOP_*; default ILS_STOP_RR */
+  int32_t form;          /* ILS_FORM_*; default ILS_FORM_PAPER */
+  int32_t precision;     /* ILS_PREC_*; default ILS_PREC_FP64 */
+  int32_t sampling;      /* ILS_SAMPLE_*; SP-SCD only */
+  const double* x_ref;   /* device, n; required iff stop_rule == ILS_STOP_XREF */
+  int64_t max_outer;     /* default 20000 (Sec. 5) */
+  int64_t max_inner;     /* randomized methods; -1 = 1000 * n */
+  double inner_tol;      /* randomized methods: stop the inner loop when
+                            ||bhat - A1^T A1 z|| <= inner_tol * ||bhat||;
+                            -1 = 1e-8 (paper form) or 1e-2 (correction form) */
+  int64_t inner_check;   /* SP-RK-RGS: inner steps between residual checks; -1 = n */
+  uint64_t seed;         /* randomized methods: Philox key */
+  uint64_t stream_offset;/* added to the outer index in the Philox counter */
+  int64_t alpha;         /* SP-SCD: 0 = alpha_t uniform on {1..n} (Alg. 5 step 7);
+                            k > 0 = fixed alpha = min(k, n); k = n is the greedy
+                            (Motzkin) choice; 1 with ILS_SAMPLE_NORM is SP-RCD */
+} ils_opts;
+
+typedef struct {
+  int32_t status;        /* same as the return value */
+  int32_t pad;
+  int64_t outer_iters;   /* outer updates performed */
+  int64_t inner_iters;   /* randomized methods: inner steps over all outer steps */
+  double rr;             /* RR at the returned x when stop_rule == ILS_STOP_RR, else NaN */
+  double rel_err;        /* ||x - x_ref|| / ||x_ref|| when x_ref is given, else -1 */
+  double device_ms;      /* time between the first and last queued kernel */
+} ils_info;
+
+typedef struct ils_handle ils_handle;
+
+/* Create a handle bound to device_ordinal.  hip_stream is a hipStream_t (or
+ * NULL, in which case the handle creates its own default-priority stream). */
+int ils_create(ils_handle** h, int device_ordinal, void* hip_stream);
+int ils_destroy(ils_handle* h);
+/* Fill *o with the defaults listed in ils_opts. */
+void ils_opts_default(ils_opts* o);
+/* Static string describing a status code. */
+const char* ils_status_string(int status);
+
+/* SP method, Algorithm 1: P = (A1^T A1)^{-1}, B = P A2^T A2, c = P A^T J b,
+ * x_{k+1} = B x_k + c (eq. Sec23).  B and c are formed by block Gauss-Jordan
+ * elimination of [A1^T A1 | A2^T A2 | A^T J b] (P itself is never stored);
+ * the correction form and the mixed precision form keep P = (A1^T A1)^{-1}
+ * and iterate x_{k+1} = x_k + P A^T J (b - A x_k).
+ * x0 may be NULL (zero start, as in Sec. 5) and may alias x. */
+int ils_sp_solve(ils_handle* h, int64_t p, int64_t q, int64_t n, const double* A, int64_t lda,
+                 const double* b, const double* x0, double* x, const ils_opts* opts,
+                 ils_info* info /* host */);
+
+/* SP-RK-RGS, Algorithm 2: each outer step runs randomized Kaczmarz steps on
+ * A1^T w = bhat (eq. Sec3.32111) interleaved with randomized Gauss-Seidel
+ * steps on A1 z = w (eq. Sec3.33111), both choosing columns of A1 with
+ * probability ||A1_(j)||^2 / ||A1||_F^2, and sets x_{k+1} = z. */
+int ils_rk_solve(ils_handle* h, int64_t p, int64_t q, int64_t n, const double* A, int64_t lda,
+                 const double* b, const double* x0, double* x, const ils_opts* opts,
+                 ils_info* info /* host */);
+
+/* SP-SCD, Algorithm 5: each outer step runs coordinate descent on
+ * A1^T A1 beta = bhat from beta = 0, taking at step t the coordinate of
+ * largest |residual| within a uniformly random subset of size alpha_t. */
+int ils_rgs_solve(ils_handle* h, int64_t p, int64_t q, int64_t n, const double* A, int64_t lda,
+                  const double* b, const double* x0, double* x, const ils_opts* opts,
+                  ils_info* info /* host */);
+
+/* ---- component entry points (used for parity checks of single steps) ---- */
+
+/* G = A[r0:r1, :]^T A[r0:r1, :] (Alg. 1 steps 2-3), full symmetric n x n,
+ * column-major with leading dimension ldg >= n.  precision ILS_PREC_MIXED
+ * rounds A to FP32 and accumulates in FP32 (result widened to FP64). */
+int ils_gram(ils_handle* h, int64_t r0, int64_t r1, int64_t n, const double* A, int64_t lda,
+             double* G, int64_t ldg, int32_t precision);
+
+/* g = A^T J b = A1^T b1 - A2^T b2 and c_j = ||A1_(j)||^2 (Alg. 1 step 4,
+ * Alg. 2 steps 3, 8, 10). */
+int ils_colpass(ils_handle* h, int64_t p, int64_t q, int64_t n, const double* A, int64_t lda,
+                const double* b, double* g, double* colnorm2);
+
+/* r = A^T J (b - A x), the residual of the normal equation (eq. Sec12). */
+int ils_residual(ils_handle* h, int64_t p, int64_t q, int64_t n, const double* A, int64_t lda,
+                 const double* b, const double* x, double* r);
+
+/* X = G^{-1} R for SPD G (n x n, ldg) and R (n x nrhs, ldr), by the block
+ * Gauss-Jordan elimination used inside ils_sp_solve.  Returns
+ * ILS_ERR_NOT_SPD if a pivot block is not positive definite. */
+int ils_spd_solve(ils_handle* h, int64_t n, int64_t nrhs, const double* G, int64_t ldg,
+                  const double* R, int64_t ldr, double* X, int64_t ldx);
+
+/* Index streams of the randomized inner loops for outer step `outer`,
+ * inner steps [t0, t0 + count): j1[i], j2[i] of SP-RK-RGS drawn with
+ * probability weight_j / sum(weight) (weights: device, n), and for SP-SCD
+ * alpha[i] and the bitmask of tau_t (member: count x ceil(n/32) uint32, bit s
+ * of word s/32 set iff s is in the subset).  Outputs are device arrays. */
+int ils_rk_indices(ils_handle* h, uint64_t seed, uint64_t outer, int64_t t0, int64_t count,
+                   const double* weights, int64_t n, int32_t* j1, int32_t* j2);
+int ils_scd_subsets(ils_handle* h, uint64_t seed, uint64_t outer, int64_t t0, int64_t count,
+                    int64_t n, int64_t alpha_opt, int32_t* alpha, uint32_t* member);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

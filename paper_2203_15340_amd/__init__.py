@@ -1,0 +1,259 @@
+"""Python binding of the gfx950 ILS splitting solver (libils.so).
+
+Argument marshalling only: every step of every method runs in the library's
+HIP kernels.  PyTorch supplies device memory and the current stream.  The
+library must have been built (``build.build()``); importing this package
+never falls back to any other implementation, and calls fail loudly if the
+library or a GPU is missing.
+
+Matrices are column-major: pass A as an (m, n) float64 CUDA tensor with
+strides (1, lda), e.g. ``torch.empty(n, lda, dtype=torch.float64,
+device='cuda').t()[:m]`` or ``ils.fortran(A)``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+
+from . import build as _build
+
+OK, ERR_ARG, ERR_NOT_SPD, ERR_NO_CONVERGENCE, ERR_NONFINITE, ERR_HIP, ERR_ALLOC = 0, -1, -2, -3, -4, -5, -6
+STOP_RR, STOP_XREF, STOP_FIXED = 0, 1, 2
+FORM_PAPER, FORM_CORRECTION = 0, 1
+PREC_FP64, PREC_MIXED = 0, 1
+SAMPLE_UNIFORM, SAMPLE_NORM = 0, 1
+
+LIB_PATH = _build.LIB
+EXPORTS = ("ils_create", "ils_destroy", "ils_opts_default", "ils_status_string", "ils_sp_solve",
+           "ils_rk_solve", "ils_rgs_solve", "ils_gram", "ils_colpass", "ils_residual",
+           "ils_spd_solve", "ils_rk_indices", "ils_scd_subsets")
+
+
+class Opts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("stop_rule", C.c_int32), ("form", C.c_int32),
+                ("precision", C.c_int32), ("sampling", C.c_int32), ("x_ref", C.c_void_p),
+                ("max_outer", C.c_int64), ("max_inner", C.c_int64), ("inner_tol", C.c_double),
+                ("inner_check", C.c_int64), ("seed", C.c_uint64), ("stream_offset", C.c_uint64),
+                ("alpha", C.c_int64)]
+
+
+class _Info(C.Structure):
+    _fields_ = [("status", C.c_int32), ("pad", C.c_int32), ("outer_iters", C.c_int64),
+                ("inner_iters", C.c_int64), ("rr", C.c_double), ("rel_err", C.c_double),
+                ("device_ms", C.c_double)]
+
+
+@dataclasses.dataclass
+class Info:
+    status: int
+    outer_iters: int
+    inner_iters: int
+    rr: float
+    rel_err: float
+    device_ms: float
+
+
+class ILSError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libils.so and declare the C ABI.  Raises if the file is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ILSError(f"{path} is missing: build it with paper_2203_15340_amd.build.build()")
+    L = C.CDLL(path)
+    P, I64, U64, I32 = C.c_void_p, C.c_int64, C.c_uint64, C.c_int32
+    solve_args = [P, I64, I64, I64, P, I64, P, P, P, P, P]
+    sig = {
+        "ils_create": (C.c_int, [C.POINTER(P), C.c_int, P]),
+        "ils_destroy": (C.c_int, [P]),
+        "ils_opts_default": (None, [P]),
+        "ils_status_string": (C.c_char_p, [C.c_int]),
+        "ils_sp_solve": (C.c_int, solve_args),
+        "ils_rk_solve": (C.c_int, solve_args),
+        "ils_rgs_solve": (C.c_int, solve_args),
+        "ils_gram": (C.c_int, [P, I64, I64, I64, P, I64, P, I64, I32]),
+        "ils_colpass": (C.c_int, [P, I64, I64, I64, P, I64, P, P, P]),
+        "ils_residual": (C.c_int, [P, I64, I64, I64, P, I64, P, P, P]),
+        "ils_spd_solve": (C.c_int, [P, I64, I64, P, I64, P, I64, P, I64]),
+        "ils_rk_indices": (C.c_int, [P, U64, U64, I64, I64, P, I64, P, P]),
+        "ils_scd_subsets": (C.c_int, [P, U64, U64, I64, I64, I64, I64, P, P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def status_string(code: int) -> str:
+    return load_library().ils_status_string(code).decode()
+
+
+def _torch():
+    import torch
+    return torch
+
+
+_handles = {}
+
+
+def handle(device=None):
+    """Library handle bound to `device` and torch's current stream there."""
+    torch = _torch()
+    if not torch.cuda.is_available():
+        raise ILSError("no GPU visible: the ILS library runs only on the GPU")
+    dev = None if device is None else torch.device(device).index
+    if dev is None:
+        dev = torch.cuda.current_device()
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    key = (dev, stream)
+    if key not in _handles:
+        h = C.c_void_p()
+        rc = load_library().ils_create(C.byref(h), dev, C.c_void_p(stream))
+        if rc != OK:
+            raise ILSError(f"ils_create failed: {status_string(rc)}")
+        _handles[key] = h
+    return _handles[key]
+
+
+def fortran(A):
+    """Column-major copy (or view) of a 2-D tensor: strides (1, m)."""
+    if A.dim() == 2 and A.stride(0) == 1 and A.stride(1) >= max(1, A.shape[0]):
+        return A
+    return A.t().contiguous().t()
+
+
+def _check_vec(v, n, name):
+    if v is None:
+        return None
+    if not v.is_cuda or v.dtype != _torch().float64 or v.numel() != n or not v.is_contiguous():
+        raise ILSError(f"{name} must be a contiguous float64 CUDA tensor with {n} entries")
+    return v
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def make_opts(tol=1e-6, stop_rule=STOP_RR, form=FORM_PAPER, precision=PREC_FP64,
+              sampling=SAMPLE_UNIFORM, x_ref=None, max_outer=20000, max_inner=-1, inner_tol=-1.0,
+              inner_check=-1, seed=0, stream_offset=0, alpha=0):
+    o = Opts()
+    load_library().ils_opts_default(C.byref(o))
+    o.tol, o.stop_rule, o.form, o.precision, o.sampling = tol, stop_rule, form, precision, sampling
+    o.x_ref = None if x_ref is None else x_ref.data_ptr()
+    o.max_outer, o.max_inner, o.inner_tol, o.inner_check = max_outer, max_inner, inner_tol, inner_check
+    o.seed, o.stream_offset, o.alpha = seed, stream_offset, alpha
+    return o
+
+
+def _solve(fname, A, b, p, x0=None, out=None, raise_on_error=False, **kw):
+    torch = _torch()
+    if A.dim() != 2 or A.dtype != torch.float64 or not A.is_cuda or A.stride(0) != 1:
+        raise ILSError("A must be a column-major (stride (1, lda)) float64 CUDA tensor")
+    m, n = A.shape
+    lda = A.stride(1) if n > 1 else max(m, 1)
+    _check_vec(b, m, "b")
+    _check_vec(x0, n, "x0")
+    x_ref = _check_vec(kw.get("x_ref"), n, "x_ref")
+    x = out if out is not None else torch.empty(n, dtype=torch.float64, device=A.device)
+    _check_vec(x, n, "out")
+    o = make_opts(**kw)
+    info = _Info()
+    h = handle(A.device)
+    rc = getattr(load_library(), fname)(h, p, m - p, n, _ptr(A), lda, _ptr(b), _ptr(x0), _ptr(x),
+                                        C.byref(o), C.byref(info))
+    del x_ref
+    res = Info(int(rc), int(info.outer_iters), int(info.inner_iters), float(info.rr),
+               float(info.rel_err), float(info.device_ms))
+    if raise_on_error and rc != OK:
+        raise ILSError(f"{fname}: {status_string(rc)}")
+    return x, res
+
+
+def sp_solve(A, b, p, x0=None, **kw):
+    """SP method (Algorithm 1).  Returns (x, Info)."""
+    return _solve("ils_sp_solve", A, b, p, x0, **kw)
+
+
+def rk_solve(A, b, p, x0=None, **kw):
+    """SP-RK-RGS (Algorithm 2).  Returns (x, Info)."""
+    return _solve("ils_rk_solve", A, b, p, x0, **kw)
+
+
+def rgs_solve(A, b, p, x0=None, **kw):
+    """SP-SCD (Algorithm 5); alpha=1 with sampling=SAMPLE_NORM is SP-RCD."""
+    return _solve("ils_rgs_solve", A, b, p, x0, **kw)
+
+
+def _rc(rc, what):
+    if rc != OK:
+        raise ILSError(f"{what}: {status_string(rc)}")
+
+
+def gram(A, r0, r1, precision=PREC_FP64):
+    """A[r0:r1]^T A[r0:r1] as an (n, n) column-major float64 tensor."""
+    torch = _torch()
+    m, n = A.shape
+    G = torch.empty(n, n, dtype=torch.float64, device=A.device).t()
+    _rc(load_library().ils_gram(handle(A.device), r0, r1, n, _ptr(A), A.stride(1), _ptr(G), n,
+                                precision), "ils_gram")
+    return G
+
+
+def colpass(A, b, p):
+    torch = _torch()
+    m, n = A.shape
+    g = torch.empty(n, dtype=torch.float64, device=A.device)
+    c = torch.empty(n, dtype=torch.float64, device=A.device)
+    rc = load_library().ils_colpass(handle(A.device), p, m - p, n, _ptr(A), A.stride(1), _ptr(b),
+                                    _ptr(g), _ptr(c))
+    return rc, g, c
+
+
+def residual(A, b, p, x):
+    torch = _torch()
+    m, n = A.shape
+    r = torch.empty(n, dtype=torch.float64, device=A.device)
+    _rc(load_library().ils_residual(handle(A.device), p, m - p, n, _ptr(A), A.stride(1), _ptr(b),
+                                    _ptr(x), _ptr(r)), "ils_residual")
+    return r
+
+
+def spd_solve(G, R):
+    """G^{-1} R by block Gauss-Jordan; returns (status, X)."""
+    torch = _torch()
+    n = G.shape[0]
+    nrhs = R.shape[1]
+    X = torch.empty(nrhs, n, dtype=torch.float64, device=G.device).t()
+    rc = load_library().ils_spd_solve(handle(G.device), n, nrhs, _ptr(G), G.stride(1), _ptr(R),
+                                      R.stride(1), _ptr(X), n)
+    return rc, X
+
+
+def rk_indices(seed, outer, t0, count, weights):
+    torch = _torch()
+    j1 = torch.empty(count, dtype=torch.int32, device=weights.device)
+    j2 = torch.empty(count, dtype=torch.int32, device=weights.device)
+    _rc(load_library().ils_rk_indices(handle(weights.device), seed, outer, t0, count, _ptr(weights),
+                                      weights.numel(), _ptr(j1), _ptr(j2)), "ils_rk_indices")
+    return j1, j2
+
+
+def scd_subsets(seed, outer, t0, count, n, alpha_opt=0, device="cuda"):
+    torch = _torch()
+    words = (n + 31) // 32
+    alpha = torch.empty(count, dtype=torch.int32, device=device)
+    mask = torch.empty(count, words, dtype=torch.int32, device=device)
+    _rc(load_library().ils_scd_subsets(handle(device), seed, outer, t0, count, n, alpha_opt,
+                                       _ptr(alpha), _ptr(mask)), "ils_scd_subsets")
+    return alpha, mask

@@ -1,0 +1,344 @@
+// ils_api.hip -- host runtime behind include/ils.h: handle, workspace,
+// argument checks and the drivers that queue the gfx950 kernels.
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "ils_common.hpp"
+#include "ils_runtime.hpp"
+
+using namespace ils;
+
+// ------------------------------------------------------------------ handle
+ils_handle::~ils_handle() {
+  for (auto& b : bufs) if (b.p) (void)hipFree(b.p);
+  if (st) (void)hipFree(st);
+  if (st_host) (void)hipHostFree(st_host);
+  if (ev0) (void)hipEventDestroy(ev0);
+  if (ev1) (void)hipEventDestroy(ev1);
+  if (own_stream && stream) (void)hipStreamDestroy(stream);
+}
+
+int ils_handle::need(int slot, size_t bytes, void** out) {
+  Buf& b = bufs[slot];
+  if (b.cap < bytes) {
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+    size_t want = bytes < 256 ? 256 : bytes;
+    if (hipMalloc(&b.p, want) != hipSuccess) {
+      b.p = nullptr;
+      return ILS_ERR_ALLOC;
+    }
+    b.cap = want;
+  }
+  *out = b.p;
+  return ILS_OK;
+}
+
+extern "C" int ils_create(ils_handle** out, int device_ordinal, void* hip_stream) {
+  if (!out) return ILS_ERR_ARG;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device_ordinal < 0 || device_ordinal >= ndev)
+    return ILS_ERR_ARG;
+  if (hipSetDevice(device_ordinal) != hipSuccess) return ILS_ERR_HIP;
+  ils_handle* h = new ils_handle();
+  h->device = device_ordinal;
+  if (hip_stream) {
+    h->stream = (hipStream_t)hip_stream;
+  } else {
+    if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete h;
+      return ILS_ERR_HIP;
+    }
+    h->own_stream = true;
+  }
+  if (hipMalloc((void**)&h->st, sizeof(LoopState)) != hipSuccess ||
+      hipHostMalloc((void**)&h->st_host, sizeof(LoopState), hipHostMallocDefault) != hipSuccess ||
+      hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess) {
+    delete h;
+    return ILS_ERR_ALLOC;
+  }
+  *out = h;
+  return ILS_OK;
+}
+
+extern "C" int ils_destroy(ils_handle* h) {
+  if (!h) return ILS_ERR_ARG;
+  (void)hipSetDevice(h->device);
+  (void)hipStreamSynchronize(h->stream);
+  delete h;
+  return ILS_OK;
+}
+
+extern "C" void ils_opts_default(ils_opts* o) {
+  if (!o) return;
+  memset(o, 0, sizeof(*o));
+  o->tol = 1e-6;
+  o->stop_rule = ILS_STOP_RR;
+  o->form = ILS_FORM_PAPER;
+  o->precision = ILS_PREC_FP64;
+  o->sampling = ILS_SAMPLE_UNIFORM;
+  o->x_ref = nullptr;
+  o->max_outer = 20000;
+  o->max_inner = -1;
+  o->inner_tol = -1.0;
+  o->inner_check = -1;
+  o->seed = 0;
+  o->stream_offset = 0;
+  o->alpha = 0;
+}
+
+extern "C" const char* ils_status_string(int status) {
+  switch (status) {
+    case ILS_OK: return "ok";
+    case ILS_ERR_ARG: return "invalid argument";
+    case ILS_ERR_NOT_SPD: return "A1^T A1 (hence A^T J A) is not positive definite";
+    case ILS_ERR_NO_CONVERGENCE: return "outer iteration limit reached";
+    case ILS_ERR_NONFINITE: return "non-finite value in the input or an iterate";
+    case ILS_ERR_HIP: return "HIP runtime error";
+    case ILS_ERR_ALLOC: return "device allocation failed";
+    default: return "unknown status";
+  }
+}
+
+// ------------------------------------------------------------------ shared checks
+int ils::check_problem(int64_t p, int64_t q, int64_t n, const double* A, int64_t lda, const double* b,
+                       const double* x, const ils_opts* o) {
+  if (!A || !b || !x || !o) return ILS_ERR_ARG;
+  if (n < 1 || q < 0 || p < n || lda < p + q) return ILS_ERR_ARG;
+  if (n > (int64_t)1 << 20 || p + q > ((int64_t)1 << 40)) return ILS_ERR_ARG;
+  if (o->stop_rule < ILS_STOP_RR || o->stop_rule > ILS_STOP_FIXED) return ILS_ERR_ARG;
+  if (o->stop_rule != ILS_STOP_FIXED && !(o->tol > 0.0)) return ILS_ERR_ARG;
+  if (o->stop_rule == ILS_STOP_XREF && !o->x_ref) return ILS_ERR_ARG;
+  if (o->max_outer < 0) return ILS_ERR_ARG;
+  if (o->form != ILS_FORM_PAPER && o->form != ILS_FORM_CORRECTION) return ILS_ERR_ARG;
+  if (o->precision != ILS_PREC_FP64 && o->precision != ILS_PREC_MIXED) return ILS_ERR_ARG;
+  if (o->precision == ILS_PREC_MIXED && o->form != ILS_FORM_CORRECTION) return ILS_ERR_ARG;
+  if (o->sampling != ILS_SAMPLE_UNIFORM && o->sampling != ILS_SAMPLE_NORM) return ILS_ERR_ARG;
+  return ILS_OK;
+}
+
+static int fail(ils_info* info, int st) {
+  if (info) {
+    memset(info, 0, sizeof(*info));
+    info->status = st;
+    info->rr = NAN;
+    info->rel_err = -1.0;
+  }
+  return st;
+}
+
+#define HIPCHK(expr)                           \
+  do {                                         \
+    if ((expr) != hipSuccess) return ILS_ERR_HIP; \
+  } while (0)
+
+// Relative error ||x - x_ref|| / ||x_ref|| on the device.
+__global__ __launch_bounds__(1024) void k_relerr(int64_t n, const double* __restrict__ x,
+                                                 const double* __restrict__ xr, double* out) {
+  __shared__ double red0[16], red1[16];
+  double a = 0.0, c = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) {
+    const double d = x[i] - xr[i];
+    a += d * d;
+    c += xr[i] * xr[i];
+  }
+  a = block_sum<1024>(a, red0);
+  c = block_sum<1024>(c, red1);
+  if (threadIdx.x == 0) out[0] = sqrt(a) / sqrt(c);
+}
+
+int ils::finish_info(ils_handle* h, int64_t n, double* x, const ils_opts* o, int status,
+                     int64_t outer, int64_t inner, double metric, ils_info* info) {
+  if (!info) return status;
+  info->status = status;
+  info->pad = 0;
+  info->outer_iters = outer;
+  info->inner_iters = inner;
+  info->rr = (o->stop_rule == ILS_STOP_RR) ? metric : NAN;
+  info->rel_err = -1.0;
+  if (o->x_ref && status != ILS_ERR_ARG && status != ILS_ERR_NOT_SPD) {
+    hipLaunchKernelGGL(k_relerr, dim3(1), dim3(1024), 0, h->stream, n, (const double*)x, o->x_ref,
+                       &h->st->scal[7]);
+    double v = -1.0;
+    if (hipMemcpyAsync(&v, &h->st->scal[7], sizeof(double), hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess)
+      return ILS_ERR_HIP;
+    info->rel_err = v;
+  }
+  float ms = 0.0f;
+  if (hipEventElapsedTime(&ms, h->ev0, h->ev1) == hipSuccess) info->device_ms = ms;
+  return status;
+}
+
+// Status of the setup kernels (non-finite input, pivot failure).
+int ils::setup_status(const LoopState& s) {
+  if (s.bits & kBitNonfinite) return ILS_ERR_NONFINITE;
+  if (s.bits & kBitNotSpd) return ILS_ERR_NOT_SPD;
+  return ILS_OK;
+}
+
+int ils::read_state(ils_handle* h) {
+  HIPCHK(hipMemcpyAsync(h->st_host, h->st, sizeof(LoopState), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return ILS_OK;
+}
+
+// ------------------------------------------------------------------ SP
+extern "C" int ils_sp_solve(ils_handle* h, int64_t p, int64_t q, int64_t n, const double* A,
+                            int64_t lda, const double* b, const double* x0, double* x,
+                            const ils_opts* o, ils_info* info) {
+  if (!h) return fail(info, ILS_ERR_ARG);
+  int st = check_problem(p, q, n, A, lda, b, x, o);
+  if (st != ILS_OK) return fail(info, st);
+  if (hipSetDevice(h->device) != hipSuccess) return fail(info, ILS_ERR_HIP);
+  hipStream_t s = h->stream;
+  const int64_t m = p + q;
+  const bool paper = o->form == ILS_FORM_PAPER;
+  const bool need_h = paper && o->stop_rule == ILS_STOP_RR;
+  const int64_t ldw = n;
+  const int64_t nrhs = paper ? n + 1 : n;
+  const int nblk = sp_step_blocks(n);
+  double *g, *W, *Mrow, *H = nullptr, *xb0, *xb1, *tv, *rv, *spart;
+  void* part;
+  int* sbad;
+  size_t part_bytes = std::max(gram_partials_size(n, p), gram_partials_size(n, q)) * sizeof(double);
+  if ((st = h->need(kBufG, sizeof(double) * n, (void**)&g)) ||
+      (st = h->need(kBufW, sizeof(double) * ldw * (n + nrhs), (void**)&W)) ||
+      (st = h->need(kBufM, sizeof(double) * n * n, (void**)&Mrow)) ||
+      (need_h && (st = h->need(kBufH, sizeof(double) * n * n, (void**)&H))) ||
+      (st = h->need(kBufPart, part_bytes, &part)) ||
+      (st = h->need(kBufX0, sizeof(double) * n, (void**)&xb0)) ||
+      (st = h->need(kBufX1, sizeof(double) * n, (void**)&xb1)) ||
+      (st = h->need(kBufT, sizeof(double) * m, (void**)&tv)) ||
+      (st = h->need(kBufR, sizeof(double) * n, (void**)&rv)) ||
+      (st = h->need(kBufSPart, sizeof(double) * nblk, (void**)&spart)) ||
+      (st = h->need(kBufSBad, sizeof(int) * nblk, (void**)&sbad)))
+    return fail(info, st);
+
+  HIPCHK(hipMemsetAsync(h->st, 0, sizeof(LoopState), s));
+  HIPCHK(hipEventRecord(h->ev0, s));
+  LoopState* ds = h->st;
+  launch_colpass(s, p, q, n, A, lda, b, g, nullptr, &ds->bits);
+  if (o->stop_rule == ILS_STOP_RR) launch_norm2(s, n, g, &ds->scal[0]);
+  if (o->stop_rule == ILS_STOP_XREF) launch_norm2(s, n, o->x_ref, &ds->scal[1]);
+  // [A1^T A1 | A2^T A2 | A^T J b] (paper form) or [A1^T A1 | I] (correction form)
+  if (o->precision == ILS_PREC_MIXED)
+    launch_gram_f32(s, p, n, A, lda, (float*)part, W, ldw);
+  else
+    launch_gram_f64(s, p, n, A, lda, (double*)part, W, ldw);
+  if (paper) {
+    launch_gram_f64(s, q, n, A + p, lda, (double*)part, W + n * ldw, ldw);
+    launch_copy_cols(s, n, 1, g, n, W + 2 * n * ldw, ldw);
+    if (need_h) launch_sub(s, n, W, ldw, W + n * ldw, ldw, H, n);
+  } else {
+    launch_eye(s, n, W + n * ldw, ldw);
+  }
+  launch_gj(s, n, nrhs, W, ldw, &ds->bits);
+  launch_transpose(s, n, n, W + n * ldw, ldw, Mrow, n);
+  launch_fill_vec(s, n, x0, xb0);
+
+  SpStepArgs a;
+  a.n = n;
+  a.Mrow = Mrow;
+  a.ldm = n;
+  a.c = W + 2 * n * ldw;
+  a.H = H;
+  a.ldh = n;
+  a.g = g;
+  a.x_ref = o->x_ref;
+  a.xbuf0 = xb0;
+  a.xbuf1 = xb1;
+  a.r = rv;
+  a.partials = spart;
+  a.nonfinite_part = sbad;
+  a.st = ds;
+  a.stop_rule = o->stop_rule;
+  a.tol = o->tol;
+  a.max_outer = o->max_outer;
+  a.form = o->form;
+
+  int64_t k = 0, chunk = 8;
+  while (true) {
+    const int64_t kend = std::min(k + chunk, o->max_outer + 1);
+    for (; k < kend; ++k) {
+      if (!paper) launch_residual(s, p, q, n, A, lda, b, k & 1 ? xb1 : xb0, tv, rv, &ds->done);
+      launch_sp_step(s, a, k);
+    }
+    HIPCHK(hipEventRecord(h->ev1, s));
+    if ((st = read_state(h))) return fail(info, st);
+    if (h->st_host->done || h->st_host->bits || k > o->max_outer) break;
+    chunk = std::min<int64_t>(chunk * 2, 64);
+  }
+  const LoopState& hs = *h->st_host;
+  st = setup_status(hs);
+  if (st != ILS_OK) return fail(info, st);
+  if (!hs.done) return fail(info, ILS_ERR_HIP);  // every queued step ran without finishing
+  st = hs.status;
+  HIPCHK(hipMemcpyAsync(x, (hs.iters & 1) ? xb1 : xb0, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return finish_info(h, n, x, o, st, hs.iters, 0, hs.metric, info);
+}
+
+// ------------------------------------------------------------------ components
+extern "C" int ils_gram(ils_handle* h, int64_t r0, int64_t r1, int64_t n, const double* A, int64_t lda,
+                        double* G, int64_t ldg, int32_t precision) {
+  if (!h || !A || !G || n < 1 || r0 < 0 || r1 < r0 || lda < r1 || ldg < n) return ILS_ERR_ARG;
+  if (precision != ILS_PREC_FP64 && precision != ILS_PREC_MIXED) return ILS_ERR_ARG;
+  HIPCHK(hipSetDevice(h->device));
+  void* part;
+  int st = h->need(kBufPart, gram_partials_size(n, r1 - r0) * sizeof(double), &part);
+  if (st) return st;
+  if (precision == ILS_PREC_MIXED)
+    launch_gram_f32(h->stream, r1 - r0, n, A + r0, lda, (float*)part, G, ldg);
+  else
+    launch_gram_f64(h->stream, r1 - r0, n, A + r0, lda, (double*)part, G, ldg);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return ILS_OK;
+}
+
+extern "C" int ils_colpass(ils_handle* h, int64_t p, int64_t q, int64_t n, const double* A, int64_t lda,
+                           const double* b, double* g, double* colnorm2) {
+  if (!h || !A || !b || !g || n < 1 || p < 0 || q < 0 || lda < p + q) return ILS_ERR_ARG;
+  HIPCHK(hipSetDevice(h->device));
+  HIPCHK(hipMemsetAsync(h->st, 0, sizeof(LoopState), h->stream));
+  launch_colpass(h->stream, p, q, n, A, lda, b, g, colnorm2, &h->st->bits);
+  int st = read_state(h);
+  if (st) return st;
+  return setup_status(*h->st_host);
+}
+
+extern "C" int ils_residual(ils_handle* h, int64_t p, int64_t q, int64_t n, const double* A, int64_t lda,
+                            const double* b, const double* x, double* r) {
+  if (!h || !A || !b || !x || !r || n < 1 || p < 0 || q < 0 || lda < p + q) return ILS_ERR_ARG;
+  HIPCHK(hipSetDevice(h->device));
+  double* tv;
+  int st = h->need(kBufT, sizeof(double) * (p + q > 0 ? p + q : 1), (void**)&tv);
+  if (st) return st;
+  launch_residual(h->stream, p, q, n, A, lda, b, x, tv, r, nullptr);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return ILS_OK;
+}
+
+extern "C" int ils_spd_solve(ils_handle* h, int64_t n, int64_t nrhs, const double* G, int64_t ldg,
+                             const double* R, int64_t ldr, double* X, int64_t ldx) {
+  if (!h || !G || !R || !X || n < 1 || nrhs < 1 || ldg < n || ldr < n || ldx < n) return ILS_ERR_ARG;
+  HIPCHK(hipSetDevice(h->device));
+  double* W;
+  int st = h->need(kBufW, sizeof(double) * n * (n + nrhs), (void**)&W);
+  if (st) return st;
+  HIPCHK(hipMemsetAsync(h->st, 0, sizeof(LoopState), h->stream));
+  launch_copy_cols(h->stream, n, n, G, ldg, W, n);
+  launch_copy_cols(h->stream, n, nrhs, R, ldr, W + n * n, n);
+  launch_gj(h->stream, n, nrhs, W, n, &h->st->bits);
+  launch_copy_cols(h->stream, n, nrhs, W + n * n, n, X, ldx);
+  if ((st = read_state(h))) return st;
+  return setup_status(*h->st_host);
+}

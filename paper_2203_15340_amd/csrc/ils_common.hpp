@@ -1,0 +1,153 @@
+// ils_common.hpp -- internal declarations shared by the gfx950 kernels and the
+// host runtime of the ILS splitting solver.  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ils.h"
+
+namespace ils {
+
+constexpr int kWave = 64;  // CDNA wavefront width
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// Status bits raised on the device; the host maps them to ils_status.
+enum : int {
+  kBitNonfinite = 1,  // NaN/Inf in A or b
+  kBitNotSpd = 2,     // a Gauss-Jordan pivot block is not positive definite
+};
+
+// Device-side state of an outer loop (one per handle).
+struct LoopState {
+  int done;           // 0 running, 1 finished
+  int status;         // ils_status of the finished loop
+  int64_t iters;      // outer updates performed when done
+  double metric;      // stop quantity at the final iterate
+  unsigned int arrive;// last-block counter (reset by the last block)
+  int bits;           // kBit* flags raised by setup kernels
+  int64_t inner_total;// randomized methods: inner steps taken
+  int inner_done;     // randomized methods: inner stop test met
+  unsigned int arrive2;// last-block counter of the inner test
+  int64_t steps;      // SP-SCD: inner steps of the current outer step
+  double scal[8];     // small device scalars: 0 ||A^T J b||^2, 1 ||x_ref||^2,
+                      // 2 ||inner target||^2, 7 relative error
+};
+
+// ---------------------------------------------------------------- reductions
+// Butterfly sum over the 64 lanes of a wavefront.  The pairing order is
+// fixed, so results are reproducible run to run.
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+__device__ inline float wave_sum(float v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// Sum over a workgroup of NT threads; every thread gets the result.  `red`
+// is LDS scratch of NT/64 doubles; the caller alternates two scratch areas
+// between consecutive calls (or separates them by a barrier).
+template <int NT, typename T>
+__device__ inline T block_sum(T v, T* red) {
+  v = wave_sum(v);
+  const int w = threadIdx.x / kWave;
+  if ((threadIdx.x & (kWave - 1)) == 0) red[w] = v;
+  __syncthreads();
+  T s = red[0];
+#pragma unroll
+  for (int i = 1; i < NT / kWave; ++i) s += red[i];
+  return s;
+}
+
+// ---------------------------------------------------------------- PRNG
+// Philox4x64 with 10 rounds (Salmon, Moraes, Dror, Shaw, SC'11).
+__device__ inline void philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                     uint64_t k0, uint64_t k1, uint64_t out[4]) {
+#pragma unroll
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) {
+      k0 += 0x9E3779B97F4A7C15ull;
+      k1 += 0xBB67AE8584CAA73Bull;
+    }
+    const uint64_t lo0 = 0xD2E7470EE14C6C93ull * c0, hi0 = __umul64hi(0xD2E7470EE14C6C93ull, c0);
+    const uint64_t lo1 = 0xCA5A826395121157ull * c2, hi1 = __umul64hi(0xCA5A826395121157ull, c2);
+    const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+// SplitMix64 output function (Steele, Lea, Flood, OOPSLA'14).
+__device__ inline uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__device__ inline double u01(uint64_t v) { return (double)(v >> 11) * (1.0 / 9007199254740992.0); }
+__device__ inline int64_t uniform_below(uint64_t v, int64_t n) { return (int64_t)__umul64hi(v, (uint64_t)n); }
+
+// Method tags in the Philox key: (seed, tag).
+constexpr uint64_t kTagRk = 0x524B524753ull;
+constexpr uint64_t kTagScd = 0x534344ull;
+
+// ---------------------------------------------------------------- launchers
+// Dense building blocks (k_dense.hip).
+void launch_colpass(hipStream_t s, int64_t p, int64_t q, int64_t n, const double* A, int64_t lda,
+                    const double* b, double* g, double* cn, int* bits);
+// r = A^T J (b - A x); t is m doubles of scratch.  Skipped when *done != 0.
+void launch_residual(hipStream_t s, int64_t p, int64_t q, int64_t n, const double* A, int64_t lda,
+                     const double* b, const double* x, double* t, double* r, const int* done);
+// Gram of rows [0, K) of A (A already offset to the first row).  `partials`
+// must hold gram_partials_size(n, K) doubles.
+size_t gram_partials_size(int64_t n, int64_t K);
+void launch_gram_f64(hipStream_t s, int64_t K, int64_t n, const double* A, int64_t lda,
+                     double* partials, double* G, int64_t ldg);
+void launch_gram_f32(hipStream_t s, int64_t K, int64_t n, const double* A, int64_t lda,
+                     float* partials, double* G, int64_t ldg);
+void launch_norm2(hipStream_t s, int64_t n, const double* v, double* out);
+void launch_transpose(hipStream_t s, int64_t n, int64_t ncol, const double* X, int64_t ldx,
+                      double* Y, int64_t ldy);
+void launch_copy_cols(hipStream_t s, int64_t n, int64_t ncol, const double* X, int64_t ldx,
+                      double* Y, int64_t ldy);
+void launch_fill_vec(hipStream_t s, int64_t n, const double* src, double* dst);
+void launch_eye(hipStream_t s, int64_t n, double* Y, int64_t ldy);
+void launch_sub(hipStream_t s, int64_t n, const double* X, int64_t ldx, const double* Y, int64_t ldy,
+                double* Z, int64_t ldz);
+
+// Block Gauss-Jordan on W = [G | R] (n x (n + nrhs), column-major, ldw).
+void launch_gj(hipStream_t s, int64_t n, int64_t nrhs, double* W, int64_t ldw, int* bits);
+
+// SP outer step kernels (k_sp.hip).
+struct SpStepArgs {
+  int64_t n;
+  const double* Mrow;   // n x n row-major iteration matrix (paper form) or P (correction form)
+  int64_t ldm;
+  const double* c;      // n, paper form constant
+  const double* H;      // n x n column-major A^T J A (RR metric, paper form), or null
+  int64_t ldh;
+  const double* g;      // A^T J b
+  const double* x_ref;  // XREF metric
+  double* xbuf0;
+  double* xbuf1;
+  const double* r;      // correction form: residual at x_k (n)
+  double* partials;     // per-block metric partials
+  int* nonfinite_part;  // per-block flags
+  LoopState* st;
+  int stop_rule;
+  double tol;
+  int64_t max_outer;
+  int form;
+};
+int sp_step_blocks(int64_t n);
+void launch_sp_step(hipStream_t s, const SpStepArgs& a, int64_t k);
+
+}  // namespace ils

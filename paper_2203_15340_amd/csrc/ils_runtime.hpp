@@ -1,0 +1,59 @@
+// ils_runtime.hpp -- the handle behind the opaque ils_handle of include/ils.h
+// and helpers shared by the solver drivers.
+#pragma once
+#include "ils_common.hpp"
+
+namespace ils {
+
+// Workspace slots owned by a handle.
+enum BufSlot {
+  kBufG = 0,    // A^T J b
+  kBufCn,       // squared column norms of A1
+  kBufW,        // Gauss-Jordan work matrix / A1^T A1
+  kBufM,        // iteration matrix, row-major
+  kBufH,        // A^T J A (RR test in the paper form)
+  kBufG2,       // A2^T A2
+  kBufPart,     // Gram split-K partial tiles
+  kBufX0,
+  kBufX1,
+  kBufT,        // m-vector scratch
+  kBufR,        // n-vector scratch (residual / right-hand side)
+  kBufSPart,    // per-block partial sums
+  kBufSBad,     // per-block flags
+  kBufW1,       // randomized inner state (w)
+  kBufS1,       // randomized inner state (s)
+  kBufZ,        // randomized inner state (z / beta)
+  kBufIdx,      // pre-drawn index streams
+  kBufMask,     // pre-drawn SCD subsets
+  kBufPrefix,   // sampler prefix sums
+  kBufA1f,      // FP32 copy of A1
+  kBufCount
+};
+
+struct Buf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
+}  // namespace ils
+
+struct ils_handle {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  ils::Buf bufs[ils::kBufCount];
+  ils::LoopState* st = nullptr;       // device
+  ils::LoopState* st_host = nullptr;  // pinned host mirror
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  ~ils_handle();
+  int need(int slot, size_t bytes, void** out);
+};
+
+namespace ils {
+int check_problem(int64_t p, int64_t q, int64_t n, const double* A, int64_t lda, const double* b,
+                  const double* x, const ils_opts* o);
+int finish_info(ils_handle* h, int64_t n, double* x, const ils_opts* o, int status, int64_t outer,
+                int64_t inner, double metric, ils_info* info);
+int setup_status(const LoopState& s);
+int read_state(ils_handle* h);
+}  // namespace ils

@@ -1,0 +1,472 @@
+// k_rand.hip -- kernels of the randomized inner loops on gfx950:
+//   * pre-drawing the column indices of SP-RK-RGS (Alg. 2 steps 8 and 10) and
+//     the subsets of SP-SCD (Alg. 5 steps 7-8) for a block of inner steps,
+//     all steps in parallel (the draws never depend on the iterate);
+//   * the inner loops themselves, one workgroup per problem, which are a
+//     chain of dependent reductions and cannot be spread across the chip;
+//   * the per-outer-step helpers (right-hand side, stop test, update).
+#include "ils_common.hpp"
+#include "k_rand.hpp"
+
+namespace ils {
+
+__device__ inline int coherent_load(const int* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ------------------------------------------------------------------ samplers
+// Inclusive prefix sums in index order by a single thread, so that the
+// weighted draw compares against exactly reproducible boundaries.
+__global__ void k_prefix(int64_t n, const double* __restrict__ w, int64_t ldw_stride,
+                         double* __restrict__ prefix) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s = 0.0;
+  for (int64_t j = 0; j < n; ++j) {
+    s += w[j * ldw_stride];
+    prefix[j] = s;
+  }
+}
+
+void launch_prefix(hipStream_t s, int64_t n, const double* w, int64_t stride, double* prefix) {
+  hipLaunchKernelGGL(k_prefix, dim3(1), dim3(64), 0, s, n, w, stride, prefix);
+}
+
+// Smallest j with prefix[j] > u * prefix[n-1]; if rounding leaves none, the
+// last index of positive weight.
+__device__ inline int weighted_pick(const double* __restrict__ prefix, int64_t n, double u) {
+  const double thr = u * prefix[n - 1];
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = lo + (hi - lo) / 2;
+    if (prefix[mid] > thr) hi = mid;
+    else lo = mid + 1;
+  }
+  if (lo < n) return (int)lo;
+  int64_t j = n - 1;
+  while (j > 0 && prefix[j] == prefix[j - 1]) --j;
+  return (int)j;
+}
+
+// SP-RK-RGS draws for inner steps [t0, t0 + count) of one outer step:
+// counter (t, outer, 0, 0), key (seed, tag); j1 from word 0, j2 from word 1.
+__global__ __launch_bounds__(256) void k_rk_draw(uint64_t seed, uint64_t outer, int64_t t0,
+                                                 int64_t count, const double* __restrict__ prefix,
+                                                 int64_t n, int* __restrict__ j1,
+                                                 int* __restrict__ j2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  uint64_t out[4];
+  philox4x64_10((uint64_t)(t0 + i), outer, 0, 0, seed, kTagRk, out);
+  j1[i] = weighted_pick(prefix, n, u01(out[0]));
+  j2[i] = weighted_pick(prefix, n, u01(out[1]));
+}
+
+void launch_rk_draw(hipStream_t s, uint64_t seed, uint64_t outer, int64_t t0, int64_t count,
+                    const double* prefix, int64_t n, int* j1, int* j2) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_rk_draw, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, seed, outer,
+                     t0, count, prefix, n, j1, j2);
+}
+
+// SP-SCD draws, one workgroup per inner step.  alpha_t is uniform on {1..n}
+// (word 0) unless fixed.  With norm sampling the column is drawn from the
+// weights (word 1).  Otherwise tau_t holds the alpha_t indices with the
+// smallest keys (SplitMix64 stream seeded with word 2, low index bits
+// replaced by the index); the alpha_t-th smallest key is found by an 8-pass
+// radix select over LDS histograms, and tau_t is written as a bitmask.
+__global__ __launch_bounds__(256) void k_scd_draw(uint64_t seed, uint64_t outer, int64_t t0,
+                                                  int64_t n, int64_t alpha_opt, int norm_mode,
+                                                  const double* __restrict__ prefix,
+                                                  int* __restrict__ alpha_out, int* __restrict__ jout,
+                                                  uint32_t* __restrict__ mask, int64_t mask_words) {
+  __shared__ uint64_t keys[kScdMaxN];
+  __shared__ unsigned hist[256];
+  __shared__ uint64_t sel_prefix;
+  __shared__ int64_t sel_rank;
+  const int64_t t = blockIdx.x;
+  uint64_t out[4];
+  philox4x64_10((uint64_t)(t0 + t), outer, 0, 0, seed, kTagScd, out);
+  const int64_t alpha = alpha_opt > 0 ? (alpha_opt < n ? alpha_opt : n) : 1 + uniform_below(out[0], n);
+  if (threadIdx.x == 0) alpha_out[t] = (int)alpha;
+  uint32_t* mrow = mask + t * mask_words;
+  if (norm_mode) {
+    if (threadIdx.x == 0) jout[t] = weighted_pick(prefix, n, u01(out[1]));
+    return;
+  }
+  if (alpha >= n) {
+    for (int64_t wd = threadIdx.x; wd < mask_words; wd += 256) {
+      const int64_t lo = wd * 32, cnt = n - lo;
+      mrow[wd] = cnt >= 32 ? 0xFFFFFFFFu : ((1u << cnt) - 1u);
+    }
+    return;
+  }
+  int b = 1;
+  while (b < 63 && ((int64_t)1 << b) < n) ++b;
+  for (int64_t s = threadIdx.x; s < n; s += 256) {
+    const uint64_t h = mix64(out[2] + (uint64_t)(s + 1) * 0x9E3779B97F4A7C15ull);
+    keys[s] = ((h >> b) << b) | (uint64_t)s;
+  }
+  if (threadIdx.x == 0) {
+    sel_prefix = 0;
+    sel_rank = alpha - 1;
+  }
+  __syncthreads();
+  for (int pass = 0; pass < 8; ++pass) {
+    const int shift = 56 - 8 * pass;
+    const uint64_t hmask = pass == 0 ? 0ull : (~0ull << (shift + 8));
+    for (int i = threadIdx.x; i < 256; i += 256) hist[i] = 0;
+    __syncthreads();
+    const uint64_t pre = sel_prefix;
+    for (int64_t s = threadIdx.x; s < n; s += 256) {
+      const uint64_t k = keys[s];
+      if ((k & hmask) == pre) atomicAdd(&hist[(k >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int64_t rank = sel_rank, cum = 0;
+      int d = 0;
+      for (; d < 255; ++d) {
+        if (cum + (int64_t)hist[d] > rank) break;
+        cum += hist[d];
+      }
+      sel_rank = rank - cum;
+      sel_prefix = pre | ((uint64_t)d << shift);
+    }
+    __syncthreads();
+  }
+  const uint64_t thr = sel_prefix;  // exact key of rank alpha - 1
+  for (int64_t wd = threadIdx.x; wd < mask_words; wd += 256) {
+    uint32_t bits = 0;
+    for (int e = 0; e < 32; ++e) {
+      const int64_t s = wd * 32 + e;
+      if (s < n && keys[s] <= thr) bits |= 1u << e;
+    }
+    mrow[wd] = bits;
+  }
+}
+
+void launch_scd_draw(hipStream_t s, uint64_t seed, uint64_t outer, int64_t t0, int64_t count, int64_t n,
+                     int64_t alpha_opt, int norm_mode, const double* prefix, int* alpha, int* jout,
+                     uint32_t* mask, int64_t mask_words) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_scd_draw, dim3((unsigned)count), dim3(256), 0, s, seed, outer, t0, n, alpha_opt,
+                     norm_mode, prefix, alpha, jout, mask, mask_words);
+}
+
+// ------------------------------------------------------------------ RK-RGS inner
+// One workgroup runs `count` inner steps of Alg. 2 (steps 8-11) in the
+// incremental form: with s = w - A1 z,
+//   gamma = (bhat_j1 - A1_(j1)^T w) / c_j1,  w += gamma A1_(j1),  s += gamma A1_(j1)
+//   delta = A1_(j2)^T s / c_j2,  z_j2 += delta,  s -= delta A1_(j2).
+// Each thread owns the rows i = tid + e * 1024 of w and s, so the only
+// synchronisation is the two block reductions per step.
+constexpr int kRkThreads = 1024;
+
+__global__ __launch_bounds__(kRkThreads) void k_rk_inner(const double* __restrict__ A1, int64_t lda,
+                                                         int64_t p, const double* __restrict__ tgt,
+                                                         const double* __restrict__ cn,
+                                                         const int* __restrict__ j1s,
+                                                         const int* __restrict__ j2s, int64_t count,
+                                                         double* __restrict__ w, double* __restrict__ s,
+                                                         double* __restrict__ z,
+                                                         const int* inner_done, const int* outer_done) {
+  if (*(volatile const int*)inner_done || *(volatile const int*)outer_done) return;
+  __shared__ double red[2][kRkThreads / kWave];
+  const int tid = threadIdx.x;
+  for (int64_t t = 0; t < count; ++t) {
+    const int j1 = j1s[t], j2 = j2s[t];
+    const double* a1 = A1 + (int64_t)j1 * lda;
+    const double* a2 = A1 + (int64_t)j2 * lda;
+    double d = 0.0;
+    for (int64_t i = tid; i < p; i += kRkThreads) d += a1[i] * w[i];
+    d = block_sum<kRkThreads>(d, red[0]);
+    const double gam = (tgt[j1] - d) / cn[j1];
+    double d2 = 0.0;
+    for (int64_t i = tid; i < p; i += kRkThreads) {
+      const double av = a1[i];
+      w[i] += gam * av;
+      const double sv = s[i] + gam * av;
+      s[i] = sv;
+      d2 += a2[i] * sv;
+    }
+    d2 = block_sum<kRkThreads>(d2, red[1]);
+    const double del = d2 / cn[j2];
+    if (tid == 0) z[j2] += del;
+    for (int64_t i = tid; i < p; i += kRkThreads) s[i] -= del * a2[i];
+  }
+}
+
+void launch_rk_inner(hipStream_t st, const double* A1, int64_t lda, int64_t p, const double* tgt,
+                     const double* cn, const int* j1, const int* j2, int64_t count, double* w, double* s,
+                     double* z, const int* inner_done, const int* outer_done) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_rk_inner, dim3(1), dim3(kRkThreads), 0, st, A1, lda, p, tgt, cn, j1, j2, count, w,
+                     s, z, inner_done, outer_done);
+}
+
+// Inner stop test of SP-RK-RGS: ||bhat - A1^T (w - s)|| <= tol * ||bhat||
+// (A1 z = w - s).  Pass 1 forms v = w - s, pass 2 is one workgroup per
+// column; the last workgroup adds the squared entries in column order.
+__global__ void k_sub_vec(int64_t p, const double* __restrict__ w, const double* __restrict__ s,
+                          double* __restrict__ v, const int* skip) {
+  if (*(volatile const int*)skip) return;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < p; i += (int64_t)gridDim.x * blockDim.x)
+    v[i] = w[i] - s[i];
+}
+
+__global__ __launch_bounds__(256) void k_rk_check(const double* __restrict__ A1, int64_t lda, int64_t p,
+                                                  int64_t n, const double* __restrict__ v,
+                                                  const double* __restrict__ tgt,
+                                                  double* __restrict__ res2, double itol2,
+                                                  const double* tn2, int* inner_done, unsigned* arrive,
+                                                  const int* skip) {
+  if (*(volatile const int*)skip) return;
+  __shared__ double red[4];
+  const int64_t j = blockIdx.x;
+  const double* col = A1 + j * lda;
+  double sacc = 0.0;
+  for (int64_t i = threadIdx.x; i < p; i += 256) sacc += col[i] * v[i];
+  sacc = block_sum<256>(sacc, red);
+  if (threadIdx.x != 0) return;
+  const double rj = tgt[j] - sacc;
+  res2[j] = rj * rj;
+  __threadfence();
+  if (atomicAdd(arrive, 1u) != gridDim.x - 1) return;
+  __threadfence();
+  double tot = 0.0;
+  for (int64_t jj = 0; jj < n; ++jj) tot += __hip_atomic_load(res2 + jj, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  *arrive = 0;
+  if (tot <= itol2 * (*tn2)) *inner_done = 1;
+}
+
+void launch_rk_check(hipStream_t st, const double* A1, int64_t lda, int64_t p, int64_t n, const double* w,
+                     const double* s, double* v, const double* tgt, double* res2, double itol2,
+                     const double* tn2, int* inner_done, unsigned* arrive, const int* skip) {
+  hipLaunchKernelGGL(k_sub_vec, dim3(64), dim3(256), 0, st, p, w, s, v, skip);
+  hipLaunchKernelGGL(k_rk_check, dim3((unsigned)n), dim3(256), 0, st, A1, lda, p, n, (const double*)v, tgt,
+                     res2, itol2, tn2, inner_done, arrive, skip);
+}
+
+// ------------------------------------------------------------------ SCD inner
+// One workgroup runs up to `count` inner steps of Alg. 5 (steps 7-11):
+// before each step it forms ||r||^2 (stop test) and, over the members of
+// tau_t, the entry of largest |r| (smallest index on ties) in one block
+// reduction, then r -= r_j / G1_jj * G1_(j) and beta_j += r_j / G1_jj.
+constexpr int kScdThreads = 1024;
+
+struct ArgMax {
+  double v;   // |r_s|
+  double r;   // r_s
+  int idx;
+};
+
+__device__ inline bool better(double v, int i, double bv, int bi) {
+  return v > bv || (v == bv && i < bi);
+}
+
+__global__ __launch_bounds__(kScdThreads) void k_scd_inner(
+    const double* __restrict__ G1, int64_t ldg, int64_t n, double* __restrict__ r,
+    double* __restrict__ beta, const uint32_t* __restrict__ mask, int64_t mask_words,
+    const int* __restrict__ jpre, int norm_mode, int64_t count, int check, double itol2,
+    const double* tn2, int* inner_done, int64_t* steps_done, const int* outer_done) {
+  if (*(volatile const int*)inner_done || *(volatile const int*)outer_done) return;
+  __shared__ double red_n[2][kScdThreads / kWave];
+  __shared__ double red_v[2][kScdThreads / kWave];
+  __shared__ double red_r[2][kScdThreads / kWave];
+  __shared__ int red_i[2][kScdThreads / kWave];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const double stop2 = itol2 * (*tn2);
+  int64_t t = 0;
+  for (; t <= count; ++t) {
+    const int par = (int)(t & 1);
+    const uint32_t* mrow = mask + t * mask_words;
+    double nrm = 0.0, bv = -1.0, br = 0.0;
+    int bi = 0x7FFFFFFF;
+    for (int64_t sidx = tid; sidx < n; sidx += kScdThreads) {
+      const double rv = r[sidx];
+      nrm += rv * rv;
+      if (!norm_mode && t < count && ((mrow[sidx >> 5] >> (sidx & 31)) & 1u)) {
+        const double av = fabs(rv);
+        if (better(av, (int)sidx, bv, bi)) {
+          bv = av;
+          br = rv;
+          bi = (int)sidx;
+        }
+      }
+    }
+    // wave reduction (fixed butterfly), then across waves in wave order
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      nrm += __shfl_xor(nrm, off, kWave);
+      const double ov = __shfl_xor(bv, off, kWave), orr = __shfl_xor(br, off, kWave);
+      const int oi = __shfl_xor(bi, off, kWave);
+      if (better(ov, oi, bv, bi)) {
+        bv = ov;
+        br = orr;
+        bi = oi;
+      }
+    }
+    if (lane == 0) {
+      red_n[par][wv] = nrm;
+      red_v[par][wv] = bv;
+      red_r[par][wv] = br;
+      red_i[par][wv] = bi;
+    }
+    __syncthreads();
+    nrm = red_n[par][0];
+    bv = red_v[par][0];
+    br = red_r[par][0];
+    bi = red_i[par][0];
+    for (int q = 1; q < kScdThreads / kWave; ++q) {
+      nrm += red_n[par][q];
+      if (better(red_v[par][q], red_i[par][q], bv, bi)) {
+        bv = red_v[par][q];
+        br = red_r[par][q];
+        bi = red_i[par][q];
+      }
+    }
+    if (check && nrm <= stop2) {
+      if (tid == 0) *inner_done = 1;
+      break;
+    }
+    if (t == count) break;
+    int j;
+    double rj;
+    if (norm_mode) {
+      j = jpre[t];
+      rj = r[j];  // each thread reads r_j; only updates below write r
+    } else {
+      j = bi;
+      rj = br;
+    }
+    if (j < 0 || j >= n) break;  // no finite candidate: the outer update flags it
+    __syncthreads();  // everyone has read r_j before it is overwritten
+    const double gam = rj / G1[(int64_t)j * ldg + j];
+    const double* col = G1 + (int64_t)j * ldg;
+    for (int64_t sidx = tid; sidx < n; sidx += kScdThreads) r[sidx] -= gam * col[sidx];
+    if (tid == 0) beta[j] += gam;
+  }
+  if (tid == 0) *steps_done += (t < count ? t : count);
+}
+
+void launch_scd_inner(hipStream_t st, const double* G1, int64_t ldg, int64_t n, double* r, double* beta,
+                      const uint32_t* mask, int64_t mask_words, const int* jpre, int norm_mode,
+                      int64_t count, int check, double itol2, const double* tn2, int* inner_done,
+                      int64_t* steps_done, const int* outer_done) {
+  hipLaunchKernelGGL(k_scd_inner, dim3(1), dim3(kScdThreads), 0, st, G1, ldg, n, r, beta, mask,
+                     mask_words, jpre, norm_mode, count, check, itol2, tn2, inner_done, steps_done,
+                     outer_done);
+}
+
+// ------------------------------------------------------------------ outer helpers
+// y = G x + g for symmetric G (column i = row i), one wave per row.
+__global__ __launch_bounds__(256) void k_symv_add(int64_t n, const double* __restrict__ G, int64_t ldg,
+                                                  const double* __restrict__ x,
+                                                  const double* __restrict__ g, double* __restrict__ y,
+                                                  const int* skip) {
+  if (*(volatile const int*)skip) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= n) return;
+  const double* gc = G + i * ldg;
+  double sacc = 0.0;
+  for (int64_t j = lane; j < n; j += kWave) sacc += gc[j] * x[j];
+  sacc = wave_sum(sacc);
+  if (lane == 0) y[i] = sacc + g[i];
+}
+
+void launch_symv_add(hipStream_t s, int64_t n, const double* G, int64_t ldg, const double* x,
+                     const double* g, double* y, const int* skip) {
+  hipLaunchKernelGGL(k_symv_add, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, n, G, ldg, x, g, y, skip);
+}
+
+// Stop test at x_k for the randomized methods (same rules as the SP step):
+// metric from x_ref or from the residual r_k; ||target||^2 for the inner test.
+__global__ __launch_bounds__(1024) void k_outer_test(int64_t n, const double* __restrict__ xk,
+                                                     const double* __restrict__ x_ref,
+                                                     const double* __restrict__ rk, int stop_rule,
+                                                     double tol, int64_t k, int64_t max_outer,
+                                                     LoopState* st) {
+  if (st->done || st->bits) return;
+  __shared__ double red[1024 / kWave];
+  double a = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) {
+    if (stop_rule == ILS_STOP_XREF) {
+      const double d = xk[i] - x_ref[i];
+      a += d * d;
+    } else if (stop_rule == ILS_STOP_RR) {
+      a += rk[i] * rk[i];
+    }
+  }
+  a = block_sum<1024>(a, red);
+  if (threadIdx.x != 0) return;
+  double metric = 0.0;
+  if (stop_rule == ILS_STOP_XREF) metric = sqrt(a) / sqrt(st->scal[1]);
+  else if (stop_rule == ILS_STOP_RR) metric = a / st->scal[0];
+  if (stop_rule != ILS_STOP_FIXED && metric < tol) {
+    st->metric = metric;
+    st->status = ILS_OK;
+    st->iters = k;
+    st->done = 1;
+  } else if (k == max_outer) {
+    st->metric = metric;
+    st->status = stop_rule == ILS_STOP_FIXED ? ILS_OK : ILS_ERR_NO_CONVERGENCE;
+    st->iters = k;
+    st->done = 1;
+  }
+}
+
+void launch_outer_test(hipStream_t s, int64_t n, const double* xk, const double* x_ref, const double* rk,
+                       int stop_rule, double tol, int64_t k, int64_t max_outer, LoopState* st) {
+  hipLaunchKernelGGL(k_outer_test, dim3(1), dim3(1024), 0, s, n, xk, x_ref, rk, stop_rule, tol, k,
+                     max_outer, st);
+}
+
+// x_{k+1} = z (paper form) or x_k + z (correction form); a non-finite entry
+// ends the loop with ILS_ERR_NONFINITE at k + 1.
+__global__ __launch_bounds__(1024) void k_outer_update(int64_t n, const double* __restrict__ xk,
+                                                       const double* __restrict__ z, int correction,
+                                                       double* __restrict__ xn, int64_t k, LoopState* st) {
+  if (st->done || st->bits) return;
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  int mybad = 0;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) {
+    const double v = correction ? xk[i] + z[i] : z[i];
+    xn[i] = v;
+    mybad |= !isfinite(v);
+  }
+  if (mybad) atomicOr(&bad, 1);
+  __syncthreads();
+  if (threadIdx.x == 0 && bad) {
+    st->status = ILS_ERR_NONFINITE;
+    st->iters = k + 1;
+    st->done = 1;
+  }
+}
+
+void launch_outer_update(hipStream_t s, int64_t n, const double* xk, const double* z, int correction,
+                         double* xn, int64_t k, LoopState* st) {
+  hipLaunchKernelGGL(k_outer_update, dim3(1), dim3(1024), 0, s, n, xk, z, correction, xn, k, st);
+}
+
+__global__ void k_diag(int64_t n, const double* __restrict__ G, int64_t ldg, double* __restrict__ d) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    d[i] = G[i * ldg + i];
+}
+
+void launch_diag(hipStream_t s, int64_t n, const double* G, int64_t ldg, double* d) {
+  hipLaunchKernelGGL(k_diag, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, G, ldg, d);
+}
+
+__global__ void k_zero_cnt(int64_t n, const double* __restrict__ c, int* bits) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    if (!(c[i] > 0.0)) atomicOr(bits, kBitNotSpd);
+}
+
+void launch_zero_col_check(hipStream_t s, int64_t n, const double* c, int* bits) {
+  hipLaunchKernelGGL(k_zero_cnt, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, c, bits);
+}
+
+}  // namespace ils

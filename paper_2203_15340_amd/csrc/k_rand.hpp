@@ -1,0 +1,34 @@
+// k_rand.hpp -- launchers of the randomized inner-loop kernels (k_rand.hip).
+#pragma once
+#include "ils_common.hpp"
+
+namespace ils {
+
+constexpr int64_t kScdMaxN = 4096;  // largest n for SP-SCD with random subsets (LDS keys)
+
+void launch_prefix(hipStream_t s, int64_t n, const double* w, int64_t stride, double* prefix);
+void launch_rk_draw(hipStream_t s, uint64_t seed, uint64_t outer, int64_t t0, int64_t count,
+                    const double* prefix, int64_t n, int* j1, int* j2);
+void launch_scd_draw(hipStream_t s, uint64_t seed, uint64_t outer, int64_t t0, int64_t count, int64_t n,
+                     int64_t alpha_opt, int norm_mode, const double* prefix, int* alpha, int* jout,
+                     uint32_t* mask, int64_t mask_words);
+void launch_rk_inner(hipStream_t st, const double* A1, int64_t lda, int64_t p, const double* tgt,
+                     const double* cn, const int* j1, const int* j2, int64_t count, double* w, double* s,
+                     double* z, const int* inner_done, const int* outer_done);
+void launch_rk_check(hipStream_t st, const double* A1, int64_t lda, int64_t p, int64_t n, const double* w,
+                     const double* s, double* v, const double* tgt, double* res2, double itol2,
+                     const double* tn2, int* inner_done, unsigned* arrive, const int* skip);
+void launch_scd_inner(hipStream_t st, const double* G1, int64_t ldg, int64_t n, double* r, double* beta,
+                      const uint32_t* mask, int64_t mask_words, const int* jpre, int norm_mode,
+                      int64_t count, int check, double itol2, const double* tn2, int* inner_done,
+                      int64_t* steps_done, const int* outer_done);
+void launch_symv_add(hipStream_t s, int64_t n, const double* G, int64_t ldg, const double* x,
+                     const double* g, double* y, const int* skip);
+void launch_outer_test(hipStream_t s, int64_t n, const double* xk, const double* x_ref, const double* rk,
+                       int stop_rule, double tol, int64_t k, int64_t max_outer, LoopState* st);
+void launch_outer_update(hipStream_t s, int64_t n, const double* xk, const double* z, int correction,
+                         double* xn, int64_t k, LoopState* st);
+void launch_diag(hipStream_t s, int64_t n, const double* G, int64_t ldg, double* d);
+void launch_zero_col_check(hipStream_t s, int64_t n, const double* c, int* bits);
+
+}  // namespace ils

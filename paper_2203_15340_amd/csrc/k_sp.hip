@@ -1,0 +1,111 @@
+// k_sp.hip -- one outer step of the SP iteration (Algorithm 1, step 6) with
+// its stopping test, as a single launch that needs no host round trip.
+//
+// Launch k reads x_k and writes x_{k+1}:
+//   paper form      x_{k+1} = B x_k + c            (B = (A1^T A1)^{-1} A2^T A2)
+//   correction form x_{k+1} = x_k + P r_k          (P = (A1^T A1)^{-1},
+//                                                    r_k = A^T J (b - A x_k))
+// It also evaluates the stop quantity at x_k (RR of Sec. 5, or the relative
+// error against x_ref).  Each workgroup handles four rows (one per wave) and
+// writes a partial sum; the last workgroup to arrive adds the partials in
+// block order and records the outcome in LoopState.  The host queues several
+// steps ahead; a launch that finds the loop finished returns at once.
+#include "ils_common.hpp"
+
+namespace ils {
+
+constexpr int kSpRows = 4;
+
+__device__ inline double load_coherent(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline int load_coherent(const int* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ __launch_bounds__(256) void k_sp_step(SpStepArgs a, int64_t k) {
+  LoopState* st = a.st;
+  if (*(volatile int*)&st->done || *(volatile int*)&st->bits) return;
+  const double* xk = (k & 1) ? a.xbuf1 : a.xbuf0;
+  double* xn = (k & 1) ? a.xbuf0 : a.xbuf1;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * kSpRows + w;
+  double mp = 0.0;
+  int bad = 0;
+  if (i < a.n) {
+    const double* row = a.Mrow + i * a.ldm;
+    const double* v = (a.form == ILS_FORM_PAPER) ? xk : a.r;
+    double s = 0.0;
+    for (int64_t j = lane; j < a.n; j += kWave) s += row[j] * v[j];
+    s = wave_sum(s);
+    const double xi = (a.form == ILS_FORM_PAPER) ? s + a.c[i] : xk[i] + s;
+    if (a.stop_rule == ILS_STOP_XREF) {
+      const double d = xk[i] - a.x_ref[i];
+      mp = d * d;
+    } else if (a.stop_rule == ILS_STOP_RR) {
+      double ri;
+      if (a.form == ILS_FORM_PAPER) {  // (A^T J b - A^T J A x_k)_i, A^T J A symmetric
+        const double* hc = a.H + i * a.ldh;
+        double h = 0.0;
+        for (int64_t j = lane; j < a.n; j += kWave) h += hc[j] * xk[j];
+        ri = a.g[i] - wave_sum(h);
+      } else {
+        ri = a.r[i];
+      }
+      mp = ri * ri;
+    }
+    if (lane == 0) xn[i] = xi;
+    bad = !isfinite(xi);
+  }
+  __shared__ double red[kSpRows];
+  __shared__ int redb[kSpRows];
+  if (lane == 0) {
+    red[w] = mp;
+    redb[w] = bad;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  a.partials[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+  a.nonfinite_part[blockIdx.x] = redb[0] | redb[1] | redb[2] | redb[3];
+  __threadfence();
+  const unsigned prev = atomicAdd(&st->arrive, 1u);
+  if (prev != gridDim.x - 1) return;
+  __threadfence();
+  double tot = 0.0;
+  int anybad = 0;
+  for (unsigned bkt = 0; bkt < gridDim.x; ++bkt) {
+    tot += load_coherent(a.partials + bkt);
+    anybad |= load_coherent(a.nonfinite_part + bkt);
+  }
+  double metric = 0.0;
+  if (a.stop_rule == ILS_STOP_XREF) metric = sqrt(tot) / sqrt(st->scal[1]);
+  else if (a.stop_rule == ILS_STOP_RR) metric = tot / st->scal[0];
+  st->arrive = 0;
+  int done = 0, status = ILS_OK;
+  int64_t iters = k;
+  if (a.stop_rule != ILS_STOP_FIXED && metric < a.tol) {
+    done = 1;
+  } else if (k == a.max_outer) {
+    done = 1;
+    status = (a.stop_rule == ILS_STOP_FIXED) ? ILS_OK : ILS_ERR_NO_CONVERGENCE;
+  } else if (anybad) {
+    done = 1;
+    status = ILS_ERR_NONFINITE;
+    iters = k + 1;
+  }
+  if (done) {
+    st->metric = metric;
+    st->status = status;
+    st->iters = iters;
+    __threadfence();
+    st->done = 1;
+  }
+}
+
+int sp_step_blocks(int64_t n) { return (int)((n + kSpRows - 1) / kSpRows); }
+
+void launch_sp_step(hipStream_t s, const SpStepArgs& a, int64_t k) {
+  hipLaunchKernelGGL(k_sp_step, dim3((unsigned)sp_step_blocks(a.n)), dim3(256), 0, s, a, k);
+}
+
+}  // namespace ils
