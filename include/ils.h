@@ -176,6 +176,21 @@ int ils_rk_indices(ils_handle* h, uint64_t seed, uint64_t outer, int64_t t0, int
 int ils_scd_subsets(ils_handle* h, uint64_t seed, uint64_t outer, int64_t t0, int64_t count,
                     int64_t n, int64_t alpha_opt, int32_t* alpha, uint32_t* member);
 
+/* ---- instrumentation ---- */
+
+/* Turn phase timing of ils_sp_solve on (enable != 0) or off.  When on, the
+ * library records HIP events between the phases of each solve on the
+ * handle's stream; kernel work is unchanged. */
+int ils_set_profiling(ils_handle* h, int enable);
+
+/* Durations in ms of the phases of the last profiled ils_sp_solve, written
+ * to ms[0 .. count-1] (host): [0] column pass and norms, [1] main Gram kernel
+ * for A1^T A1, [2] its split-K reduction, [3] A2^T A2 and right-hand side
+ * assembly, [4] block Gauss-Jordan, [5] iteration matrix layout and start
+ * vector, [6] outer iterations (including the host's polls of the stop flag).
+ * Returns the number of phases written, or a negative ils_status. */
+int ils_get_phase_times(ils_handle* h, double* ms, int count);
+
 #ifdef __cplusplus
 }
 #endif

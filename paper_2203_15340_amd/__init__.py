@@ -27,7 +27,10 @@ SAMPLE_UNIFORM, SAMPLE_NORM = 0, 1
 LIB_PATH = _build.LIB
 EXPORTS = ("ils_create", "ils_destroy", "ils_opts_default", "ils_status_string", "ils_sp_solve",
            "ils_rk_solve", "ils_rgs_solve", "ils_gram", "ils_colpass", "ils_residual",
-           "ils_spd_solve", "ils_rk_indices", "ils_scd_subsets")
+           "ils_spd_solve", "ils_rk_indices", "ils_scd_subsets", "ils_set_profiling",
+           "ils_get_phase_times")
+PHASES = ("colpass", "gram_a1", "gram_a1_reduce", "gram_a2_rhs", "gauss_jordan", "layout",
+          "iterations")
 
 
 class Opts(C.Structure):
@@ -85,6 +88,8 @@ def load_library(path: str = LIB_PATH):
         "ils_spd_solve": (C.c_int, [P, I64, I64, P, I64, P, I64, P, I64]),
         "ils_rk_indices": (C.c_int, [P, U64, U64, I64, I64, P, I64, P, P]),
         "ils_scd_subsets": (C.c_int, [P, U64, U64, I64, I64, I64, I64, P, P]),
+        "ils_set_profiling": (C.c_int, [P, C.c_int]),
+        "ils_get_phase_times": (C.c_int, [P, P, C.c_int]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -257,3 +262,16 @@ def scd_subsets(seed, outer, t0, count, n, alpha_opt=0, device="cuda"):
     _rc(load_library().ils_scd_subsets(handle(device), seed, outer, t0, count, n, alpha_opt,
                                        _ptr(alpha), _ptr(mask)), "ils_scd_subsets")
     return alpha, mask
+
+
+def set_profiling(enable=True, device=None):
+    _rc(load_library().ils_set_profiling(handle(device), int(bool(enable))), "ils_set_profiling")
+
+
+def phase_times(device=None):
+    """Phase durations (ms) of the last profiled sp_solve, keyed by PHASES."""
+    buf = (C.c_double * len(PHASES))()
+    n = load_library().ils_get_phase_times(handle(device), buf, len(PHASES))
+    if n < 0:
+        raise ILSError(f"ils_get_phase_times: {status_string(n)}")
+    return dict(zip(PHASES, list(buf)[:n]))

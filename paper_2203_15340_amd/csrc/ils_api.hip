@@ -19,6 +19,8 @@ ils_handle::~ils_handle() {
   if (st_host) (void)hipHostFree(st_host);
   if (ev0) (void)hipEventDestroy(ev0);
   if (ev1) (void)hipEventDestroy(ev1);
+  for (auto& e : pev)
+    if (e) (void)hipEventDestroy(e);
   if (own_stream && stream) (void)hipStreamDestroy(stream);
 }
 
@@ -62,6 +64,12 @@ extern "C" int ils_create(ils_handle** out, int device_ordinal, void* hip_stream
       hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess) {
     delete h;
     return ILS_ERR_ALLOC;
+  }
+  for (auto& e : h->pev) {
+    if (hipEventCreate(&e) != hipSuccess) {
+      delete h;
+      return ILS_ERR_ALLOC;
+    }
   }
   *out = h;
   return ILS_OK;
@@ -223,15 +231,19 @@ extern "C" int ils_sp_solve(ils_handle* h, int64_t p, int64_t q, int64_t n, cons
 
   HIPCHK(hipMemsetAsync(h->st, 0, sizeof(LoopState), s));
   HIPCHK(hipEventRecord(h->ev0, s));
+  h->mark(0);
   LoopState* ds = h->st;
   launch_colpass(s, p, q, n, A, lda, b, g, nullptr, &ds->bits);
   if (o->stop_rule == ILS_STOP_RR) launch_norm2(s, n, g, &ds->scal[0]);
   if (o->stop_rule == ILS_STOP_XREF) launch_norm2(s, n, o->x_ref, &ds->scal[1]);
+  h->mark(1);
   // [A1^T A1 | A2^T A2 | A^T J b] (paper form) or [A1^T A1 | I] (correction form)
+  hipEvent_t mid = h->profile ? h->pev[2] : nullptr;
   if (o->precision == ILS_PREC_MIXED)
-    launch_gram_f32(s, p, n, A, lda, (float*)part, W, ldw);
+    launch_gram_f32(s, p, n, A, lda, (float*)part, W, ldw, mid);
   else
-    launch_gram_f64(s, p, n, A, lda, (double*)part, W, ldw);
+    launch_gram_f64(s, p, n, A, lda, (double*)part, W, ldw, mid);
+  h->mark(3);
   if (paper) {
     launch_gram_f64(s, q, n, A + p, lda, (double*)part, W + n * ldw, ldw);
     launch_copy_cols(s, n, 1, g, n, W + 2 * n * ldw, ldw);
@@ -239,9 +251,12 @@ extern "C" int ils_sp_solve(ils_handle* h, int64_t p, int64_t q, int64_t n, cons
   } else {
     launch_eye(s, n, W + n * ldw, ldw);
   }
+  h->mark(4);
   launch_gj(s, n, nrhs, W, ldw, &ds->bits);
+  h->mark(5);
   launch_transpose(s, n, n, W + n * ldw, ldw, Mrow, n);
   launch_fill_vec(s, n, x0, xb0);
+  h->mark(6);
 
   SpStepArgs a;
   a.n = n;
@@ -275,6 +290,7 @@ extern "C" int ils_sp_solve(ils_handle* h, int64_t p, int64_t q, int64_t n, cons
     if (h->st_host->done || h->st_host->bits || k > o->max_outer) break;
     chunk = std::min<int64_t>(chunk * 2, 64);
   }
+  h->mark(7);
   const LoopState& hs = *h->st_host;
   st = setup_status(hs);
   if (st != ILS_OK) return fail(info, st);
@@ -341,4 +357,24 @@ extern "C" int ils_spd_solve(ils_handle* h, int64_t n, int64_t nrhs, const doubl
   launch_copy_cols(h->stream, n, nrhs, W + n * n, n, X, ldx);
   if ((st = read_state(h))) return st;
   return setup_status(*h->st_host);
+}
+
+// ------------------------------------------------------------------ instrumentation
+extern "C" int ils_set_profiling(ils_handle* h, int enable) {
+  if (!h) return ILS_ERR_ARG;
+  h->profile = enable != 0;
+  return ILS_OK;
+}
+
+extern "C" int ils_get_phase_times(ils_handle* h, double* ms, int count) {
+  if (!h || !ms || count < 0) return ILS_ERR_ARG;
+  HIPCHK(hipSetDevice(h->device));
+  HIPCHK(hipEventSynchronize(h->pev[ils_handle::kPhases]));
+  const int nph = count < ils_handle::kPhases ? count : ils_handle::kPhases;
+  for (int i = 0; i < nph; ++i) {
+    float v = 0.0f;
+    HIPCHK(hipEventElapsedTime(&v, h->pev[i], h->pev[i + 1]));
+    ms[i] = v;
+  }
+  return nph;
 }

@@ -110,9 +110,9 @@ void launch_residual(hipStream_t s, int64_t p, int64_t q, int64_t n, const doubl
 // must hold gram_partials_size(n, K) doubles.
 size_t gram_partials_size(int64_t n, int64_t K);
 void launch_gram_f64(hipStream_t s, int64_t K, int64_t n, const double* A, int64_t lda,
-                     double* partials, double* G, int64_t ldg);
+                     double* partials, double* G, int64_t ldg, hipEvent_t mid = nullptr);
 void launch_gram_f32(hipStream_t s, int64_t K, int64_t n, const double* A, int64_t lda,
-                     float* partials, double* G, int64_t ldg);
+                     float* partials, double* G, int64_t ldg, hipEvent_t mid = nullptr);
 void launch_norm2(hipStream_t s, int64_t n, const double* v, double* out);
 void launch_transpose(hipStream_t s, int64_t n, int64_t ncol, const double* X, int64_t ldx,
                       double* Y, int64_t ldy);

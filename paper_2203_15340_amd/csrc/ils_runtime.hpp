@@ -45,6 +45,12 @@ struct ils_handle {
   ils::LoopState* st = nullptr;       // device
   ils::LoopState* st_host = nullptr;  // pinned host mirror
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  static constexpr int kPhases = 7;
+  bool profile = false;
+  hipEvent_t pev[kPhases + 1] = {};
+  void mark(int i) {
+    if (profile) (void)hipEventRecord(pev[i], stream);
+  }
   ~ils_handle();
   int need(int slot, size_t bytes, void** out);
 };

@@ -22,16 +22,35 @@ __global__ __launch_bounds__(kColThreads) void k_colpass(const double* __restric
   const double* col = A + j * lda;
   double s1 = 0.0, s2 = 0.0, c = 0.0;
   bool ok = true;
-  for (int64_t i = threadIdx.x; i < p; i += kColThreads) {
-    const double a = col[i], bi = b[i];
-    s1 += a * bi;
-    c += a * a;
-    ok &= isfinite(a) && isfinite(bi);
+  constexpr int U = 4;  // loads in flight per thread per round
+  for (int64_t i0 = 0; i0 < p; i0 += U * kColThreads) {
+    double av[U], bv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = i0 + threadIdx.x + u * kColThreads;
+      av[u] = i < p ? col[i] : 0.0;
+      bv[u] = i < p ? b[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      s1 += av[u] * bv[u];
+      c += av[u] * av[u];
+      ok &= isfinite(av[u]) && isfinite(bv[u]);
+    }
   }
-  for (int64_t i = p + threadIdx.x; i < p + q; i += kColThreads) {
-    const double a = col[i], bi = b[i];
-    s2 += a * bi;
-    ok &= isfinite(a) && isfinite(bi);
+  for (int64_t i0 = p; i0 < p + q; i0 += U * kColThreads) {
+    double av[U], bv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = i0 + threadIdx.x + u * kColThreads;
+      av[u] = i < p + q ? col[i] : 0.0;
+      bv[u] = i < p + q ? b[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      s2 += av[u] * bv[u];
+      ok &= isfinite(av[u]) && isfinite(bv[u]);
+    }
   }
   if (__any(!ok) && (threadIdx.x & (kWave - 1)) == 0) atomicOr(bits, kBitNonfinite);
   s1 = block_sum<kColThreads>(s1, red[0]);
@@ -75,6 +94,26 @@ __global__ __launch_bounds__(256) void k_resid_rows(const double* __restrict__ A
   if (w == 0 && i < m) t[i] = b[i] - (((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane]);
 }
 
+// Sum of x[i] y[i] over i in [i0, i1), thread share of a workgroup of NT
+// threads: four loads in flight per thread per round, summed in index order.
+template <int NT>
+__device__ inline double strided_dot(const double* __restrict__ x, const double* __restrict__ y,
+                                     int64_t i0, int64_t i1) {
+  double s = 0.0;
+  for (int64_t b0 = i0; b0 < i1; b0 += 4 * NT) {
+    double xv[4], yv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t i = b0 + threadIdx.x + u * NT;
+      xv[u] = i < i1 ? x[i] : 0.0;
+      yv[u] = i < i1 ? y[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s += xv[u] * yv[u];
+  }
+  return s;
+}
+
 // Pass 2: r_j = A1_(j)^T t1 - A2_(j)^T t2, one workgroup per column.
 __global__ __launch_bounds__(kColThreads) void k_resid_cols(const double* __restrict__ A,
                                                              int64_t lda, int64_t p, int64_t q,
@@ -86,8 +125,8 @@ __global__ __launch_bounds__(kColThreads) void k_resid_cols(const double* __rest
   const int64_t j = blockIdx.x;
   const double* col = A + j * lda;
   double s1 = 0.0, s2 = 0.0;
-  for (int64_t i = threadIdx.x; i < p; i += kColThreads) s1 += col[i] * t[i];
-  for (int64_t i = p + threadIdx.x; i < p + q; i += kColThreads) s2 += col[i] * t[i];
+  s1 = strided_dot<kColThreads>(col, t, 0, p);
+  s2 = strided_dot<kColThreads>(col, t, p, p + q);
   s1 = block_sum<kColThreads>(s1, red[0]);
   s2 = block_sum<kColThreads>(s2, red[1]);
   if (threadIdx.x == 0) r[j] = s1 - s2;
@@ -104,12 +143,13 @@ void launch_residual(hipStream_t s, int64_t p, int64_t q, int64_t n, const doubl
 
 // ------------------------------------------------------------------ Gram (MFMA)
 // G = A^T A for K rows of A (A1^T A1 or A2^T A2, Alg. 1 steps 2-3).
-// Workgroup = one 64x64 tile of the lower triangle of G over one slice of the
-// K rows (split-K); four waves each own a 32x32 quadrant made of 2x2 MFMA
-// 16x16 blocks.  Columns of A are K-contiguous, so a 64-column x 16-row
-// panel is staged through LDS with 128-byte coalesced loads.  Slices write
-// partial tiles; a second kernel adds them in slice order (deterministic).
-constexpr int kGT = 64;        // tile edge
+// Workgroup = one TM x TM tile of the lower triangle of G over one slice of
+// the K rows (split-K); its four waves each own a (TM/2)^2 quadrant made of
+// MFMA 16x16 blocks.  Columns of A are K-contiguous, so a TM-column x 16-row
+// panel of each operand is read with 128-byte coalesced loads into registers
+// one stage ahead, then written to the other half of a double-buffered LDS
+// area: one barrier per stage.  Slices write partial tiles; a second kernel
+// adds them in slice order (deterministic).
 constexpr int kGK = 16;        // rows of A per LDS stage
 constexpr int kGLd = kGK + 1;  // padded LDS row
 
@@ -142,12 +182,14 @@ __device__ inline void tile_of(int tile, int& ti, int& tj) {
   tj = tile - r * (r + 1) / 2;
 }
 
-template <typename T>
+template <typename T, int TM>
 __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ A, int64_t lda, int64_t K,
                                               int n, int64_t klen, T* __restrict__ partials) {
   typedef typename Mma<T>::acc_t acc_t;
-  __shared__ T As[kGT][kGLd];
-  __shared__ T Bs[kGT][kGLd];
+  constexpr int NB = TM / 32;       // 16x16 blocks per wave edge
+  constexpr int NL = TM / 16;       // loads per thread per operand per stage
+  __shared__ T As[2][TM][kGLd];
+  __shared__ T Bs[2][TM][kGLd];
   const int tile = blockIdx.x, split = blockIdx.y;
   int ti, tj;
   tile_of(tile, ti, tj);
@@ -155,81 +197,120 @@ __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ A, int6
   const int64_t kbeg = (int64_t)split * klen;
   const int64_t kend = kbeg + klen < K ? kbeg + klen : K;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
-  const int lk = t & 15, lc = t >> 4;
-  acc_t acc[2][2];
+  const int wr = (w >> 1) * (TM / 2), wc = (w & 1) * (TM / 2);
+  const int lk = t & 15, lc = t >> 4, lr = lane & 15;
+  acc_t acc[NB][NB];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < NB; ++a)
 #pragma unroll
-    for (int c = 0; c < 2; ++c) acc[a][c] = acc_t{};
-  const double* Ai = A + (int64_t)ti * kGT * lda;
-  const double* Aj = A + (int64_t)tj * kGT * lda;
-  const int ci_lim = n - ti * kGT, cj_lim = n - tj * kGT;
-  for (int64_t k0 = kbeg; k0 < kend; k0 += kGK) {
+    for (int c = 0; c < NB; ++c) acc[a][c] = acc_t{};
+  const double* Ai = A + (int64_t)ti * TM * lda;
+  const double* Aj = A + (int64_t)tj * TM * lda;
+  const int ci_lim = n - ti * TM, cj_lim = n - tj * TM;
+  T ra[NL], rb[NL];
+  auto fetch = [&](int64_t k0) {
     const int64_t k = k0 + lk;
     const bool kin = k < kend;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < NL; ++r) {
       const int c = lc + 16 * r;
-      As[c][lk] = (kin && c < ci_lim) ? (T)Ai[k + (int64_t)c * lda] : (T)0;
-      if (!diag) Bs[c][lk] = (kin && c < cj_lim) ? (T)Aj[k + (int64_t)c * lda] : (T)0;
+      ra[r] = (kin && c < ci_lim) ? (T)Ai[k + (int64_t)c * lda] : (T)0;
+      if (!diag) rb[r] = (kin && c < cj_lim) ? (T)Aj[k + (int64_t)c * lda] : (T)0;
     }
-    __syncthreads();
-    T(*Bp)[kGLd] = diag ? As : Bs;
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < NL; ++r) {
+      As[buf][lc + 16 * r][lk] = ra[r];
+      if (!diag) Bs[buf][lc + 16 * r][lk] = rb[r];
+    }
+  };
+  if (kbeg < kend) {
+    fetch(kbeg);
+    stash(0);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int64_t k0 = kbeg; k0 < kend; k0 += kGK) {
+    const bool more = k0 + kGK < kend;
+    if (more) fetch(k0 + kGK);
+    T(*Ap)[kGLd] = As[buf];
+    T(*Bp)[kGLd] = diag ? As[buf] : Bs[buf];
 #pragma unroll
     for (int kk = 0; kk < kGK; kk += 4) {
-      const int kr = kk + (lane >> 4), lr = lane & 15;
-      const T a0 = As[wr + lr][kr], a1 = As[wr + 16 + lr][kr];
-      const T b0 = Bp[wc + lr][kr], b1 = Bp[wc + 16 + lr][kr];
-      acc[0][0] = Mma<T>::run(a0, b0, acc[0][0]);
-      acc[0][1] = Mma<T>::run(a0, b1, acc[0][1]);
-      acc[1][0] = Mma<T>::run(a1, b0, acc[1][0]);
-      acc[1][1] = Mma<T>::run(a1, b1, acc[1][1]);
+      const int kr = kk + (lane >> 4);
+      T fa[NB], fb[NB];
+#pragma unroll
+      for (int a = 0; a < NB; ++a) fa[a] = Ap[wr + a * 16 + lr][kr];
+#pragma unroll
+      for (int c = 0; c < NB; ++c) fb[c] = Bp[wc + c * 16 + lr][kr];
+#pragma unroll
+      for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int c = 0; c < NB; ++c) acc[a][c] = Mma<T>::run(fa[a], fb[c], acc[a][c]);
     }
+    if (more) stash(buf ^ 1);
     __syncthreads();
+    buf ^= 1;
   }
-  T* P = partials + ((size_t)split * gridDim.x + tile) * (kGT * kGT);
+  T* P = partials + ((size_t)split * gridDim.x + tile) * (TM * TM);
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < NB; ++a)
 #pragma unroll
-    for (int c = 0; c < 2; ++c)
+    for (int c = 0; c < NB; ++c)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = wr + a * 16 + Mma<T>::row(lane, v);
-        const int col = wc + c * 16 + (lane & 15);
-        P[row * kGT + col] = acc[a][c][v];
+        const int col = wc + c * 16 + lr;
+        P[row * TM + col] = acc[a][c][v];
       }
 }
 
 // Sum the slices of each tile in slice order and write the tile and its
-// mirror image into the full symmetric G (column-major, ldg).
-template <typename T>
+// mirror image into the full symmetric G (column-major, ldg).  One element
+// per thread; the slice values are loaded together, then added in order.
+template <typename T, int TM>
 __global__ __launch_bounds__(256) void k_gram_finalize(const T* __restrict__ partials, int nsplit,
                                                        int ntiles, int n, double* __restrict__ G,
                                                        int64_t ldg) {
-  const int tile = blockIdx.x;
+  const int tile = blockIdx.y;
   int ti, tj;
   tile_of(tile, ti, tj);
-  for (int e = threadIdx.x; e < kGT * kGT; e += 256) {
-    const int row = e / kGT, col = e % kGT;
-    const int i = ti * kGT + row, j = tj * kGT + col;
-    if (i >= n || j >= n || (ti == tj && row < col)) continue;
-    double s = 0.0;
-    for (int sp = 0; sp < nsplit; ++sp) s += (double)partials[((size_t)sp * ntiles + tile) * (kGT * kGT) + e];
-    G[i + (int64_t)j * ldg] = s;
-    G[j + (int64_t)i * ldg] = s;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  const int row = e / TM, col = e % TM;
+  const int i = ti * TM + row, j = tj * TM + col;
+  if (i >= n || j >= n || (ti == tj && row < col)) return;
+  const T* src = partials + (size_t)tile * (TM * TM) + e;
+  const size_t stride = (size_t)ntiles * (TM * TM);
+  double s = 0.0;
+  int sp = 0;
+  for (; sp + 8 <= nsplit; sp += 8) {
+    T v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = src[(size_t)(sp + u) * stride];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += (double)v[u];
   }
+  for (; sp < nsplit; ++sp) s += (double)src[(size_t)sp * stride];
+  G[i + (int64_t)j * ldg] = s;
+  G[j + (int64_t)i * ldg] = s;
 }
 
-static void gram_plan(int64_t n, int64_t K, int& ntiles, int& nsplit, int64_t& klen) {
-  const int nt = (int)((n + kGT - 1) / kGT);
+// Tile edge: 128 when the matrix is large enough to give the 128-tiles
+// split-K work for every CU, else 64.
+static int gram_tile(int64_t n) { return n >= 512 ? 128 : 64; }
+
+static void gram_plan(int64_t n, int64_t K, int& tm, int& ntiles, int& nsplit, int64_t& klen) {
+  tm = gram_tile(n);
+  const int nt = (int)((n + tm - 1) / tm);
   ntiles = nt * (nt + 1) / 2;
   if (K <= 0) {
     nsplit = 1;
     klen = kGK;
     return;
   }
-  int64_t want = (1024 + ntiles - 1) / ntiles;  // aim for ~4 workgroups per CU
+  const int64_t target = tm == 128 ? 512 : 1024;  // workgroups to fill 256 CUs
+  int64_t want = (target + ntiles - 1) / ntiles;
   int64_t maxs = (K + 255) / 256;               // at least 256 rows per slice
   if (want > maxs) want = maxs;
   if (want < 1) want = 1;
@@ -240,32 +321,42 @@ static void gram_plan(int64_t n, int64_t K, int& ntiles, int& nsplit, int64_t& k
 }
 
 size_t gram_partials_size(int64_t n, int64_t K) {
-  int ntiles, nsplit;
+  int tm, ntiles, nsplit;
   int64_t klen;
-  gram_plan(n, K, ntiles, nsplit, klen);
-  return (size_t)ntiles * nsplit * kGT * kGT;
+  gram_plan(n, K, tm, ntiles, nsplit, klen);
+  return (size_t)ntiles * nsplit * tm * tm;
+}
+
+template <typename T, int TM>
+static void gram_launch(hipStream_t s, int64_t K, int64_t n, const double* A, int64_t lda, T* partials,
+                        double* G, int64_t ldg, hipEvent_t mid, int ntiles, int nsplit, int64_t klen) {
+  hipLaunchKernelGGL((k_gram<T, TM>), dim3(ntiles, nsplit), dim3(256), 0, s, A, lda, K, (int)n, klen,
+                     partials);
+  if (mid) (void)hipEventRecord(mid, s);
+  hipLaunchKernelGGL((k_gram_finalize<T, TM>), dim3(TM * TM / 256, ntiles), dim3(256), 0, s, partials,
+                     nsplit, ntiles, (int)n, G, ldg);
 }
 
 template <typename T>
 static void gram_run(hipStream_t s, int64_t K, int64_t n, const double* A, int64_t lda, T* partials,
-                     double* G, int64_t ldg) {
-  int ntiles, nsplit;
+                     double* G, int64_t ldg, hipEvent_t mid) {
+  int tm, ntiles, nsplit;
   int64_t klen;
-  gram_plan(n, K, ntiles, nsplit, klen);
-  hipLaunchKernelGGL(k_gram<T>, dim3(ntiles, nsplit), dim3(256), 0, s, A, lda, K, (int)n, klen,
-                     partials);
-  hipLaunchKernelGGL(k_gram_finalize<T>, dim3(ntiles), dim3(256), 0, s, partials, nsplit, ntiles,
-                     (int)n, G, ldg);
+  gram_plan(n, K, tm, ntiles, nsplit, klen);
+  if (tm == 128)
+    gram_launch<T, 128>(s, K, n, A, lda, partials, G, ldg, mid, ntiles, nsplit, klen);
+  else
+    gram_launch<T, 64>(s, K, n, A, lda, partials, G, ldg, mid, ntiles, nsplit, klen);
 }
 
 void launch_gram_f64(hipStream_t s, int64_t K, int64_t n, const double* A, int64_t lda,
-                     double* partials, double* G, int64_t ldg) {
-  gram_run<double>(s, K, n, A, lda, partials, G, ldg);
+                     double* partials, double* G, int64_t ldg, hipEvent_t mid) {
+  gram_run<double>(s, K, n, A, lda, partials, G, ldg, mid);
 }
 
 void launch_gram_f32(hipStream_t s, int64_t K, int64_t n, const double* A, int64_t lda,
-                     float* partials, double* G, int64_t ldg) {
-  gram_run<float>(s, K, n, A, lda, partials, G, ldg);
+                     float* partials, double* G, int64_t ldg, hipEvent_t mid) {
+  gram_run<float>(s, K, n, A, lda, partials, G, ldg, mid);
 }
 
 // ------------------------------------------------------------------ helpers

@@ -222,21 +222,30 @@ __global__ __launch_bounds__(256) void k_rk_check(const double* __restrict__ A1,
                                                   const int* skip) {
   if (*(volatile const int*)skip) return;
   __shared__ double red[4];
+  __shared__ int is_last;
   const int64_t j = blockIdx.x;
   const double* col = A1 + j * lda;
   double sacc = 0.0;
   for (int64_t i = threadIdx.x; i < p; i += 256) sacc += col[i] * v[i];
   sacc = block_sum<256>(sacc, red);
-  if (threadIdx.x != 0) return;
-  const double rj = tgt[j] - sacc;
-  res2[j] = rj * rj;
-  __threadfence();
-  if (atomicAdd(arrive, 1u) != gridDim.x - 1) return;
+  if (threadIdx.x == 0) {
+    const double rj = tgt[j] - sacc;
+    res2[j] = rj * rj;
+    __threadfence();
+    is_last = atomicAdd(arrive, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!is_last) return;
   __threadfence();
   double tot = 0.0;
-  for (int64_t jj = 0; jj < n; ++jj) tot += __hip_atomic_load(res2 + jj, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  *arrive = 0;
-  if (tot <= itol2 * (*tn2)) *inner_done = 1;
+  for (int64_t jj = threadIdx.x; jj < n; jj += 256)
+    tot += __hip_atomic_load(res2 + jj, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  tot = block_sum<256>(tot, red);
+  if (threadIdx.x == 0) {
+    *arrive = 0;
+    if (tot <= itol2 * (*tn2)) *inner_done = 1;
+  }
 }
 
 void launch_rk_check(hipStream_t st, const double* A1, int64_t lda, int64_t p, int64_t n, const double* w,

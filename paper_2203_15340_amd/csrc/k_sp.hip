@@ -23,6 +23,26 @@ __device__ inline int load_coherent(const int* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Dot product of a contiguous row with v by one wave: each lane issues four
+// loads per round before using them; lane partials are added by a fixed
+// butterfly.
+__device__ inline double dot_row(const double* __restrict__ row, const double* __restrict__ v,
+                                 int64_t n, int lane) {
+  double s = 0.0;
+  for (int64_t j0 = 0; j0 < n; j0 += 4 * kWave) {
+    double rv[4], vv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t j = j0 + lane + u * kWave;
+      rv[u] = j < n ? row[j] : 0.0;
+      vv[u] = j < n ? v[j] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s += rv[u] * vv[u];
+  }
+  return wave_sum(s);
+}
+
 __global__ __launch_bounds__(256) void k_sp_step(SpStepArgs a, int64_t k) {
   LoopState* st = a.st;
   if (*(volatile int*)&st->done || *(volatile int*)&st->bits) return;
@@ -35,23 +55,16 @@ __global__ __launch_bounds__(256) void k_sp_step(SpStepArgs a, int64_t k) {
   if (i < a.n) {
     const double* row = a.Mrow + i * a.ldm;
     const double* v = (a.form == ILS_FORM_PAPER) ? xk : a.r;
-    double s = 0.0;
-    for (int64_t j = lane; j < a.n; j += kWave) s += row[j] * v[j];
-    s = wave_sum(s);
-    const double xi = (a.form == ILS_FORM_PAPER) ? s + a.c[i] : xk[i] + s;
+    const double xi = (a.form == ILS_FORM_PAPER) ? dot_row(row, v, a.n, lane) + a.c[i]
+                                                 : xk[i] + dot_row(row, v, a.n, lane);
     if (a.stop_rule == ILS_STOP_XREF) {
       const double d = xk[i] - a.x_ref[i];
       mp = d * d;
     } else if (a.stop_rule == ILS_STOP_RR) {
-      double ri;
-      if (a.form == ILS_FORM_PAPER) {  // (A^T J b - A^T J A x_k)_i, A^T J A symmetric
-        const double* hc = a.H + i * a.ldh;
-        double h = 0.0;
-        for (int64_t j = lane; j < a.n; j += kWave) h += hc[j] * xk[j];
-        ri = a.g[i] - wave_sum(h);
-      } else {
-        ri = a.r[i];
-      }
+      // (A^T J b - A^T J A x_k)_i in the paper form (A^T J A symmetric), r_k in
+      // the correction form
+      const double ri = (a.form == ILS_FORM_PAPER) ? a.g[i] - dot_row(a.H + i * a.ldh, xk, a.n, lane)
+                                                   : a.r[i];
       mp = ri * ri;
     }
     if (lane == 0) xn[i] = xi;
@@ -59,24 +72,33 @@ __global__ __launch_bounds__(256) void k_sp_step(SpStepArgs a, int64_t k) {
   }
   __shared__ double red[kSpRows];
   __shared__ int redb[kSpRows];
+  __shared__ int is_last;
+  __shared__ double tred[256 / kWave];
   if (lane == 0) {
     red[w] = mp;
     redb[w] = bad;
   }
   __syncthreads();
-  if (threadIdx.x != 0) return;
-  a.partials[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
-  a.nonfinite_part[blockIdx.x] = redb[0] | redb[1] | redb[2] | redb[3];
+  if (threadIdx.x == 0) {
+    a.partials[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+    a.nonfinite_part[blockIdx.x] = redb[0] | redb[1] | redb[2] | redb[3];
+    __threadfence();
+    is_last = atomicAdd(&st->arrive, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!is_last) return;
   __threadfence();
-  const unsigned prev = atomicAdd(&st->arrive, 1u);
-  if (prev != gridDim.x - 1) return;
-  __threadfence();
+  // last workgroup: add the partials in a fixed order (strided per thread,
+  // then the block tree), OR the non-finite flags
   double tot = 0.0;
   int anybad = 0;
-  for (unsigned bkt = 0; bkt < gridDim.x; ++bkt) {
+  for (unsigned bkt = threadIdx.x; bkt < gridDim.x; bkt += 256) {
     tot += load_coherent(a.partials + bkt);
     anybad |= load_coherent(a.nonfinite_part + bkt);
   }
+  tot = block_sum<256>(tot, tred);
+  anybad = __syncthreads_or(anybad);
+  if (threadIdx.x != 0) return;
   double metric = 0.0;
   if (a.stop_rule == ILS_STOP_XREF) metric = sqrt(tot) / sqrt(st->scal[1]);
   else if (a.stop_rule == ILS_STOP_RR) metric = tot / st->scal[0];
