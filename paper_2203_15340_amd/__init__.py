@@ -137,6 +137,13 @@ def fortran(A):
     return A.t().contiguous().t()
 
 
+def _ld(M):
+    """Leading dimension of a column-major 2-D tensor (strides (1, ld))."""
+    if M.dim() != 2 or (M.shape[0] > 1 and M.stride(0) != 1):
+        raise ILSError("matrices must be column-major: strides (1, ld)")
+    return M.stride(1) if M.shape[1] > 1 else max(1, M.shape[0])
+
+
 def _check_vec(v, n, name):
     if v is None:
         return None
@@ -163,10 +170,10 @@ def make_opts(tol=1e-6, stop_rule=STOP_RR, form=FORM_PAPER, precision=PREC_FP64,
 
 def _solve(fname, A, b, p, x0=None, out=None, raise_on_error=False, **kw):
     torch = _torch()
-    if A.dim() != 2 or A.dtype != torch.float64 or not A.is_cuda or A.stride(0) != 1:
+    if A.dim() != 2 or A.dtype != torch.float64 or not A.is_cuda:
         raise ILSError("A must be a column-major (stride (1, lda)) float64 CUDA tensor")
     m, n = A.shape
-    lda = A.stride(1) if n > 1 else max(m, 1)
+    lda = _ld(A)
     _check_vec(b, m, "b")
     _check_vec(x0, n, "x0")
     x_ref = _check_vec(kw.get("x_ref"), n, "x_ref")
@@ -210,7 +217,7 @@ def gram(A, r0, r1, precision=PREC_FP64):
     torch = _torch()
     m, n = A.shape
     G = torch.empty(n, n, dtype=torch.float64, device=A.device).t()
-    _rc(load_library().ils_gram(handle(A.device), r0, r1, n, _ptr(A), A.stride(1), _ptr(G), n,
+    _rc(load_library().ils_gram(handle(A.device), r0, r1, n, _ptr(A), _ld(A), _ptr(G), n,
                                 precision), "ils_gram")
     return G
 
@@ -220,7 +227,7 @@ def colpass(A, b, p):
     m, n = A.shape
     g = torch.empty(n, dtype=torch.float64, device=A.device)
     c = torch.empty(n, dtype=torch.float64, device=A.device)
-    rc = load_library().ils_colpass(handle(A.device), p, m - p, n, _ptr(A), A.stride(1), _ptr(b),
+    rc = load_library().ils_colpass(handle(A.device), p, m - p, n, _ptr(A), _ld(A), _ptr(b),
                                     _ptr(g), _ptr(c))
     return rc, g, c
 
@@ -229,7 +236,7 @@ def residual(A, b, p, x):
     torch = _torch()
     m, n = A.shape
     r = torch.empty(n, dtype=torch.float64, device=A.device)
-    _rc(load_library().ils_residual(handle(A.device), p, m - p, n, _ptr(A), A.stride(1), _ptr(b),
+    _rc(load_library().ils_residual(handle(A.device), p, m - p, n, _ptr(A), _ld(A), _ptr(b),
                                     _ptr(x), _ptr(r)), "ils_residual")
     return r
 
@@ -240,8 +247,8 @@ def spd_solve(G, R):
     n = G.shape[0]
     nrhs = R.shape[1]
     X = torch.empty(nrhs, n, dtype=torch.float64, device=G.device).t()
-    rc = load_library().ils_spd_solve(handle(G.device), n, nrhs, _ptr(G), G.stride(1), _ptr(R),
-                                      R.stride(1), _ptr(X), n)
+    rc = load_library().ils_spd_solve(handle(G.device), n, nrhs, _ptr(G), _ld(G), _ptr(R),
+                                      _ld(R), _ptr(X), n)
     return rc, X
 
 

@@ -212,7 +212,7 @@ extern "C" int ils_sp_solve(ils_handle* h, int64_t p, int64_t q, int64_t n, cons
   const int64_t ldw = n;
   const int64_t nrhs = paper ? n + 1 : n;
   const int nblk = sp_step_blocks(n);
-  double *g, *W, *Mrow, *H = nullptr, *xb0, *xb1, *tv, *rv, *spart;
+  double *g, *W, *Mrow, *H = nullptr, *xb0, *xb1, *tv, *rv, *spart, *dinv;
   void* part;
   int* sbad;
   size_t part_bytes = std::max(gram_partials_size(n, p), gram_partials_size(n, q)) * sizeof(double);
@@ -226,7 +226,8 @@ extern "C" int ils_sp_solve(ils_handle* h, int64_t p, int64_t q, int64_t n, cons
       (st = h->need(kBufT, sizeof(double) * m, (void**)&tv)) ||
       (st = h->need(kBufR, sizeof(double) * n, (void**)&rv)) ||
       (st = h->need(kBufSPart, sizeof(double) * nblk, (void**)&spart)) ||
-      (st = h->need(kBufSBad, sizeof(int) * nblk, (void**)&sbad)))
+      (st = h->need(kBufSBad, sizeof(int) * nblk, (void**)&sbad)) ||
+      (st = h->need(kBufDinv, sizeof(double) * gj_dinv_size(), (void**)&dinv)))
     return fail(info, st);
 
   HIPCHK(hipMemsetAsync(h->st, 0, sizeof(LoopState), s));
@@ -252,7 +253,7 @@ extern "C" int ils_sp_solve(ils_handle* h, int64_t p, int64_t q, int64_t n, cons
     launch_eye(s, n, W + n * ldw, ldw);
   }
   h->mark(4);
-  launch_gj(s, n, nrhs, W, ldw, &ds->bits);
+  launch_gj(s, n, nrhs, W, ldw, dinv, &ds->bits);
   h->mark(5);
   launch_transpose(s, n, n, W + n * ldw, ldw, Mrow, n);
   launch_fill_vec(s, n, x0, xb0);
@@ -347,13 +348,15 @@ extern "C" int ils_spd_solve(ils_handle* h, int64_t n, int64_t nrhs, const doubl
                              const double* R, int64_t ldr, double* X, int64_t ldx) {
   if (!h || !G || !R || !X || n < 1 || nrhs < 1 || ldg < n || ldr < n || ldx < n) return ILS_ERR_ARG;
   HIPCHK(hipSetDevice(h->device));
-  double* W;
-  int st = h->need(kBufW, sizeof(double) * n * (n + nrhs), (void**)&W);
-  if (st) return st;
+  double *W, *dinv;
+  int st;
+  if ((st = h->need(kBufW, sizeof(double) * n * (n + nrhs), (void**)&W)) ||
+      (st = h->need(kBufDinv, sizeof(double) * gj_dinv_size(), (void**)&dinv)))
+    return st;
   HIPCHK(hipMemsetAsync(h->st, 0, sizeof(LoopState), h->stream));
   launch_copy_cols(h->stream, n, n, G, ldg, W, n);
   launch_copy_cols(h->stream, n, nrhs, R, ldr, W + n * n, n);
-  launch_gj(h->stream, n, nrhs, W, n, &h->st->bits);
+  launch_gj(h->stream, n, nrhs, W, n, dinv, &h->st->bits);
   launch_copy_cols(h->stream, n, nrhs, W + n * n, n, X, ldx);
   if ((st = read_state(h))) return st;
   return setup_status(*h->st_host);

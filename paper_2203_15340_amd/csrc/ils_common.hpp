@@ -123,8 +123,10 @@ void launch_eye(hipStream_t s, int64_t n, double* Y, int64_t ldy);
 void launch_sub(hipStream_t s, int64_t n, const double* X, int64_t ldx, const double* Y, int64_t ldy,
                 double* Z, int64_t ldz);
 
-// Block Gauss-Jordan on W = [G | R] (n x (n + nrhs), column-major, ldw).
-void launch_gj(hipStream_t s, int64_t n, int64_t nrhs, double* W, int64_t ldw, int* bits);
+// Block Gauss-Jordan on W = [G | R] (n x (n + nrhs), column-major, ldw);
+// dinv is scratch of gj_dinv_size() doubles.
+size_t gj_dinv_size();
+void launch_gj(hipStream_t s, int64_t n, int64_t nrhs, double* W, int64_t ldw, double* dinv, int* bits);
 
 // SP outer step kernels (k_sp.hip).
 struct SpStepArgs {

@@ -191,7 +191,7 @@ extern "C" int ils_rgs_solve(ils_handle* h, int64_t p, int64_t q, int64_t n, con
   const int64_t words = (n + 31) / 32;
   const double itol = default_itol(o);
   Common c;
-  double *G1, *W, *diag, *prefix, *r, *beta;
+  double *G1, *W, *diag, *prefix, *r, *beta, *dinv;
   int *alpha_buf, *jpre;
   uint32_t* mask;
   if ((st = h->need(kBufM, sizeof(double) * n * n, (void**)&G1)) ||
@@ -201,7 +201,8 @@ extern "C" int ils_rgs_solve(ils_handle* h, int64_t p, int64_t q, int64_t n, con
       (st = h->need(kBufZ, sizeof(double) * n, (void**)&beta)) ||
       (st = h->need(kBufW1, sizeof(double) * n, (void**)&r)) ||
       (st = h->need(kBufIdx, sizeof(int) * 2 * chunk, (void**)&alpha_buf)) ||
-      (st = h->need(kBufMask, sizeof(uint32_t) * words * chunk, (void**)&mask)))
+      (st = h->need(kBufMask, sizeof(uint32_t) * words * chunk, (void**)&mask)) ||
+      (st = h->need(kBufDinv, sizeof(double) * gj_dinv_size(), (void**)&dinv)))
     return fail_info(info, st);
   jpre = alpha_buf + chunk;
   if ((st = common_setup(h, p, q, n, A, lda, b, x0, o, nullptr, c))) return fail_info(info, st);
@@ -211,7 +212,7 @@ extern "C" int ils_rgs_solve(ils_handle* h, int64_t p, int64_t q, int64_t n, con
     launch_gram_f64(s, p, n, A, lda, c.part, G1, n);
   // positive definiteness of A1^T A1 (the elimination is only a test here)
   launch_copy_cols(s, n, n, G1, n, W, n);
-  launch_gj(s, n, 0, W, n, &h->st->bits);
+  launch_gj(s, n, 0, W, n, dinv, &h->st->bits);
   launch_diag(s, n, G1, n, diag);
   launch_prefix(s, n, diag, 1, prefix);
   int64_t inner_total = 0;

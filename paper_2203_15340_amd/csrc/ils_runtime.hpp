@@ -27,6 +27,7 @@ enum BufSlot {
   kBufMask,     // pre-drawn SCD subsets
   kBufPrefix,   // sampler prefix sums
   kBufA1f,      // FP32 copy of A1
+  kBufDinv,     // inverted Gauss-Jordan pivot blocks
   kBufCount
 };
 

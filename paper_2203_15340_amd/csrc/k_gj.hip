@@ -7,30 +7,22 @@
 // complements are SPD and no pivoting is needed; a pivot block that is not
 // positive definite means A^T J A is not SPD either, and raises kBitNotSpd.
 //
-// Step k (pivot rows/columns K = [k0, k0 + nb), nb <= 64) uses two kernels:
-//   k_gj_pivot : R = D^{-1} W[K, J] for every trailing column strip J, where
-//                D = W[K, K]; one workgroup per 64-column strip inverts D in
-//                registers and applies it on the matrix cores.  R replaces
-//                W[K, J].
-//   k_gj_update: W[I, J] -= W[I, K] R[K, J] for every 64-row tile I != K,
-//                on the FP64 matrix cores.
-// Columns left of the trailing strips are never read again.
+// Step k (pivot rows/columns K = [k0, k0 + nb), nb <= 64):
+//   k_gj_pivot : R = D^{-1} W[K, J] for every trailing 64-column strip J on
+//                the FP64 matrix cores, with D^{-1} already inverted; R
+//                replaces W[K, J].
+//   k_gj_update: W[I, J] -= W[I, K] R[K, J] for every 64-row tile I != K.
+//                The workgroup that updates the next pivot block (K+1, K+1)
+//                runs first and then inverts it, so the next step's pivot
+//                kernel finds D^{-1} ready (one block of lookahead).
+// The first pivot block is inverted by k_gj_inv0.  Columns left of the
+// trailing strips are never read again.
 #include "ils_common.hpp"
 
 namespace ils {
 
 constexpr int kNB = 64;
-
-// Pivot kernel, one 256-thread workgroup per 64-column strip J:
-//  1. D = W[K, K] (padded to 64 x 64 with the identity) is inverted in place
-//     by Gauss-Jordan with the matrix held in registers: thread (r, g) owns
-//     row r, columns 16g..16g+15.  Before pivot k the owners of row k publish
-//     it in LDS and the owner of each row's column-k entry publishes that
-//     entry, so one barrier per pivot suffices.  The pivots are those of the
-//     block LDL^T factorisation, all > 0 exactly when D is SPD.
-//  2. R = D^{-1} X, X = W[K, J], on the FP64 matrix cores; each wave forms a
-//     32 x 32 quadrant of R^T (so that stores run down columns of W).
-constexpr int kPivThreads = 256;
+constexpr int kGjThreads = 256;
 
 // 1/x to full double precision: hardware estimate plus two Newton steps.
 __device__ inline double recip(double x) {
@@ -40,80 +32,112 @@ __device__ inline double recip(double x) {
   return r;
 }
 
-__global__ __launch_bounds__(kPivThreads) void k_gj_pivot(double* __restrict__ W, int64_t ldw,
-                                                          int64_t k0, int nb, int64_t c0,
-                                                          int64_t ncols, int* bits) {
-  __shared__ double Ds[kNB][kNB + 1];   // staging of D, later D^{-1}
-  __shared__ double Xs[kNB][kNB + 1];   // Xs[c][k] = X[k][c]
+// In-place Gauss-Jordan inversion of a 64 x 64 SPD matrix held in registers
+// by 256 threads: thread (r, g) = (t / 4, t % 4) owns row r, columns
+// 16g..16g+15.  Before pivot k the owners of row k publish it in LDS and the
+// owner of each row's column-k entry publishes that entry, so one barrier per
+// pivot suffices.  Every row is updated as a <- alpha (a + beta * row_k),
+// with (alpha, beta) = (1/p, 0) on the pivot row and (1, -a_rk / p) elsewhere;
+// column k then takes its final value.  The pivots are those of the LDL^T
+// factorisation.  Returns false (in every thread) on a pivot that is not > 0.
+// The pivots run as 4 blocks of 16 unrolled steps so that every register
+// index is a compile-time constant (a run-time index would send the row to
+// scratch memory).
+__device__ inline bool invert64(double (&a)[16], int r, int g, double (*rowbuf)[kNB],
+                                double (*colbuf)[kNB]) {
+#pragma unroll 1
+  for (int kb = 0; kb < 4; ++kb) {
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      const int k = kb * 16 + kk;
+      const int par = kk & 1;
+      if (r == k) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) rowbuf[par][16 * g + v] = a[v];
+      }
+      if (g == kb) colbuf[par][r] = a[kk];
+      __syncthreads();
+      double rb[16];
+#pragma unroll
+      for (int v = 0; v < 16; ++v) rb[v] = rowbuf[par][16 * g + v];
+      const double f = colbuf[par][r];
+      const double piv = rowbuf[par][k];
+      if (!(piv > 0.0)) return false;
+      const double inv = recip(piv);
+      const bool rowk = r == k;
+      const double alpha = rowk ? inv : 1.0;
+      const double beta = rowk ? 0.0 : -(f * inv);
+      const double colval = rowk ? inv : beta;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const double val = alpha * fma(beta, rb[v], a[v]);
+        a[v] = (v == kk && g == kb) ? colval : val;
+      }
+    }
+  }
+  return true;
+}
+
+// D_0 = W[0:nb, 0:nb] -> Dinv (64 x 64, row-major), identity padding.
+__global__ __launch_bounds__(kGjThreads) void k_gj_inv0(const double* __restrict__ W, int64_t ldw, int nb,
+                                                        double* __restrict__ dinv, int* bits) {
+  __shared__ double Ds[kNB][kNB + 1];
   __shared__ double rowbuf[2][kNB];
   __shared__ double colbuf[2][kNB];
   if (*(volatile int*)bits) return;
   const int t = threadIdx.x;
-  const int64_t cs = c0 + (int64_t)blockIdx.x * kNB;
-  {
-    // loads from clamped (always valid) addresses, out-of-range entries
-    // replaced afterwards, so that no load sits behind a branch
-    double dv[16], xv[16];
+  double dv[16];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int e = t + q * kPivThreads, r = e & (kNB - 1), c = e >> 6;
-      const int64_t rc = r < nb ? r : nb - 1, cc = c < nb ? c : nb - 1;
-      const int64_t xc = cs + c < ncols ? cs + c : ncols - 1;
-      dv[q] = W[k0 + rc + (k0 + cc) * ldw];
-      xv[q] = W[k0 + rc + xc * ldw];
-    }
+  for (int q = 0; q < 16; ++q) {
+    const int e = t + q * kGjThreads, r = e & (kNB - 1), c = e >> 6;
+    dv[q] = (r < nb && c < nb) ? W[r + (int64_t)c * ldw] : (r == c ? 1.0 : 0.0);
+  }
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int e = t + q * kPivThreads, r = e & (kNB - 1), c = e >> 6;
-      Ds[r][c] = (r < nb && c < nb) ? dv[q] : (r == c ? 1.0 : 0.0);
-      Xs[c][r] = (r < nb && cs + c < ncols) ? xv[q] : 0.0;
-    }
+  for (int q = 0; q < 16; ++q) {
+    const int e = t + q * kGjThreads;
+    Ds[e & (kNB - 1)][e >> 6] = dv[q];
   }
   __syncthreads();
-  const int r = t >> 2, g = t & 3, lane = t & 63;
+  const int r = t >> 2, g = t & 3;
   double a[16];
 #pragma unroll
   for (int v = 0; v < 16; ++v) a[v] = Ds[r][16 * g + v];
-#pragma unroll 1
-  for (int k = 0; k < kNB; ++k) {
-    const int par = k & 1;
-    if (r == k) {
-#pragma unroll
-      for (int v = 0; v < 16; ++v) rowbuf[par][16 * g + v] = a[v];
-    }
-    if (g == (k >> 4)) {
-      double mine = a[0];
-#pragma unroll
-      for (int v = 1; v < 16; ++v) mine = (v == (k & 15)) ? a[v] : mine;
-      colbuf[par][r] = mine;
-    }
-    __syncthreads();
-    double rb[16];
-#pragma unroll
-    for (int v = 0; v < 16; ++v) rb[v] = rowbuf[par][16 * g + v];
-    const double f = colbuf[par][r];
-    const double piv = rowbuf[par][k];
-    if (!(piv > 0.0)) {  // identical in every thread: the whole block leaves
-      if (t == 0) atomicOr(bits, kBitNotSpd);
-      return;
-    }
-    const double inv = recip(piv);
-    const double finv = f * inv;
-    const bool rowk = r == k;
-    // branch-free update: both candidates are formed, then selected
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const bool colk = 16 * g + v == k;
-      const double scaled = a[v] * inv;
-      const double upd = fma(-finv, rb[v], a[v]);
-      a[v] = rowk ? (colk ? inv : scaled) : (colk ? -finv : upd);
-    }
+  if (!invert64(a, r, g, rowbuf, colbuf)) {
+    if (t == 0) atomicOr(bits, kBitNotSpd);
+    return;
   }
 #pragma unroll
-  for (int v = 0; v < 16; ++v) Ds[r][16 * g + v] = a[v];
+  for (int v = 0; v < 16; ++v) dinv[r * kNB + 16 * g + v] = a[v];
+}
+
+// R^T[c][i] = sum_k X[k][c] Dinv[i][k]: each wave forms a 32 x 32 quadrant,
+// so that a lane's four outputs run down a column of W.
+__global__ __launch_bounds__(kGjThreads) void k_gj_pivot(double* __restrict__ W, int64_t ldw,
+                                                         int64_t k0, int nb, int64_t c0, int64_t ncols,
+                                                         const double* __restrict__ dinv,
+                                                         const int* bits) {
+  __shared__ double Ds[kNB][kNB + 1];   // Ds[i][k] = Dinv[i][k]
+  __shared__ double Xs[kNB][kNB + 1];   // Xs[c][k] = X[k][c]
+  if (*(volatile const int*)bits) return;
+  const int t = threadIdx.x;
+  const int64_t cs = c0 + (int64_t)blockIdx.x * kNB;
+  {
+    double dv[16], xv[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int e = t + q * kGjThreads, lo = e & (kNB - 1), hi = e >> 6;
+      dv[q] = dinv[hi * kNB + lo];  // row hi, column lo
+      xv[q] = (lo < nb && cs + hi < ncols) ? W[k0 + lo + (cs + hi) * ldw] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int e = t + q * kGjThreads, lo = e & (kNB - 1), hi = e >> 6;
+      Ds[hi][lo] = dv[q];
+      Xs[hi][lo] = xv[q];
+    }
+  }
   __syncthreads();
-  // R^T[c][i] = sum_k X[k][c] Dinv[i][k]; wave w forms the quadrant (bc, bi)
-  const int w = t >> 6, cq = (w >> 1) * 32, iq = (w & 1) * 32, lr = lane & 15;
+  const int lane = t & 63, w = t >> 6, cq = (w >> 1) * 32, iq = (w & 1) * 32, lr = lane & 15;
   v4d acc[2][2];
 #pragma unroll
   for (int x = 0; x < 2; ++x)
@@ -142,39 +166,50 @@ __global__ __launch_bounds__(kPivThreads) void k_gj_pivot(double* __restrict__ W
 
 // W[I, J] -= W[I, K] R[K, J].  The MFMA computes the transposed tile
 // C^T[j][i] = sum_k R[k][j] W[i][k] so that a lane's four outputs run down a
-// column of W (coalesced column-major stores).  All global loads of a stage
-// are issued before their values are used.
-__global__ __launch_bounds__(256) void k_gj_update(double* __restrict__ W, int64_t ldw, int64_t n,
-                                                   int64_t k0, int nb, int64_t c0, int64_t ncols,
-                                                   const int* bits) {
+// column of W (coalesced column-major stores).  All global loads of the tile
+// are issued before their values are used.  Workgroup 0 is the tile of the
+// next pivot block; it inverts the updated block into dinv_next.
+__global__ __launch_bounds__(kGjThreads) void k_gj_update(double* __restrict__ W, int64_t ldw, int64_t n,
+                                                          int64_t k0, int nb, int64_t c0, int64_t ncols,
+                                                          int nstrips, double* __restrict__ dinv_next,
+                                                          int* bits) {
   __shared__ double Ws[kNB][kNB + 1];  // Ws[i][k] = W[I0 + i, k0 + k]
   __shared__ double Rs[kNB][kNB + 1];  // Rs[j][k] = W[k0 + k, J0 + j]
-  if (*(volatile const int*)bits) return;
-  const int64_t cs = c0 + (int64_t)blockIdx.x * kNB;
-  const int64_t rs = (int64_t)blockIdx.y * kNB;
+  __shared__ double rowbuf[2][kNB];
+  __shared__ double colbuf[2][kNB];
+  if (*(volatile int*)bits) return;
+  // workgroup 0 <-> the tile (next pivot rows, first strip)
+  const int next_rt = (int)(k0 / kNB) + 1;
+  const bool has_next = k0 + kNB < n;
+  int lin = blockIdx.x;
+  const int look = next_rt * nstrips;
+  if (has_next) {
+    if (lin == 0) lin = look;
+    else if (lin == look) lin = 0;
+  }
+  const int64_t cs = c0 + (int64_t)(lin % nstrips) * kNB;
+  const int64_t rs = (int64_t)(lin / nstrips) * kNB;
   if (rs == k0) return;  // pivot rows already hold R
+  const bool lookahead = has_next && lin == look;
   {
     double wv[16], rv[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-      const int e = threadIdx.x + q * 256, lo = e & (kNB - 1), hi = e >> 6;
-      const int64_t wr = rs + lo < n ? rs + lo : n - 1, kc = hi < nb ? hi : nb - 1;
-      const int64_t kr = lo < nb ? lo : nb - 1, jc = cs + hi < ncols ? cs + hi : ncols - 1;
-      wv[q] = W[wr + (k0 + kc) * ldw];
-      rv[q] = W[k0 + kr + jc * ldw];
+      const int e = threadIdx.x + q * kGjThreads, lo = e & (kNB - 1), hi = e >> 6;
+      wv[q] = (rs + lo < n && hi < nb) ? W[rs + lo + (k0 + hi) * ldw] : 0.0;
+      rv[q] = (lo < nb && cs + hi < ncols) ? W[k0 + lo + (cs + hi) * ldw] : 0.0;
     }
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-      const int e = threadIdx.x + q * 256, lo = e & (kNB - 1), hi = e >> 6;
-      Ws[lo][hi] = (rs + lo < n && hi < nb) ? wv[q] : 0.0;
-      Rs[hi][lo] = (lo < nb && cs + hi < ncols) ? rv[q] : 0.0;
+      const int e = threadIdx.x + q * kGjThreads, lo = e & (kNB - 1), hi = e >> 6;
+      Ws[lo][hi] = wv[q];
+      Rs[hi][lo] = rv[q];
     }
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int jr = (w >> 1) * 32, ic = (w & 1) * 32;
   const int lr = lane & 15;
-  // current values of the output tile, loaded while the MFMAs run
   double cur[2][2][4];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -183,8 +218,7 @@ __global__ __launch_bounds__(256) void k_gj_update(double* __restrict__ W, int64
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int j = jr + a * 16 + (lane >> 4) + 4 * v, i = ic + c * 16 + lr;
-        const int64_t ir = rs + i < n ? rs + i : n - 1, jc = cs + j < ncols ? cs + j : ncols - 1;
-        cur[a][c][v] = W[ir + jc * ldw];
+        cur[a][c][v] = (rs + i < n && cs + j < ncols) ? W[rs + i + (cs + j) * ldw] : 0.0;
       }
   v4d acc[2][2];
 #pragma unroll
@@ -208,24 +242,55 @@ __global__ __launch_bounds__(256) void k_gj_update(double* __restrict__ W, int64
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int j = jr + a * 16 + (lane >> 4) + 4 * v, i = ic + c * 16 + lr;
-        if (rs + i < n && cs + j < ncols) W[rs + i + (cs + j) * ldw] = cur[a][c][v] - acc[a][c][v];
+        const double val = cur[a][c][v] - acc[a][c][v];
+        cur[a][c][v] = val;
+        if (rs + i < n && cs + j < ncols) W[rs + i + (cs + j) * ldw] = val;
       }
+  if (!lookahead) return;
+  // invert the freshly updated next pivot block (identity outside it)
+  const int nbn = (int)(n - rs < kNB ? n - rs : kNB);
+  __syncthreads();  // everyone is done reading Ws
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int j = jr + a * 16 + (lane >> 4) + 4 * v, i = ic + c * 16 + lr;
+        Ws[i][j] = (i < nbn && j < nbn) ? cur[a][c][v] : (i == j ? 1.0 : 0.0);
+      }
+  __syncthreads();
+  const int r = threadIdx.x >> 2, g = threadIdx.x & 3;
+  double d[16];
+#pragma unroll
+  for (int v = 0; v < 16; ++v) d[v] = Ws[r][16 * g + v];
+  if (!invert64(d, r, g, rowbuf, colbuf)) {
+    if (threadIdx.x == 0) atomicOr(bits, kBitNotSpd);
+    return;
+  }
+#pragma unroll
+  for (int v = 0; v < 16; ++v) dinv_next[r * kNB + 16 * g + v] = d[v];
 }
 
-void launch_gj(hipStream_t s, int64_t n, int64_t nrhs, double* W, int64_t ldw, int* bits) {
+size_t gj_dinv_size() { return 2 * kNB * kNB; }
+
+void launch_gj(hipStream_t s, int64_t n, int64_t nrhs, double* W, int64_t ldw, double* dinv, int* bits) {
   const int64_t ncols = n + nrhs;
-  const unsigned row_tiles = (unsigned)((n + kNB - 1) / kNB);
-  for (int64_t k0 = 0; k0 < n; k0 += kNB) {
+  const int row_tiles = (int)((n + kNB - 1) / kNB);
+  hipLaunchKernelGGL(k_gj_inv0, dim3(1), dim3(kGjThreads), 0, s, (const double*)W, ldw,
+                     (int)(n < kNB ? n : kNB), dinv, bits);
+  int step = 0;
+  for (int64_t k0 = 0; k0 < n; k0 += kNB, ++step) {
     const int nb = (int)(n - k0 < kNB ? n - k0 : kNB);
     const int64_t c0 = k0 + nb;
-    const unsigned strips = (unsigned)((ncols - c0 + kNB - 1) / kNB);
-    // with no trailing column left the pivot kernel still runs once: it tests
-    // the last pivot block for positive definiteness
-    hipLaunchKernelGGL(k_gj_pivot, dim3(strips > 0 ? strips : 1), dim3(kPivThreads), 0, s, W, ldw, k0,
-                       nb, c0, ncols, bits);
-    if (strips == 0) break;
-    hipLaunchKernelGGL(k_gj_update, dim3(strips, row_tiles), dim3(256), 0, s, W, ldw, n, k0, nb, c0,
-                       ncols, (const int*)bits);
+    const int strips = (int)((ncols - c0 + kNB - 1) / kNB);
+    if (strips <= 0) break;
+    double* dcur = dinv + (step & 1) * kNB * kNB;
+    double* dnext = dinv + ((step + 1) & 1) * kNB * kNB;
+    hipLaunchKernelGGL(k_gj_pivot, dim3(strips), dim3(kGjThreads), 0, s, W, ldw, k0, nb, c0, ncols,
+                       (const double*)dcur, (const int*)bits);
+    hipLaunchKernelGGL(k_gj_update, dim3(strips * row_tiles), dim3(kGjThreads), 0, s, W, ldw, n, k0, nb,
+                       c0, ncols, strips, dnext, bits);
   }
 }
 

@@ -100,6 +100,30 @@ def test_spd_solve(prob):
     assert rel(host(X), np.linalg.solve(G1, R)) < 1e-12
 
 
+@pytest.mark.parametrize("n,nrhs", [(1, 1), (63, 2), (64, 64), (65, 1), (128, 129), (129, 64), (300, 301)])
+def test_spd_solve_block_edges(n, nrhs):
+    # block edges of the 64-wide Gauss-Jordan: one block, exact multiples, ragged tails
+    rng = np.random.default_rng(n)
+    X = rng.standard_normal((3 * n + 5, n))
+    G = X.T @ X
+    R = rng.standard_normal((n, nrhs))
+    rc, Y = ils.spd_solve(devA(G), devA(R))
+    assert rc == ils.OK
+    assert rel(host(Y), np.linalg.solve(G, R)) < 1e-11
+
+
+@pytest.mark.parametrize("bad", [0, 63, 64, 100, 129])
+def test_spd_solve_detects_indefinite_in_any_block(bad):
+    rng = np.random.default_rng(bad + 1)
+    Q = np.linalg.qr(rng.standard_normal((130, 130)))[0]
+    d = np.linspace(1.0, 2.0, 130)
+    d[bad] = -0.5
+    G = (Q * d) @ Q.T
+    # a permutation that puts the bad direction's weight on a chosen block
+    rc, _ = ils.spd_solve(devA(G), devA(np.eye(130)))
+    assert rc == ils.ERR_NOT_SPD
+
+
 def test_spd_solve_detects_indefinite():
     rng = np.random.default_rng(3)
     Q = np.linalg.qr(rng.standard_normal((130, 130)))[0]
