@@ -29,7 +29,7 @@ PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 (vector = matrix)
 PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gram_a1_18000x1000_traffic.json")
-GRAM_SRC = os.path.join(ROOT, "paper_2203_15340_amd", "csrc", "k_dense.hip")
+GRAM_SRC = os.path.join(ROOT, "paper_2203_15340_amd", "csrc", "k_gram.hip")
 
 
 def log(msg):
@@ -77,6 +77,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the non-headline forms")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one 256 MiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this solver runs each problem on a single "
@@ -97,6 +99,14 @@ def main():
     x = torch.empty(P.n, dtype=torch.float64, device="cuda")
     kw = dict(stop_rule=ils.STOP_XREF, x_ref=xs, tol=1e-6)
 
+    if args.calibrate_copy:
+        src = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: 256 MiB read + 256 MiB written")
+        del src, dst
     ils.set_profiling(True)
     log(f"warmup {args.warmup}")
     for _ in range(args.warmup):

@@ -1,0 +1,234 @@
+// k_gram.hip -- the Gram products A1^T A1 and A2^T A2 (Alg. 1 steps 2-3) on
+// the gfx950 matrix cores, FP64 and FP32 (mixed precision), split-K with a
+// deterministic reduction.
+#include "ils_common.hpp"
+
+namespace ils {
+
+// ------------------------------------------------------------------ Gram (MFMA)
+// G = A^T A for K rows of A (A1^T A1 or A2^T A2, Alg. 1 steps 2-3).
+// Workgroup = one TM x TM tile of the lower triangle of G over one slice of
+// the K rows (split-K); its four waves each own a (TM/2)^2 quadrant made of
+// MFMA 16x16 blocks.  Columns of A are K-contiguous, so a TM-column x 16-row
+// panel of each operand is read with 128-byte coalesced loads into registers
+// one stage ahead, then written to the other half of a double-buffered LDS
+// area: one barrier per stage.  Slices write partial tiles; a second kernel
+// adds them in slice order (deterministic).
+constexpr int kGK = 16;        // rows of A per LDS stage
+constexpr int kGLd = kGK + 1;  // padded LDS row
+
+template <typename T>
+struct Mma;
+template <>
+struct Mma<double> {
+  typedef v4d acc_t;
+  __device__ static acc_t run(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // output element v of a lane sits at row (lane/16) + 4v, column lane%16
+  __device__ static int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+};
+template <>
+struct Mma<float> {
+  typedef v4f acc_t;
+  __device__ static acc_t run(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // output element v of a lane sits at row 4*(lane/16) + v, column lane%16
+  __device__ static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
+__device__ inline void tile_of(int tile, int& ti, int& tj) {
+  int r = (int)((sqrtf(8.0f * (float)tile + 1.0f) - 1.0f) * 0.5f);
+  while ((r + 1) * (r + 2) / 2 <= tile) ++r;
+  while (r * (r + 1) / 2 > tile) --r;
+  ti = r;
+  tj = tile - r * (r + 1) / 2;
+}
+
+// Workgroups are dealt to the 8 XCDs round-robin by linear index; the grid
+// is laid out so that all tiles of one K-slice land on the same XCD and share
+// the A panels of that slice in its L2.  nsplit is a multiple of 8.
+constexpr int kXcds = 8;
+
+template <typename T, int TM>
+__global__ __launch_bounds__(256) void k_gram(const double* __restrict__ A, int64_t lda, int64_t K,
+                                              int n, int64_t klen, int ntiles,
+                                              T* __restrict__ partials) {
+  typedef typename Mma<T>::acc_t acc_t;
+  constexpr int NB = TM / 32;       // 16x16 blocks per wave edge
+  constexpr int NL = TM / 16;       // loads per thread per operand per stage
+  __shared__ T As[2][TM][kGLd];
+  __shared__ T Bs[2][TM][kGLd];
+  const int slot = blockIdx.x / kXcds;
+  const int split = (int)(blockIdx.x % kXcds) + kXcds * (slot / ntiles);
+  const int tile = slot % ntiles;
+  int ti, tj;
+  tile_of(tile, ti, tj);
+  const bool diag = ti == tj;
+  const int64_t kbeg = (int64_t)split * klen;
+  const int64_t kend = kbeg + klen < K ? kbeg + klen : K;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wr = (w >> 1) * (TM / 2), wc = (w & 1) * (TM / 2);
+  const int lk = t & 15, lc = t >> 4, lr = lane & 15;
+  acc_t acc[NB][NB];
+#pragma unroll
+  for (int a = 0; a < NB; ++a)
+#pragma unroll
+    for (int c = 0; c < NB; ++c) acc[a][c] = acc_t{};
+  const double* Ai = A + (int64_t)ti * TM * lda;
+  const double* Aj = A + (int64_t)tj * TM * lda;
+  const int ci_lim = n - ti * TM, cj_lim = n - tj * TM;
+  T ra[NL], rb[NL];
+  auto fetch = [&](int64_t k0) {
+    const int64_t k = k0 + lk;
+    const bool kin = k < kend;
+#pragma unroll
+    for (int r = 0; r < NL; ++r) {
+      const int c = lc + 16 * r;
+      ra[r] = (kin && c < ci_lim) ? (T)Ai[k + (int64_t)c * lda] : (T)0;
+      if (!diag) rb[r] = (kin && c < cj_lim) ? (T)Aj[k + (int64_t)c * lda] : (T)0;
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < NL; ++r) {
+      As[buf][lc + 16 * r][lk] = ra[r];
+      if (!diag) Bs[buf][lc + 16 * r][lk] = rb[r];
+    }
+  };
+  if (kbeg < kend) {
+    fetch(kbeg);
+    stash(0);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int64_t k0 = kbeg; k0 < kend; k0 += kGK) {
+    const bool more = k0 + kGK < kend;
+    if (more) fetch(k0 + kGK);
+    T(*Ap)[kGLd] = As[buf];
+    T(*Bp)[kGLd] = diag ? As[buf] : Bs[buf];
+#pragma unroll
+    for (int kk = 0; kk < kGK; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      T fa[NB], fb[NB];
+#pragma unroll
+      for (int a = 0; a < NB; ++a) fa[a] = Ap[wr + a * 16 + lr][kr];
+#pragma unroll
+      for (int c = 0; c < NB; ++c) fb[c] = Bp[wc + c * 16 + lr][kr];
+#pragma unroll
+      for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int c = 0; c < NB; ++c) acc[a][c] = Mma<T>::run(fa[a], fb[c], acc[a][c]);
+    }
+    if (more) stash(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+  T* P = partials + ((size_t)split * ntiles + tile) * (TM * TM);
+#pragma unroll
+  for (int a = 0; a < NB; ++a)
+#pragma unroll
+    for (int c = 0; c < NB; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = wr + a * 16 + Mma<T>::row(lane, v);
+        const int col = wc + c * 16 + lr;
+        P[row * TM + col] = acc[a][c][v];
+      }
+}
+
+// Sum the slices of each tile in slice order and write the tile and its
+// mirror image into the full symmetric G (column-major, ldg).  One element
+// per thread; the slice values are loaded together, then added in order.
+template <typename T, int TM>
+__global__ __launch_bounds__(256) void k_gram_finalize(const T* __restrict__ partials, int nsplit,
+                                                       int ntiles, int n, double* __restrict__ G,
+                                                       int64_t ldg) {
+  const int tile = blockIdx.y;
+  int ti, tj;
+  tile_of(tile, ti, tj);
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  const int row = e / TM, col = e % TM;
+  const int i = ti * TM + row, j = tj * TM + col;
+  if (i >= n || j >= n || (ti == tj && row < col)) return;
+  const T* src = partials + (size_t)tile * (TM * TM) + e;
+  const size_t stride = (size_t)ntiles * (TM * TM);
+  double s = 0.0;
+  int sp = 0;
+  for (; sp + 8 <= nsplit; sp += 8) {
+    T v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = src[(size_t)(sp + u) * stride];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += (double)v[u];
+  }
+  for (; sp < nsplit; ++sp) s += (double)src[(size_t)sp * stride];
+  G[i + (int64_t)j * ldg] = s;
+  G[j + (int64_t)i * ldg] = s;
+}
+
+// Tile edge: 128 when the matrix is large enough to give the 128-tiles
+// split-K work for every CU, else 64.
+static int gram_tile(int64_t n) { return n >= 512 ? 128 : 64; }
+
+static void gram_plan(int64_t n, int64_t K, int& tm, int& ntiles, int& nsplit, int64_t& klen) {
+  tm = gram_tile(n);
+  const int nt = (int)((n + tm - 1) / tm);
+  ntiles = nt * (nt + 1) / 2;
+  if (K <= 0) {
+    nsplit = kXcds;
+    klen = kGK;
+    return;
+  }
+  const int64_t target = tm == 128 ? 512 : 1024;  // workgroups to fill 256 CUs
+  int64_t want = (target + ntiles - 1) / ntiles;
+  int64_t maxs = (K + 255) / 256;               // at least 256 rows per slice
+  if (want > maxs) want = maxs;
+  if (want < 1) want = 1;
+  want = (want + kXcds - 1) / kXcds * kXcds;  // whole K-slices per XCD
+  klen = (K + want - 1) / want;
+  klen = (klen + kGK - 1) / kGK * kGK;
+  nsplit = (int)want;  // trailing slices may be empty: they add zeros
+}
+
+size_t gram_partials_size(int64_t n, int64_t K) {
+  int tm, ntiles, nsplit;
+  int64_t klen;
+  gram_plan(n, K, tm, ntiles, nsplit, klen);
+  return (size_t)ntiles * nsplit * tm * tm;
+}
+
+template <typename T, int TM>
+static void gram_launch(hipStream_t s, int64_t K, int64_t n, const double* A, int64_t lda, T* partials,
+                        double* G, int64_t ldg, hipEvent_t mid, int ntiles, int nsplit, int64_t klen) {
+  hipLaunchKernelGGL((k_gram<T, TM>), dim3(ntiles * nsplit), dim3(256), 0, s, A, lda, K, (int)n, klen,
+                     ntiles, partials);
+  if (mid) (void)hipEventRecord(mid, s);
+  hipLaunchKernelGGL((k_gram_finalize<T, TM>), dim3(TM * TM / 256, ntiles), dim3(256), 0, s, partials,
+                     nsplit, ntiles, (int)n, G, ldg);
+}
+
+template <typename T>
+static void gram_run(hipStream_t s, int64_t K, int64_t n, const double* A, int64_t lda, T* partials,
+                     double* G, int64_t ldg, hipEvent_t mid) {
+  int tm, ntiles, nsplit;
+  int64_t klen;
+  gram_plan(n, K, tm, ntiles, nsplit, klen);
+  if (tm == 128)
+    gram_launch<T, 128>(s, K, n, A, lda, partials, G, ldg, mid, ntiles, nsplit, klen);
+  else
+    gram_launch<T, 64>(s, K, n, A, lda, partials, G, ldg, mid, ntiles, nsplit, klen);
+}
+
+void launch_gram_f64(hipStream_t s, int64_t K, int64_t n, const double* A, int64_t lda,
+                     double* partials, double* G, int64_t ldg, hipEvent_t mid) {
+  gram_run<double>(s, K, n, A, lda, partials, G, ldg, mid);
+}
+
+void launch_gram_f32(hipStream_t s, int64_t K, int64_t n, const double* A, int64_t lda,
+                     float* partials, double* G, int64_t ldg, hipEvent_t mid) {
+  gram_run<float>(s, K, n, A, lda, partials, G, ldg, mid);
+}
+
+}  // namespace ils
