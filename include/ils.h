@@ -143,6 +143,34 @@ int ils_rgs_solve(ils_handle* h, int64_t p, int64_t q, int64_t n, const double* 
                   const double* b, const double* x0, double* x, const ils_opts* opts,
                   ils_info* info /* host */);
 
+/* ---- many small problems in one launch ---- */
+
+/* One problem of a batch; all pointers are device pointers (x0 may be NULL,
+ * x_ref is required iff stop_rule == ILS_STOP_XREF). */
+typedef struct {
+  int64_t p, q, n, lda;
+  const double* A;
+  const double* b;
+  const double* x0;
+  const double* x_ref;
+  double* x;
+} ils_problem;
+
+/* SP (Algorithm 1) on `batch` independent problems in one persistent launch:
+ * each workgroup takes problems from a queue, largest n first, and runs the
+ * column pass, the Gram products on the matrix cores, the block Gauss-Jordan
+ * elimination and the outer steps for one problem at a time.
+ * probs: host array of `batch` descriptors; infos: host array of `batch`
+ * results (device_ms is the whole launch).  Supported: ILS_FORM_PAPER with
+ * ILS_PREC_FP64, and ILS_FORM_CORRECTION with ILS_PREC_FP64 or ILS_PREC_MIXED
+ * (FP32 Gram, FP64 elimination and residual); n <= 256 and p + q <= 4096 per
+ * problem (else ILS_ERR_ARG).  The launch is captured once in a hipGraph per
+ * (batch size, options) and replayed.  Returns ILS_OK, or the first non-OK
+ * status among the problems in index order; x of a problem that ended in
+ * ILS_ERR_NOT_SPD or ILS_ERR_NONFINITE (input) is left untouched. */
+int ils_sp_solve_batched(ils_handle* h, int64_t batch, const ils_problem* probs, const ils_opts* opts,
+                         ils_info* infos);
+
 /* ---- component entry points (used for parity checks of single steps) ---- */
 
 /* G = A[r0:r1, :]^T A[r0:r1, :] (Alg. 1 steps 2-3), full symmetric n x n,

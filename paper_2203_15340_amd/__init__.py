@@ -28,7 +28,7 @@ LIB_PATH = _build.LIB
 EXPORTS = ("ils_create", "ils_destroy", "ils_opts_default", "ils_status_string", "ils_sp_solve",
            "ils_rk_solve", "ils_rgs_solve", "ils_gram", "ils_colpass", "ils_residual",
            "ils_spd_solve", "ils_rk_indices", "ils_scd_subsets", "ils_set_profiling",
-           "ils_get_phase_times")
+           "ils_get_phase_times", "ils_sp_solve_batched")
 PHASES = ("colpass", "gram_a1", "gram_a1_reduce", "gram_a2_rhs", "gauss_jordan", "layout",
           "iterations")
 
@@ -39,6 +39,12 @@ class Opts(C.Structure):
                 ("max_outer", C.c_int64), ("max_inner", C.c_int64), ("inner_tol", C.c_double),
                 ("inner_check", C.c_int64), ("seed", C.c_uint64), ("stream_offset", C.c_uint64),
                 ("alpha", C.c_int64)]
+
+
+class Problem(C.Structure):
+    _fields_ = [("p", C.c_int64), ("q", C.c_int64), ("n", C.c_int64), ("lda", C.c_int64),
+                ("A", C.c_void_p), ("b", C.c_void_p), ("x0", C.c_void_p), ("x_ref", C.c_void_p),
+                ("x", C.c_void_p)]
 
 
 class _Info(C.Structure):
@@ -89,6 +95,7 @@ def load_library(path: str = LIB_PATH):
         "ils_rk_indices": (C.c_int, [P, U64, U64, I64, I64, P, I64, P, P]),
         "ils_scd_subsets": (C.c_int, [P, U64, U64, I64, I64, I64, I64, P, P]),
         "ils_set_profiling": (C.c_int, [P, C.c_int]),
+        "ils_sp_solve_batched": (C.c_int, [P, I64, P, P, P]),
         "ils_get_phase_times": (C.c_int, [P, P, C.c_int]),
     }
     for name, (res, args) in sig.items():
@@ -282,3 +289,29 @@ def phase_times(device=None):
     if n < 0:
         raise ILSError(f"ils_get_phase_times: {status_string(n)}")
     return dict(zip(PHASES, list(buf)[:n]))
+
+
+def sp_solve_batched(problems, x_refs=None, x0s=None, outs=None, **kw):
+    """SP on many problems in one launch.  problems: list of (A, b, p) with A a
+    column-major float64 CUDA tensor.  Returns (list of x, list of Info, rc)."""
+    torch = _torch()
+    nb = len(problems)
+    arr = (Problem * nb)()
+    xs, keep = [], []
+    for i, (A, b, p) in enumerate(problems):
+        m, n = A.shape
+        x = outs[i] if outs is not None else torch.empty(n, dtype=torch.float64, device=A.device)
+        xr = x_refs[i] if x_refs is not None else None
+        x0 = x0s[i] if x0s is not None else None
+        arr[i] = Problem(p, m - p, n, _ld(A), A.data_ptr(), b.data_ptr(),
+                         None if x0 is None else x0.data_ptr(),
+                         None if xr is None else xr.data_ptr(), x.data_ptr())
+        xs.append(x)
+        keep.append((A, b, x0, xr))
+    o = make_opts(**kw)
+    infos = (_Info * nb)()
+    dev = problems[0][0].device
+    rc = load_library().ils_sp_solve_batched(handle(dev), nb, arr, C.byref(o), infos)
+    res = [Info(int(f.status), int(f.outer_iters), int(f.inner_iters), float(f.rr),
+                float(f.rel_err), float(f.device_ms)) for f in infos]
+    return xs, res, int(rc)

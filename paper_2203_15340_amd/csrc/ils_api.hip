@@ -21,6 +21,9 @@ ils_handle::~ils_handle() {
   if (ev1) (void)hipEventDestroy(ev1);
   for (auto& e : pev)
     if (e) (void)hipEventDestroy(e);
+  if (bexec) (void)hipGraphExecDestroy(bexec);
+  if (bgraph) (void)hipGraphDestroy(bgraph);
+  if (pinned) (void)hipHostFree(pinned);
   if (own_stream && stream) (void)hipStreamDestroy(stream);
 }
 

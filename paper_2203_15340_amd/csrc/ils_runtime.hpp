@@ -1,6 +1,8 @@
 // ils_runtime.hpp -- the handle behind the opaque ils_handle of include/ils.h
 // and helpers shared by the solver drivers.
 #pragma once
+#include <vector>
+
 #include "ils_common.hpp"
 
 namespace ils {
@@ -28,6 +30,11 @@ enum BufSlot {
   kBufPrefix,   // sampler prefix sums
   kBufA1f,      // FP32 copy of A1
   kBufDinv,     // inverted Gauss-Jordan pivot blocks
+  kBufBProbs,   // batched: problem descriptors
+  kBufBOrder,   // batched: processing order
+  kBufBRes,     // batched: per-problem results
+  kBufBWork,    // batched: per-workgroup slots
+  kBufBQueue,   // batched: work-queue counters
   kBufCount
 };
 
@@ -49,6 +56,13 @@ struct ils_handle {
   static constexpr int kPhases = 7;
   bool profile = false;
   hipEvent_t pev[kPhases + 1] = {};
+  // batched solver: pinned staging, last uploaded descriptors, captured launch
+  void* pinned = nullptr;
+  size_t pinned_cap = 0;
+  std::vector<char> batch_uploaded;
+  hipGraph_t bgraph = nullptr;
+  hipGraphExec_t bexec = nullptr;
+  std::vector<char> bkey;
   void mark(int i) {
     if (profile) (void)hipEventRecord(pev[i], stream);
   }

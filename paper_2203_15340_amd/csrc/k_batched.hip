@@ -1,0 +1,511 @@
+// k_batched.hip -- many small ILS problems in one persistent launch (gfx950).
+//
+// Each workgroup takes problems from an atomic queue (largest first) and
+// solves each one alone, keeping its working matrices in a private slot of
+// device memory (L2-resident at these sizes):
+//   1. column pass: g = A1^T b1 - A2^T b2 (Alg. 1 step 4), non-finite scan;
+//   2. Gram A1^T A1 on the matrix cores (FP64, or FP32 inputs with FP32
+//      accumulation in the mixed form), and A2^T A2 in the paper form;
+//   3. block Gauss-Jordan on [A1^T A1 | A2^T A2 | g] (paper form, giving B, c
+//      of Alg. 1) or [A1^T A1 | I] (correction form, giving P), 64-wide blocks,
+//      pivot blocks inverted in registers;
+//   4. outer steps x_{k+1} = B x_k + c, or x_{k+1} = x_k + P A^T J (b - A x_k)
+//      with the residual in FP64 (iterative refinement in the mixed form),
+//      with the stop test of the single-problem solver.
+// All sums run in a fixed order, so results do not depend on which workgroup
+// solves a problem.  The last workgroup to finish resets the queue, so the
+// same launch can be replayed (hipGraph) without a host-side reset.
+#include "ils_blocks.hpp"
+#include "ils_common.hpp"
+#include "k_batched.hpp"
+
+namespace ils {
+
+namespace {
+
+constexpr int NT = 256;
+
+struct Smem {
+  union {
+    struct {
+      double T0[kNB][kNB + 1];
+      double T1[kNB][kNB + 1];
+    } gj;
+    struct {
+      double As[2][kNB][17];
+      double Bs[2][kNB][17];
+    } g64;
+    struct {
+      float As[2][kNB][17];
+      float Bs[2][kNB][17];
+    } g32;
+    double vec[2 * kNB * (kNB + 1)];  // iteration phase: t (m), x_k (n)
+  } u;
+  double rowbuf[2][kNB];
+  double colbuf[2][kNB];
+  double red[2][NT / kWave];
+  int id;
+};
+
+template <typename T>
+struct Mma;
+template <>
+struct Mma<double> {
+  typedef v4d acc_t;
+  __device__ static acc_t run(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+};
+template <>
+struct Mma<float> {
+  typedef v4f acc_t;
+  __device__ static acc_t run(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
+template <typename T>
+__device__ inline T (*stage_a(Smem& s, int buf))[17];
+template <>
+__device__ inline double (*stage_a<double>(Smem& s, int buf))[17] { return s.u.g64.As[buf]; }
+template <>
+__device__ inline float (*stage_a<float>(Smem& s, int buf))[17] { return s.u.g32.As[buf]; }
+template <typename T>
+__device__ inline T (*stage_b(Smem& s, int buf))[17];
+template <>
+__device__ inline double (*stage_b<double>(Smem& s, int buf))[17] { return s.u.g64.Bs[buf]; }
+template <>
+__device__ inline float (*stage_b<float>(Smem& s, int buf))[17] { return s.u.g32.Bs[buf]; }
+
+__device__ inline double block_sum2(double v, Smem& s, int which) {
+  v = wave_sum(v);
+  const int w = threadIdx.x / kWave;
+  if ((threadIdx.x & (kWave - 1)) == 0) s.red[which][w] = v;
+  __syncthreads();
+  double r = s.red[which][0];
+#pragma unroll
+  for (int i = 1; i < NT / kWave; ++i) r += s.red[which][i];
+  return r;
+}
+
+// G = A[0:K, :]^T A[0:K, :] (n x n, full) into W (ldw), one 64 x 64 lower tile
+// at a time; each tile streams K in stages of 16 rows through LDS with the
+// next stage's loads in registers.
+template <typename T>
+__device__ __attribute__((noinline)) void wg_gram(const double* __restrict__ A, int64_t lda, int K, int n, double* W, int64_t ldw,
+                        Smem& s) {
+  typedef typename Mma<T>::acc_t acc_t;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32, lr = lane & 15;
+  const int lk = t & 15, lc = t >> 4;
+  const int nt = (n + kNB - 1) / kNB;
+  for (int ti = 0; ti < nt; ++ti) {
+    for (int tj = 0; tj <= ti; ++tj) {
+      const bool diag = ti == tj;
+      const double* Ai = A + (int64_t)ti * kNB * lda;
+      const double* Aj = A + (int64_t)tj * kNB * lda;
+      const int ci = n - ti * kNB, cj = n - tj * kNB;
+      acc_t acc[2][2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) acc[a][c] = acc_t{};
+      T ra[4], rb[4];
+      auto fetch = [&](int k0) {
+        const int k = k0 + lk;
+        const bool kin = k < K;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int c = lc + 16 * r;
+          ra[r] = (kin && c < ci) ? (T)Ai[k + (int64_t)c * lda] : (T)0;
+          if (!diag) rb[r] = (kin && c < cj) ? (T)Aj[k + (int64_t)c * lda] : (T)0;
+        }
+      };
+      auto stash = [&](int buf) {
+        T(*As)[17] = stage_a<T>(s, buf);
+        T(*Bs)[17] = stage_b<T>(s, buf);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          As[lc + 16 * r][lk] = ra[r];
+          if (!diag) Bs[lc + 16 * r][lk] = rb[r];
+        }
+      };
+      __syncthreads();  // LDS free from the previous tile / phase
+      if (K > 0) {
+        fetch(0);
+        stash(0);
+      }
+      __syncthreads();
+      int buf = 0;
+      for (int k0 = 0; k0 < K; k0 += 16) {
+        const bool more = k0 + 16 < K;
+        if (more) fetch(k0 + 16);
+        T(*Ap)[17] = stage_a<T>(s, buf);
+        T(*Bp)[17] = diag ? stage_a<T>(s, buf) : stage_b<T>(s, buf);
+#pragma unroll
+        for (int kk = 0; kk < 16; kk += 4) {
+          const int kr = kk + (lane >> 4);
+          const T a0 = Ap[wr + lr][kr], a1 = Ap[wr + 16 + lr][kr];
+          const T b0 = Bp[wc + lr][kr], b1 = Bp[wc + 16 + lr][kr];
+          acc[0][0] = Mma<T>::run(a0, b0, acc[0][0]);
+          acc[0][1] = Mma<T>::run(a0, b1, acc[0][1]);
+          acc[1][0] = Mma<T>::run(a1, b0, acc[1][0]);
+          acc[1][1] = Mma<T>::run(a1, b1, acc[1][1]);
+        }
+        if (more) stash(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int i = ti * kNB + wr + a * 16 + Mma<T>::row(lane, v);
+            const int j = tj * kNB + wc + c * 16 + lr;
+            if (i < n && j < n) {
+              const double val = (double)acc[a][c][v];
+              W[i + (int64_t)j * ldw] = val;
+              if (!diag) W[j + (int64_t)i * ldw] = val;
+            }
+          }
+    }
+  }
+  __syncthreads();
+}
+
+// Block Gauss-Jordan on W = [G | R] (n x ncols), 64-wide blocks, inside one
+// workgroup.  Returns false when a pivot block is not positive definite.
+__device__ __attribute__((noinline)) bool wg_gauss_jordan(double* W, int64_t ldw, int n, int ncols, Smem& s) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, lr = lane & 15;
+  const int hq = (w >> 1) * 32, lq = (w & 1) * 32;
+  for (int k0 = 0; k0 < n; k0 += kNB) {
+    const int nb = n - k0 < kNB ? n - k0 : kNB;
+    __syncthreads();
+    {
+      double dv[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int e = t + q * NT, r = e & (kNB - 1), c = e >> 6;
+        dv[q] = (r < nb && c < nb) ? W[k0 + r + (int64_t)(k0 + c) * ldw] : (r == c ? 1.0 : 0.0);
+      }
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int e = t + q * NT;
+        s.u.gj.T0[e & (kNB - 1)][e >> 6] = dv[q];
+      }
+    }
+    __syncthreads();
+    const int r = t >> 2, g = t & 3;
+    double a[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) a[v] = s.u.gj.T0[r][16 * g + v];
+    if (!invert64(a, r, g, s.rowbuf, s.colbuf)) return false;
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < 16; ++v) s.u.gj.T0[r][16 * g + v] = a[v];  // D^{-1}, row-major
+    // pivot rows: R = D^{-1} X for every trailing strip (R^T formed so stores run down columns)
+    for (int cs = k0 + nb; cs < ncols; cs += kNB) {
+      __syncthreads();
+      {
+        double xv[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const int e = t + q * NT, lo = e & (kNB - 1), hi = e >> 6;
+          xv[q] = (lo < nb && cs + hi < ncols) ? W[k0 + lo + (int64_t)(cs + hi) * ldw] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const int e = t + q * NT;
+          s.u.gj.T1[e >> 6][e & (kNB - 1)] = xv[q];
+        }
+      }
+      __syncthreads();
+      v4d acc[2][2];
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[x][y] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kk = 0; kk < kNB; kk += 4) {
+        const int kr = kk + (lane >> 4);
+        const double x0 = s.u.gj.T1[hq + lr][kr], x1 = s.u.gj.T1[hq + 16 + lr][kr];
+        const double d0 = s.u.gj.T0[lq + lr][kr], d1 = s.u.gj.T0[lq + 16 + lr][kr];
+        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, d0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, d1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, d0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, d1, acc[1][1], 0, 0, 0);
+      }
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int c = hq + x * 16 + (lane >> 4) + 4 * v, i = lq + y * 16 + lr;
+            if (i < nb && cs + c < ncols) W[k0 + i + (int64_t)(cs + c) * ldw] = acc[x][y][v];
+          }
+    }
+    // other rows: W[I, J] -= W[I, K] R[K, J]
+    for (int rs = 0; rs < n; rs += kNB) {
+      if (rs == k0) continue;
+      __syncthreads();
+      {
+        double wv[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const int e = t + q * NT, lo = e & (kNB - 1), hi = e >> 6;
+          wv[q] = (rs + lo < n && hi < nb) ? W[rs + lo + (int64_t)(k0 + hi) * ldw] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const int e = t + q * NT;
+          s.u.gj.T0[e & (kNB - 1)][e >> 6] = wv[q];
+        }
+      }
+      for (int cs = k0 + nb; cs < ncols; cs += kNB) {
+        __syncthreads();
+        {
+          double rv[16];
+#pragma unroll
+          for (int q = 0; q < 16; ++q) {
+            const int e = t + q * NT, lo = e & (kNB - 1), hi = e >> 6;
+            rv[q] = (lo < nb && cs + hi < ncols) ? W[k0 + lo + (int64_t)(cs + hi) * ldw] : 0.0;
+          }
+#pragma unroll
+          for (int q = 0; q < 16; ++q) {
+            const int e = t + q * NT;
+            s.u.gj.T1[e >> 6][e & (kNB - 1)] = rv[q];
+          }
+        }
+        __syncthreads();
+        double cur[2][2][4];
+#pragma unroll
+        for (int a2 = 0; a2 < 2; ++a2)
+#pragma unroll
+          for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int j = hq + a2 * 16 + (lane >> 4) + 4 * v, i = lq + c * 16 + lr;
+              cur[a2][c][v] = (rs + i < n && cs + j < ncols) ? W[rs + i + (int64_t)(cs + j) * ldw] : 0.0;
+            }
+        v4d acc[2][2];
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y) acc[x][y] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < kNB; kk += 4) {
+          const int kr = kk + (lane >> 4);
+          const double a0 = s.u.gj.T1[hq + lr][kr], a1 = s.u.gj.T1[hq + 16 + lr][kr];
+          const double b0 = s.u.gj.T0[lq + lr][kr], b1 = s.u.gj.T0[lq + 16 + lr][kr];
+          acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+          acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+          acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+          acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+        }
+#pragma unroll
+        for (int a2 = 0; a2 < 2; ++a2)
+#pragma unroll
+          for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int j = hq + a2 * 16 + (lane >> 4) + 4 * v, i = lq + c * 16 + lr;
+              if (rs + i < n && cs + j < ncols) W[rs + i + (int64_t)(cs + j) * ldw] = cur[a2][c][v] - acc[a2][c][v];
+            }
+      }
+    }
+  }
+  __syncthreads();
+  return true;
+}
+
+// t = b - A x (x staged in LDS), then r = A^T J t; t lives in LDS.
+__device__ __attribute__((noinline)) void wg_residual(const double* __restrict__ A, int64_t lda, int p, int q, int n,
+                            const double* __restrict__ b, const double* xs, double* ts, double* r) {
+  const int m = p + q, t = threadIdx.x, lane = t & 63, w = t >> 6;
+  for (int i = t; i < m; i += NT) {
+    double acc = 0.0;
+    const double* ai = A + i;
+#pragma unroll 8
+    for (int j = 0; j < n; ++j) acc += ai[(int64_t)j * lda] * xs[j];
+    ts[i] = b[i] - acc;
+  }
+  __syncthreads();
+  for (int j = w; j < n; j += NT / kWave) {
+    const double* col = A + (int64_t)j * lda;
+    double s1 = 0.0, s2 = 0.0;
+    for (int i = lane; i < p; i += kWave) s1 += col[i] * ts[i];
+    for (int i = p + lane; i < m; i += kWave) s2 += col[i] * ts[i];
+    s1 = wave_sum(s1);
+    s2 = wave_sum(s2);
+    if (lane == 0) r[j] = s1 - s2;
+  }
+  __syncthreads();
+}
+
+template <typename T>
+__device__ void solve_one(const BatchArgs& a, const BatchProblem& P, double* slot, Smem& s,
+                          BatchResult& out) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int n = (int)P.n, p = (int)P.p, q = (int)P.q, m = p + q;
+  const int64_t lda = P.lda, ldw = a.ldw;
+  const bool paper = a.form == ILS_FORM_PAPER;
+  double* W = slot;
+  double* g = slot + a.w_doubles;
+  double* xa = g + a.nmax;
+  double* xb = xa + a.nmax;
+  double* r = xb + a.nmax;
+  out.iters = 0;
+  out.metric = 0.0;
+  // 1. column pass
+  bool ok = true;
+  for (int j = w; j < n; j += NT / kWave) {
+    const double* col = P.A + (int64_t)j * lda;
+    double s1 = 0.0, s2 = 0.0;
+    for (int i = lane; i < p; i += kWave) {
+      const double av = col[i], bv = P.b[i];
+      s1 += av * bv;
+      ok &= isfinite(av) && isfinite(bv);
+    }
+    for (int i = p + lane; i < m; i += kWave) {
+      const double av = col[i], bv = P.b[i];
+      s2 += av * bv;
+      ok &= isfinite(av) && isfinite(bv);
+    }
+    s1 = wave_sum(s1);
+    s2 = wave_sum(s2);
+    if (lane == 0) g[j] = s1 - s2;
+  }
+  if (__syncthreads_or(!ok)) {
+    out.status = ILS_ERR_NONFINITE;
+    return;
+  }
+  double gn2 = 0.0, xr2 = 0.0;
+  for (int j = t; j < n; j += NT) gn2 += g[j] * g[j];
+  gn2 = block_sum2(gn2, s, 0);
+  if (a.stop_rule == ILS_STOP_XREF) {
+    for (int j = t; j < n; j += NT) xr2 += P.x_ref[j] * P.x_ref[j];
+    xr2 = block_sum2(xr2, s, 1);
+  }
+  // 2. [A1^T A1 | A2^T A2 | g] or [A1^T A1 | I]
+  wg_gram<T>(P.A, lda, p, n, W, ldw, s);
+  int nrhs;
+  if (paper) {
+    wg_gram<double>(P.A + p, lda, q, n, W + (int64_t)n * ldw, ldw, s);
+    for (int j = t; j < n; j += NT) W[j + (int64_t)2 * n * ldw] = g[j];
+    nrhs = n + 1;
+  } else {
+    for (int e = t; e < n * n; e += NT) {
+      const int i = e % n, j = e / n;
+      W[i + (int64_t)(n + j) * ldw] = (i == j) ? 1.0 : 0.0;
+    }
+    nrhs = n;
+  }
+  __syncthreads();
+  // 3. elimination
+  if (!wg_gauss_jordan(W, ldw, n, n + nrhs, s)) {
+    out.status = ILS_ERR_NOT_SPD;
+    return;
+  }
+  const double* M = W + (int64_t)n * ldw;  // B (paper) or P (correction)
+  const double* c = W + (int64_t)2 * n * ldw;
+  // 4. outer steps
+  double* ts = s.u.vec;          // m entries
+  double* xs = s.u.vec + 4096;   // n entries (x_k staged for the residual)
+  for (int j = t; j < n; j += NT) xa[j] = P.x0 ? P.x0[j] : 0.0;
+  __syncthreads();
+  double* xk = xa;
+  double* xn = xb;
+  const bool need_r = !paper || a.stop_rule == ILS_STOP_RR;
+  int status = ILS_OK;
+  int64_t k = 0;
+  double metric = 0.0;
+  for (;; ++k) {
+    if (need_r) {
+      for (int j = t; j < n; j += NT) xs[j] = xk[j];
+      __syncthreads();
+      wg_residual(P.A, lda, p, q, n, P.b, xs, ts, r);
+    }
+    double mp = 0.0;
+    for (int j = t; j < n; j += NT) {
+      if (a.stop_rule == ILS_STOP_XREF) {
+        const double d = xk[j] - P.x_ref[j];
+        mp += d * d;
+      } else if (a.stop_rule == ILS_STOP_RR) {
+        mp += r[j] * r[j];
+      }
+    }
+    mp = block_sum2(mp, s, (int)(k & 1));
+    metric = a.stop_rule == ILS_STOP_XREF ? sqrt(mp) / sqrt(xr2) : mp / gn2;
+    if (a.stop_rule != ILS_STOP_FIXED && metric < a.tol) break;
+    if (k == a.max_outer) {
+      status = a.stop_rule == ILS_STOP_FIXED ? ILS_OK : ILS_ERR_NO_CONVERGENCE;
+      break;
+    }
+    bool bad = false;
+    for (int i = t; i < n; i += NT) {
+      double acc = 0.0;
+      const double* v = paper ? xk : r;
+#pragma unroll 8
+      for (int j = 0; j < n; ++j) acc += M[i + (int64_t)j * ldw] * v[j];
+      const double xi = paper ? acc + c[i] : xk[i] + acc;
+      xn[i] = xi;
+      bad |= !isfinite(xi);
+    }
+    bad = __syncthreads_or(bad);
+    double* tmp = xk;
+    xk = xn;
+    xn = tmp;
+    if (bad) {
+      status = ILS_ERR_NONFINITE;
+      ++k;
+      break;
+    }
+  }
+  for (int j = t; j < n; j += NT) P.x[j] = xk[j];
+  out.status = status;
+  out.iters = k;
+  out.metric = metric;
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_batched(BatchArgs a) {
+  __shared__ Smem s;
+  double* slot = a.work + (int64_t)blockIdx.x * a.slot_doubles;
+  for (;;) {
+    if (threadIdx.x == 0) s.id = (int)atomicAdd(&a.queue[0], 1u);
+    __syncthreads();
+    const int id = s.id;
+    __syncthreads();
+    if (id >= a.count) break;
+    const int idx = a.order[id];
+    BatchResult res;
+    res.status = ILS_OK;
+    solve_one<T>(a, a.probs[idx], slot, s, res);
+    if (threadIdx.x == 0) a.res[idx] = res;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    __threadfence();
+    if (atomicAdd(&a.queue[1], 1u) == gridDim.x - 1) {
+      a.queue[0] = 0;
+      a.queue[1] = 0;
+      __threadfence();
+    }
+  }
+}
+
+}  // namespace
+
+void launch_batched(hipStream_t s, const BatchArgs& a, int workgroups) {
+  if (a.precision == ILS_PREC_MIXED)
+    hipLaunchKernelGGL(k_batched<float>, dim3(workgroups), dim3(NT), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_batched<double>, dim3(workgroups), dim3(NT), 0, s, a);
+}
+
+}  // namespace ils
