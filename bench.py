@@ -70,6 +70,52 @@ def cpu_baseline(P):
                       f"{info.outer_iters} outer iterations"}
 
 
+def bench_batched(ils, W, np, torch, count=4096, single_sample=256):
+    """4096 independent problems, n ~ U{32..256}, p = 4n, q = n/2, solved to
+    rel.err 1e-6 in one persistent launch (graph replay) vs one ils_sp_solve
+    call per problem (FP64 SP) on the first `single_sample` problems."""
+    log(f"batched workload: {count} problems")
+    B = W.batched(count, seed=3, threads=len(os.sched_getaffinity(0)))
+    dv = [(torch.from_numpy(np.ascontiguousarray(P.A.T)).cuda().t(), torch.from_numpy(P.b).cuda(), P.p)
+          for P in B]
+    xr = [torch.from_numpy(P.x_star).cuda() for P in B]
+    plan = ils.BatchPlan(dv, x_refs=xr)
+    out = {"problems": count, "n_range": [min(P.n for P in B), max(P.n for P in B)],
+           "total_flop_gram_a1": int(sum(P.p * P.n * (P.n + 1) for P in B))}
+    kw = dict(stop_rule=ils.STOP_XREF, tol=1e-6)
+    for name, extra, reps in (("fp64_paper", dict(form=ils.FORM_PAPER), 5),
+                              ("mixed_correction", dict(form=ils.FORM_CORRECTION,
+                                                        precision=ils.PREC_MIXED), 3)):
+        rc = plan.solve(**kw, **extra)  # captures the launch
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            rc = plan.solve(**kw, **extra)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / reps
+        res = plan.results()
+        out[name] = {"solves_per_s": count / el, "ms_per_batch": el * 1e3, "status": rc,
+                     "max_rel_err": max(r.rel_err for r in res),
+                     "max_outer": max(r.outer_iters for r in res),
+                     "device_ms": res[0].device_ms}
+        log(f"batched {name}: {count / el:.0f} solves/s ({el * 1e3:.2f} ms per batch)")
+    xs = torch.empty(max(P.n for P in B), dtype=torch.float64, device="cuda")
+    ils.sp_solve(*dv[0][:2], dv[0][2], out=xs[:B[0].n], x_ref=xr[0], **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    worst = 0.0
+    for i in range(single_sample):
+        _, inf = ils.sp_solve(dv[i][0], dv[i][1], dv[i][2], out=xs[:B[i].n], x_ref=xr[i], **kw)
+        worst = max(worst, inf.rel_err)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / single_sample
+    out["fp64_sp_one_call_each"] = {"solves_per_s": 1.0 / el, "ms_per_solve": el * 1e3,
+                                    "sample": f"first {single_sample} of the {count} problems",
+                                    "max_rel_err": worst}
+    log(f"one ils_sp_solve per problem: {1.0 / el:.0f} solves/s")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,6 +123,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the non-headline forms")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 4096-problem batch")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 256 MiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -152,6 +199,10 @@ def main():
         forms["sp_scd_correction"] = time_form(ils.rgs_solve, 1, form=ils.FORM_CORRECTION, **kw)
         ils.set_profiling(True)
 
+    batched = None
+    if not args.no_batched:
+        batched = bench_batched(ils, W, np, torch)
+
     line = {
         "metric": "ILS solves/s to rel.err 1e-6, plain FP64 SP vs chosen form; % HBM/MFMA peak",
         "value": value,
@@ -176,6 +227,7 @@ def main():
                      "flops_per_launch": gram_flops, "avg_launch_ms": ph["gram_a1"]},
         "phases_ms": ph,
         "forms": forms,
+        "batched": batched,
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")

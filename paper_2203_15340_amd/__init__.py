@@ -291,27 +291,42 @@ def phase_times(device=None):
     return dict(zip(PHASES, list(buf)[:n]))
 
 
+class BatchPlan:
+    """Descriptors of a batch built once (ctypes array + the tensors it points
+    to), so that repeated solves cost one library call."""
+
+    def __init__(self, problems, x_refs=None, x0s=None, outs=None):
+        torch = _torch()
+        nb = len(problems)
+        self.arr = (Problem * nb)()
+        self.xs, self._keep = [], []
+        for i, (A, b, p) in enumerate(problems):
+            m, n = A.shape
+            x = outs[i] if outs is not None else torch.empty(n, dtype=torch.float64, device=A.device)
+            xr = x_refs[i] if x_refs is not None else None
+            x0 = x0s[i] if x0s is not None else None
+            self.arr[i] = Problem(p, m - p, n, _ld(A), A.data_ptr(), b.data_ptr(),
+                                  None if x0 is None else x0.data_ptr(),
+                                  None if xr is None else xr.data_ptr(), x.data_ptr())
+            self.xs.append(x)
+            self._keep.append((A, b, x0, xr))
+        self.device = problems[0][0].device
+        self.infos = (_Info * nb)()
+
+    def solve(self, **kw):
+        o = make_opts(**kw)
+        rc = load_library().ils_sp_solve_batched(handle(self.device), len(self.xs), self.arr,
+                                                 C.byref(o), self.infos)
+        return int(rc)
+
+    def results(self):
+        return [Info(int(f.status), int(f.outer_iters), int(f.inner_iters), float(f.rr),
+                     float(f.rel_err), float(f.device_ms)) for f in self.infos]
+
+
 def sp_solve_batched(problems, x_refs=None, x0s=None, outs=None, **kw):
     """SP on many problems in one launch.  problems: list of (A, b, p) with A a
     column-major float64 CUDA tensor.  Returns (list of x, list of Info, rc)."""
-    torch = _torch()
-    nb = len(problems)
-    arr = (Problem * nb)()
-    xs, keep = [], []
-    for i, (A, b, p) in enumerate(problems):
-        m, n = A.shape
-        x = outs[i] if outs is not None else torch.empty(n, dtype=torch.float64, device=A.device)
-        xr = x_refs[i] if x_refs is not None else None
-        x0 = x0s[i] if x0s is not None else None
-        arr[i] = Problem(p, m - p, n, _ld(A), A.data_ptr(), b.data_ptr(),
-                         None if x0 is None else x0.data_ptr(),
-                         None if xr is None else xr.data_ptr(), x.data_ptr())
-        xs.append(x)
-        keep.append((A, b, x0, xr))
-    o = make_opts(**kw)
-    infos = (_Info * nb)()
-    dev = problems[0][0].device
-    rc = load_library().ils_sp_solve_batched(handle(dev), nb, arr, C.byref(o), infos)
-    res = [Info(int(f.status), int(f.outer_iters), int(f.inner_iters), float(f.rr),
-                float(f.rel_err), float(f.device_ms)) for f in infos]
-    return xs, res, int(rc)
+    plan = BatchPlan(problems, x_refs, x0s, outs)
+    rc = plan.solve(**kw)
+    return plan.xs, plan.results(), rc

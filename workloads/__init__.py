@@ -47,12 +47,15 @@ def _rng(seed):
 
 
 def dense_ils(p: int, q: int, n: int, ratio: float = 0.5, seed=0,
-              noise: float = 0.0, a1: np.ndarray | None = None) -> DenseILS:
+              noise: float = 0.0, a1: np.ndarray | None = None,
+              spectral: str = "svd") -> DenseILS:
     """Gaussian ILS instance with A2 scaled to ||A2||_2 = ratio * sigma_min(A1).
 
     Draw order from numpy.random.default_rng(seed): A1 (p x n), A2 (q x n),
     x* (n), noise (m).  `a1` lets two instances share the same A1 (the
-    ratio-0.5 and ratio-0.9 variants of one problem).
+    ratio-0.5 and ratio-0.9 variants of one problem).  spectral="svd" takes
+    sigma_min(A1) and ||A2||_2 from singular values; "eig" from the extreme
+    eigenvalues of A1^T A1 and A2^T A2 (cheaper, for large batches).
     """
     rng = _rng(seed)
     A1 = rng.standard_normal((p, n)) if a1 is None else np.array(a1, dtype=np.float64)
@@ -62,8 +65,12 @@ def dense_ils(p: int, q: int, n: int, ratio: float = 0.5, seed=0,
     x_star = rng.standard_normal(n)
     e = rng.standard_normal(p + q)
     if q > 0:
-        smin = np.linalg.svd(A1, compute_uv=False)[-1]
-        a2n = np.linalg.svd(A2, compute_uv=False)[0]
+        if spectral == "eig":
+            smin = float(np.sqrt(np.linalg.eigvalsh(A1.T @ A1)[0]))
+            a2n = float(np.sqrt(np.linalg.eigvalsh(A2.T @ A2)[-1]))
+        else:
+            smin = np.linalg.svd(A1, compute_uv=False)[-1]
+            a2n = np.linalg.svd(A2, compute_uv=False)[0]
         A2 = A2 * (ratio * smin / a2n)
     A = np.asfortranarray(np.vstack([A1, A2]))
     b = A @ x_star
@@ -96,7 +103,17 @@ def batched_sizes(count: int = 4096, seed: int = 3, lo: int = 32, hi: int = 256)
 
 def batched_instance(i: int, n: int, seed: int = 3) -> DenseILS:
     p, q = 4 * n, n // 2
-    return dense_ils(p, q, n, ratio=0.5, seed=(seed, i))
+    return dense_ils(p, q, n, ratio=0.5, seed=(seed, i), spectral="eig")
+
+
+def batched(count: int = 4096, seed: int = 3, threads: int = 16):
+    """The batch: instance i has n_i from batched_sizes and seed (seed, i)."""
+    import concurrent.futures as cf
+
+    from threadpoolctl import threadpool_limits
+    sizes = batched_sizes(count, seed)
+    with threadpool_limits(1), cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        return list(ex.map(lambda a: batched_instance(a[0], a[1][2], seed), enumerate(sizes)))
 
 
 def paper_family(p: int, q: int, n: int, seed=0) -> DenseILS:
