@@ -50,8 +50,9 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_build.LIB) or (
-                os.path.getmtime(_build.LIB) < os.path.getmtime(_build.SRC)):
+        if not os.path.exists(_build.LIB) or any(
+                os.path.getmtime(_build.LIB) < os.path.getmtime(s)
+                for s in _build.SRCS + [os.path.join(_build.HERE, "ils_oracle.h")]):
             _build.build()
         L = C.CDLL(_build.LIB)
         P, I64, U64, D = C.c_void_p, C.c_int64, C.c_uint64, C.c_double
@@ -73,6 +74,12 @@ def lib():
             "ora_normal_solve": (C.c_int, [I64, I64, I64, P, I64, P, P]),
             "ora_qr_cholesky": (C.c_int, [I64, I64, I64, P, I64, P, P]),
             "ora_opts_default": (None, [P]),
+            "ora_mlp_nparams": (I64, [P]),
+            "ora_mlp_forward": (None, [P, P, I64, P, P, P, P]),
+            "ora_mlp_loss": (D, [P, P, I64, P, P]),
+            "ora_mlp_grad": (D, [P, P, I64, P, P, P]),
+            "ora_adam_step": (None, [I64, P, P, P, P, I64, D, D, D, D]),
+            "ora_bf16_round": (D, [D]),
         }
         for name in ("ora_sp_solve", "ora_rk_solve", "ora_rgs_solve"):
             sig[name] = (C.c_int, [I64, I64, I64, P, I64, P, P, P, P, P])
@@ -241,3 +248,56 @@ def rk_solve(A, b, p, **kw):
 def rgs_solve(A, b, p, **kw):
     """SP-SCD (Algorithm 5); alpha=1 with sampling=SAMPLE_NORM is SP-RCD."""
     return _solve("ora_rgs_solve", A, b, p, **kw)
+
+
+# ---------------------------------------------------------------- warm-start MLP
+def _dims(d):
+    return np.asarray(d, dtype=np.int64)
+
+
+def mlp_nparams(d):
+    dd = _dims(d)
+    return int(lib().ora_mlp_nparams(_ptr(dd)))
+
+
+def mlp_forward(d, theta, U):
+    """U: (d0, B) array, one sample per column.  Returns Y (d3, B), H1, H2."""
+    dd = _dims(d)
+    th = _c(theta)
+    Uf = _f(U)
+    B = Uf.shape[1]
+    Y = np.zeros((d[3], B), order="F")
+    H1 = np.zeros((d[1], B), order="F")
+    H2 = np.zeros((d[2], B), order="F")
+    lib().ora_mlp_forward(_ptr(dd), _ptr(th), B, _ptr(Uf), _ptr(Y), _ptr(H1), _ptr(H2))
+    return Y, H1, H2
+
+
+def mlp_loss(d, theta, U, T):
+    dd = _dims(d)
+    Uf, Tf = _f(U), _f(T)
+    return float(lib().ora_mlp_loss(_ptr(dd), _ptr(_c(theta)), Uf.shape[1], _ptr(Uf), _ptr(Tf)))
+
+
+def mlp_grad(d, theta, U, T):
+    """Returns (loss, gradient of the loss with respect to theta)."""
+    dd = _dims(d)
+    th = _c(theta)
+    Uf, Tf = _f(U), _f(T)
+    g = np.zeros_like(th)
+    loss = lib().ora_mlp_grad(_ptr(dd), _ptr(th), Uf.shape[1], _ptr(Uf), _ptr(Tf), _ptr(g))
+    return float(loss), g
+
+
+def adam_step(w, m, v, g, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """In-place Adam update of float64 arrays w, m, v with gradient g at step t >= 1."""
+    for a in (w, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    gc = _c(g)
+    lib().ora_adam_step(len(w), _ptr(w), _ptr(m), _ptr(v), _ptr(gc), t, lr, beta1, beta2, eps)
+
+
+def bf16_round(a):
+    """Round every entry to the nearest bfloat16 value (ties to even)."""
+    f = np.vectorize(lambda x: lib().ora_bf16_round(float(x)), otypes=[np.float64])
+    return f(np.asarray(a, dtype=np.float64))

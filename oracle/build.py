@@ -1,4 +1,4 @@
-"""Build step for the CPU oracle: ils_oracle.c -> liboracle.so (gcc, -O2, OpenMP).
+"""Build step for the CPU oracle: oracle/*.c -> liboracle.so (gcc, -O2, OpenMP).
 
 Test infrastructure only; called by __graft_entry__.build() and, when the
 library is missing, by the oracle's own loader.
@@ -8,14 +8,15 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "ils_oracle.c")
+SRCS = [os.path.join(HERE, f) for f in ("ils_oracle.c", "mlp_oracle.c")]
+SRC = SRCS[0]
 LIB = os.path.join(HERE, "liboracle.so")
 
 
 def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = ["gcc", "-std=c11", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
-           "-fPIC", "-shared", "-Wall", "-Wno-unused-function", SRC, "-o", tmp, "-lm"]
+           "-fPIC", "-shared", "-Wall", "-Wno-unused-function", *SRCS, "-o", tmp, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -97,6 +97,18 @@ int ora_rgs_solve(int64_t p, int64_t q, int64_t n, const double* A, int64_t lda,
                   const double* b, const double* x0, double* x, const ora_opts* o,
                   ora_info* info);
 
+/* ---- warm-start network (mlp_oracle.c): d = {d0, d1, d2, d3} ---- */
+int64_t ora_mlp_nparams(const int64_t d[4]);
+void ora_mlp_forward(const int64_t d[4], const double* theta, int64_t B, const double* U,
+                     double* Y, double* H1, double* H2);
+double ora_mlp_loss(const int64_t d[4], const double* theta, int64_t B, const double* U,
+                    const double* T);
+double ora_mlp_grad(const int64_t d[4], const double* theta, int64_t B, const double* U,
+                    const double* T, double* grad);
+void ora_adam_step(int64_t len, double* w, double* m, double* v, const double* g, int64_t t,
+                   double lr, double beta1, double beta2, double eps);
+double ora_bf16_round(double x);
+
 #ifdef __cplusplus
 }
 #endif
