@@ -143,6 +143,28 @@ int ils_rgs_solve(ils_handle* h, int64_t p, int64_t q, int64_t n, const double* 
                   const double* b, const double* x0, double* x, const ils_opts* opts,
                   ils_info* info /* host */);
 
+/* ---- many right-hand sides sharing one A ---- */
+
+/* SP (Algorithm 1) for nrhs right-hand sides B = [b_1 .. b_nrhs] (m x nrhs,
+ * column-major, ldb >= p + q) with the same A: A1^T A1 and A2^T A2 are formed
+ * and eliminated once, [A1^T A1 | A2^T A2 | A^T J B] -> [I | B_sp | C], and
+ * every outer step X_{k+1} = B_sp X_k + C is one product over the columns
+ * still iterating.  Each column has its own stop test (Sec. 5) at X_k and is
+ * frozen once it passes; opts->x_ref, when given, is n x nrhs with leading
+ * dimension n (the reference solution of every column).  X0 (n x nrhs,
+ * ldx0 >= n) may be NULL for the zero start; X is n x nrhs with ldx >= n.
+ * Only ILS_FORM_PAPER with ILS_PREC_FP64 (else ILS_ERR_ARG).
+ * iters (host, nrhs entries, may be NULL) receives each column's outer count.
+ * info->outer_iters, info->rr and info->rel_err are the maxima over columns.
+ * Returns ILS_ERR_NO_CONVERGENCE if any column is still above tol after
+ * max_outer steps (every column then holds its last iterate), and
+ * ILS_ERR_NONFINITE if any column's stop quantity is not finite.  Workspace
+ * grows with n * (2n + 4 nrhs) doubles. */
+int ils_sp_solve_multi(ils_handle* h, int64_t p, int64_t q, int64_t n, const double* A, int64_t lda,
+                       int64_t nrhs, const double* B, int64_t ldb, const double* X0, int64_t ldx0,
+                       double* X, int64_t ldx, const ils_opts* opts, int64_t* iters /* host */,
+                       ils_info* info /* host */);
+
 /* ---- many small problems in one launch ---- */
 
 /* One problem of a batch; all pointers are device pointers (x0 may be NULL,

@@ -33,6 +33,8 @@ struct LoopState {
   int64_t steps;      // SP-SCD: inner steps of the current outer step
   double scal[8];     // small device scalars: 0 ||A^T J b||^2, 1 ||x_ref||^2,
                       // 2 ||inner target||^2, 7 relative error
+  int nactive;        // multi-right-hand-side solve: columns still iterating
+  int pad;
 };
 
 // ---------------------------------------------------------------- reductions
@@ -151,5 +153,48 @@ struct SpStepArgs {
 };
 int sp_step_blocks(int64_t n);
 void launch_sp_step(hipStream_t s, const SpStepArgs& a, int64_t k);
+
+// C = alpha X^T S Y + beta C0 (k_gemm.hip); S = diag(+1 for k < kneg, -1 after).
+struct GemmTnArgs {
+  int64_t M, N, K;
+  const double* X;
+  int64_t ldx;          // K x M, column-major
+  const double* Y;
+  int64_t ldy;          // K x N, column-major
+  int64_t kneg;         // first negated row of Y (>= K: none)
+  double alpha, beta;
+  const double* C0;     // read iff beta != 0
+  int64_t ldc0;
+  double* C;
+  int64_t ldc;
+  const int* active;    // optional column mask
+  const double* keep;   // inactive columns: C[:, j] = keep[:, j] (null: left as is)
+  int64_t ldkeep;
+};
+void launch_gemm_tn(hipStream_t s, const GemmTnArgs& g);
+
+// Multi-right-hand-side helpers (k_multi.hip).
+void launch_mat_copy(hipStream_t s, int64_t rows, int64_t cols, const double* X, int64_t ldx,
+                     double* Y, int64_t ldy);
+void launch_colnorm2(hipStream_t s, int64_t rows, int64_t cols, const double* V, int64_t ldv,
+                     double* out);
+void launch_fill_int(hipStream_t s, int64_t n, int value, int* dst);
+struct MultiMetricArgs {
+  int64_t n, N;
+  const double* V;      // X_k (XREF) or R = H X_k - G (RR), n x N
+  int64_t ldv;
+  const double* Xref;   // XREF: n x N
+  int64_t ldr;
+  const double* den2;   // per column: ||x_ref_j||^2 (XREF) or ||g_j||^2 (RR)
+  int stop_rule;
+  double tol;
+  int report;           // 1: only write metric[j] for every column
+  int* active;
+  int64_t* iters;
+  double* metric;
+  int* nactive;
+  int* bits;
+};
+void launch_multi_metric(hipStream_t s, const MultiMetricArgs& a, int64_t k);
 
 }  // namespace ils

@@ -35,6 +35,15 @@ enum BufSlot {
   kBufBRes,     // batched: per-problem results
   kBufBWork,    // batched: per-workgroup slots
   kBufBQueue,   // batched: work-queue counters
+  kBufMG,       // multi-RHS: A^T J B
+  kBufMX0,      // multi-RHS: iterates (ping)
+  kBufMX1,      // multi-RHS: iterates (pong)
+  kBufMR,       // multi-RHS: residuals for the RR test
+  kBufMAct,     // multi-RHS: active-column mask
+  kBufMIters,   // multi-RHS: per-column outer counts
+  kBufMMetric,  // multi-RHS: per-column stop metric
+  kBufMDen,     // multi-RHS: per-column metric denominators
+  kBufMBt,      // multi-RHS: B^T
   kBufCount
 };
 

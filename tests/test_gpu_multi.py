@@ -1,0 +1,127 @@
+"""GPU parity of the multi-right-hand-side SP solve (ils_sp_solve_multi)
+against the oracle's single-right-hand-side SP (Algorithm 1 with the
+explicit P, B, c), column by column, on the same seeded inputs.
+
+Every column must follow the oracle's iterates to 1e-10 relative (FP64),
+stop at the same outer count, and report the same status.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+torch = pytest.importorskip("torch")
+import paper_2203_15340_amd as ils  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def devA(A):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(A).T)).to(DEV).t()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def banner(msg):
+    print(f"[gpu-multi] {msg}", flush=True)
+
+
+# (p, q, n, nrhs): one tile, ragged tiles in both directions, many columns
+CASES = [(500, 100, 50, 7), (700, 90, 150, 70), (1100, 130, 200, 130), (300, 0, 77, 65)]
+
+
+@pytest.fixture(scope="module", params=CASES, ids=lambda c: "p%d_q%d_n%d_r%d" % c)
+def fam(request):
+    p, q, n, r = request.param
+    banner(f"family p={p} q={q} n={n} nrhs={r}")
+    P = W.dense_ils(p, q, n, ratio=0.5, seed=p + n + r)
+    Xs = W.planted_columns(n, r, seed=(p, n, r))
+    B = np.asfortranarray(P.A @ Xs)
+    return P, Xs, B, devA(P.A), devA(B)
+
+
+def oracle_cols(P, B, **kw):
+    out, infos = [], []
+    for j in range(B.shape[1]):
+        k2 = dict(kw)
+        if "x_refs" in k2:
+            k2["x_ref"] = k2.pop("x_refs")[:, j]
+        if "x0s" in k2:
+            k2["x0"] = k2.pop("x0s")[:, j]
+        x, inf = O.sp_solve(P.A, B[:, j], P.p, variant=O.SP_EXPLICIT, **k2)
+        out.append(x)
+        infos.append(inf)
+    return np.stack(out, axis=1), infos
+
+
+def colrel(X, Y):
+    return np.linalg.norm(X - Y, axis=0) / np.linalg.norm(Y, axis=0)
+
+
+@pytest.mark.parametrize("steps", [1, 4])
+def test_fixed_schedule_iterates(fam, steps):
+    P, Xs, B, A, Bd = fam
+    rng = np.random.default_rng(steps)
+    X0 = np.asfortranarray(rng.standard_normal(Xs.shape))
+    X, info, iters = ils.sp_solve_multi(A, Bd, P.p, X0=devA(X0), stop_rule=ils.STOP_FIXED,
+                                        max_outer=steps)
+    assert info.status == ils.OK
+    assert np.all(iters == steps)
+    ref, _ = oracle_cols(P, B, x0s=X0, stop_rule=O.STOP_FIXED, max_outer=steps)
+    assert colrel(host(X), ref).max() < 1e-10
+
+
+@pytest.mark.parametrize("rule", ["xref", "rr"])
+def test_converged_columns_match_oracle(fam, rule):
+    P, Xs, B, A, Bd = fam
+    if rule == "xref":
+        kw = dict(stop_rule=ils.STOP_XREF, tol=1e-9)
+        okw = dict(stop_rule=O.STOP_XREF, tol=1e-9, x_refs=Xs)
+        X, info, iters = ils.sp_solve_multi(A, Bd, P.p, x_ref=devA(Xs), **kw)
+    else:
+        kw = dict(stop_rule=ils.STOP_RR, tol=1e-18)
+        okw = dict(stop_rule=O.STOP_RR, tol=1e-18)
+        X, info, iters = ils.sp_solve_multi(A, Bd, P.p, **kw)
+    assert info.status == ils.OK
+    ref, rinf = oracle_cols(P, B, **okw)
+    assert all(i.status == O.OK for i in rinf)
+    np.testing.assert_array_equal(iters, [i.outer_iters for i in rinf])
+    assert info.outer_iters == max(i.outer_iters for i in rinf)
+    assert colrel(host(X), ref).max() < 1e-10
+    assert colrel(host(X), Xs).max() < (1e-8 if rule == "xref" else 1e-6)
+
+
+def test_no_convergence_keeps_last_iterate(fam):
+    P, Xs, B, A, Bd = fam
+    if P.q == 0:
+        pytest.skip("q = 0 converges in one step")
+    X, info, iters = ils.sp_solve_multi(A, Bd, P.p, stop_rule=ils.STOP_XREF, tol=1e-14,
+                                        x_ref=devA(Xs), max_outer=2)
+    assert info.status == ils.ERR_NO_CONVERGENCE
+    assert np.all(iters == 2)
+    ref, _ = oracle_cols(P, B, stop_rule=O.STOP_FIXED, max_outer=2)
+    assert colrel(host(X), ref).max() < 1e-10
+
+
+def test_one_column_matches_single_solver(fam):
+    P, Xs, B, A, Bd = fam
+    b = torch.from_numpy(np.ascontiguousarray(B[:, 0])).to(DEV)
+    xr = torch.from_numpy(np.ascontiguousarray(Xs[:, 0])).to(DEV)
+    x1, i1 = ils.sp_solve(A, b, P.p, stop_rule=ils.STOP_XREF, x_ref=xr, tol=1e-9)
+    Xm, im, _ = ils.sp_solve_multi(A, Bd[:, :1], P.p, stop_rule=ils.STOP_XREF,
+                                   x_ref=devA(Xs[:, :1]), tol=1e-9)
+    assert i1.status == im.status == ils.OK
+    assert i1.outer_iters == im.outer_iters
+    assert colrel(host(Xm), host(x1)[:, None]).max() < 1e-12
+
+
+def test_argument_errors(fam):
+    P, Xs, B, A, Bd = fam
+    for kw in (dict(form=ils.FORM_CORRECTION), dict(form=ils.FORM_CORRECTION, precision=ils.PREC_MIXED),
+               dict(stop_rule=ils.STOP_XREF)):
+        _, info, _ = ils.sp_solve_multi(A, Bd, P.p, **kw)
+        assert info.status == ils.ERR_ARG

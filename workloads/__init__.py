@@ -116,6 +116,44 @@ def batched(count: int = 4096, seed: int = 3, threads: int = 16):
         return list(ex.map(lambda a: batched_instance(a[0], a[1][2], seed), enumerate(sizes)))
 
 
+def planted_columns(n: int, nrhs: int, seed, basis=None, noise: float = 0.0) -> np.ndarray:
+    """Planted solutions X* (n x nrhs, Fortran order) for right-hand sides
+    B = A X* that share A: i.i.d. N(0,1) entries, or, given an orthonormal
+    basis U (n x r), X* = U theta + noise * eps with theta ~ N(0, I_r) and
+    eps ~ N(0, I_n) per column (draw order theta, eps)."""
+    rng = _rng(seed)
+    if basis is None:
+        return np.asfortranarray(rng.standard_normal((nrhs, n)).T)
+    theta = rng.standard_normal((nrhs, basis.shape[1])).T
+    eps = rng.standard_normal((nrhs, n)).T
+    return np.asfortranarray(basis @ theta + noise * eps)
+
+
+# Warm-start family: one A of the 18000 + 2000 x 1000 shape (ratio 0.5),
+# solutions in a random 32-dimensional subspace plus 1e-3 noise, and the
+# network input = every 10th row of b (2000 rows).
+WS_RANK = 32
+WS_NOISE = 1e-3
+WS_IN_STRIDE = 10
+
+
+def ws_problem(seed: int = 4):
+    """(A's instance, U): A as `large` with ratio 0.5 from `seed` (no noise),
+    U the Q factor of a 1000 x 32 Gaussian matrix drawn from (seed, 1)."""
+    P = dense_ils(18000, 2000, 1000, ratio=0.5, seed=seed)
+    U, _ = np.linalg.qr(_rng((seed, 1)).standard_normal((P.n, WS_RANK)))
+    return P, np.asfortranarray(U)
+
+
+def ws_in_rows(m: int) -> np.ndarray:
+    return np.arange(0, m, WS_IN_STRIDE, dtype=np.int64)
+
+
+def ws_solutions(U: np.ndarray, count: int, seed) -> np.ndarray:
+    """count planted x = U theta + 1e-3 eps (n x count)."""
+    return planted_columns(U.shape[0], count, seed, basis=U, noise=WS_NOISE)
+
+
 def paper_family(p: int, q: int, n: int, seed=0) -> DenseILS:
     """The experiment family of Sec. 5.2 (q = n) and Sec. 5.3 (q = 1).
 
