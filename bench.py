@@ -116,6 +116,90 @@ def bench_batched(ils, W, np, torch, count=4096, single_sample=256):
     return out
 
 
+def bench_warm_start(ils, W, np, torch, n_train=50000, n_test=2000, epochs=20, single_sample=20):
+    """Learned warm start on a family sharing A (18000 + 2000 x 1000, ratio
+    0.5): x = U theta + 1e-3 eps with U a random 1000 x 32 orthonormal basis,
+    b = A x.  Training pairs (b, x_SP) come from the multi-right-hand-side SP
+    solve at RR < 1e-20 (relative residual 1e-10); the network sees every
+    10th row of b.  Test: n_test fresh right-hand sides solved to rel.err
+    1e-6 from the zero start and from the network's x0 (inference timed)."""
+    log("warm start: generating the family")
+    P, U = W.ws_problem(seed=4)
+    A = torch.from_numpy(np.ascontiguousarray(P.A.T)).cuda().t()
+    rows = W.ws_in_rows(P.m)
+
+    def rhs(X):
+        # b = A x for every column (input construction on the device)
+        Xd = torch.from_numpy(np.ascontiguousarray(X.T)).cuda().t()
+        Bd = torch.empty((X.shape[1], P.m), dtype=torch.float64, device="cuda").t()
+        torch.matmul(A, Xd, out=Bd)
+        return Xd, Bd
+
+    Xtr, Btr = rhs(W.ws_solutions(U, n_train, seed=(4, 2)))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Xsp, inf, _ = ils.sp_solve_multi(A, Btr, P.p, stop_rule=ils.STOP_RR, tol=1e-20, max_outer=200)
+    torch.cuda.synchronize()
+    t_sp = time.perf_counter() - t0
+    assert inf.status == ils.OK, inf
+    sp_err = float(((Xsp - Xtr).norm(dim=0) / Xtr.norm(dim=0)).max())
+    log(f"training targets: {n_train} SP solves in {t_sp:.2f} s, max outer {inf.outer_iters}, "
+        f"max rel.err vs planted {sp_err:.1e}")
+    del Xtr
+    ws = ils.WarmStart(P.m, P.n, rows, hidden=512, seed=4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss = ws.train(Btr, Xsp, epochs=epochs, batch=256, lr=1e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    log(f"training: {epochs} epochs in {t_train:.2f} s, final loss {loss:.3e}")
+    del Btr, Xsp
+    torch.cuda.empty_cache()
+
+    Xte, Bte = rhs(W.ws_solutions(U, n_test, seed=(4, 3)))
+    kw = dict(stop_rule=ils.STOP_XREF, tol=1e-6, x_ref=Xte)
+    out = {"family": "A 18000+2000 x 1000 ratio 0.5 (seed 4); x = U theta + 1e-3 eps, U 1000 x 32",
+           "train_pairs": n_train, "test_rhs": n_test, "epochs": epochs, "final_loss": loss,
+           "train_s": t_train, "train_targets": {"sp_solves_per_s": n_train / t_sp,
+                                                 "max_outer": inf.outer_iters, "rr_tol": 1e-20,
+                                                 "max_rel_err_vs_planted": sp_err}}
+    X0 = ws.infer(Bte)
+    e0 = ((X0 - Xte).norm(dim=0) / Xte.norm(dim=0)).cpu().numpy()
+    out["warm_start_initial_rel_err"] = {"median": float(np.median(e0)), "max": float(e0.max())}
+    for name in ("zero_start", "warm_start"):
+        reps = 5
+        ils.sp_solve_multi(A, Bte, P.p, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            x0 = ws.infer(Bte) if name == "warm_start" else None
+            X, inf, it = ils.sp_solve_multi(A, Bte, P.p, X0=x0, **kw)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / reps
+        out[name] = {"solves_per_s": n_test / el, "ms_per_batch": el * 1e3, "status": inf.status,
+                     "mean_outer": float(it.mean()), "max_outer": int(it.max()),
+                     "max_rel_err": inf.rel_err}
+        log(f"{name}: {n_test / el:.0f} solves/s, mean outer {it.mean():.2f}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        ws.infer(Bte)
+    torch.cuda.synchronize()
+    out["inference_ms_per_batch"] = (time.perf_counter() - t0) / 3 * 1e3
+    x = torch.empty(P.n, dtype=torch.float64, device="cuda")
+    ils.sp_solve(A, Bte[:, 0], P.p, out=x, stop_rule=ils.STOP_XREF, tol=1e-6, x_ref=Xte[:, 0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j in range(single_sample):
+        ils.sp_solve(A, Bte[:, j], P.p, out=x, stop_rule=ils.STOP_XREF, tol=1e-6,
+                     x_ref=Xte[:, j].contiguous())
+    torch.cuda.synchronize()
+    out["fp64_sp_one_call_each"] = {"solves_per_s": single_sample / (time.perf_counter() - t0),
+                                    "sample": f"first {single_sample} test right-hand sides"}
+    ws.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -124,6 +208,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the non-headline forms")
     ap.add_argument("--no-batched", action="store_true", help="skip the 4096-problem batch")
+    ap.add_argument("--no-warm-start", action="store_true", help="skip the learned warm start")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 256 MiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -202,6 +287,9 @@ def main():
     batched = None
     if not args.no_batched:
         batched = bench_batched(ils, W, np, torch)
+    warm = None
+    if not args.no_warm_start:
+        warm = bench_warm_start(ils, W, np, torch)
 
     line = {
         "metric": "ILS solves/s to rel.err 1e-6, plain FP64 SP vs chosen form; % HBM/MFMA peak",
@@ -228,6 +316,7 @@ def main():
         "phases_ms": ph,
         "forms": forms,
         "batched": batched,
+        "warm_start": warm,
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")

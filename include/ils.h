@@ -193,6 +193,55 @@ typedef struct {
 int ils_sp_solve_batched(ils_handle* h, int64_t batch, const ils_problem* probs, const ils_opts* opts,
                          ils_info* infos);
 
+/* ---- learned warm start for a family of problems that share A ---- */
+
+/* A three-layer perceptron d_in -> hidden -> hidden -> n (ReLU after the two
+ * hidden layers, linear output) maps rows in_rows[0 .. d_in) of b to an
+ * initial value x0 for the SP iteration; SP converges from any x0 (Thm. 2.1),
+ * so the network changes only the number of outer steps and the zero start
+ * stays the fallback.  Products run in bf16 on the matrix cores with FP32
+ * accumulation; master weights, Adam moments and the loss are FP32.  Inputs
+ * and targets are standardised per feature with the statistics of the last
+ * training set (identity until the first ils_ws_train).
+ * theta = [W1, b1, W2, b2, W3, b3], W_l row-major (d_l x d_{l-1}).
+ * All arrays are device arrays unless marked host. */
+typedef struct ils_ws ils_ws;
+
+/* in_rows: host, d_in row indices in [0, m).  Weights ~ N(0, 2 / fan_in)
+ * from Philox4x64-10 keyed by seed, biases 0.  The network belongs to h's
+ * device and stream; destroy it before h. */
+int ils_ws_create(ils_handle* h, int64_t m, int64_t n, int64_t d_in, const int64_t* in_rows, int64_t hidden,
+                  uint64_t seed, ils_ws** net);
+int ils_ws_destroy(ils_ws* net);
+
+/* Train on N pairs (columns of B, m x N, ldb >= m; columns of X, n x N,
+ * ldx >= n) for `epochs` passes in shuffled mini-batches of `batch` samples,
+ * minimising the mean squared error of the standardised output with Adam
+ * (lr, beta1 0.9, beta2 0.999, eps 1e-8).  *final_loss (host, may be NULL):
+ * mean loss over the last epoch.  Returns ILS_ERR_NONFINITE if it diverges. */
+int ils_ws_train(ils_ws* net, int64_t N, const double* B, int64_t ldb, const double* X, int64_t ldx,
+                 int32_t epochs, int64_t batch, double lr, double* final_loss /* host */);
+
+/* X0 (n x N, ldx0 >= n) = network estimate for each column of B. */
+int ils_ws_infer(ils_ws* net, int64_t N, const double* B, int64_t ldb, double* X0, int64_t ldx0);
+
+/* Save / load dimensions, input rows, standardisation, weights and Adam state
+ * (host file path).  ils_ws_load needs a network of the same dimensions. */
+int ils_ws_save(ils_ws* net, const char* path);
+int ils_ws_load(ils_ws* net, const char* path);
+
+/* Check entry points on standardised data (FP32, N columns; U is rounded to
+ * bf16 as in training): number of parameters (host out), parameter copy-out
+ * and copy-in (copy-in also resets the Adam state), the network output
+ * Y (n x N), the loss gradient (grad: FP32, nparams; *loss host), and one
+ * Adam step with a given gradient. */
+int ils_ws_nparams(const ils_ws* net, int64_t* nparams /* host */);
+int ils_ws_get_params(ils_ws* net, float* theta);
+int ils_ws_set_params(ils_ws* net, const float* theta);
+int ils_ws_forward(ils_ws* net, int64_t N, const float* U, float* Y);
+int ils_ws_grad(ils_ws* net, int64_t N, const float* U, const float* T, float* grad, double* loss /* host */);
+int ils_ws_adam(ils_ws* net, const float* grad, double lr);
+
 /* ---- component entry points (used for parity checks of single steps) ---- */
 
 /* G = A[r0:r1, :]^T A[r0:r1, :] (Alg. 1 steps 2-3), full symmetric n x n,

@@ -28,7 +28,10 @@ LIB_PATH = _build.LIB
 EXPORTS = ("ils_create", "ils_destroy", "ils_opts_default", "ils_status_string", "ils_sp_solve",
            "ils_rk_solve", "ils_rgs_solve", "ils_gram", "ils_colpass", "ils_residual",
            "ils_spd_solve", "ils_rk_indices", "ils_scd_subsets", "ils_set_profiling",
-           "ils_get_phase_times", "ils_sp_solve_batched", "ils_sp_solve_multi")
+           "ils_get_phase_times", "ils_sp_solve_batched", "ils_sp_solve_multi", "ils_ws_create",
+           "ils_ws_destroy", "ils_ws_train", "ils_ws_infer", "ils_ws_save", "ils_ws_load",
+           "ils_ws_nparams", "ils_ws_get_params", "ils_ws_set_params", "ils_ws_forward", "ils_ws_grad",
+           "ils_ws_adam")
 PHASES = ("colpass", "gram_a1", "gram_a1_reduce", "gram_a2_rhs", "gauss_jordan", "layout",
           "iterations")
 
@@ -99,6 +102,18 @@ def load_library(path: str = LIB_PATH):
         "ils_get_phase_times": (C.c_int, [P, P, C.c_int]),
         "ils_sp_solve_multi": (C.c_int, [P, I64, I64, I64, P, I64, I64, P, I64, P, I64, P, I64, P,
                                          P, P]),
+        "ils_ws_create": (C.c_int, [P, I64, I64, I64, P, I64, U64, C.POINTER(P)]),
+        "ils_ws_destroy": (C.c_int, [P]),
+        "ils_ws_train": (C.c_int, [P, I64, P, I64, P, I64, I32, I64, C.c_double, P]),
+        "ils_ws_infer": (C.c_int, [P, I64, P, I64, P, I64]),
+        "ils_ws_save": (C.c_int, [P, C.c_char_p]),
+        "ils_ws_load": (C.c_int, [P, C.c_char_p]),
+        "ils_ws_nparams": (C.c_int, [P, P]),
+        "ils_ws_get_params": (C.c_int, [P, P]),
+        "ils_ws_set_params": (C.c_int, [P, P]),
+        "ils_ws_forward": (C.c_int, [P, I64, P, P]),
+        "ils_ws_grad": (C.c_int, [P, I64, P, P, P, P]),
+        "ils_ws_adam": (C.c_int, [P, P, C.c_double]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -374,3 +389,88 @@ def sp_solve_batched(problems, x_refs=None, x0s=None, outs=None, **kw):
     plan = BatchPlan(problems, x_refs, x0s, outs)
     rc = plan.solve(**kw)
     return plan.xs, plan.results(), rc
+
+
+class WarmStart:
+    """The learned warm start (ils_ws_*): a BF16 perceptron mapping rows
+    `in_rows` of b to an initial x for SP.  Arrays are CUDA tensors."""
+
+    def __init__(self, m, n, in_rows, hidden=512, seed=0, device=None):
+        import numpy as np
+        torch = _torch()
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None \
+            else torch.device(device)
+        self.m, self.n = m, n
+        rows = np.ascontiguousarray(in_rows, dtype=np.int64)
+        self.d_in, self.hidden = len(rows), hidden
+        self._h = handle(self.device)
+        net = C.c_void_p()
+        _rc(load_library().ils_ws_create(self._h, m, n, len(rows), rows.ctypes.data, hidden, seed,
+                                         C.byref(net)), "ils_ws_create")
+        self._net = net
+        np_ = C.c_int64()
+        _rc(load_library().ils_ws_nparams(self._net, C.byref(np_)), "ils_ws_nparams")
+        self.nparams = int(np_.value)
+
+    def close(self):
+        if self._net:
+            load_library().ils_ws_destroy(self._net)
+            self._net = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def train(self, B, X, epochs=10, batch=256, lr=1e-3):
+        """B: (m, N), X: (n, N) column-major float64.  Returns the last epoch's mean loss."""
+        loss = C.c_double()
+        _rc(load_library().ils_ws_train(self._net, B.shape[1], _ptr(B), _ld(B), _ptr(X), _ld(X),
+                                        epochs, batch, lr, C.byref(loss)), "ils_ws_train")
+        return float(loss.value)
+
+    def infer(self, B, out=None):
+        torch = _torch()
+        N = B.shape[1]
+        X0 = out if out is not None else torch.empty((N, self.n), dtype=torch.float64,
+                                                     device=B.device).t()
+        _rc(load_library().ils_ws_infer(self._net, N, _ptr(B), _ld(B), _ptr(X0), _ld(X0)),
+            "ils_ws_infer")
+        return X0
+
+    def save(self, path):
+        _rc(load_library().ils_ws_save(self._net, str(path).encode()), "ils_ws_save")
+
+    def load(self, path):
+        _rc(load_library().ils_ws_load(self._net, str(path).encode()), "ils_ws_load")
+
+    def get_params(self):
+        torch = _torch()
+        th = torch.empty(self.nparams, dtype=torch.float32, device=self.device)
+        _rc(load_library().ils_ws_get_params(self._net, _ptr(th)), "ils_ws_get_params")
+        return th
+
+    def set_params(self, theta):
+        _rc(load_library().ils_ws_set_params(self._net, _ptr(theta.contiguous())), "ils_ws_set_params")
+
+    def forward(self, U):
+        """U: (d_in, N) float32 standardised inputs.  Returns Y (n, N) float32."""
+        torch = _torch()
+        U = U.t().contiguous().t()
+        Y = torch.empty((U.shape[1], self.n), dtype=torch.float32, device=U.device).t()
+        _rc(load_library().ils_ws_forward(self._net, U.shape[1], _ptr(U), _ptr(Y)), "ils_ws_forward")
+        return Y
+
+    def grad(self, U, T):
+        torch = _torch()
+        U = U.t().contiguous().t()
+        T = T.t().contiguous().t()
+        g = torch.empty(self.nparams, dtype=torch.float32, device=U.device)
+        loss = C.c_double()
+        _rc(load_library().ils_ws_grad(self._net, U.shape[1], _ptr(U), _ptr(T), _ptr(g),
+                                       C.byref(loss)), "ils_ws_grad")
+        return float(loss.value), g
+
+    def adam(self, grad, lr=1e-3):
+        _rc(load_library().ils_ws_adam(self._net, _ptr(grad.contiguous()), lr), "ils_ws_adam")
