@@ -193,6 +193,45 @@ typedef struct {
 int ils_sp_solve_batched(ils_handle* h, int64_t batch, const ils_problem* probs, const ils_opts* opts,
                          ils_info* infos);
 
+/* ---- sparse A ---- */
+
+/* A = [A1; A2] (m = p + q rows, n columns) in CSR: rowptr (m + 1 int64),
+ * colidx (nnz int32, any order within a row), val (nnz doubles), all device
+ * arrays owned by the caller and read again by every solve: they must stay
+ * alive and unchanged until ils_csr_destroy.  Creation checks the structure
+ * (rowptr[0] = 0, rowptr[m] = nnz, non-decreasing, 0 <= colidx < n;
+ * ILS_ERR_ARG otherwise) and the values (ILS_ERR_NONFINITE), and builds a
+ * column-major copy (CSC, rows ascending within each column; equal rows,
+ * i.e. duplicate entries, ordered by value) owned by the library.
+ * Limits: 1 <= n <= 20480 (the Gram products accumulate a dense column of
+ * length n on chip), m and nnz below 2^31.  The handle belongs to h's device. */
+typedef struct ils_csr ils_csr;
+int ils_csr_create(ils_handle* h, int64_t p, int64_t q, int64_t n, int64_t nnz, const int64_t* rowptr,
+                   const int32_t* colidx, const double* val, ils_csr** A);
+int ils_csr_destroy(ils_csr* A);
+
+/* The three methods on a sparse A, with the same options and results as the
+ * dense entry points: SP (Algorithm 1) with A1^T A1 and A2^T A2 formed as
+ * dense n x n matrices from the sparse factors, SP-RK-RGS (Algorithm 2) on
+ * the sparse columns of A1 (CSC), SP-SCD (Algorithm 5) on the dense A1^T A1.
+ * The residual A^T J (b - A x) uses the CSR for A x and the CSC for A^T.
+ * Only ILS_PREC_FP64 (else ILS_ERR_ARG). */
+int ils_sp_solve_csr(ils_handle* h, const ils_csr* A, const double* b, const double* x0, double* x,
+                     const ils_opts* opts, ils_info* info /* host */);
+int ils_rk_solve_csr(ils_handle* h, const ils_csr* A, const double* b, const double* x0, double* x,
+                     const ils_opts* opts, ils_info* info /* host */);
+int ils_rgs_solve_csr(ils_handle* h, const ils_csr* A, const double* b, const double* x0, double* x,
+                      const ils_opts* opts, ils_info* info /* host */);
+
+/* Components on a sparse A: G = A1^T A1 (part 0) or A2^T A2 (part 1), full
+ * symmetric, leading dimension ldg >= n; g = A^T J b and (colnorm2 may be
+ * NULL) ||A1_(j)||^2; r = A^T J (b - A x); and a copy of the CSC arrays
+ * (colptr n + 1, rowidx and val nnz, a1len n = entries of A1 per column). */
+int ils_csr_gram(ils_handle* h, const ils_csr* A, int32_t part, double* G, int64_t ldg);
+int ils_csr_colpass(ils_handle* h, const ils_csr* A, const double* b, double* g, double* colnorm2);
+int ils_csr_residual(ils_handle* h, const ils_csr* A, const double* b, const double* x, double* r);
+int ils_csr_export_csc(const ils_csr* A, int64_t* colptr, int32_t* rowidx, double* val, int32_t* a1len);
+
 /* ---- learned warm start for a family of problems that share A ---- */
 
 /* A three-layer perceptron d_in -> hidden -> hidden -> n (ReLU after the two

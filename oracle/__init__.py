@@ -80,6 +80,7 @@ def lib():
             "ora_mlp_grad": (D, [P, P, I64, P, P, P]),
             "ora_adam_step": (None, [I64, P, P, P, P, I64, D, D, D, D]),
             "ora_bf16_round": (D, [D]),
+            "ora_csr_to_csc": (None, [I64, I64, I64, P, P, P, P, P, P, P]),
         }
         for name in ("ora_sp_solve", "ora_rk_solve", "ora_rgs_solve"):
             sig[name] = (C.c_int, [I64, I64, I64, P, I64, P, P, P, P, P])
@@ -301,3 +302,20 @@ def bf16_round(a):
     """Round every entry to the nearest bfloat16 value (ties to even)."""
     f = np.vectorize(lambda x: lib().ora_bf16_round(float(x)), otypes=[np.float64])
     return f(np.asarray(a, dtype=np.float64))
+
+
+# ---------------------------------------------------------------- sparse
+def csr_to_csc(S, p):
+    """(colptr, rowidx, val, a1len) of the CSC copy of scipy CSR matrix S:
+    rows ascending per column, duplicates by value bits; a1len = rows < p."""
+    S = S.tocsr()
+    m, n = S.shape
+    rp = np.ascontiguousarray(S.indptr, dtype=np.int64)
+    ci = np.ascontiguousarray(S.indices, dtype=np.int32)
+    v = np.ascontiguousarray(S.data, dtype=np.float64)
+    cp = np.zeros(n + 1, dtype=np.int64)
+    ri = np.zeros(len(v), dtype=np.int32)
+    cv = np.zeros(len(v), dtype=np.float64)
+    a1 = np.zeros(n, dtype=np.int32)
+    lib().ora_csr_to_csc(m, n, p, _ptr(rp), _ptr(ci), _ptr(v), _ptr(cp), _ptr(ri), _ptr(cv), _ptr(a1))
+    return cp, ri, cv, a1

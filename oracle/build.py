@@ -8,7 +8,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRCS = [os.path.join(HERE, f) for f in ("ils_oracle.c", "mlp_oracle.c")]
+SRCS = [os.path.join(HERE, f) for f in ("ils_oracle.c", "mlp_oracle.c", "sparse_oracle.c")]
 SRC = SRCS[0]
 LIB = os.path.join(HERE, "liboracle.so")
 

@@ -109,6 +109,10 @@ void ora_adam_step(int64_t len, double* w, double* m, double* v, const double* g
                    double lr, double beta1, double beta2, double eps);
 double ora_bf16_round(double x);
 
+/* ---- sparse matrices (sparse_oracle.c) ---- */
+void ora_csr_to_csc(int64_t m, int64_t n, int64_t p, const int64_t* rowptr, const int32_t* colidx,
+                    const double* val, int64_t* colptr, int32_t* rowidx, double* cval, int32_t* a1len);
+
 #ifdef __cplusplus
 }
 #endif

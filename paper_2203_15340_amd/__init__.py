@@ -31,7 +31,9 @@ EXPORTS = ("ils_create", "ils_destroy", "ils_opts_default", "ils_status_string",
            "ils_get_phase_times", "ils_sp_solve_batched", "ils_sp_solve_multi", "ils_ws_create",
            "ils_ws_destroy", "ils_ws_train", "ils_ws_infer", "ils_ws_save", "ils_ws_load",
            "ils_ws_nparams", "ils_ws_get_params", "ils_ws_set_params", "ils_ws_forward", "ils_ws_grad",
-           "ils_ws_adam")
+           "ils_ws_adam", "ils_csr_create", "ils_csr_destroy", "ils_sp_solve_csr", "ils_rk_solve_csr",
+           "ils_rgs_solve_csr", "ils_csr_gram", "ils_csr_colpass", "ils_csr_residual",
+           "ils_csr_export_csc")
 PHASES = ("colpass", "gram_a1", "gram_a1_reduce", "gram_a2_rhs", "gauss_jordan", "layout",
           "iterations")
 
@@ -114,6 +116,15 @@ def load_library(path: str = LIB_PATH):
         "ils_ws_forward": (C.c_int, [P, I64, P, P]),
         "ils_ws_grad": (C.c_int, [P, I64, P, P, P, P]),
         "ils_ws_adam": (C.c_int, [P, P, C.c_double]),
+        "ils_csr_create": (C.c_int, [P, I64, I64, I64, I64, P, P, P, C.POINTER(P)]),
+        "ils_csr_destroy": (C.c_int, [P]),
+        "ils_sp_solve_csr": (C.c_int, [P, P, P, P, P, P, P]),
+        "ils_rk_solve_csr": (C.c_int, [P, P, P, P, P, P, P]),
+        "ils_rgs_solve_csr": (C.c_int, [P, P, P, P, P, P, P]),
+        "ils_csr_gram": (C.c_int, [P, P, I32, P, I64]),
+        "ils_csr_colpass": (C.c_int, [P, P, P, P, P]),
+        "ils_csr_residual": (C.c_int, [P, P, P, P, P]),
+        "ils_csr_export_csc": (C.c_int, [P, P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -474,3 +485,99 @@ class WarmStart:
 
     def adam(self, grad, lr=1e-3):
         _rc(load_library().ils_ws_adam(self._net, _ptr(grad.contiguous()), lr), "ils_ws_adam")
+
+
+class SparseA:
+    """A = [A1; A2] in CSR on the device (ils_csr_*).  rowptr int64 (m + 1),
+    colidx int32, val float64 CUDA tensors; they are kept referenced here
+    because every solve reads them."""
+
+    def __init__(self, p, q, n, rowptr, colidx, val):
+        torch = _torch()
+        for t, dt, name in ((rowptr, torch.int64, "rowptr"), (colidx, torch.int32, "colidx"),
+                            (val, torch.float64, "val")):
+            if not t.is_cuda or t.dtype != dt or t.dim() != 1 or not t.is_contiguous():
+                raise ILSError(f"{name} must be a contiguous 1-D {dt} CUDA tensor")
+        if rowptr.numel() != p + q + 1 or colidx.numel() != val.numel():
+            raise ILSError("CSR arrays have inconsistent sizes")
+        self.p, self.q, self.n, self.nnz = p, q, n, val.numel()
+        self.m = p + q
+        self.device = val.device
+        self._keep = (rowptr, colidx, val)
+        self._h = handle(self.device)
+        A = C.c_void_p()
+        _rc(load_library().ils_csr_create(self._h, p, q, n, self.nnz, _ptr(rowptr), _ptr(colidx), _ptr(val),
+                                          C.byref(A)), "ils_csr_create")
+        self._A = A
+
+    @classmethod
+    def from_scipy(cls, S, p, device="cuda"):
+        """From a scipy.sparse matrix with m = S.shape[0] rows (A1 = the first p)."""
+        torch = _torch()
+        S = S.tocsr()
+        return cls(p, S.shape[0] - p, S.shape[1],
+                   torch.from_numpy(S.indptr.astype("int64")).to(device),
+                   torch.from_numpy(S.indices.astype("int32")).to(device),
+                   torch.from_numpy(S.data.astype("float64")).to(device))
+
+    def close(self):
+        if self._A:
+            load_library().ils_csr_destroy(self._A)
+            self._A = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _solve(self, fname, b, x0=None, out=None, **kw):
+        torch = _torch()
+        _check_vec(b, self.m, "b")
+        _check_vec(x0, self.n, "x0")
+        _check_vec(kw.get("x_ref"), self.n, "x_ref")
+        x = out if out is not None else torch.empty(self.n, dtype=torch.float64, device=self.device)
+        o = make_opts(**kw)
+        info = _Info()
+        rc = getattr(load_library(), fname)(self._h, self._A, _ptr(b), _ptr(x0), _ptr(x), C.byref(o),
+                                            C.byref(info))
+        return x, Info(int(rc), int(info.outer_iters), int(info.inner_iters), float(info.rr),
+                       float(info.rel_err), float(info.device_ms))
+
+    def sp_solve(self, b, x0=None, **kw):
+        return self._solve("ils_sp_solve_csr", b, x0, **kw)
+
+    def rk_solve(self, b, x0=None, **kw):
+        return self._solve("ils_rk_solve_csr", b, x0, **kw)
+
+    def rgs_solve(self, b, x0=None, **kw):
+        return self._solve("ils_rgs_solve_csr", b, x0, **kw)
+
+    def gram(self, part):
+        torch = _torch()
+        G = torch.empty((self.n, self.n), dtype=torch.float64, device=self.device)
+        _rc(load_library().ils_csr_gram(self._h, self._A, part, _ptr(G), self.n), "ils_csr_gram")
+        return G.t()
+
+    def colpass(self, b):
+        torch = _torch()
+        g = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        c = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        rc = load_library().ils_csr_colpass(self._h, self._A, _ptr(b), _ptr(g), _ptr(c))
+        return int(rc), g, c
+
+    def residual(self, b, x):
+        torch = _torch()
+        r = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        _rc(load_library().ils_csr_residual(self._h, self._A, _ptr(b), _ptr(x), _ptr(r)), "ils_csr_residual")
+        return r
+
+    def csc(self):
+        torch = _torch()
+        cp = torch.empty(self.n + 1, dtype=torch.int64, device=self.device)
+        ri = torch.empty(self.nnz, dtype=torch.int32, device=self.device)
+        cv = torch.empty(self.nnz, dtype=torch.float64, device=self.device)
+        a1 = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        _rc(load_library().ils_csr_export_csc(self._A, _ptr(cp), _ptr(ri), _ptr(cv), _ptr(a1)),
+            "ils_csr_export_csc")
+        return cp, ri, cv, a1

@@ -201,14 +201,14 @@ int ils::read_state(ils_handle* h) {
 }
 
 // ------------------------------------------------------------------ SP
-extern "C" int ils_sp_solve(ils_handle* h, int64_t p, int64_t q, int64_t n, const double* A,
-                            int64_t lda, const double* b, const double* x0, double* x,
-                            const ils_opts* o, ils_info* info) {
+int ils::sp_solve_op(ils_handle* h, const MatOp& M, const double* b, const double* x0, double* x,
+                     const ils_opts* o, ils_info* info) {
   if (!h) return fail(info, ILS_ERR_ARG);
-  int st = check_problem(p, q, n, A, lda, b, x, o);
+  int st = check_op(M, b, x, o);
   if (st != ILS_OK) return fail(info, st);
   if (hipSetDevice(h->device) != hipSuccess) return fail(info, ILS_ERR_HIP);
   hipStream_t s = h->stream;
+  const int64_t p = M.p, q = M.q, n = M.n;
   const int64_t m = p + q;
   const bool paper = o->form == ILS_FORM_PAPER;
   const bool need_h = paper && o->stop_rule == ILS_STOP_RR;
@@ -218,7 +218,7 @@ extern "C" int ils_sp_solve(ils_handle* h, int64_t p, int64_t q, int64_t n, cons
   double *g, *W, *Mrow, *H = nullptr, *xb0, *xb1, *tv, *rv, *spart, *dinv;
   void* part;
   int* sbad;
-  size_t part_bytes = std::max(gram_partials_size(n, p), gram_partials_size(n, q)) * sizeof(double);
+  const size_t part_bytes = mat_gram_partials(M) * sizeof(double);
   if ((st = h->need(kBufG, sizeof(double) * n, (void**)&g)) ||
       (st = h->need(kBufW, sizeof(double) * ldw * (n + nrhs), (void**)&W)) ||
       (st = h->need(kBufM, sizeof(double) * n * n, (void**)&Mrow)) ||
@@ -237,19 +237,16 @@ extern "C" int ils_sp_solve(ils_handle* h, int64_t p, int64_t q, int64_t n, cons
   HIPCHK(hipEventRecord(h->ev0, s));
   h->mark(0);
   LoopState* ds = h->st;
-  launch_colpass(s, p, q, n, A, lda, b, g, nullptr, &ds->bits);
+  mat_colpass(s, M, b, g, nullptr, &ds->bits);
   if (o->stop_rule == ILS_STOP_RR) launch_norm2(s, n, g, &ds->scal[0]);
   if (o->stop_rule == ILS_STOP_XREF) launch_norm2(s, n, o->x_ref, &ds->scal[1]);
   h->mark(1);
   // [A1^T A1 | A2^T A2 | A^T J b] (paper form) or [A1^T A1 | I] (correction form)
   hipEvent_t mid = h->profile ? h->pev[2] : nullptr;
-  if (o->precision == ILS_PREC_MIXED)
-    launch_gram_f32(s, p, n, A, lda, (float*)part, W, ldw, mid);
-  else
-    launch_gram_f64(s, p, n, A, lda, (double*)part, W, ldw, mid);
+  mat_gram(s, M, 0, o->precision, part, W, ldw, mid);
   h->mark(3);
   if (paper) {
-    launch_gram_f64(s, q, n, A + p, lda, (double*)part, W + n * ldw, ldw);
+    mat_gram(s, M, 1, ILS_PREC_FP64, part, W + n * ldw, ldw);
     launch_copy_cols(s, n, 1, g, n, W + 2 * n * ldw, ldw);
     if (need_h) launch_sub(s, n, W, ldw, W + n * ldw, ldw, H, n);
   } else {
@@ -286,7 +283,7 @@ extern "C" int ils_sp_solve(ils_handle* h, int64_t p, int64_t q, int64_t n, cons
   while (true) {
     const int64_t kend = std::min(k + chunk, o->max_outer + 1);
     for (; k < kend; ++k) {
-      if (!paper) launch_residual(s, p, q, n, A, lda, b, k & 1 ? xb1 : xb0, tv, rv, &ds->done);
+      if (!paper) mat_residual(s, M, b, k & 1 ? xb1 : xb0, tv, rv, &ds->done);
       launch_sp_step(s, a, k);
     }
     HIPCHK(hipEventRecord(h->ev1, s));
@@ -303,6 +300,17 @@ extern "C" int ils_sp_solve(ils_handle* h, int64_t p, int64_t q, int64_t n, cons
   HIPCHK(hipMemcpyAsync(x, (hs.iters & 1) ? xb1 : xb0, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
   HIPCHK(hipStreamSynchronize(s));
   return finish_info(h, n, x, o, st, hs.iters, 0, hs.metric, info);
+}
+
+extern "C" int ils_sp_solve(ils_handle* h, int64_t p, int64_t q, int64_t n, const double* A, int64_t lda,
+                            const double* b, const double* x0, double* x, const ils_opts* o, ils_info* info) {
+  MatOp M;
+  M.p = p;
+  M.q = q;
+  M.n = n;
+  M.A = A;
+  M.lda = lda;
+  return sp_solve_op(h, M, b, x0, x, o, info);
 }
 
 // ------------------------------------------------------------------ components

@@ -49,10 +49,11 @@ struct Common {
 
 // Setup shared by both methods: A^T J b, norms for the stop test, A2^T A2
 // (paper form), the start vector.
-static int common_setup(ils_handle* h, int64_t p, int64_t q, int64_t n, const double* A, int64_t lda,
-                        const double* b, const double* x0, const ils_opts* o, double* cn, Common& c) {
+static int common_setup(ils_handle* h, const MatOp& M, const double* b, const double* x0, const ils_opts* o,
+                        double* cn, Common& c) {
   hipStream_t s = h->stream;
-  const int64_t m = p + q;
+  const int64_t n = M.n;
+  const int64_t m = M.p + M.q;
   int st;
   const bool paper = o->form == ILS_FORM_PAPER;
   if ((st = h->need(kBufG, sizeof(double) * n, (void**)&c.g)) ||
@@ -61,28 +62,29 @@ static int common_setup(ils_handle* h, int64_t p, int64_t q, int64_t n, const do
       (st = h->need(kBufSPart, sizeof(double) * n, (void**)&c.tgt)) ||
       (st = h->need(kBufR, sizeof(double) * n, (void**)&c.rk)) ||
       (st = h->need(kBufT, sizeof(double) * (m > 0 ? m : 1), (void**)&c.tv)) ||
-      (st = h->need(kBufPart, gram_partials_size(n, std::max(p, q)) * sizeof(double), (void**)&c.part)) ||
+      (st = h->need(kBufPart, mat_gram_partials(M) * sizeof(double), (void**)&c.part)) ||
       (paper && (st = h->need(kBufG2, sizeof(double) * n * n, (void**)&c.G2))))
     return st;
   if (!paper) c.G2 = nullptr;
   HIPCHK(hipMemsetAsync(h->st, 0, sizeof(LoopState), s));
   HIPCHK(hipEventRecord(h->ev0, s));
-  launch_colpass(s, p, q, n, A, lda, b, c.g, cn, &h->st->bits);
+  mat_colpass(s, M, b, c.g, cn, &h->st->bits);
   if (o->stop_rule == ILS_STOP_RR) launch_norm2(s, n, c.g, &h->st->scal[0]);
   if (o->stop_rule == ILS_STOP_XREF) launch_norm2(s, n, o->x_ref, &h->st->scal[1]);
-  if (paper) launch_gram_f64(s, q, n, A + p, lda, c.part, c.G2, n);
+  if (paper) mat_gram(s, M, 1, ILS_PREC_FP64, c.part, c.G2, n);
   launch_fill_vec(s, n, x0, c.xb0);
   return ILS_OK;
 }
 
 // Stop test at x_k; returns 1 when the outer loop is over.
-static int outer_begin(ils_handle* h, int64_t p, int64_t q, int64_t n, const double* A, int64_t lda,
-                       const double* b, const ils_opts* o, Common& c, int64_t k, int* over) {
+static int outer_begin(ils_handle* h, const MatOp& M, const double* b, const ils_opts* o, Common& c, int64_t k,
+                       int* over) {
   hipStream_t s = h->stream;
+  const int64_t n = M.n;
   const double* xk = (k & 1) ? c.xb1 : c.xb0;
   const bool paper = o->form == ILS_FORM_PAPER;
   if (o->stop_rule == ILS_STOP_RR || !paper)
-    launch_residual(s, p, q, n, A, lda, b, xk, c.tv, c.rk, nullptr);
+    mat_residual(s, M, b, xk, c.tv, c.rk, nullptr);
   launch_outer_test(s, n, xk, o->x_ref, c.rk, o->stop_rule, o->tol, k, o->max_outer, h->st);
   if (paper) launch_symv_add(s, n, c.G2, n, xk, c.g, c.tgt, &h->st->done);
   else launch_fill_vec(s, n, c.rk, c.tgt);
@@ -111,11 +113,11 @@ static int finish(ils_handle* h, int64_t n, double* x, const ils_opts* o, Common
 }
 
 // ------------------------------------------------------------------ SP-RK-RGS
-extern "C" int ils_rk_solve(ils_handle* h, int64_t p, int64_t q, int64_t n, const double* A, int64_t lda,
-                            const double* b, const double* x0, double* x, const ils_opts* o,
-                            ils_info* info) {
+int ils::rk_solve_op(ils_handle* h, const MatOp& M, const double* b, const double* x0, double* x,
+                     const ils_opts* o, ils_info* info) {
   if (!h) return fail_info(info, ILS_ERR_ARG);
-  int st = check_problem(p, q, n, A, lda, b, x, o);
+  const int64_t p = M.p, n = M.n;
+  int st = check_op(M, b, x, o);
   if (st == ILS_OK && o->precision != ILS_PREC_FP64) st = ILS_ERR_ARG;
   if (st != ILS_OK) return fail_info(info, st);
   if (hipSetDevice(h->device) != hipSuccess) return fail_info(info, ILS_ERR_HIP);
@@ -137,13 +139,13 @@ extern "C" int ils_rk_solve(ils_handle* h, int64_t p, int64_t q, int64_t n, cons
       (st = h->need(kBufH, sizeof(double) * n, (void**)&res2)) ||
       (st = h->need(kBufIdx, sizeof(int) * 2 * chunk, (void**)&jj)))
     return fail_info(info, st);
-  if ((st = common_setup(h, p, q, n, A, lda, b, x0, o, cn, c))) return fail_info(info, st);
+  if ((st = common_setup(h, M, b, x0, o, cn, c))) return fail_info(info, st);
   launch_zero_col_check(s, n, cn, &h->st->bits);  // a zero column of A1: rank(A1) < n
   launch_prefix(s, n, cn, 1, prefix);
   int64_t inner_total = 0;
   for (int64_t k = 0;; ++k) {
     int over = 0;
-    if ((st = outer_begin(h, p, q, n, A, lda, b, o, c, k, &over))) return fail_info(info, st);
+    if ((st = outer_begin(h, M, b, o, c, k, &over))) return fail_info(info, st);
     if (over) break;
     HIPCHK(hipMemsetAsync(w, 0, sizeof(double) * p, s));
     HIPCHK(hipMemsetAsync(sv, 0, sizeof(double) * p, s));
@@ -156,12 +158,11 @@ extern "C" int ils_rk_solve(ils_handle* h, int64_t p, int64_t q, int64_t n, cons
     while (t < max_inner && !(!fixed && h->st_host->inner_done)) {
       const int64_t cnt = std::min(chunk, max_inner - t);
       launch_rk_draw(s, o->seed, (uint64_t)k + o->stream_offset, t, cnt, prefix, n, jj, jj + chunk);
-      launch_rk_inner(s, A, lda, p, c.tgt, cn, jj, jj + chunk, cnt, w, sv, z, &h->st->inner_done,
-                      &h->st->done);
+      mat_rk_inner(s, M, c.tgt, cn, jj, jj + chunk, cnt, w, sv, z, &h->st->inner_done, &h->st->done);
       t += cnt;
       if (!fixed && t % check == 0) {
-        launch_rk_check(s, A, lda, p, n, w, sv, v, c.tgt, res2, itol * itol, &h->st->scal[2],
-                        &h->st->inner_done, &h->st->arrive2, &h->st->done);
+        mat_rk_check(s, M, w, sv, v, c.tgt, res2, itol * itol, &h->st->scal[2], &h->st->inner_done,
+                     &h->st->arrive2, &h->st->done);
         if ((st = read_state(h))) return fail_info(info, st);
       }
     }
@@ -172,12 +173,23 @@ extern "C" int ils_rk_solve(ils_handle* h, int64_t p, int64_t q, int64_t n, cons
   return finish(h, n, x, o, c, inner_total, info);
 }
 
+extern "C" int ils_rk_solve(ils_handle* h, int64_t p, int64_t q, int64_t n, const double* A, int64_t lda,
+                            const double* b, const double* x0, double* x, const ils_opts* o, ils_info* info) {
+  MatOp M;
+  M.p = p;
+  M.q = q;
+  M.n = n;
+  M.A = A;
+  M.lda = lda;
+  return rk_solve_op(h, M, b, x0, x, o, info);
+}
+
 // ------------------------------------------------------------------ SP-SCD
-extern "C" int ils_rgs_solve(ils_handle* h, int64_t p, int64_t q, int64_t n, const double* A,
-                             int64_t lda, const double* b, const double* x0, double* x,
-                             const ils_opts* o, ils_info* info) {
+int ils::rgs_solve_op(ils_handle* h, const MatOp& M, const double* b, const double* x0, double* x,
+                      const ils_opts* o, ils_info* info) {
   if (!h) return fail_info(info, ILS_ERR_ARG);
-  int st = check_problem(p, q, n, A, lda, b, x, o);
+  const int64_t n = M.n;
+  int st = check_op(M, b, x, o);
   if (st == ILS_OK && o->sampling == ILS_SAMPLE_NORM && o->alpha != 1) st = ILS_ERR_ARG;
   if (st == ILS_OK && o->sampling == ILS_SAMPLE_UNIFORM && !(o->alpha >= n) && n > kScdMaxN)
     st = ILS_ERR_ARG;
@@ -205,11 +217,8 @@ extern "C" int ils_rgs_solve(ils_handle* h, int64_t p, int64_t q, int64_t n, con
       (st = h->need(kBufDinv, sizeof(double) * gj_dinv_size(), (void**)&dinv)))
     return fail_info(info, st);
   jpre = alpha_buf + chunk;
-  if ((st = common_setup(h, p, q, n, A, lda, b, x0, o, nullptr, c))) return fail_info(info, st);
-  if (o->precision == ILS_PREC_MIXED)
-    launch_gram_f32(s, p, n, A, lda, (float*)c.part, G1, n);
-  else
-    launch_gram_f64(s, p, n, A, lda, c.part, G1, n);
+  if ((st = common_setup(h, M, b, x0, o, nullptr, c))) return fail_info(info, st);
+  mat_gram(s, M, 0, o->precision, c.part, G1, n);
   // positive definiteness of A1^T A1 (the elimination is only a test here)
   launch_copy_cols(s, n, n, G1, n, W, n);
   launch_gj(s, n, 0, W, n, dinv, &h->st->bits);
@@ -218,7 +227,7 @@ extern "C" int ils_rgs_solve(ils_handle* h, int64_t p, int64_t q, int64_t n, con
   int64_t inner_total = 0;
   for (int64_t k = 0;; ++k) {
     int over = 0;
-    if ((st = outer_begin(h, p, q, n, A, lda, b, o, c, k, &over))) return fail_info(info, st);
+    if ((st = outer_begin(h, M, b, o, c, k, &over))) return fail_info(info, st);
     if (over) break;
     launch_fill_vec(s, n, c.tgt, r);
     HIPCHK(hipMemsetAsync(beta, 0, sizeof(double) * n, s));
@@ -238,6 +247,17 @@ extern "C" int ils_rgs_solve(ils_handle* h, int64_t p, int64_t q, int64_t n, con
                         (k & 1) ? c.xb0 : c.xb1, k, h->st);
   }
   return finish(h, n, x, o, c, inner_total, info);
+}
+
+extern "C" int ils_rgs_solve(ils_handle* h, int64_t p, int64_t q, int64_t n, const double* A, int64_t lda,
+                             const double* b, const double* x0, double* x, const ils_opts* o, ils_info* info) {
+  MatOp M;
+  M.p = p;
+  M.q = q;
+  M.n = n;
+  M.A = A;
+  M.lda = lda;
+  return rgs_solve_op(h, M, b, x0, x, o, info);
 }
 
 // ------------------------------------------------------------------ index streams

@@ -79,7 +79,38 @@ struct ils_handle {
   int need(int slot, size_t bytes, void** out);
 };
 
+struct ils_csr;
+
 namespace ils {
+// The matrix A = [A1; A2] as the solver drivers see it: dense column-major
+// (A, lda) or sparse (sp: CSR plus the library's CSC copy).
+struct MatOp {
+  int64_t p = 0, q = 0, n = 0;
+  const double* A = nullptr;
+  int64_t lda = 0;
+  const ils_csr* sp = nullptr;
+};
+int check_op(const MatOp& M, const double* b, const double* x, const ils_opts* o);
+size_t mat_gram_partials(const MatOp& M);  // doubles of split-K scratch for mat_gram
+void mat_colpass(hipStream_t s, const MatOp& M, const double* b, double* g, double* cn, int* bits);
+void mat_residual(hipStream_t s, const MatOp& M, const double* b, const double* x, double* t, double* r,
+                  const int* done);
+// G = A1^T A1 (second == 0) or A2^T A2 (second == 1).
+void mat_gram(hipStream_t s, const MatOp& M, int second, int precision, void* part, double* G, int64_t ldg,
+              hipEvent_t mid = nullptr);
+void mat_rk_inner(hipStream_t st, const MatOp& M, const double* tgt, const double* cn, const int* j1,
+                  const int* j2, int64_t count, double* w, double* s, double* z, const int* inner_done,
+                  const int* outer_done);
+void mat_rk_check(hipStream_t st, const MatOp& M, const double* w, const double* s, double* v, const double* tgt,
+                  double* res2, double itol2, const double* tn2, int* inner_done, unsigned* arrive,
+                  const int* skip);
+int sp_solve_op(ils_handle* h, const MatOp& M, const double* b, const double* x0, double* x, const ils_opts* o,
+                ils_info* info);
+int rk_solve_op(ils_handle* h, const MatOp& M, const double* b, const double* x0, double* x, const ils_opts* o,
+                ils_info* info);
+int rgs_solve_op(ils_handle* h, const MatOp& M, const double* b, const double* x0, double* x, const ils_opts* o,
+                 ils_info* info);
+
 int check_problem(int64_t p, int64_t q, int64_t n, const double* A, int64_t lda, const double* b,
                   const double* x, const ils_opts* o);
 int finish_info(ils_handle* h, int64_t n, double* x, const ils_opts* o, int status, int64_t outer,

@@ -154,6 +154,82 @@ def ws_solutions(U: np.ndarray, count: int, seed) -> np.ndarray:
     return planted_columns(U.shape[0], count, seed, basis=U, noise=WS_NOISE)
 
 
+@dataclasses.dataclass
+class SparseILS:
+    A: object              # scipy.sparse.csr_matrix (m, n), float64, int32 indices
+    b: np.ndarray
+    p: int
+    q: int
+    x_star: np.ndarray
+    ratio: float
+    seed: object
+
+    @property
+    def m(self) -> int:
+        return self.p + self.q
+
+    @property
+    def n(self) -> int:
+        return self.A.shape[1]
+
+
+def sparse_ils(p: int, q: int, n: int, density: float = 0.005, ratio: float = 0.7, seed=2,
+               power_iters: int = 200) -> SparseILS:
+    """Sparse ILS instance: every entry of A (m x n) is nonzero independently
+    with probability `density` (a Bernoulli process over the row-major
+    positions, drawn as geometric gaps) with an N(0,1) value; A1[i, i] += 1
+    for i < n (full rank); A2 scaled to ||A2||_2 = ratio * sigma_min(A1),
+    with ||A2||_2 from `power_iters` power iterations on A2^T A2 times
+    (1 + 1e-3) and sigma_min(A1) from the eigenvalues of the dense A1^T A1.
+    x* ~ N(0, I), b = A x*.  Draw order: gaps, values, power-iteration start,
+    x*."""
+    import scipy.sparse as sps
+    rng = _rng(seed)
+    m = p + q
+    total = m * n
+    pos = np.empty(0, dtype=np.int64)
+    last = -1
+    while True:
+        want = int((total - last) * density * 1.05) + 1024
+        gaps = rng.geometric(density, size=want).astype(np.int64)
+        chunk = last + np.cumsum(gaps)
+        pos = np.concatenate([pos, chunk[chunk < total]])
+        if chunk[-1] >= total:
+            break
+        last = int(chunk[-1])
+    vals = rng.standard_normal(len(pos))
+    rows, cols = pos // n, pos % n
+    d = np.arange(min(n, p))
+    A = sps.coo_matrix((np.concatenate([vals, np.ones(len(d))]),
+                        (np.concatenate([rows, d]), np.concatenate([cols, d]))), shape=(m, n)).tocsr()
+    A.sum_duplicates()
+    A.sort_indices()
+    v = rng.standard_normal(n)
+    x_star = rng.standard_normal(n)
+    A1, A2 = A[:p], A[p:]
+    if q > 0:
+        v /= np.linalg.norm(v)
+        lam = 0.0
+        for _ in range(power_iters):
+            u = A2.T @ (A2 @ v)
+            lam = float(np.linalg.norm(u))
+            v = u / lam
+        a2n = np.sqrt(lam) * (1 + 1e-3)
+        smin = float(np.sqrt(np.linalg.eigvalsh((A1.T @ A1).toarray())[0]))
+        A2 = A2 * (ratio * smin / a2n)
+        A = sps.vstack([A1, A2]).tocsr()
+        A.sort_indices()
+    A.indices = A.indices.astype(np.int32)
+    A.indptr = A.indptr.astype(np.int64)
+    b = A @ x_star
+    return SparseILS(A=A, b=np.ascontiguousarray(b), p=p, q=q, x_star=x_star, ratio=ratio, seed=seed)
+
+
+def sparse_large(seed: int = 2) -> SparseILS:
+    """p = 180000, q = 20000, n = 4000, density 0.005, ratio 0.7."""
+    return sparse_ils(180000, 20000, 4000, density=0.005, ratio=0.7, seed=seed)
+
+
 def paper_family(p: int, q: int, n: int, seed=0) -> DenseILS:
     """The experiment family of Sec. 5.2 (q = n) and Sec. 5.3 (q = 1).
 
