@@ -200,6 +200,74 @@ def bench_warm_start(ils, W, np, torch, n_train=50000, n_test=2000, epochs=20, s
     return out
 
 
+def bench_sparse(ils, W, np, torch, reps=3, rk_steps=20000):
+    """Sparse ILS: p = 180000, q = 20000, n = 4000, i.i.d. Bernoulli(0.005)
+    pattern with N(0,1) values, A1[i, i] += 1, A2 scaled to ratio 0.7;
+    b = A x*.  SP and SP-SCD to rel.err 1e-6; SP-RK-RGS timed per inner step
+    on a fixed schedule (a full solve needs ~47 n inner steps per outer step)."""
+    log("sparse workload: generating")
+    P = W.sparse_large(seed=2)
+    t0 = time.perf_counter()
+    S = ils.SparseA.from_scipy(P.A, P.p)
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    b = torch.from_numpy(P.b).cuda()
+    xs = torch.from_numpy(P.x_star).cuda()
+    kw = dict(stop_rule=ils.STOP_XREF, x_ref=xs, tol=1e-6)
+    out = {"workload": "sparse A 180000+20000 x 4000, density 0.005, ratio 0.7", "nnz": int(P.A.nnz),
+           "csr_upload_and_csc_build_s": t_build}
+    ils.set_profiling(True)
+    S.sp_solve(b, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    phases = []
+    for _ in range(reps):
+        _, inf = S.sp_solve(b, **kw)
+        phases.append(ils.phase_times())
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / reps
+    ph = {k: statistics.mean(q[k] for q in phases) for k in ils.PHASES}
+    out["sp_fp64_paper"] = {"solves_per_s": 1.0 / el, "ms": el * 1e3, "outer": inf.outer_iters,
+                            "rel_err": inf.rel_err, "status": inf.status, "phases_ms": ph}
+    log(f"sparse SP: {1.0 / el:.2f} solves/s, outer {inf.outer_iters}, phases {ph}")
+    for name, extra in (("sp_fp64_correction", dict(form=ils.FORM_CORRECTION)),):
+        t0 = time.perf_counter()
+        _, inf = S.sp_solve(b, **kw, **extra)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[name] = {"solves_per_s": 1.0 / el, "outer": inf.outer_iters, "rel_err": inf.rel_err,
+                     "status": inf.status}
+    t0 = time.perf_counter()
+    _, inf = S.rgs_solve(b, form=ils.FORM_CORRECTION, seed=1, **kw)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    out["sp_scd_correction"] = {"solves_per_s": 1.0 / el, "outer": inf.outer_iters,
+                                "inner": inf.inner_iters, "rel_err": inf.rel_err, "status": inf.status}
+    log(f"sparse SP-SCD: {1.0 / el:.3f} solves/s, outer {inf.outer_iters}, inner {inf.inner_iters}")
+    S.rk_solve(b, stop_rule=ils.STOP_FIXED, max_outer=1, max_inner=1000, seed=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, inf = S.rk_solve(b, stop_rule=ils.STOP_FIXED, max_outer=1, max_inner=rk_steps, seed=1)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    out["sp_rk_rgs_inner_step_us"] = el / rk_steps * 1e6
+    log(f"sparse SP-RK-RGS: {el / rk_steps * 1e6:.2f} us per inner step")
+    # residual sweep A^T J (b - A x): CSR + CSC bytes against HBM
+    x = torch.zeros(P.n, dtype=torch.float64, device="cuda")
+    S.residual(b, x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(20):
+        S.residual(b, x)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / 20
+    nbytes = 2 * 12 * P.A.nnz + 8 * (P.m + 1) + 8 * (P.n + 1) + 8 * 3 * P.m + 8 * 2 * P.n
+    out["residual"] = {"ms": el * 1e3, "algorithmic_bytes": nbytes, "GB_per_s": nbytes / el / 1e9,
+                       "note": "host-timed call incl. launch and sync"}
+    S.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -209,6 +277,7 @@ def main():
     ap.add_argument("--no-forms", action="store_true", help="skip the non-headline forms")
     ap.add_argument("--no-batched", action="store_true", help="skip the 4096-problem batch")
     ap.add_argument("--no-warm-start", action="store_true", help="skip the learned warm start")
+    ap.add_argument("--no-sparse", action="store_true", help="skip the sparse workload")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 256 MiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -290,6 +359,9 @@ def main():
     warm = None
     if not args.no_warm_start:
         warm = bench_warm_start(ils, W, np, torch)
+    sparse = None
+    if not args.no_sparse:
+        sparse = bench_sparse(ils, W, np, torch)
 
     line = {
         "metric": "ILS solves/s to rel.err 1e-6, plain FP64 SP vs chosen form; % HBM/MFMA peak",
@@ -317,6 +389,7 @@ def main():
         "forms": forms,
         "batched": batched,
         "warm_start": warm,
+        "sparse": sparse,
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
