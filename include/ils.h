@@ -131,7 +131,10 @@ int ils_sp_solve(ils_handle* h, int64_t p, int64_t q, int64_t n, const double* A
 /* SP-RK-RGS, Algorithm 2: each outer step runs randomized Kaczmarz steps on
  * A1^T w = bhat (eq. Sec3.32111) interleaved with randomized Gauss-Seidel
  * steps on A1 z = w (eq. Sec3.33111), both choosing columns of A1 with
- * probability ||A1_(j)||^2 / ||A1||_F^2, and sets x_{k+1} = z. */
+ * probability ||A1_(j)||^2 / ||A1||_F^2, and sets x_{k+1} = z.
+ * ILS_PREC_MIXED (with ILS_FORM_CORRECTION): the inner sweeps read an FP32
+ * copy of A1 and keep w, s in FP32 with FP32 sums; the outer residual
+ * A^T J (b - A x_k), z and x stay FP64 (iterative refinement). */
 int ils_rk_solve(ils_handle* h, int64_t p, int64_t q, int64_t n, const double* A, int64_t lda,
                  const double* b, const double* x0, double* x, const ils_opts* opts,
                  ils_info* info /* host */);
@@ -313,6 +316,33 @@ int ils_rk_indices(ils_handle* h, uint64_t seed, uint64_t outer, int64_t t0, int
                    const double* weights, int64_t n, int32_t* j1, int32_t* j2);
 int ils_scd_subsets(ils_handle* h, uint64_t seed, uint64_t outer, int64_t t0, int64_t count,
                     int64_t n, int64_t alpha_opt, int32_t* alpha, uint32_t* member);
+
+/* ---- autotuning ---- */
+
+enum { ILS_TUNE_GRAM = 0 };
+typedef struct {
+  int32_t kernel;       /* ILS_TUNE_* */
+  int32_t precision;    /* ILS_PREC_* */
+  int64_t n, K;         /* shape the sweep ran on */
+  int32_t tile;         /* tile edge, 64 or 128 */
+  int32_t workgroups;   /* workgroups aimed at (sets the K-split) */
+  double ms;            /* mean time of one launch */
+} ils_tune_entry;
+
+/* Time every launch configuration of the Gram kernel (tile edge 64 / 128 x
+ * 256 .. 4096 workgroups) on G = A[0:K, :]^T A[0:K, :] (reps launches each,
+ * after one warm-up; the matrix is only read) and keep the fastest for the
+ * bucket (precision, ceil(log2 n), ceil(log2 K)) in the process-wide table
+ * that all Gram launches consult (every solver, every handle).  *best (host,
+ * may be NULL) receives the choice.  Results of later solves differ from the
+ * default configuration only by the order of the K-split additions. */
+int ils_tune_gram(ils_handle* h, int64_t K, int64_t n, const double* A, int64_t lda, int32_t precision,
+                  int32_t reps, ils_tune_entry* best /* host */);
+/* Save / load the table as JSON (host path); load adds to the table and
+ * rejects malformed files with ILS_ERR_ARG.  Clear restores the defaults. */
+int ils_tune_save(const char* path);
+int ils_tune_load(const char* path);
+int ils_tune_clear(void);
 
 /* ---- instrumentation ---- */
 

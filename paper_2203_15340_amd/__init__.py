@@ -33,7 +33,7 @@ EXPORTS = ("ils_create", "ils_destroy", "ils_opts_default", "ils_status_string",
            "ils_ws_nparams", "ils_ws_get_params", "ils_ws_set_params", "ils_ws_forward", "ils_ws_grad",
            "ils_ws_adam", "ils_csr_create", "ils_csr_destroy", "ils_sp_solve_csr", "ils_rk_solve_csr",
            "ils_rgs_solve_csr", "ils_csr_gram", "ils_csr_colpass", "ils_csr_residual",
-           "ils_csr_export_csc")
+           "ils_csr_export_csc", "ils_tune_gram", "ils_tune_save", "ils_tune_load", "ils_tune_clear")
 PHASES = ("colpass", "gram_a1", "gram_a1_reduce", "gram_a2_rhs", "gauss_jordan", "layout",
           "iterations")
 
@@ -125,6 +125,10 @@ def load_library(path: str = LIB_PATH):
         "ils_csr_colpass": (C.c_int, [P, P, P, P, P]),
         "ils_csr_residual": (C.c_int, [P, P, P, P, P]),
         "ils_csr_export_csc": (C.c_int, [P, P, P, P, P]),
+        "ils_tune_gram": (C.c_int, [P, I64, I64, P, I64, I32, I32, P]),
+        "ils_tune_save": (C.c_int, [C.c_char_p]),
+        "ils_tune_load": (C.c_int, [C.c_char_p]),
+        "ils_tune_clear": (C.c_int, []),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -581,3 +585,31 @@ class SparseA:
         _rc(load_library().ils_csr_export_csc(self._A, _ptr(cp), _ptr(ri), _ptr(cv), _ptr(a1)),
             "ils_csr_export_csc")
         return cp, ri, cv, a1
+
+
+class _TuneEntry(C.Structure):
+    _fields_ = [("kernel", C.c_int32), ("precision", C.c_int32), ("n", C.c_int64), ("K", C.c_int64),
+                ("tile", C.c_int32), ("workgroups", C.c_int32), ("ms", C.c_double)]
+
+
+def tune_gram(A, r0, r1, precision=PREC_FP64, reps=5):
+    """Sweep the Gram kernel's launch configurations on rows [r0, r1) of A;
+    the fastest becomes the configuration for that shape bucket."""
+    e = _TuneEntry()
+    _rc(load_library().ils_tune_gram(handle(A.device), r1 - r0, A.shape[1],
+                                     C.c_void_p(A.data_ptr() + 8 * r0), _ld(A), precision, reps,
+                                     C.byref(e)), "ils_tune_gram")
+    return {"kernel": "gram", "precision": int(e.precision), "n": int(e.n), "K": int(e.K),
+            "tile": int(e.tile), "workgroups": int(e.workgroups), "ms": float(e.ms)}
+
+
+def tune_save(path):
+    _rc(load_library().ils_tune_save(str(path).encode()), "ils_tune_save")
+
+
+def tune_load(path):
+    _rc(load_library().ils_tune_load(str(path).encode()), "ils_tune_load")
+
+
+def tune_clear():
+    _rc(load_library().ils_tune_clear(), "ils_tune_clear")

@@ -115,6 +115,24 @@ void launch_gram_f64(hipStream_t s, int64_t K, int64_t n, const double* A, int64
                      double* partials, double* G, int64_t ldg, hipEvent_t mid = nullptr);
 void launch_gram_f32(hipStream_t s, int64_t K, int64_t n, const double* A, int64_t lda,
                      float* partials, double* G, int64_t ldg, hipEvent_t mid = nullptr);
+// Gram launch configuration (tile edge 64 or 128, workgroups aimed at) and
+// the tuning table consulted by launch_gram_f64/f32.
+struct GramCfg {
+  int tile;
+  int workgroups;
+};
+struct GramCfgEntry {
+  int precision, n_bucket, k_bucket;
+  GramCfg cfg;
+};
+GramCfg gram_default_cfg(int64_t n);
+GramCfg gram_cfg(int precision, int64_t n, int64_t K);
+void gram_set_cfg(int precision, int64_t n, int64_t K, GramCfg c);
+void gram_set_cfg_bucket(int precision, int n_bucket, int k_bucket, GramCfg c);
+void gram_clear_cfg();
+size_t gram_partials_size_cfg(int64_t n, int64_t K, GramCfg c);
+void launch_gram_cfg(hipStream_t s, int precision, int64_t K, int64_t n, const double* A, int64_t lda,
+                     void* partials, double* G, int64_t ldg, GramCfg cfg);
 void launch_norm2(hipStream_t s, int64_t n, const double* v, double* out);
 void launch_transpose(hipStream_t s, int64_t n, int64_t ncol, const double* X, int64_t ldx,
                       double* Y, int64_t ldy);

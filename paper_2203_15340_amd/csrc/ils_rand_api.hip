@@ -118,7 +118,6 @@ int ils::rk_solve_op(ils_handle* h, const MatOp& M, const double* b, const doubl
   if (!h) return fail_info(info, ILS_ERR_ARG);
   const int64_t p = M.p, n = M.n;
   int st = check_op(M, b, x, o);
-  if (st == ILS_OK && o->precision != ILS_PREC_FP64) st = ILS_ERR_ARG;
   if (st != ILS_OK) return fail_info(info, st);
   if (hipSetDevice(h->device) != hipSuccess) return fail_info(info, ILS_ERR_HIP);
   hipStream_t s = h->stream;
@@ -139,7 +138,13 @@ int ils::rk_solve_op(ils_handle* h, const MatOp& M, const double* b, const doubl
       (st = h->need(kBufH, sizeof(double) * n, (void**)&res2)) ||
       (st = h->need(kBufIdx, sizeof(int) * 2 * chunk, (void**)&jj)))
     return fail_info(info, st);
+  // mixed precision: FP32 copy of A1; w and s are FP32 (same slots, half used)
+  const bool mixed = o->precision == ILS_PREC_MIXED;
+  float* a1f = nullptr;
+  if (mixed && (st = h->need(kBufA1f32, sizeof(float) * p * n, (void**)&a1f))) return fail_info(info, st);
+  const size_t wbytes = (mixed ? sizeof(float) : sizeof(double)) * p;
   if ((st = common_setup(h, M, b, x0, o, cn, c))) return fail_info(info, st);
+  if (mixed) launch_to_f32(s, p, n, M.A, M.lda, a1f);
   launch_zero_col_check(s, n, cn, &h->st->bits);  // a zero column of A1: rank(A1) < n
   launch_prefix(s, n, cn, 1, prefix);
   int64_t inner_total = 0;
@@ -147,8 +152,8 @@ int ils::rk_solve_op(ils_handle* h, const MatOp& M, const double* b, const doubl
     int over = 0;
     if ((st = outer_begin(h, M, b, o, c, k, &over))) return fail_info(info, st);
     if (over) break;
-    HIPCHK(hipMemsetAsync(w, 0, sizeof(double) * p, s));
-    HIPCHK(hipMemsetAsync(sv, 0, sizeof(double) * p, s));
+    HIPCHK(hipMemsetAsync(w, 0, wbytes, s));
+    HIPCHK(hipMemsetAsync(sv, 0, wbytes, s));
     HIPCHK(hipMemsetAsync(z, 0, sizeof(double) * n, s));
     if (!fixed) hipLaunchKernelGGL(k_check0, dim3(1), dim3(64), 0, s, &h->st->scal[2], itol * itol, &h->st->inner_done);
     int64_t t = 0;
@@ -158,11 +163,19 @@ int ils::rk_solve_op(ils_handle* h, const MatOp& M, const double* b, const doubl
     while (t < max_inner && !(!fixed && h->st_host->inner_done)) {
       const int64_t cnt = std::min(chunk, max_inner - t);
       launch_rk_draw(s, o->seed, (uint64_t)k + o->stream_offset, t, cnt, prefix, n, jj, jj + chunk);
-      mat_rk_inner(s, M, c.tgt, cn, jj, jj + chunk, cnt, w, sv, z, &h->st->inner_done, &h->st->done);
+      if (mixed)
+        launch_rk_inner_f32(s, a1f, p, p, c.tgt, cn, jj, jj + chunk, cnt, (float*)w, (float*)sv, z,
+                            &h->st->inner_done, &h->st->done);
+      else
+        mat_rk_inner(s, M, c.tgt, cn, jj, jj + chunk, cnt, w, sv, z, &h->st->inner_done, &h->st->done);
       t += cnt;
       if (!fixed && t % check == 0) {
-        mat_rk_check(s, M, w, sv, v, c.tgt, res2, itol * itol, &h->st->scal[2], &h->st->inner_done,
-                     &h->st->arrive2, &h->st->done);
+        if (mixed)
+          launch_rk_check_f32(s, M.A, M.lda, p, n, (const float*)w, (const float*)sv, v, c.tgt, res2,
+                              itol * itol, &h->st->scal[2], &h->st->inner_done, &h->st->arrive2, &h->st->done);
+        else
+          mat_rk_check(s, M, w, sv, v, c.tgt, res2, itol * itol, &h->st->scal[2], &h->st->inner_done,
+                       &h->st->arrive2, &h->st->done);
         if ((st = read_state(h))) return fail_info(info, st);
       }
     }

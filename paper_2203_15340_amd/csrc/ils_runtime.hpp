@@ -44,6 +44,7 @@ enum BufSlot {
   kBufMMetric,  // multi-RHS: per-column stop metric
   kBufMDen,     // multi-RHS: per-column metric denominators
   kBufMBt,      // multi-RHS: B^T
+  kBufA1f32,    // FP32 copy of A1 (mixed-precision RK-RGS inner sweeps)
   kBufCount
 };
 

@@ -1,6 +1,11 @@
 // k_gram.hip -- the Gram products A1^T A1 and A2^T A2 (Alg. 1 steps 2-3) on
 // the gfx950 matrix cores, FP64 and FP32 (mixed precision), split-K with a
 // deterministic reduction.
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <vector>
+
 #include "ils_common.hpp"
 
 namespace ils {
@@ -168,12 +173,68 @@ __global__ __launch_bounds__(256) void k_gram_finalize(const T* __restrict__ par
   G[j + (int64_t)i * ldg] = s;
 }
 
-// Tile edge: 128 when the matrix is large enough to give the 128-tiles
-// split-K work for every CU, else 64.
-static int gram_tile(int64_t n) { return n >= 512 ? 128 : 64; }
+// Launch configuration: tile edge and the number of workgroups to aim for
+// (the K-split follows from it).  Defaults: 128-tiles when the matrix is
+// large enough to give them split-K work for every CU (512 workgroups), else
+// 64-tiles (1024 workgroups).  The autotuner (ils_tune_gram) overrides the
+// default per (precision, log2 n bucket, log2 K bucket).
+static std::mutex g_cfg_mu;
+static std::map<uint32_t, GramCfg> g_cfg;
 
-static void gram_plan(int64_t n, int64_t K, int& tm, int& ntiles, int& nsplit, int64_t& klen) {
-  tm = gram_tile(n);
+static int log2_bucket(int64_t x) {
+  int b = 0;
+  while (((int64_t)1 << b) < x) ++b;
+  return b;
+}
+
+static uint32_t cfg_key(int precision, int64_t n, int64_t K) {
+  return ((uint32_t)precision << 16) | ((uint32_t)log2_bucket(n) << 8) | (uint32_t)log2_bucket(K);
+}
+
+GramCfg gram_default_cfg(int64_t n) {
+  GramCfg c;
+  c.tile = n >= 512 ? 128 : 64;
+  c.workgroups = c.tile == 128 ? 512 : 1024;
+  return c;
+}
+
+GramCfg gram_cfg(int precision, int64_t n, int64_t K) {
+  std::lock_guard<std::mutex> lk(g_cfg_mu);
+  auto it = g_cfg.find(cfg_key(precision, n, K));
+  return it == g_cfg.end() ? gram_default_cfg(n) : it->second;
+}
+
+void gram_set_cfg(int precision, int64_t n, int64_t K, GramCfg c) {
+  std::lock_guard<std::mutex> lk(g_cfg_mu);
+  g_cfg[cfg_key(precision, n, K)] = c;
+}
+
+void gram_clear_cfg() {
+  std::lock_guard<std::mutex> lk(g_cfg_mu);
+  g_cfg.clear();
+}
+
+std::vector<GramCfgEntry> gram_cfg_entries() {
+  std::lock_guard<std::mutex> lk(g_cfg_mu);
+  std::vector<GramCfgEntry> out;
+  for (const auto& kv : g_cfg) {
+    GramCfgEntry e;
+    e.precision = (int)(kv.first >> 16);
+    e.n_bucket = (int)((kv.first >> 8) & 0xff);
+    e.k_bucket = (int)(kv.first & 0xff);
+    e.cfg = kv.second;
+    out.push_back(e);
+  }
+  return out;
+}
+
+void gram_set_cfg_bucket(int precision, int n_bucket, int k_bucket, GramCfg c) {
+  std::lock_guard<std::mutex> lk(g_cfg_mu);
+  g_cfg[((uint32_t)precision << 16) | ((uint32_t)n_bucket << 8) | (uint32_t)k_bucket] = c;
+}
+
+static void gram_plan_cfg(int64_t n, int64_t K, GramCfg cfg, int& tm, int& ntiles, int& nsplit, int64_t& klen) {
+  tm = cfg.tile;
   const int nt = (int)((n + tm - 1) / tm);
   ntiles = nt * (nt + 1) / 2;
   if (K <= 0) {
@@ -181,7 +242,7 @@ static void gram_plan(int64_t n, int64_t K, int& tm, int& ntiles, int& nsplit, i
     klen = kGK;
     return;
   }
-  const int64_t target = tm == 128 ? 512 : 1024;  // workgroups to fill 256 CUs
+  const int64_t target = cfg.workgroups;
   int64_t want = (target + ntiles - 1) / ntiles;
   int64_t maxs = (K + 255) / 256;               // at least 256 rows per slice
   if (want > maxs) want = maxs;
@@ -192,12 +253,19 @@ static void gram_plan(int64_t n, int64_t K, int& tm, int& ntiles, int& nsplit, i
   nsplit = (int)want;  // trailing slices may be empty: they add zeros
 }
 
-size_t gram_partials_size(int64_t n, int64_t K) {
+static size_t plan_size(int64_t n, int64_t K, GramCfg c) {
   int tm, ntiles, nsplit;
   int64_t klen;
-  gram_plan(n, K, tm, ntiles, nsplit, klen);
+  gram_plan_cfg(n, K, c, tm, ntiles, nsplit, klen);
   return (size_t)ntiles * nsplit * tm * tm;
 }
+
+// Partial-tile scratch in doubles, enough for either precision's configuration.
+size_t gram_partials_size(int64_t n, int64_t K) {
+  return std::max(plan_size(n, K, gram_cfg(ILS_PREC_FP64, n, K)), plan_size(n, K, gram_cfg(ILS_PREC_MIXED, n, K)));
+}
+
+size_t gram_partials_size_cfg(int64_t n, int64_t K, GramCfg c) { return plan_size(n, K, c); }
 
 template <typename T, int TM>
 static void gram_launch(hipStream_t s, int64_t K, int64_t n, const double* A, int64_t lda, T* partials,
@@ -211,24 +279,32 @@ static void gram_launch(hipStream_t s, int64_t K, int64_t n, const double* A, in
 
 template <typename T>
 static void gram_run(hipStream_t s, int64_t K, int64_t n, const double* A, int64_t lda, T* partials,
-                     double* G, int64_t ldg, hipEvent_t mid) {
+                     double* G, int64_t ldg, hipEvent_t mid, GramCfg cfg) {
   int tm, ntiles, nsplit;
   int64_t klen;
-  gram_plan(n, K, tm, ntiles, nsplit, klen);
+  gram_plan_cfg(n, K, cfg, tm, ntiles, nsplit, klen);
   if (tm == 128)
     gram_launch<T, 128>(s, K, n, A, lda, partials, G, ldg, mid, ntiles, nsplit, klen);
   else
     gram_launch<T, 64>(s, K, n, A, lda, partials, G, ldg, mid, ntiles, nsplit, klen);
 }
 
+void launch_gram_cfg(hipStream_t s, int precision, int64_t K, int64_t n, const double* A, int64_t lda,
+                     void* partials, double* G, int64_t ldg, GramCfg cfg) {
+  if (precision == ILS_PREC_MIXED)
+    gram_run<float>(s, K, n, A, lda, (float*)partials, G, ldg, nullptr, cfg);
+  else
+    gram_run<double>(s, K, n, A, lda, (double*)partials, G, ldg, nullptr, cfg);
+}
+
 void launch_gram_f64(hipStream_t s, int64_t K, int64_t n, const double* A, int64_t lda,
                      double* partials, double* G, int64_t ldg, hipEvent_t mid) {
-  gram_run<double>(s, K, n, A, lda, partials, G, ldg, mid);
+  gram_run<double>(s, K, n, A, lda, partials, G, ldg, mid, gram_cfg(ILS_PREC_FP64, n, K));
 }
 
 void launch_gram_f32(hipStream_t s, int64_t K, int64_t n, const double* A, int64_t lda,
                      float* partials, double* G, int64_t ldg, hipEvent_t mid) {
-  gram_run<float>(s, K, n, A, lda, partials, G, ldg, mid);
+  gram_run<float>(s, K, n, A, lda, partials, G, ldg, mid, gram_cfg(ILS_PREC_MIXED, n, K));
 }
 
 }  // namespace ils

@@ -162,36 +162,39 @@ void launch_scd_draw(hipStream_t s, uint64_t seed, uint64_t outer, int64_t t0, i
 // synchronisation is the two block reductions per step.
 constexpr int kRkThreads = 1024;
 
-__global__ __launch_bounds__(kRkThreads) void k_rk_inner(const double* __restrict__ A1, int64_t lda,
+// T = double (FP64 path) or float (mixed precision: FP32 copy of A1, FP32 w
+// and s, FP32 sums; z and the right-hand side stay FP64).
+template <typename T>
+__global__ __launch_bounds__(kRkThreads) void k_rk_inner(const T* __restrict__ A1, int64_t lda,
                                                          int64_t p, const double* __restrict__ tgt,
                                                          const double* __restrict__ cn,
                                                          const int* __restrict__ j1s,
                                                          const int* __restrict__ j2s, int64_t count,
-                                                         double* __restrict__ w, double* __restrict__ s,
+                                                         T* __restrict__ w, T* __restrict__ s,
                                                          double* __restrict__ z,
                                                          const int* inner_done, const int* outer_done) {
   if (*(volatile const int*)inner_done || *(volatile const int*)outer_done) return;
-  __shared__ double red[2][kRkThreads / kWave];
+  __shared__ T red[2][kRkThreads / kWave];
   const int tid = threadIdx.x;
   for (int64_t t = 0; t < count; ++t) {
     const int j1 = j1s[t], j2 = j2s[t];
-    const double* a1 = A1 + (int64_t)j1 * lda;
-    const double* a2 = A1 + (int64_t)j2 * lda;
-    double d = 0.0;
+    const T* a1 = A1 + (int64_t)j1 * lda;
+    const T* a2 = A1 + (int64_t)j2 * lda;
+    T d = 0;
     for (int64_t i = tid; i < p; i += kRkThreads) d += a1[i] * w[i];
     d = block_sum<kRkThreads>(d, red[0]);
-    const double gam = (tgt[j1] - d) / cn[j1];
-    double d2 = 0.0;
+    const T gam = (T)((tgt[j1] - (double)d) / cn[j1]);
+    T d2 = 0;
     for (int64_t i = tid; i < p; i += kRkThreads) {
-      const double av = a1[i];
+      const T av = a1[i];
       w[i] += gam * av;
-      const double sv = s[i] + gam * av;
+      const T sv = s[i] + gam * av;
       s[i] = sv;
       d2 += a2[i] * sv;
     }
     d2 = block_sum<kRkThreads>(d2, red[1]);
-    const double del = d2 / cn[j2];
-    if (tid == 0) z[j2] += del;
+    const T del = (T)((double)d2 / cn[j2]);
+    if (tid == 0) z[j2] += (double)del;
     for (int64_t i = tid; i < p; i += kRkThreads) s[i] -= del * a2[i];
   }
 }
@@ -200,18 +203,42 @@ void launch_rk_inner(hipStream_t st, const double* A1, int64_t lda, int64_t p, c
                      const double* cn, const int* j1, const int* j2, int64_t count, double* w, double* s,
                      double* z, const int* inner_done, const int* outer_done) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_rk_inner, dim3(1), dim3(kRkThreads), 0, st, A1, lda, p, tgt, cn, j1, j2, count, w,
-                     s, z, inner_done, outer_done);
+  hipLaunchKernelGGL(k_rk_inner<double>, dim3(1), dim3(kRkThreads), 0, st, A1, lda, p, tgt, cn, j1, j2, count,
+                     w, s, z, inner_done, outer_done);
+}
+
+void launch_rk_inner_f32(hipStream_t st, const float* A1, int64_t lda, int64_t p, const double* tgt,
+                         const double* cn, const int* j1, const int* j2, int64_t count, float* w, float* s,
+                         double* z, const int* inner_done, const int* outer_done) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_rk_inner<float>, dim3(1), dim3(kRkThreads), 0, st, A1, lda, p, tgt, cn, j1, j2, count,
+                     w, s, z, inner_done, outer_done);
+}
+
+// FP32 copy of A1 (p x n, leading dimension p) for the mixed inner sweeps.
+__global__ void k_to_f32(int64_t p, int64_t n, const double* __restrict__ A, int64_t lda, float* __restrict__ Af) {
+  const int64_t total = p * n;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    const int64_t j = e / p, i = e - j * p;
+    Af[e] = (float)A[i + j * lda];
+  }
+}
+
+void launch_to_f32(hipStream_t s, int64_t p, int64_t n, const double* A, int64_t lda, float* Af) {
+  int64_t b = (p * n + 255) / 256;
+  if (b > 8192) b = 8192;
+  hipLaunchKernelGGL(k_to_f32, dim3((unsigned)b), dim3(256), 0, s, p, n, A, lda, Af);
 }
 
 // Inner stop test of SP-RK-RGS: ||bhat - A1^T (w - s)|| <= tol * ||bhat||
 // (A1 z = w - s).  Pass 1 forms v = w - s, pass 2 is one workgroup per
 // column; the last workgroup adds the squared entries in column order.
-__global__ void k_sub_vec(int64_t p, const double* __restrict__ w, const double* __restrict__ s,
+template <typename T>
+__global__ void k_sub_vec(int64_t p, const T* __restrict__ w, const T* __restrict__ s,
                           double* __restrict__ v, const int* skip) {
   if (*(volatile const int*)skip) return;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < p; i += (int64_t)gridDim.x * blockDim.x)
-    v[i] = w[i] - s[i];
+    v[i] = (double)w[i] - (double)s[i];
 }
 
 __global__ __launch_bounds__(256) void k_rk_check(const double* __restrict__ A1, int64_t lda, int64_t p,
@@ -251,7 +278,15 @@ __global__ __launch_bounds__(256) void k_rk_check(const double* __restrict__ A1,
 void launch_rk_check(hipStream_t st, const double* A1, int64_t lda, int64_t p, int64_t n, const double* w,
                      const double* s, double* v, const double* tgt, double* res2, double itol2,
                      const double* tn2, int* inner_done, unsigned* arrive, const int* skip) {
-  hipLaunchKernelGGL(k_sub_vec, dim3(64), dim3(256), 0, st, p, w, s, v, skip);
+  hipLaunchKernelGGL(k_sub_vec<double>, dim3(64), dim3(256), 0, st, p, w, s, v, skip);
+  hipLaunchKernelGGL(k_rk_check, dim3((unsigned)n), dim3(256), 0, st, A1, lda, p, n, (const double*)v, tgt,
+                     res2, itol2, tn2, inner_done, arrive, skip);
+}
+
+void launch_rk_check_f32(hipStream_t st, const double* A1, int64_t lda, int64_t p, int64_t n, const float* w,
+                         const float* s, double* v, const double* tgt, double* res2, double itol2,
+                         const double* tn2, int* inner_done, unsigned* arrive, const int* skip) {
+  hipLaunchKernelGGL(k_sub_vec<float>, dim3(64), dim3(256), 0, st, p, w, s, v, skip);
   hipLaunchKernelGGL(k_rk_check, dim3((unsigned)n), dim3(256), 0, st, A1, lda, p, n, (const double*)v, tgt,
                      res2, itol2, tn2, inner_done, arrive, skip);
 }

@@ -18,6 +18,13 @@ void launch_rk_inner(hipStream_t st, const double* A1, int64_t lda, int64_t p, c
 void launch_rk_check(hipStream_t st, const double* A1, int64_t lda, int64_t p, int64_t n, const double* w,
                      const double* s, double* v, const double* tgt, double* res2, double itol2,
                      const double* tn2, int* inner_done, unsigned* arrive, const int* skip);
+void launch_rk_inner_f32(hipStream_t st, const float* A1, int64_t lda, int64_t p, const double* tgt,
+                         const double* cn, const int* j1, const int* j2, int64_t count, float* w, float* s,
+                         double* z, const int* inner_done, const int* outer_done);
+void launch_rk_check_f32(hipStream_t st, const double* A1, int64_t lda, int64_t p, int64_t n, const float* w,
+                         const float* s, double* v, const double* tgt, double* res2, double itol2,
+                         const double* tn2, int* inner_done, unsigned* arrive, const int* skip);
+void launch_to_f32(hipStream_t s, int64_t p, int64_t n, const double* A, int64_t lda, float* Af);
 void launch_scd_inner(hipStream_t st, const double* G1, int64_t ldg, int64_t n, double* r, double* beta,
                       const uint32_t* mask, int64_t mask_words, const int* jpre, int norm_mode,
                       int64_t count, int check, double itol2, const double* tn2, int* inner_done,

@@ -291,6 +291,22 @@ def test_scd_mixed_reaches_x_ils():
     assert rel(host(x), P.x_star) < 1e-6
 
 
+@pytest.mark.parametrize("shape", [(500, 100, 50), (700, 90, 150)])
+def test_rk_mixed_reaches_x_ils(shape):
+    """FP32 inner sweeps (FP32 copy of A1, FP32 w and s) inside FP64
+    refinement: the correction form's fixed point is the FP64 x_ILS."""
+    P = W.dense_ils(*shape, ratio=0.5, seed=sum(shape))
+    A, b, xs = devA(P.A), dev(P.b), dev(P.x_star)
+    x, info = ils.rk_solve(A, b, P.p, precision=ils.PREC_MIXED, form=ils.FORM_CORRECTION,
+                           stop_rule=ils.STOP_XREF, x_ref=xs, tol=1e-8, seed=1)
+    assert info.status == ils.OK
+    st, x_ils = O.normal_solve(P.A, P.b, P.p)
+    assert st == O.OK
+    assert rel(host(x), x_ils) < 1e-6
+    _, info = ils.rk_solve(A, b, P.p, precision=ils.PREC_MIXED, form=ils.FORM_PAPER)
+    assert info.status == ils.ERR_ARG
+
+
 def test_randomized_error_codes():
     P = W.dense_ils(60, 10, 20, ratio=0.5, seed=3)
     Az = P.A.copy()
