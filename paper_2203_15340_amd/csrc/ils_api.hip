@@ -226,7 +226,7 @@ int ils::sp_solve_op(ils_handle* h, const MatOp& M, const double* b, const doubl
       (st = h->need(kBufPart, part_bytes, &part)) ||
       (st = h->need(kBufX0, sizeof(double) * n, (void**)&xb0)) ||
       (st = h->need(kBufX1, sizeof(double) * n, (void**)&xb1)) ||
-      (st = h->need(kBufT, sizeof(double) * m, (void**)&tv)) ||
+      (st = h->need(kBufT, sizeof(double) * residual_scratch(m, n), (void**)&tv)) ||
       (st = h->need(kBufR, sizeof(double) * n, (void**)&rv)) ||
       (st = h->need(kBufSPart, sizeof(double) * nblk, (void**)&spart)) ||
       (st = h->need(kBufSBad, sizeof(int) * nblk, (void**)&sbad)) ||
@@ -347,7 +347,7 @@ extern "C" int ils_residual(ils_handle* h, int64_t p, int64_t q, int64_t n, cons
   if (!h || !A || !b || !x || !r || n < 1 || p < 0 || q < 0 || lda < p + q) return ILS_ERR_ARG;
   HIPCHK(hipSetDevice(h->device));
   double* tv;
-  int st = h->need(kBufT, sizeof(double) * (p + q > 0 ? p + q : 1), (void**)&tv);
+  int st = h->need(kBufT, sizeof(double) * residual_scratch(p + q, n), (void**)&tv);
   if (st) return st;
   launch_residual(h->stream, p, q, n, A, lda, b, x, tv, r, nullptr);
   HIPCHK(hipGetLastError());

@@ -105,7 +105,9 @@ constexpr uint64_t kTagScd = 0x534344ull;
 // Dense building blocks (k_dense.hip).
 void launch_colpass(hipStream_t s, int64_t p, int64_t q, int64_t n, const double* A, int64_t lda,
                     const double* b, double* g, double* cn, int* bits);
-// r = A^T J (b - A x); t is m doubles of scratch.  Skipped when *done != 0.
+// r = A^T J (b - A x); t is residual_scratch(m, n) doubles of scratch (t = b - A x
+// in the first m).  Skipped when *done != 0.
+size_t residual_scratch(int64_t m, int64_t n);
 void launch_residual(hipStream_t s, int64_t p, int64_t q, int64_t n, const double* A, int64_t lda,
                      const double* b, const double* x, double* t, double* r, const int* done);
 // Gram of rows [0, K) of A (A already offset to the first row).  `partials`

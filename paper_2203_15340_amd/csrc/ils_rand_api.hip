@@ -61,7 +61,7 @@ static int common_setup(ils_handle* h, const MatOp& M, const double* b, const do
       (st = h->need(kBufX1, sizeof(double) * n, (void**)&c.xb1)) ||
       (st = h->need(kBufSPart, sizeof(double) * n, (void**)&c.tgt)) ||
       (st = h->need(kBufR, sizeof(double) * n, (void**)&c.rk)) ||
-      (st = h->need(kBufT, sizeof(double) * (m > 0 ? m : 1), (void**)&c.tv)) ||
+      (st = h->need(kBufT, sizeof(double) * residual_scratch(m, n), (void**)&c.tv)) ||
       (st = h->need(kBufPart, mat_gram_partials(M) * sizeof(double), (void**)&c.part)) ||
       (paper && (st = h->need(kBufG2, sizeof(double) * n * n, (void**)&c.G2))))
     return st;

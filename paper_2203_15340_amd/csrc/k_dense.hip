@@ -69,28 +69,68 @@ void launch_colpass(hipStream_t s, int64_t p, int64_t q, int64_t n, const double
 
 // ------------------------------------------------------------------ residual
 // r = A^T J (b - A x) in two passes over A.
-// Pass 1: t = b - A x, 64 rows per workgroup, the four waves split the columns
-// and their partial sums are added in a fixed order.
+// Pass 1: t = b - A x.  A is column-major, so a wavefront owns 64 rows and
+// walks a range of columns (coalesced 512-byte column segments, eight loads
+// in flight).  The columns are cut into 4 * ngroups ranges: the four waves of
+// a workgroup take four of them and add their partial sums in LDS, and the
+// ngroups workgroups per row block write partial vectors that a second kernel
+// adds in group order (deterministic).  The column split gives enough
+// wavefronts to stream A at HBM rate even when m is small.
 constexpr int kResRows = 64;
 
+static int64_t resid_groups(int64_t m, int64_t n) {
+  const int64_t rb = (m + kResRows - 1) / kResRows;
+  int64_t g = (2048 + rb - 1) / rb;      // aim at ~2048 workgroups
+  const int64_t gmax = (n + 31) / 32;    // at least 8 columns per wave
+  if (g > gmax) g = gmax;
+  return g < 1 ? 1 : g;
+}
+
+size_t residual_scratch(int64_t m, int64_t n) { return (size_t)(resid_groups(m, n) + 1) * (size_t)(m > 0 ? m : 1); }
+
 __global__ __launch_bounds__(256) void k_resid_rows(const double* __restrict__ A, int64_t lda,
-                                                     int64_t m, int64_t n,
-                                                     const double* __restrict__ b,
+                                                     int64_t m, int64_t n, int64_t cw,
                                                      const double* __restrict__ x,
-                                                     double* __restrict__ t, const int* done) {
+                                                     double* __restrict__ part, const int* done) {
   if (done && *done) return;
-  __shared__ double part[4][kResRows];
+  __shared__ double red[4][kResRows];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t i = (int64_t)blockIdx.x * kResRows + lane;
-  const int64_t jq = (n + 3) / 4, j0 = w * jq, j1 = j0 + jq < n ? j0 + jq : n;
+  const int64_t j0 = ((int64_t)blockIdx.y * 4 + w) * cw;
+  const int64_t j1 = j0 + cw < n ? j0 + cw : n;
   double s = 0.0;
   if (i < m) {
     const double* a = A + i;
-    for (int64_t j = j0; j < j1; ++j) s += a[j * lda] * x[j];
+    int64_t j = j0;
+    double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (; j + 8 <= j1; j += 8) {
+      double av[8], xv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        av[u] = a[(j + u) * lda];
+        xv[u] = x[j + u];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[u] = fma(av[u], xv[u], acc[u]);
+    }
+    for (; j < j1; ++j) acc[0] = fma(a[j * lda], x[j], acc[0]);
+    s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
   }
-  part[w][lane] = s;
+  red[w][lane] = s;
   __syncthreads();
-  if (w == 0 && i < m) t[i] = b[i] - (((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane]);
+  if (w == 0 && i < m) part[(int64_t)blockIdx.y * m + i] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+}
+
+// t = b - sum of the group partials, in group order.
+__global__ __launch_bounds__(256) void k_resid_fin(int64_t m, int64_t groups, const double* __restrict__ b,
+                                                    const double* __restrict__ part, double* __restrict__ t,
+                                                    const int* done) {
+  if (done && *done) return;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= m) return;
+  double s = 0.0;
+  for (int64_t g = 0; g < groups; ++g) s += part[g * m + i];
+  t[i] = b[i] - s;
 }
 
 // Sum of x[i] y[i] over i in [i0, i1), thread share of a workgroup of NT
@@ -134,8 +174,13 @@ __global__ __launch_bounds__(kColThreads) void k_resid_cols(const double* __rest
 void launch_residual(hipStream_t s, int64_t p, int64_t q, int64_t n, const double* A, int64_t lda,
                      const double* b, const double* x, double* t, double* r, const int* done) {
   const int64_t m = p + q;
-  hipLaunchKernelGGL(k_resid_rows, dim3((unsigned)((m + kResRows - 1) / kResRows)), dim3(256), 0, s,
-                     A, lda, m, n, b, x, t, done);
+  const int64_t groups = resid_groups(m, n);
+  const int64_t cw = (n + 4 * groups - 1) / (4 * groups);
+  double* part = t + m;
+  hipLaunchKernelGGL(k_resid_rows, dim3((unsigned)((m + kResRows - 1) / kResRows), (unsigned)groups), dim3(256),
+                     0, s, A, lda, m, n, cw, x, part, done);
+  hipLaunchKernelGGL(k_resid_fin, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, m, groups, b,
+                     (const double*)part, t, done);
   hipLaunchKernelGGL(k_resid_cols, dim3((unsigned)n), dim3(kColThreads), 0, s, A, lda, p, q, t, r,
                      done);
 }

@@ -178,24 +178,44 @@ void launch_f2bf(hipStream_t s, int64_t n, const float* x, uint16_t* y) {
 }
 
 // Output layer: dY = 2 (y - t) / (N d3) (FP32 and bf16), bias gradient
-// db3[i] = sum_s dY[i, s], and per-row loss sums.  One thread per row i.
-__global__ __launch_bounds__(256) void k_mlp_outgrad(int64_t d3, int64_t N, const float* __restrict__ Y,
-                                                     const float* __restrict__ T, uint16_t* __restrict__ dYb,
-                                                     float* __restrict__ db, double* __restrict__ loss_rows) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= d3) return;
+// db3[i] = sum_s dY[i, s], and per-row loss sums.  Workgroup = 64 rows x 16
+// waves; wave w takes samples w, w + 16, ... (coalesced 64-row segments) and
+// the 16 partial sums are added in wave order.
+constexpr int kRowWaves = 16;
+
+__global__ __launch_bounds__(64 * kRowWaves) void k_mlp_outgrad(int64_t d3, int64_t N, const float* __restrict__ Y,
+                                                               const float* __restrict__ T,
+                                                               uint16_t* __restrict__ dYb, float* __restrict__ db,
+                                                               double* __restrict__ loss_rows) {
+  __shared__ float rb[kRowWaves][64];
+  __shared__ double rl[kRowWaves][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 64 + lane;
   const float sc = 2.0f / (float)((double)N * (double)d3);
   float sb = 0.0f;
   double sl = 0.0;
-  for (int64_t s = 0; s < N; ++s) {
-    const float e = Y[i + s * d3] - T[i + s * d3];
-    const float dy = sc * e;
-    dYb[i + s * d3] = f2bf(dy);
-    sb += dy;
-    sl += (double)e * (double)e;
+  if (i < d3) {
+    for (int64_t s = w; s < N; s += kRowWaves) {
+      const float e = Y[i + s * d3] - T[i + s * d3];
+      const float dy = sc * e;
+      dYb[i + s * d3] = f2bf(dy);
+      sb += dy;
+      sl += (double)e * (double)e;
+    }
   }
-  db[i] = sb;
-  loss_rows[i] = sl;
+  rb[w][lane] = sb;
+  rl[w][lane] = sl;
+  __syncthreads();
+  if (w == 0 && i < d3) {
+    float tb = 0.0f;
+    double tl = 0.0;
+    for (int k = 0; k < kRowWaves; ++k) {
+      tb += rb[k][lane];
+      tl += rl[k][lane];
+    }
+    db[i] = tb;
+    loss_rows[i] = tl;
+  }
 }
 
 // loss = sum(loss_rows) / (N d3), one workgroup
@@ -210,27 +230,36 @@ __global__ __launch_bounds__(256) void k_mlp_loss(int64_t d3, int64_t N, const d
 
 void launch_mlp_outgrad(hipStream_t s, int64_t d3, int64_t N, const float* Y, const float* T, uint16_t* dYb,
                         float* db, double* loss_rows, double* loss) {
-  hipLaunchKernelGGL(k_mlp_outgrad, dim3((unsigned)((d3 + 255) / 256)), dim3(256), 0, s, d3, N, Y, T, dYb, db,
-                     loss_rows);
+  hipLaunchKernelGGL(k_mlp_outgrad, dim3((unsigned)((d3 + 63) / 64)), dim3(64 * kRowWaves), 0, s, d3, N, Y, T,
+                     dYb, db, loss_rows);
   hipLaunchKernelGGL(k_mlp_loss, dim3(1), dim3(256), 0, s, d3, N, (const double*)loss_rows, loss);
 }
 
-// Hidden layer: db[i] = sum_s dZ[i, s] and dZ -> bf16.  One thread per row.
-__global__ __launch_bounds__(256) void k_mlp_rowsum(int64_t d, int64_t N, const float* __restrict__ dZ,
-                                                    uint16_t* __restrict__ dZb, float* __restrict__ db) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= d) return;
+// Hidden layer: db[i] = sum_s dZ[i, s] and dZ -> bf16, same layout as above.
+__global__ __launch_bounds__(64 * kRowWaves) void k_mlp_rowsum(int64_t d, int64_t N, const float* __restrict__ dZ,
+                                                              uint16_t* __restrict__ dZb, float* __restrict__ db) {
+  __shared__ float rb[kRowWaves][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 64 + lane;
   float sb = 0.0f;
-  for (int64_t s = 0; s < N; ++s) {
-    const float v = dZ[i + s * d];
-    dZb[i + s * d] = f2bf(v);
-    sb += v;
+  if (i < d) {
+    for (int64_t s = w; s < N; s += kRowWaves) {
+      const float v = dZ[i + s * d];
+      dZb[i + s * d] = f2bf(v);
+      sb += v;
+    }
   }
-  db[i] = sb;
+  rb[w][lane] = sb;
+  __syncthreads();
+  if (w == 0 && i < d) {
+    float tb = 0.0f;
+    for (int k = 0; k < kRowWaves; ++k) tb += rb[k][lane];
+    db[i] = tb;
+  }
 }
 
 void launch_mlp_rowsum(hipStream_t s, int64_t d, int64_t N, const float* dZ, uint16_t* dZb, float* db) {
-  hipLaunchKernelGGL(k_mlp_rowsum, dim3((unsigned)((d + 255) / 256)), dim3(256), 0, s, d, N, dZ, dZb, db);
+  hipLaunchKernelGGL(k_mlp_rowsum, dim3((unsigned)((d + 63) / 64)), dim3(64 * kRowWaves), 0, s, d, N, dZ, dZb, db);
 }
 
 // Adam (Kingma & Ba 2015) on the FP32 master copy, then the bf16 copy used by
