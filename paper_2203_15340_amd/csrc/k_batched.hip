@@ -41,7 +41,7 @@ struct Smem {
     } g32;
     double vec[2 * kNB * (kNB + 1)];  // iteration phase: t (m), x_k (n)
   } u;
-  double rowbuf[2][kNB];
+  double rowbuf[2][kRowBuf];
   double colbuf[2][kNB];
   double red[2][NT / kWave];
   int id;
