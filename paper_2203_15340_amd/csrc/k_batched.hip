@@ -32,12 +32,12 @@ struct Smem {
       double T1[kNB][kNB + 1];
     } gj;
     struct {
-      double As[2][kNB][17];
-      double Bs[2][kNB][17];
+      double As[kNB][kNB + 1];  // As[column][k] of the current 64-row stage
+      double Bs[kNB][kNB + 1];
     } g64;
     struct {
-      float As[2][kNB][17];
-      float Bs[2][kNB][17];
+      float As[kNB][kNB + 1];
+      float Bs[kNB][kNB + 1];
     } g32;
     double vec[2 * kNB * (kNB + 1)];  // iteration phase: t (m), x_k (n)
   } u;
@@ -67,17 +67,17 @@ struct Mma<float> {
 };
 
 template <typename T>
-__device__ inline T (*stage_a(Smem& s, int buf))[17];
+__device__ inline T (*stage_a(Smem& s))[kNB + 1];
 template <>
-__device__ inline double (*stage_a<double>(Smem& s, int buf))[17] { return s.u.g64.As[buf]; }
+__device__ inline double (*stage_a<double>(Smem& s))[kNB + 1] { return s.u.g64.As; }
 template <>
-__device__ inline float (*stage_a<float>(Smem& s, int buf))[17] { return s.u.g32.As[buf]; }
+__device__ inline float (*stage_a<float>(Smem& s))[kNB + 1] { return s.u.g32.As; }
 template <typename T>
-__device__ inline T (*stage_b(Smem& s, int buf))[17];
+__device__ inline T (*stage_b(Smem& s))[kNB + 1];
 template <>
-__device__ inline double (*stage_b<double>(Smem& s, int buf))[17] { return s.u.g64.Bs[buf]; }
+__device__ inline double (*stage_b<double>(Smem& s))[kNB + 1] { return s.u.g64.Bs; }
 template <>
-__device__ inline float (*stage_b<float>(Smem& s, int buf))[17] { return s.u.g32.Bs[buf]; }
+__device__ inline float (*stage_b<float>(Smem& s))[kNB + 1] { return s.u.g32.Bs; }
 
 __device__ inline double block_sum2(double v, Smem& s, int which) {
   v = wave_sum(v);
@@ -91,16 +91,22 @@ __device__ inline double block_sum2(double v, Smem& s, int which) {
 }
 
 // G = A[0:K, :]^T A[0:K, :] (n x n, full) into W (ldw), one 64 x 64 lower tile
-// at a time; each tile streams K in stages of 16 rows through LDS with the
-// next stage's loads in registers.
+// at a time.  Each tile streams K in stages of 64 rows: a thread holds 16
+// values of each operand panel in flight (one 512-byte column segment per
+// wave per load), then the stage goes through LDS and the next stage's loads
+// are issued before the matrix-core work on the current one.  One workgroup
+// streams a whole problem alone, so loads in flight, not bandwidth, set the
+// rate.
 template <typename T>
 __device__ __attribute__((noinline)) void wg_gram(const double* __restrict__ A, int64_t lda, int K, int n, double* W, int64_t ldw,
                         Smem& s) {
   typedef typename Mma<T>::acc_t acc_t;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wr = (w >> 1) * 32, wc = (w & 1) * 32, lr = lane & 15;
-  const int lk = t & 15, lc = t >> 4;
+  const int lk = t & 63, lc = t >> 6;
   const int nt = (n + kNB - 1) / kNB;
+  T(*As)[kNB + 1] = stage_a<T>(s);
+  T(*Bs)[kNB + 1] = stage_b<T>(s);
   for (int ti = 0; ti < nt; ++ti) {
     for (int tj = 0; tj <= ti; ++tj) {
       const bool diag = ti == tj;
@@ -112,51 +118,38 @@ __device__ __attribute__((noinline)) void wg_gram(const double* __restrict__ A, 
       for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int c = 0; c < 2; ++c) acc[a][c] = acc_t{};
-      T ra[4], rb[4];
+      T ra[16], rb[16];
       auto fetch = [&](int k0) {
         const int k = k0 + lk;
         const bool kin = k < K;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int c = lc + 16 * r;
-          ra[r] = (kin && c < ci) ? (T)Ai[k + (int64_t)c * lda] : (T)0;
-          if (!diag) rb[r] = (kin && c < cj) ? (T)Aj[k + (int64_t)c * lda] : (T)0;
+        for (int q = 0; q < 16; ++q) {
+          const int c = lc + 4 * q;
+          ra[q] = (kin && c < ci) ? (T)Ai[k + (int64_t)c * lda] : (T)0;
+          if (!diag) rb[q] = (kin && c < cj) ? (T)Aj[k + (int64_t)c * lda] : (T)0;
         }
       };
-      auto stash = [&](int buf) {
-        T(*As)[17] = stage_a<T>(s, buf);
-        T(*Bs)[17] = stage_b<T>(s, buf);
+      if (K > 0) fetch(0);
+      for (int k0 = 0; k0 < K; k0 += kNB) {
+        __syncthreads();  // LDS free (previous stage, tile or phase)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          As[lc + 16 * r][lk] = ra[r];
-          if (!diag) Bs[lc + 16 * r][lk] = rb[r];
+        for (int q = 0; q < 16; ++q) {
+          As[lc + 4 * q][lk] = ra[q];
+          if (!diag) Bs[lc + 4 * q][lk] = rb[q];
         }
-      };
-      __syncthreads();  // LDS free from the previous tile / phase
-      if (K > 0) {
-        fetch(0);
-        stash(0);
-      }
-      __syncthreads();
-      int buf = 0;
-      for (int k0 = 0; k0 < K; k0 += 16) {
-        const bool more = k0 + 16 < K;
-        if (more) fetch(k0 + 16);
-        T(*Ap)[17] = stage_a<T>(s, buf);
-        T(*Bp)[17] = diag ? stage_a<T>(s, buf) : stage_b<T>(s, buf);
+        __syncthreads();
+        if (k0 + kNB < K) fetch(k0 + kNB);
+        T(*Bp)[kNB + 1] = diag ? As : Bs;
 #pragma unroll
-        for (int kk = 0; kk < 16; kk += 4) {
+        for (int kk = 0; kk < kNB; kk += 4) {
           const int kr = kk + (lane >> 4);
-          const T a0 = Ap[wr + lr][kr], a1 = Ap[wr + 16 + lr][kr];
+          const T a0 = As[wr + lr][kr], a1 = As[wr + 16 + lr][kr];
           const T b0 = Bp[wc + lr][kr], b1 = Bp[wc + 16 + lr][kr];
           acc[0][0] = Mma<T>::run(a0, b0, acc[0][0]);
           acc[0][1] = Mma<T>::run(a0, b1, acc[0][1]);
           acc[1][0] = Mma<T>::run(a1, b0, acc[1][0]);
           acc[1][1] = Mma<T>::run(a1, b1, acc[1][1]);
         }
-        if (more) stash(buf ^ 1);
-        __syncthreads();
-        buf ^= 1;
       }
 #pragma unroll
       for (int a = 0; a < 2; ++a)
@@ -338,7 +331,9 @@ __device__ __attribute__((noinline)) void wg_residual(const double* __restrict__
   for (int j = w; j < n; j += NT / kWave) {
     const double* col = A + (int64_t)j * lda;
     double s1 = 0.0, s2 = 0.0;
+#pragma unroll 8
     for (int i = lane; i < p; i += kWave) s1 += col[i] * ts[i];
+#pragma unroll 8
     for (int i = p + lane; i < m; i += kWave) s2 += col[i] * ts[i];
     s1 = wave_sum(s1);
     s2 = wave_sum(s2);
@@ -361,20 +356,29 @@ __device__ void solve_one(const BatchArgs& a, const BatchProblem& P, double* slo
   double* r = xb + a.nmax;
   out.iters = 0;
   out.metric = 0.0;
-  // 1. column pass
+  // 1. column pass (b staged in LDS; A columns read eight loads deep)
   bool ok = true;
+  double* bs = s.u.vec;
+  for (int i = t; i < m; i += NT) {
+    const double bv = P.b[i];
+    bs[i] = bv;
+    ok &= isfinite(bv);
+  }
+  __syncthreads();
   for (int j = w; j < n; j += NT / kWave) {
     const double* col = P.A + (int64_t)j * lda;
     double s1 = 0.0, s2 = 0.0;
+#pragma unroll 8
     for (int i = lane; i < p; i += kWave) {
-      const double av = col[i], bv = P.b[i];
-      s1 += av * bv;
-      ok &= isfinite(av) && isfinite(bv);
+      const double av = col[i];
+      s1 += av * bs[i];
+      ok &= isfinite(av);
     }
+#pragma unroll 8
     for (int i = p + lane; i < m; i += kWave) {
-      const double av = col[i], bv = P.b[i];
-      s2 += av * bv;
-      ok &= isfinite(av) && isfinite(bv);
+      const double av = col[i];
+      s2 += av * bs[i];
+      ok &= isfinite(av);
     }
     s1 = wave_sum(s1);
     s2 = wave_sum(s2);
