@@ -318,6 +318,7 @@ def main():
     if not args.no_tune:
         tuned = ils.tune_gram(A, 0, P.p, precision=ils.PREC_FP64, reps=5)
         ils.tune_gram(A, 0, P.p, precision=ils.PREC_MIXED, reps=5)
+        ils.tune_gram(A, P.p, P.m, precision=ils.PREC_FP64, reps=5)  # A2^T A2
         log(f"autotuned A1 Gram: {tuned}")
     ils.set_profiling(True)
     log(f"warmup {args.warmup}")

@@ -330,7 +330,7 @@ typedef struct {
 } ils_tune_entry;
 
 /* Time every launch configuration of the Gram kernel (tile edge 64 / 128 x
- * 256 .. 4096 workgroups) on G = A[0:K, :]^T A[0:K, :] (reps launches each,
+ * 256 .. 8192 workgroups) on G = A[0:K, :]^T A[0:K, :] (reps launches each,
  * after one warm-up; the matrix is only read) and keep the fastest for the
  * bucket (precision, ceil(log2 n), ceil(log2 K)) in the process-wide table
  * that all Gram launches consult (every solver, every handle).  *best (host,

@@ -31,7 +31,7 @@ extern "C" int ils_tune_gram(ils_handle* h, int64_t K, int64_t n, const double* 
   HIPCHK(hipSetDevice(h->device));
   hipStream_t s = h->stream;
   const int tiles[2] = {64, 128};
-  const int targets[5] = {256, 512, 1024, 2048, 4096};
+  const int targets[6] = {256, 512, 1024, 2048, 4096, 8192};
   size_t part_max = 0;
   for (int t : tiles)
     for (int w : targets) part_max = std::max(part_max, gram_partials_size_cfg(n, K, GramCfg{t, w}));

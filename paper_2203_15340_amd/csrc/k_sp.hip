@@ -23,22 +23,24 @@ __device__ inline int load_coherent(const int* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Dot product of a contiguous row with v by one wave: each lane issues four
-// loads per round before using them; lane partials are added by a fixed
-// butterfly.
+// Dot product of a contiguous row with v by one wave: each lane issues
+// sixteen loads per round before using them (a 1000-long row is one round);
+// lane partials are added by a fixed butterfly.
+constexpr int kDotDepth = 16;
+
 __device__ inline double dot_row(const double* __restrict__ row, const double* __restrict__ v,
                                  int64_t n, int lane) {
   double s = 0.0;
-  for (int64_t j0 = 0; j0 < n; j0 += 4 * kWave) {
-    double rv[4], vv[4];
+  for (int64_t j0 = 0; j0 < n; j0 += kDotDepth * kWave) {
+    double rv[kDotDepth], vv[kDotDepth];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < kDotDepth; ++u) {
       const int64_t j = j0 + lane + u * kWave;
       rv[u] = j < n ? row[j] : 0.0;
       vv[u] = j < n ? v[j] : 0.0;
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) s += rv[u] * vv[u];
+    for (int u = 0; u < kDotDepth; ++u) s = fma(rv[u], vv[u], s);
   }
   return wave_sum(s);
 }

@@ -27,7 +27,7 @@ def test_tuned_gram_matches_oracle(tmp_path, prec):
     try:
         best = ils.tune_gram(A, 0, P.p, precision=prec, reps=3)
         print(f"[gpu-tune] precision {prec}: {best}", flush=True)
-        assert best["tile"] in (64, 128) and 256 <= best["workgroups"] <= 4096 and best["ms"] > 0
+        assert best["tile"] in (64, 128) and 256 <= best["workgroups"] <= 8192 and best["ms"] > 0
         G = ils.gram(A, 0, P.p, precision=prec).cpu().numpy()
         ref = O.gram(P.A, 0, P.p)
         if prec == ils.PREC_FP64:
