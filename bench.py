@@ -273,6 +273,48 @@ def bench_sparse(ils, W, np, torch, reps=3, rk_steps=20000):
     return out
 
 
+# The paper's Tables 2-5 (Sec. 5): MATLAB CPU seconds on an i7-9700, quoted as context only.
+PAPER_TABLES = [
+    ("q=n", 30000, 13000, 13000, {"sp": 559.3, "sp_rk_rgs": 514.6313, "sp_scd": 227.7141}),
+    ("q=n", 30000, 14000, 14000, {"sp": 619.1, "sp_rk_rgs": 592.2625, "sp_scd": 286.9359}),
+    ("q=n", 30000, 15000, 15000, {"sp": 830.2, "sp_rk_rgs": 803.0406, "sp_scd": 324.5609}),
+    ("q=1", 50000, 1, 13000, {"sp": 566.9453}),
+    ("q=1", 50000, 1, 14000, {"sp": 731.0016}),
+    ("q=1", 50000, 1, 15000, {"sp": 881.0750}),
+]
+
+
+def bench_paper_tables(ils, W, np, torch):
+    """The paper's own family at the paper's sizes: A1 = U[0,1) p x n, A2 =
+    7 eye(q, n), b = U[0,1), x0 = 0, RR < 1e-6 (Sec. 5).  SP (Algorithm 1)
+    and SP-RK-RGS (Algorithm 2, paper form) on the GPU; the paper's CPU
+    times are context, not a target (different machine and precision of
+    measurement)."""
+    out = []
+    for tag, p, q, n, paper_cpu in PAPER_TABLES:
+        log(f"paper family {tag}: {p + q} x {n}")
+        P = W.paper_family(p, q, n, seed=0)
+        A = torch.from_numpy(np.ascontiguousarray(P.A.T)).cuda().t()
+        del P.A
+        b = torch.from_numpy(P.b).cuda()
+        x = torch.empty(n, dtype=torch.float64, device="cuda")
+        row = {"family": tag, "m": p + q, "n": n, "paper_cpu_s": paper_cpu}
+        for name, fn, kw in (("sp", ils.sp_solve, {}),
+                             ("sp_rk_rgs", ils.rk_solve, {"seed": 1, "max_inner": 200000, "max_outer": 3})):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, inf = fn(A, b, p, out=x, stop_rule=ils.STOP_RR, tol=1e-6, **kw)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            row[name] = {"s": el, "it": inf.outer_iters, "it_inner": inf.inner_iters, "rr": inf.rr,
+                         "status": inf.status}
+            log(f"  {name}: {el:.3f} s, IT {inf.outer_iters}, inner {inf.inner_iters}, RR {inf.rr:.2e}")
+        out.append(row)
+        del A, b
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -284,6 +326,8 @@ def main():
     ap.add_argument("--no-warm-start", action="store_true", help="skip the learned warm start")
     ap.add_argument("--no-sparse", action="store_true", help="skip the sparse workload")
     ap.add_argument("--no-tune", action="store_true", help="keep the default Gram configuration")
+    ap.add_argument("--paper-tables", action="store_true",
+                    help="also run the paper's own family at the paper's sizes (several GB, minutes)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 256 MiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -363,6 +407,9 @@ def main():
         forms["sp_mixed_correction"] = time_form(ils.sp_solve, 5, form=ils.FORM_CORRECTION,
                                                  precision=ils.PREC_MIXED, **kw)
         forms["sp_scd_correction"] = time_form(ils.rgs_solve, 1, form=ils.FORM_CORRECTION, **kw)
+        forms["sp_rk_rgs_correction"] = time_form(ils.rk_solve, 1, form=ils.FORM_CORRECTION, **kw)
+        forms["sp_rk_rgs_mixed_correction"] = time_form(ils.rk_solve, 1, form=ils.FORM_CORRECTION,
+                                                        precision=ils.PREC_MIXED, **kw)
         ils.set_profiling(True)
 
     batched = None
@@ -374,6 +421,7 @@ def main():
     sparse = None
     if not args.no_sparse:
         sparse = bench_sparse(ils, W, np, torch)
+    paper_tables = bench_paper_tables(ils, W, np, torch) if args.paper_tables else None
 
     line = {
         "metric": "ILS solves/s to rel.err 1e-6, plain FP64 SP vs chosen form; % HBM/MFMA peak",
@@ -403,6 +451,7 @@ def main():
         "batched": batched,
         "warm_start": warm,
         "sparse": sparse,
+        "paper_tables": paper_tables,
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
