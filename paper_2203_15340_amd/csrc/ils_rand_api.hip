@@ -143,6 +143,9 @@ int ils::rk_solve_op(ils_handle* h, const MatOp& M, const double* b, const doubl
   float* a1f = nullptr;
   if (mixed && (st = h->need(kBufA1f32, sizeof(float) * p * n, (void**)&a1f))) return fail_info(info, st);
   const size_t wbytes = (mixed ? sizeof(float) : sizeof(double)) * p;
+  // dense A: inner steps in blocks over the whole GPU; sparse A: one workgroup
+  double* rkb = nullptr;
+  if (!M.sp && (st = h->need(kBufRkb, sizeof(double) * rk_block_scratch(p), (void**)&rkb))) return fail_info(info, st);
   if ((st = common_setup(h, M, b, x0, o, cn, c))) return fail_info(info, st);
   if (mixed) launch_to_f32(s, p, n, M.A, M.lda, a1f);
   launch_zero_col_check(s, n, cn, &h->st->bits);  // a zero column of A1: rank(A1) < n
@@ -164,8 +167,11 @@ int ils::rk_solve_op(ils_handle* h, const MatOp& M, const double* b, const doubl
       const int64_t cnt = std::min(chunk, max_inner - t);
       launch_rk_draw(s, o->seed, (uint64_t)k + o->stream_offset, t, cnt, prefix, n, jj, jj + chunk);
       if (mixed)
-        launch_rk_inner_f32(s, a1f, p, p, c.tgt, cn, jj, jj + chunk, cnt, (float*)w, (float*)sv, z,
-                            &h->st->inner_done, &h->st->done);
+        launch_rk_blocks_f32(s, a1f, p, p, c.tgt, cn, jj, jj + chunk, cnt, (float*)w, (float*)sv, z, rkb,
+                             &h->st->inner_done, &h->st->done);
+      else if (!M.sp)
+        launch_rk_blocks(s, M.A, M.lda, p, c.tgt, cn, jj, jj + chunk, cnt, w, sv, z, rkb, &h->st->inner_done,
+                         &h->st->done);
       else
         mat_rk_inner(s, M, c.tgt, cn, jj, jj + chunk, cnt, w, sv, z, &h->st->inner_done, &h->st->done);
       t += cnt;

@@ -45,6 +45,7 @@ enum BufSlot {
   kBufMDen,     // multi-RHS: per-column metric denominators
   kBufMBt,      // multi-RHS: B^T
   kBufA1f32,    // FP32 copy of A1 (mixed-precision RK-RGS inner sweeps)
+  kBufRkb,      // blocked RK-RGS inner steps: slice partials, C, coefficients
   kBufCount
 };
 
