@@ -66,79 +66,160 @@ __device__ inline bool invert64(double (&a)[16], int r, int g, double (*rowbuf)[
   return true;
 }
 
-// LDS scratch of invert64_2d (two pivot rows and two pivot columns per
-// stage, double-buffered by stage parity).
-struct InvScratch2 {
-  double rows[2][2][kNB];
-  double cols[2][2][kNB];
+// ------------------------------------------------- 64 x 64 SPD inverse by 16 x 16 blocks
+// The same in-place Gauss-Jordan inversion as invert64, carried out on 4 x 4
+// blocks of 16 x 16: for each block pivot K with P = A_KK^{-1},
+//   A_KJ <- P A_KJ,  A_IK <- -A_IK P,  A_IJ <- A_IJ + A_IK(new) A_KJ(old),
+//   A_KK <- P          (I, J != K),
+// with the block products on the FP64 matrix cores and the 16 x 16 inversions
+// done by one wave in registers.  Two LDS buffers alternate as the matrix
+// before and after each block step.  Wave 0 forms the next diagonal block
+// and inverts it while the other three waves update the rest, so one block
+// step costs about one 16 x 16 inversion.
+constexpr int kLds = kNB + 1;  // row stride (doubles) of the 64 x 64 LDS buffers
+
+struct InvBlk {
+  double x[16][17];  // wave 0's 16 x 16 staging block
+  int bad;
 };
 
-// The inversion of invert64 with thread (ti, tj) = (t / 16, t % 16) owning the
-// 4 x 4 sub-block rows 4ti.., columns 4tj.. and two pivots per barrier: a
-// thread reads 2 x 4 row and 2 x 4 column values per stage instead of 16 row
-// values per pivot, which is what bounds the one-row-per-thread layout (LDS
-// bandwidth).  Stage K = {k, k + 1}: with P = a[K][K] and Q = P^{-1}, rows
-// outside K take a[i][c] -= (a[i][K] Q) a[K][c] and a[i][K] = -a[i][K] Q,
-// rows in K take Q a[K][c] and Q (block Gauss-Jordan, the same as two single
-// pivots in exact arithmetic).  P must have p00 > 0 and det > 0 (the LDL^T
-// pivots p00 and det / p00); otherwise every thread returns false.
-__device__ inline bool invert64_2d(double (&a)[4][4], int ti, int tj, InvScratch2& S) {
+__device__ inline double lane_read(double v, int src) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+  return __hiloint2double(hi, lo);
+}
+
+// In-place inverse of a 16 x 16 SPD block by one wave: lane l holds row l % 16,
+// columns 4 (l / 16) .. 4 (l / 16) + 3.  Pivot k broadcasts row k within each
+// group of 16 lanes and the column-k entry of each row across the groups.
+// Returns false when a pivot is not > 0.
+__device__ inline bool leaf_inv16(double (&a)[4], int lane) {
+  const int i = lane & 15, g = lane >> 4;
   bool bad = false;
-#pragma unroll 1
-  for (int kq = 0; kq < 16; ++kq) {
 #pragma unroll
-    for (int kh = 0; kh < 2; ++kh) {
-      const int kk = 2 * kh, k = 4 * kq + kk;
-      if (ti == kq) {
+  for (int k = 0; k < 16; ++k) {
+    const int kg = k >> 2, kc = k & 3;
+    double pr[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          S.rows[kh][0][4 * tj + j] = a[kk][j];
-          S.rows[kh][1][4 * tj + j] = a[kk + 1][j];
-        }
-      }
-      if (tj == kq) {
+    for (int c = 0; c < 4; ++c) pr[c] = __shfl(a[c], (lane & 48) | k);
+    const double pc = __shfl(a[kc], i | (kg << 4));
+    const double piv = lane_read(a[kc], k | (kg << 4));
+    bad |= !(piv > 0.0);
+    const double r = recip(piv);
+    const bool prow = i == k;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          S.cols[kh][0][4 * ti + i] = a[i][kk];
-          S.cols[kh][1][4 * ti + i] = a[i][kk + 1];
-        }
-      }
-      __syncthreads();
-      double r0[4], r1[4], c0[4], c1[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        r0[j] = S.rows[kh][0][4 * tj + j];
-        r1[j] = S.rows[kh][1][4 * tj + j];
-      }
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        c0[i] = S.cols[kh][0][4 * ti + i];
-        c1[i] = S.cols[kh][1][4 * ti + i];
-      }
-      const double p00 = S.rows[kh][0][k], p01 = S.rows[kh][0][k + 1];
-      const double p10 = S.rows[kh][1][k], p11 = S.rows[kh][1][k + 1];
-      const double det = fma(p00, p11, -p01 * p10);
-      bad |= !(p00 > 0.0) || !(det > 0.0);
-      const double id = recip(det);
-      const double q00 = p11 * id, q01 = -p01 * id, q10 = -p10 * id, q11 = p00 * id;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const bool k0row = ti == kq && i == kk, k1row = ti == kq && i == kk + 1;
-        double u0 = fma(c0[i], q00, c1[i] * q10), u1 = fma(c0[i], q01, c1[i] * q11);
-        u0 = k0row ? 1.0 - q00 : (k1row ? -q10 : u0);
-        u1 = k0row ? -q01 : (k1row ? 1.0 - q11 : u1);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          double val = fma(-u0, r0[j], a[i][j]);
-          val = fma(-u1, r1[j], val);
-          if (j == kk) val = tj == kq ? (k0row ? 1.0 : 0.0) - u0 : val;
-          if (j == kk + 1) val = tj == kq ? (k1row ? 1.0 : 0.0) - u1 : val;
-          a[i][j] = val;
-        }
-      }
+    for (int c = 0; c < 4; ++c) {
+      const bool kcol = g == kg && c == kc;
+      const double prr = pr[c] * r;
+      const double off = kcol ? -pc * r : fma(-pc, prr, a[c]);
+      a[c] = prow ? (kcol ? r : prr) : off;
     }
   }
   return !bad;
+}
+
+__device__ inline const double* blk16(const double* B, int I, int J) { return B + 16 * I * kLds + 16 * J; }
+__device__ inline double* blk16(double* B, int I, int J) { return B + 16 * I * kLds + 16 * J; }
+
+// acc += X Y for 16 x 16 blocks in LDS (row strides ldx, ldy), one wave.
+// Lane l supplies X[l % 16][k + l / 16] and Y[k + l / 16][l % 16]; acc[v] is
+// entry (l / 16 + 4 v, l % 16).
+__device__ inline v4d mm16(const double* X, int ldx, const double* Y, int ldy, v4d acc, int lane) {
+  const int lr = lane & 15, lq = lane >> 4;
+#pragma unroll
+  for (int kk = 0; kk < 16; kk += 4)
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(X[lr * ldx + kk + lq], Y[(kk + lq) * ldy + lr], acc, 0, 0, 0);
+  return acc;
+}
+__device__ inline v4d ld16(const double* Z, int ldz, int lane) {
+  const int lr = lane & 15, lq = lane >> 4;
+  return v4d{Z[lq * ldz + lr], Z[(lq + 4) * ldz + lr], Z[(lq + 8) * ldz + lr], Z[(lq + 12) * ldz + lr]};
+}
+__device__ inline void st16(double* Z, int ldz, v4d v, int lane) {
+  const int lr = lane & 15, lq = lane >> 4;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) Z[(lq + 4 * e) * ldz + lr] = v[e];
+}
+
+// Row I != K of a block step: nxt_IK = -cur_IK P, then
+// nxt_IJ = cur_IJ + nxt_IK cur_KJ for J != K, J != skip.
+__device__ inline void blk_row(const double* cur, double* nxt, const double* P, int I, int K, int skip, int lane) {
+  const v4d zero = {0.0, 0.0, 0.0, 0.0};
+  const v4d x = mm16(blk16(cur, I, K), kLds, P, kLds, zero, lane);
+  st16(blk16(nxt, I, K), kLds, -x, lane);
+  __threadfence_block();
+#pragma unroll
+  for (int J = 0; J < 4; ++J) {
+    if (J == K || J == skip) continue;
+    const v4d acc = mm16(blk16(nxt, I, K), kLds, blk16(cur, K, J), kLds, ld16(blk16(cur, I, J), kLds, lane), lane);
+    st16(blk16(nxt, I, J), kLds, acc, lane);
+  }
+}
+
+// Inverse of the 64 x 64 SPD matrix in B0 (row stride kLds, LDS), written back
+// into B0; B1 is a second buffer of the same shape.  All 256 threads call it
+// after a barrier that makes B0 complete; returns false in every thread when
+// a pivot is not > 0 (the matrix is not positive definite).
+__device__ __attribute__((always_inline)) inline bool invert64_blk(double* B0, double* B1, InvBlk& S) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const v4d zero = {0.0, 0.0, 0.0, 0.0};
+  if (w == 0) {
+    double a[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) a[c] = B0[li * kLds + 4 * lg + c];
+    const bool ok = leaf_inv16(a, lane);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) B1[li * kLds + 4 * lg + c] = a[c];
+    if (lane == 0) S.bad = ok ? 0 : 1;
+  }
+  __syncthreads();
+#pragma unroll 1
+  for (int K = 0; K < 4; ++K) {
+    double* cur = (K & 1) ? B1 : B0;
+    double* nxt = (K & 1) ? B0 : B1;
+    const double* P = blk16(nxt, K, K);
+    if (K < 3) {
+      const int Ia = K == 0 ? 2 : 0, Ib = K == 2 ? 1 : 3;  // the rows other than K, K + 1
+      if (w == 0) {
+        // next diagonal block cur_(K+1)(K+1) - cur_(K+1)K P cur_K(K+1), inverted
+        // into cur_(K+1)(K+1), which no other wave reads in this step
+        const v4d x = mm16(blk16(cur, K + 1, K), kLds, P, kLds, zero, lane);
+        st16(&S.x[0][0], 17, -x, lane);
+        __threadfence_block();
+        const v4d d = mm16(&S.x[0][0], 17, blk16(cur, K, K + 1), kLds, ld16(blk16(cur, K + 1, K + 1), kLds, lane),
+                           lane);
+        __threadfence_block();
+        st16(&S.x[0][0], 17, d, lane);
+        __threadfence_block();
+        double a[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) a[c] = S.x[li][4 * lg + c];
+        const bool ok = leaf_inv16(a, lane);
+        double* D = blk16(cur, K + 1, K + 1);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) D[li * kLds + 4 * lg + c] = a[c];
+        if (!ok && lane == 0) S.bad = 1;
+      } else if (w == 1) {
+        blk_row(cur, nxt, P, Ia, K, -1, lane);
+      } else if (w == 2) {
+        blk_row(cur, nxt, P, Ib, K, -1, lane);
+      } else {
+#pragma unroll
+        for (int J = 0; J < 4; ++J)
+          if (J != K) st16(blk16(nxt, K, J), kLds, mm16(P, kLds, blk16(cur, K, J), kLds, zero, lane), lane);
+        blk_row(cur, nxt, P, K + 1, K, K + 1, lane);  // row K + 1 without its diagonal block
+      }
+    } else if (w < 3) {
+      blk_row(cur, nxt, P, w, K, -1, lane);
+    } else {
+#pragma unroll
+      for (int J = 0; J < 4; ++J)
+        if (J != K) st16(blk16(nxt, K, J), kLds, mm16(P, kLds, blk16(cur, K, J), kLds, zero, lane), lane);
+    }
+    __syncthreads();
+  }
+  return S.bad == 0;
 }
 
 }  // namespace ils

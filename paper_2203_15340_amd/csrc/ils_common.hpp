@@ -34,7 +34,7 @@ struct LoopState {
   double scal[8];     // small device scalars: 0 ||A^T J b||^2, 1 ||x_ref||^2,
                       // 2 ||inner target||^2, 7 relative error
   int nactive;        // multi-right-hand-side solve: columns still iterating
-  int pad;
+  unsigned int arrive3;// last-block counter of the blocked RK-RGS steps
 };
 
 // ---------------------------------------------------------------- reductions

@@ -168,10 +168,10 @@ int ils::rk_solve_op(ils_handle* h, const MatOp& M, const double* b, const doubl
       launch_rk_draw(s, o->seed, (uint64_t)k + o->stream_offset, t, cnt, prefix, n, jj, jj + chunk);
       if (mixed)
         launch_rk_blocks_f32(s, a1f, p, p, c.tgt, cn, jj, jj + chunk, cnt, (float*)w, (float*)sv, z, rkb,
-                             &h->st->inner_done, &h->st->done);
+                             &h->st->arrive3, &h->st->inner_done, &h->st->done);
       else if (!M.sp)
-        launch_rk_blocks(s, M.A, M.lda, p, c.tgt, cn, jj, jj + chunk, cnt, w, sv, z, rkb, &h->st->inner_done,
-                         &h->st->done);
+        launch_rk_blocks(s, M.A, M.lda, p, c.tgt, cn, jj, jj + chunk, cnt, w, sv, z, rkb, &h->st->arrive3,
+                         &h->st->inner_done, &h->st->done);
       else
         mat_rk_inner(s, M, c.tgt, cn, jj, jj + chunk, cnt, w, sv, z, &h->st->inner_done, &h->st->done);
       t += cnt;

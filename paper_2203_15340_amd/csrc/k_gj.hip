@@ -27,8 +27,9 @@ constexpr int kGjThreads = 256;
 // D_0 = W[0:nb, 0:nb] -> Dinv (64 x 64, row-major), identity padding.
 __global__ __launch_bounds__(kGjThreads) void k_gj_inv0(const double* __restrict__ W, int64_t ldw, int nb,
                                                         double* __restrict__ dinv, int* bits) {
-  __shared__ double Ds[kNB][kNB + 1];
-  __shared__ InvScratch2 inv;
+  __shared__ double Ds[kNB][kLds];
+  __shared__ double Es[kNB][kLds];
+  __shared__ InvBlk inv;
   if (*(volatile int*)bits) return;
   const int t = threadIdx.x;
   double dv[16];
@@ -43,20 +44,15 @@ __global__ __launch_bounds__(kGjThreads) void k_gj_inv0(const double* __restrict
     Ds[e & (kNB - 1)][e >> 6] = dv[q];
   }
   __syncthreads();
-  const int ti = t >> 4, tj = t & 15;
-  double a[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) a[i][j] = Ds[4 * ti + i][4 * tj + j];
-  if (!invert64_2d(a, ti, tj, inv)) {
+  if (!invert64_blk(&Ds[0][0], &Es[0][0], inv)) {
     if (t == 0) atomicOr(bits, kBitNotSpd);
     return;
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) dinv[(4 * ti + i) * kNB + 4 * tj + j] = a[i][j];
+  for (int q = 0; q < 16; ++q) {
+    const int e = t + q * kGjThreads;
+    dinv[e] = Ds[e >> 6][e & (kNB - 1)];
+  }
 }
 
 // R^T[c][i] = sum_k X[k][c] Dinv[i][k]: each wave forms a 32 x 32 quadrant,
@@ -124,7 +120,7 @@ __global__ __launch_bounds__(kGjThreads) void k_gj_update(double* __restrict__ W
                                                           int* bits) {
   __shared__ double Ws[kNB][kNB + 1];  // Ws[i][k] = W[I0 + i, k0 + k]
   __shared__ double Rs[kNB][kNB + 1];  // Rs[j][k] = W[k0 + k, J0 + j]
-  __shared__ InvScratch2 inv;
+  __shared__ InvBlk inv;
   if (*(volatile int*)bits) return;
   // workgroup 0 <-> the tile (next pivot rows, first strip)
   const int next_rt = (int)(k0 / kNB) + 1;
@@ -208,20 +204,15 @@ __global__ __launch_bounds__(kGjThreads) void k_gj_update(double* __restrict__ W
         Ws[i][j] = (i < nbn && j < nbn) ? cur[a][c][v] : (i == j ? 1.0 : 0.0);
       }
   __syncthreads();
-  const int ti = threadIdx.x >> 4, tj = threadIdx.x & 15;
-  double d[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) d[i][j] = Ws[4 * ti + i][4 * tj + j];
-  if (!invert64_2d(d, ti, tj, inv)) {
+  if (!invert64_blk(&Ws[0][0], &Rs[0][0], inv)) {
     if (threadIdx.x == 0) atomicOr(bits, kBitNotSpd);
     return;
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) dinv_next[(4 * ti + i) * kNB + 4 * tj + j] = d[i][j];
+  for (int q = 0; q < 16; ++q) {
+    const int e = threadIdx.x + q * kGjThreads;
+    dinv_next[e] = Ws[e >> 6][e & (kNB - 1)];
+  }
 }
 
 size_t gj_dinv_size() { return 2 * kNB * kNB; }

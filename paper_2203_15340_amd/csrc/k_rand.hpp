@@ -26,16 +26,18 @@ void launch_rk_check_f32(hipStream_t st, const double* A1, int64_t lda, int64_t 
                          const double* tn2, int* inner_done, unsigned* arrive, const int* skip);
 void launch_to_f32(hipStream_t s, int64_t p, int64_t n, const double* A, int64_t lda, float* Af);
 // SP-RK-RGS inner steps in blocks spread over the GPU (k_rkblock.hip);
-// scratch: rk_block_scratch(p) doubles.
+// scratch: rk_block_scratch(p) doubles; arrive: a zero last-block counter
+// (left zero).
 int64_t rk_block_steps();
 int64_t rk_block_slice_rows(int64_t p);
 size_t rk_block_scratch(int64_t p);
 void launch_rk_blocks(hipStream_t st, const double* A1, int64_t lda, int64_t p, const double* tgt, const double* cn,
                       const int* j1, const int* j2, int64_t count, double* w, double* s, double* z, double* scratch,
-                      const int* inner_done, const int* outer_done);
+                      unsigned* arrive, const int* inner_done, const int* outer_done);
 void launch_rk_blocks_f32(hipStream_t st, const float* A1, int64_t lda, int64_t p, const double* tgt,
                           const double* cn, const int* j1, const int* j2, int64_t count, float* w, float* s,
-                          double* z, double* scratch, const int* inner_done, const int* outer_done);
+                          double* z, double* scratch, unsigned* arrive, const int* inner_done,
+                          const int* outer_done);
 void launch_scd_inner(hipStream_t st, const double* G1, int64_t ldg, int64_t n, double* r, double* beta,
                       const uint32_t* mask, int64_t mask_words, const int* jpre, int norm_mode,
                       int64_t count, int check, double itol2, const double* tn2, int* inner_done,
