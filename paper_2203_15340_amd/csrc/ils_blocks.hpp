@@ -89,32 +89,58 @@ __device__ inline double lane_read(double v, int src) {
   return __hiloint2double(hi, lo);
 }
 
+// Lane K of each row of 16 lanes, for every lane (DPP row broadcast).
+template <int K>
+__device__ inline double row_bcast(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x150 | K, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x150 | K, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+
+// 1/x to full double precision from the hardware estimate r0:
+// r0 (1 + e + e^2) with e = 1 - x r0 (the estimate's error cubed is far
+// below double rounding).
+__device__ inline double recip_e2(double x) {
+  const double r0 = __builtin_amdgcn_rcp(x);
+  const double e = fma(-x, r0, 1.0);
+  return fma(r0, fma(e, e, e), r0);
+}
+
+// One pivot of leaf_inv16.  The pivot row is left unscaled: every other row
+// takes row_i - (a_ik / a_kk) row_k, column k takes -a_ik / a_kk on those
+// rows and 1 on row k, and row k's pivot a_kk is kept in dsv by the lanes of
+// row k.  The inverse is the result with each row divided by its pivot.
+template <int K>
+__device__ inline void leaf_pivot(double (&a)[4], int lane, bool& bad, double& dsv) {
+  constexpr int kg = K >> 2, kc = K & 3;
+  const int i = lane & 15, g = lane >> 4;
+  double pr[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) pr[c] = row_bcast<K>(a[c]);
+  const double pc = __shfl(a[kc], i | (kg << 4));
+  const double piv = lane_read(a[kc], K | (kg << 4));
+  bad |= !(piv > 0.0);
+  const double r = recip_e2(piv);
+  const bool prow = i == K;
+  const double beta = prow ? 0.0 : -pc * r;
+  dsv = prow ? piv : dsv;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) a[c] = fma(beta, pr[c], a[c]);
+  if (g == kg) a[kc] = prow ? 1.0 : beta;
+  if constexpr (K < 15) leaf_pivot<K + 1>(a, lane, bad, dsv);
+}
+
 // In-place inverse of a 16 x 16 SPD block by one wave: lane l holds row l % 16,
 // columns 4 (l / 16) .. 4 (l / 16) + 3.  Pivot k broadcasts row k within each
-// group of 16 lanes and the column-k entry of each row across the groups.
-// Returns false when a pivot is not > 0.
+// group of 16 lanes (DPP) and the column-k entry of each row across the
+// groups (lane permute).  Returns false when a pivot is not > 0.
 __device__ inline bool leaf_inv16(double (&a)[4], int lane) {
-  const int i = lane & 15, g = lane >> 4;
   bool bad = false;
+  double dsv = 1.0;
+  leaf_pivot<0>(a, lane, bad, dsv);
+  const double rd = recip(dsv);
 #pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    const int kg = k >> 2, kc = k & 3;
-    double pr[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) pr[c] = __shfl(a[c], (lane & 48) | k);
-    const double pc = __shfl(a[kc], i | (kg << 4));
-    const double piv = lane_read(a[kc], k | (kg << 4));
-    bad |= !(piv > 0.0);
-    const double r = recip(piv);
-    const bool prow = i == k;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const bool kcol = g == kg && c == kc;
-      const double prr = pr[c] * r;
-      const double off = kcol ? -pc * r : fma(-pc, prr, a[c]);
-      a[c] = prow ? (kcol ? r : prr) : off;
-    }
-  }
+  for (int c = 0; c < 4; ++c) a[c] *= rd;
   return !bad;
 }
 

@@ -8,7 +8,7 @@
 // positive definite means A^T J A is not SPD either, and raises kBitNotSpd.
 //
 // Step k (pivot rows/columns K = [k0, k0 + nb), nb <= 64):
-//   k_gj_pivot : R = D^{-1} W[K, J] for every trailing 64-column strip J on
+//   k_gj_pivot : R = D^{-1} W[K, J] for every trailing 16-column strip J on
 //                the FP64 matrix cores, with D^{-1} already inverted; R
 //                replaces W[K, J].
 //   k_gj_update: W[I, J] -= W[I, K] R[K, J] for every 64-row tile I != K.
@@ -55,58 +55,52 @@ __global__ __launch_bounds__(kGjThreads) void k_gj_inv0(const double* __restrict
   }
 }
 
-// R^T[c][i] = sum_k X[k][c] Dinv[i][k]: each wave forms a 32 x 32 quadrant,
-// so that a lane's four outputs run down a column of W.
+// R^T[c][i] = sum_k X[k][c] Dinv[i][k] for a strip of 16 columns per
+// workgroup (wave w forms rows 16w..16w+15 of R), so that a lane's four
+// outputs run down a column of W.
+constexpr int kPivCols = 16;
+
 __global__ __launch_bounds__(kGjThreads) void k_gj_pivot(double* __restrict__ W, int64_t ldw,
                                                          int64_t k0, int nb, int64_t c0, int64_t ncols,
                                                          const double* __restrict__ dinv,
                                                          const int* bits) {
-  __shared__ double Ds[kNB][kNB + 1];   // Ds[i][k] = Dinv[i][k]
-  __shared__ double Xs[kNB][kNB + 1];   // Xs[c][k] = X[k][c]
+  __shared__ double Ds[kNB][kNB + 1];         // Ds[i][k] = Dinv[i][k]
+  __shared__ double Xs[kPivCols][kNB + 1];    // Xs[c][k] = X[k][c]
   if (*(volatile const int*)bits) return;
   const int t = threadIdx.x;
-  const int64_t cs = c0 + (int64_t)blockIdx.x * kNB;
+  const int64_t cs = c0 + (int64_t)blockIdx.x * kPivCols;
   {
-    double dv[16], xv[16];
+    double dv[16], xv[4];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
+    for (int q = 0; q < 16; ++q) dv[q] = dinv[t + q * kGjThreads];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
       const int e = t + q * kGjThreads, lo = e & (kNB - 1), hi = e >> 6;
-      dv[q] = dinv[hi * kNB + lo];  // row hi, column lo
       xv[q] = (lo < nb && cs + hi < ncols) ? W[k0 + lo + (cs + hi) * ldw] : 0.0;
     }
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-      const int e = t + q * kGjThreads, lo = e & (kNB - 1), hi = e >> 6;
-      Ds[hi][lo] = dv[q];
-      Xs[hi][lo] = xv[q];
+      const int e = t + q * kGjThreads;
+      Ds[e >> 6][e & (kNB - 1)] = dv[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = t + q * kGjThreads;
+      Xs[e >> 6][e & (kNB - 1)] = xv[q];
     }
   }
   __syncthreads();
-  const int lane = t & 63, w = t >> 6, cq = (w >> 1) * 32, iq = (w & 1) * 32, lr = lane & 15;
-  v4d acc[2][2];
+  const int lane = t & 63, w = t >> 6, lr = lane & 15, lq = lane >> 4;
+  v4d acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int kk = 0; kk < kNB; kk += 4)
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Xs[lr][kk + lq], Ds[16 * w + lr][kk + lq], acc, 0, 0, 0);
+  const int i = 16 * w + lr;
 #pragma unroll
-    for (int y = 0; y < 2; ++y) acc[x][y] = v4d{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int kk = 0; kk < kNB; kk += 4) {
-    const int kr = kk + (lane >> 4);
-    const double x0 = Xs[cq + lr][kr], x1 = Xs[cq + 16 + lr][kr];
-    const double d0 = Ds[iq + lr][kr], d1 = Ds[iq + 16 + lr][kr];
-    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, d0, acc[0][0], 0, 0, 0);
-    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, d1, acc[0][1], 0, 0, 0);
-    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, d0, acc[1][0], 0, 0, 0);
-    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, d1, acc[1][1], 0, 0, 0);
+  for (int v = 0; v < 4; ++v) {
+    const int c = lq + 4 * v;
+    if (i < nb && cs + c < ncols) W[k0 + i + (cs + c) * ldw] = acc[v];
   }
-#pragma unroll
-  for (int x = 0; x < 2; ++x)
-#pragma unroll
-    for (int y = 0; y < 2; ++y)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int c = cq + x * 16 + (lane >> 4) + 4 * v, i = iq + y * 16 + lr;
-        if (i < nb && cs + c < ncols) W[k0 + i + (cs + c) * ldw] = acc[x][y][v];
-      }
 }
 
 // W[I, J] -= W[I, K] R[K, J].  The MFMA computes the transposed tile
@@ -230,7 +224,8 @@ void launch_gj(hipStream_t s, int64_t n, int64_t nrhs, double* W, int64_t ldw, d
     if (strips <= 0) break;
     double* dcur = dinv + (step & 1) * kNB * kNB;
     double* dnext = dinv + ((step + 1) & 1) * kNB * kNB;
-    hipLaunchKernelGGL(k_gj_pivot, dim3(strips), dim3(kGjThreads), 0, s, W, ldw, k0, nb, c0, ncols,
+    const int pstrips = (int)((ncols - c0 + kPivCols - 1) / kPivCols);
+    hipLaunchKernelGGL(k_gj_pivot, dim3(pstrips), dim3(kGjThreads), 0, s, W, ldw, k0, nb, c0, ncols,
                        (const double*)dcur, (const int*)bits);
     hipLaunchKernelGGL(k_gj_update, dim3(strips * row_tiles), dim3(kGjThreads), 0, s, W, ldw, n, k0, nb,
                        c0, ncols, strips, dnext, bits);
