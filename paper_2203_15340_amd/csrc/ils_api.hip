@@ -228,8 +228,8 @@ int ils::sp_solve_op(ils_handle* h, const MatOp& M, const double* b, const doubl
       (st = h->need(kBufX1, sizeof(double) * n, (void**)&xb1)) ||
       (st = h->need(kBufT, sizeof(double) * residual_scratch(m, n), (void**)&tv)) ||
       (st = h->need(kBufR, sizeof(double) * n, (void**)&rv)) ||
-      (st = h->need(kBufSPart, sizeof(double) * nblk, (void**)&spart)) ||
-      (st = h->need(kBufSBad, sizeof(int) * nblk, (void**)&sbad)) ||
+      (st = h->need(kBufSPart, sizeof(double) * 2 * nblk, (void**)&spart)) ||
+      (st = h->need(kBufSBad, sizeof(int) * 2 * nblk, (void**)&sbad)) ||
       (st = h->need(kBufDinv, sizeof(double) * gj_dinv_size(), (void**)&dinv)))
     return fail(info, st);
 
@@ -279,16 +279,18 @@ int ils::sp_solve_op(ils_handle* h, const MatOp& M, const double* b, const doubl
   a.max_outer = o->max_outer;
   a.form = o->form;
 
-  int64_t k = 0, chunk = 8;
+  // launch k computes x_{k+1} and decides on x_{k-1}; launch max_outer + 1
+  // only decides
+  int64_t k = 0, chunk = h->sp_queue;
   while (true) {
-    const int64_t kend = std::min(k + chunk, o->max_outer + 1);
+    const int64_t kend = std::min(k + chunk, o->max_outer + 2);
     for (; k < kend; ++k) {
-      if (!paper) mat_residual(s, M, b, k & 1 ? xb1 : xb0, tv, rv, &ds->done);
+      if (!paper && k <= o->max_outer) mat_residual(s, M, b, k & 1 ? xb1 : xb0, tv, rv, &ds->done);
       launch_sp_step(s, a, k);
     }
     HIPCHK(hipEventRecord(h->ev1, s));
     if ((st = read_state(h))) return fail(info, st);
-    if (h->st_host->done || h->st_host->bits || k > o->max_outer) break;
+    if (h->st_host->done || h->st_host->bits || k > o->max_outer + 1) break;
     chunk = std::min<int64_t>(chunk * 2, 64);
   }
   h->mark(7);
@@ -297,6 +299,7 @@ int ils::sp_solve_op(ils_handle* h, const MatOp& M, const double* b, const doubl
   if (st != ILS_OK) return fail(info, st);
   if (!hs.done) return fail(info, ILS_ERR_HIP);  // every queued step ran without finishing
   st = hs.status;
+  h->sp_queue = std::min<int64_t>(std::max<int64_t>(hs.iters + 2, 4), 64);
   HIPCHK(hipMemcpyAsync(x, (hs.iters & 1) ? xb1 : xb0, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
   HIPCHK(hipStreamSynchronize(s));
   return finish_info(h, n, x, o, st, hs.iters, 0, hs.metric, info);

@@ -25,7 +25,6 @@ struct LoopState {
   int status;         // ils_status of the finished loop
   int64_t iters;      // outer updates performed when done
   double metric;      // stop quantity at the final iterate
-  unsigned int arrive;// last-block counter (reset by the last block)
   int bits;           // kBit* flags raised by setup kernels
   int64_t inner_total;// randomized methods: inner steps taken
   int inner_done;     // randomized methods: inner stop test met
@@ -163,8 +162,8 @@ struct SpStepArgs {
   double* xbuf0;
   double* xbuf1;
   const double* r;      // correction form: residual at x_k (n)
-  double* partials;     // per-block metric partials
-  int* nonfinite_part;  // per-block flags
+  double* partials;     // per-block metric partials, two sets of sp_step_blocks(n)
+  int* nonfinite_part;  // per-block flags, two sets
   LoopState* st;
   int stop_rule;
   double tol;

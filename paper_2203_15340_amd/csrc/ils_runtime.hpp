@@ -67,6 +67,10 @@ struct ils_handle {
   static constexpr int kPhases = 7;
   bool profile = false;
   hipEvent_t pev[kPhases + 1] = {};
+  // SP outer launches queued before the first look at the loop state: the
+  // previous solve's count plus the deciding launch (a guess; too few costs a
+  // host round trip, too many a few launches that return at once)
+  int64_t sp_queue = 8;
   // batched solver: pinned staging, last uploaded descriptors, captured launch
   void* pinned = nullptr;
   size_t pinned_cap = 0;

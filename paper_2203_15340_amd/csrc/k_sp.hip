@@ -5,23 +5,18 @@
 //   paper form      x_{k+1} = B x_k + c            (B = (A1^T A1)^{-1} A2^T A2)
 //   correction form x_{k+1} = x_k + P r_k          (P = (A1^T A1)^{-1},
 //                                                    r_k = A^T J (b - A x_k))
-// It also evaluates the stop quantity at x_k (RR of Sec. 5, or the relative
-// error against x_ref).  Each workgroup handles four rows (one per wave) and
-// writes a partial sum; the last workgroup to arrive adds the partials in
-// block order and records the outcome in LoopState.  The host queues several
-// steps ahead; a launch that finds the loop finished returns at once.
+// Each workgroup handles four rows (one per wave) and also writes its partial
+// sum of the stop quantity at x_k (RR of Sec. 5, or the relative error
+// against x_ref).  The stopping test for x_k is taken at the start of launch
+// k + 1: every workgroup adds the partials of launch k in the same fixed
+// order, so all reach the same decision without atomics or fences, and
+// workgroup 0 records it in LoopState.  The host queues several steps ahead;
+// a launch that finds the loop finished returns at once.
 #include "ils_common.hpp"
 
 namespace ils {
 
 constexpr int kSpRows = 4;
-
-__device__ inline double load_coherent(const double* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ inline int load_coherent(const int* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 // Dot product of a contiguous row with v by one wave: each lane issues
 // sixteen loads per round before using them (a 1000-long row is one round);
@@ -48,6 +43,47 @@ __device__ inline double dot_row(const double* __restrict__ row, const double* _
 __global__ __launch_bounds__(256) void k_sp_step(SpStepArgs a, int64_t k) {
   LoopState* st = a.st;
   if (*(volatile int*)&st->done || *(volatile int*)&st->bits) return;
+  __shared__ double tred[256 / kWave];
+  const unsigned nblk = gridDim.x;
+  if (k >= 1) {
+    // stopping test for x_{k-1} from the partials of launch k - 1: strided
+    // per thread, then the block tree (the same order in every workgroup)
+    const int64_t kk = k - 1;
+    const double* part = a.partials + (kk & 1) * nblk;
+    const int* pbad = a.nonfinite_part + (kk & 1) * nblk;
+    double tot = 0.0;
+    int anybad = 0;
+    for (unsigned bkt = threadIdx.x; bkt < nblk; bkt += 256) {
+      tot += part[bkt];
+      anybad |= pbad[bkt];
+    }
+    tot = block_sum<256>(tot, tred);
+    anybad = __syncthreads_or(anybad);
+    double metric = 0.0;
+    if (a.stop_rule == ILS_STOP_XREF) metric = sqrt(tot) / sqrt(st->scal[1]);
+    else if (a.stop_rule == ILS_STOP_RR) metric = tot / st->scal[0];
+    int done = 0, status = ILS_OK;
+    int64_t iters = kk;
+    if (a.stop_rule != ILS_STOP_FIXED && metric < a.tol) {
+      done = 1;
+    } else if (kk == a.max_outer) {
+      done = 1;
+      status = (a.stop_rule == ILS_STOP_FIXED) ? ILS_OK : ILS_ERR_NO_CONVERGENCE;
+    } else if (anybad) {
+      done = 1;
+      status = ILS_ERR_NONFINITE;
+      iters = kk + 1;
+    }
+    if (done) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->metric = metric;
+        st->status = status;
+        st->iters = iters;
+        st->done = 1;
+      }
+      return;
+    }
+  }
   const double* xk = (k & 1) ? a.xbuf1 : a.xbuf0;
   double* xn = (k & 1) ? a.xbuf0 : a.xbuf1;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -74,55 +110,14 @@ __global__ __launch_bounds__(256) void k_sp_step(SpStepArgs a, int64_t k) {
   }
   __shared__ double red[kSpRows];
   __shared__ int redb[kSpRows];
-  __shared__ int is_last;
-  __shared__ double tred[256 / kWave];
   if (lane == 0) {
     red[w] = mp;
     redb[w] = bad;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    a.partials[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
-    a.nonfinite_part[blockIdx.x] = redb[0] | redb[1] | redb[2] | redb[3];
-    __threadfence();
-    is_last = atomicAdd(&st->arrive, 1u) == gridDim.x - 1;
-  }
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
-  // last workgroup: add the partials in a fixed order (strided per thread,
-  // then the block tree), OR the non-finite flags
-  double tot = 0.0;
-  int anybad = 0;
-  for (unsigned bkt = threadIdx.x; bkt < gridDim.x; bkt += 256) {
-    tot += load_coherent(a.partials + bkt);
-    anybad |= load_coherent(a.nonfinite_part + bkt);
-  }
-  tot = block_sum<256>(tot, tred);
-  anybad = __syncthreads_or(anybad);
-  if (threadIdx.x != 0) return;
-  double metric = 0.0;
-  if (a.stop_rule == ILS_STOP_XREF) metric = sqrt(tot) / sqrt(st->scal[1]);
-  else if (a.stop_rule == ILS_STOP_RR) metric = tot / st->scal[0];
-  st->arrive = 0;
-  int done = 0, status = ILS_OK;
-  int64_t iters = k;
-  if (a.stop_rule != ILS_STOP_FIXED && metric < a.tol) {
-    done = 1;
-  } else if (k == a.max_outer) {
-    done = 1;
-    status = (a.stop_rule == ILS_STOP_FIXED) ? ILS_OK : ILS_ERR_NO_CONVERGENCE;
-  } else if (anybad) {
-    done = 1;
-    status = ILS_ERR_NONFINITE;
-    iters = k + 1;
-  }
-  if (done) {
-    st->metric = metric;
-    st->status = status;
-    st->iters = iters;
-    __threadfence();
-    st->done = 1;
+    a.partials[(k & 1) * nblk + blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+    a.nonfinite_part[(k & 1) * nblk + blockIdx.x] = redb[0] | redb[1] | redb[2] | redb[3];
   }
 }
 
