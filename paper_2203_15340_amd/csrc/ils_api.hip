@@ -173,7 +173,9 @@ int ils::finish_info(ils_handle* h, int64_t n, double* x, const ils_opts* o, int
   info->inner_iters = inner;
   info->rr = (o->stop_rule == ILS_STOP_RR) ? metric : NAN;
   info->rel_err = -1.0;
-  if (o->x_ref && status != ILS_ERR_ARG && status != ILS_ERR_NOT_SPD) {
+  if (o->stop_rule == ILS_STOP_XREF && (status == ILS_OK || status == ILS_ERR_NO_CONVERGENCE)) {
+    info->rel_err = metric;  // the stop quantity is the relative error of the returned iterate
+  } else if (o->x_ref && status != ILS_ERR_ARG && status != ILS_ERR_NOT_SPD) {
     hipLaunchKernelGGL(k_relerr, dim3(1), dim3(1024), 0, h->stream, n, (const double*)x, o->x_ref,
                        &h->st->scal[7]);
     double v = -1.0;
@@ -270,6 +272,7 @@ int ils::sp_solve_op(ils_handle* h, const MatOp& M, const double* b, const doubl
   a.x_ref = o->x_ref;
   a.xbuf0 = xb0;
   a.xbuf1 = xb1;
+  a.x_out = x;
   a.r = rv;
   a.partials = spart;
   a.nonfinite_part = sbad;
@@ -300,8 +303,6 @@ int ils::sp_solve_op(ils_handle* h, const MatOp& M, const double* b, const doubl
   if (!hs.done) return fail(info, ILS_ERR_HIP);  // every queued step ran without finishing
   st = hs.status;
   h->sp_queue = std::min<int64_t>(std::max<int64_t>(hs.iters + 2, 4), 64);
-  HIPCHK(hipMemcpyAsync(x, (hs.iters & 1) ? xb1 : xb0, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-  HIPCHK(hipStreamSynchronize(s));
   return finish_info(h, n, x, o, st, hs.iters, 0, hs.metric, info);
 }
 

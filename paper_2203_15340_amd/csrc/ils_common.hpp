@@ -161,6 +161,7 @@ struct SpStepArgs {
   const double* x_ref;  // XREF metric
   double* xbuf0;
   double* xbuf1;
+  double* x_out;        // the caller's x, written when the loop finishes
   const double* r;      // correction form: residual at x_k (n)
   double* partials;     // per-block metric partials, two sets of sp_step_blocks(n)
   int* nonfinite_part;  // per-block flags, two sets

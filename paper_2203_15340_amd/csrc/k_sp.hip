@@ -10,7 +10,8 @@
 // against x_ref).  The stopping test for x_k is taken at the start of launch
 // k + 1: every workgroup adds the partials of launch k in the same fixed
 // order, so all reach the same decision without atomics or fences, and
-// workgroup 0 records it in LoopState.  The host queues several steps ahead;
+// workgroup 0 records it in LoopState; the deciding launch also copies the
+// returned iterate into the caller's x.  The host queues several steps ahead;
 // a launch that finds the loop finished returns at once.
 #include "ils_common.hpp"
 
@@ -75,6 +76,10 @@ __global__ __launch_bounds__(256) void k_sp_step(SpStepArgs a, int64_t k) {
       iters = kk + 1;
     }
     if (done) {
+      // the returned iterate goes straight to the caller's x
+      const double* xs = (iters & 1) ? a.xbuf1 : a.xbuf0;
+      const int64_t i = (int64_t)blockIdx.x * kSpRows + (threadIdx.x >> 6);
+      if ((threadIdx.x & 63) == 0 && i < a.n) a.x_out[i] = xs[i];
       if (blockIdx.x == 0 && threadIdx.x == 0) {
         st->metric = metric;
         st->status = status;
