@@ -239,15 +239,28 @@ int ils::sp_solve_op(ils_handle* h, const MatOp& M, const double* b, const doubl
   HIPCHK(hipEventRecord(h->ev0, s));
   h->mark(0);
   LoopState* ds = h->st;
-  mat_colpass(s, M, b, g, nullptr, &ds->bits);
-  if (o->stop_rule == ILS_STOP_RR) launch_norm2(s, n, g, &ds->scal[0]);
+  // dense paper form: A^T J b = A1^T b1 - A2^T b2 comes from the Gram
+  // products of the bordered blocks [A1 b1] and [A2 b2], so A is read once
+  const bool bordered = paper && !M.sp;
+  if (!bordered) {
+    mat_colpass(s, M, b, g, nullptr, &ds->bits);
+    if (o->stop_rule == ILS_STOP_RR) launch_norm2(s, n, g, &ds->scal[0]);
+  }
   if (o->stop_rule == ILS_STOP_XREF) launch_norm2(s, n, o->x_ref, &ds->scal[1]);
   h->mark(1);
   // [A1^T A1 | A2^T A2 | A^T J b] (paper form) or [A1^T A1 | I] (correction form)
   hipEvent_t mid = h->profile ? h->pev[2] : nullptr;
-  mat_gram(s, M, 0, o->precision, part, W, ldw, mid);
+  if (bordered)
+    launch_gram_f64(s, p, n, M.A, M.lda, (double*)part, W, ldw, mid, b, g);
+  else
+    mat_gram(s, M, 0, o->precision, part, W, ldw, mid);
   h->mark(3);
-  if (paper) {
+  if (bordered) {
+    launch_gram_f64(s, q, n, M.A + p, M.lda, (double*)part, W + n * ldw, ldw, nullptr, b + p, rv);
+    launch_border_combine(s, n, g, rv, W, W + n * ldw, ldw, W + 2 * n * ldw, &ds->bits);
+    if (o->stop_rule == ILS_STOP_RR) launch_norm2(s, n, g, &ds->scal[0]);
+    if (need_h) launch_sub(s, n, W, ldw, W + n * ldw, ldw, H, n);
+  } else if (paper) {
     mat_gram(s, M, 1, ILS_PREC_FP64, part, W + n * ldw, ldw);
     launch_copy_cols(s, n, 1, g, n, W + 2 * n * ldw, ldw);
     if (need_h) launch_sub(s, n, W, ldw, W + n * ldw, ldw, H, n);

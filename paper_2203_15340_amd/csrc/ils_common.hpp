@@ -106,14 +106,19 @@ void launch_colpass(hipStream_t s, int64_t p, int64_t q, int64_t n, const double
                     const double* b, double* g, double* cn, int* bits);
 // r = A^T J (b - A x); t is residual_scratch(m, n) doubles of scratch (t = b - A x
 // in the first m).  Skipped when *done != 0.
+void launch_border_combine(hipStream_t s, int64_t n, double* g, const double* g2, const double* G1,
+                           const double* G2, int64_t ldg, double* gcol, int* bits);
 size_t residual_scratch(int64_t m, int64_t n);
 void launch_residual(hipStream_t s, int64_t p, int64_t q, int64_t n, const double* A, int64_t lda,
                      const double* b, const double* x, double* t, double* r, const int* done);
 // Gram of rows [0, K) of A (A already offset to the first row).  `partials`
 // must hold gram_partials_size(n, K) doubles.
 size_t gram_partials_size(int64_t n, int64_t K);
+// With a border column vb (K entries, may be null) the product of the
+// bordered matrix [A vb] also yields A^T vb, written to gv (n entries).
 void launch_gram_f64(hipStream_t s, int64_t K, int64_t n, const double* A, int64_t lda,
-                     double* partials, double* G, int64_t ldg, hipEvent_t mid = nullptr);
+                     double* partials, double* G, int64_t ldg, hipEvent_t mid = nullptr,
+                     const double* vb = nullptr, double* gv = nullptr);
 void launch_gram_f32(hipStream_t s, int64_t K, int64_t n, const double* A, int64_t lda,
                      float* partials, double* G, int64_t ldg, hipEvent_t mid = nullptr);
 // Gram launch configuration (tile edge 64 or 128, workgroups aimed at) and

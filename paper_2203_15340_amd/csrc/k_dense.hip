@@ -67,6 +67,32 @@ void launch_colpass(hipStream_t s, int64_t p, int64_t q, int64_t n, const double
                      bits);
 }
 
+// g = g1 - g2 with g1 = A1^T b1 and g2 = A2^T b2 taken from the bordered Gram
+// products, copied into gcol as well.  A non-finite entry of g or of either
+// Gram diagonal (a non-finite entry of A or b, or a column whose squares
+// overflow) raises kBitNonfinite.
+__global__ __launch_bounds__(256) void k_border_combine(int64_t n, double* __restrict__ g,
+                                                        const double* __restrict__ g2,
+                                                        const double* __restrict__ G1,
+                                                        const double* __restrict__ G2, int64_t ldg,
+                                                        double* __restrict__ gcol, int* bits) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  int bad = 0;
+  if (j < n) {
+    const double v = g[j] - g2[j];
+    g[j] = v;
+    gcol[j] = v;
+    bad = !isfinite(v) || !isfinite(G1[j + j * ldg]) || !isfinite(G2[j + j * ldg]);
+  }
+  if (__syncthreads_or(bad) && threadIdx.x == 0) atomicOr(bits, kBitNonfinite);
+}
+
+void launch_border_combine(hipStream_t s, int64_t n, double* g, const double* g2, const double* G1,
+                           const double* G2, int64_t ldg, double* gcol, int* bits) {
+  hipLaunchKernelGGL(k_border_combine, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, g, g2, G1, G2,
+                     ldg, gcol, bits);
+}
+
 // ------------------------------------------------------------------ residual
 // r = A^T J (b - A x) in two passes over A.
 // Pass 1: t = b - A x.  A is column-major, so a wavefront owns 64 rows and

@@ -58,7 +58,7 @@ constexpr int kXcds = 8;
 
 template <typename T, int TM>
 __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ A, int64_t lda, int64_t K,
-                                              int n, int64_t klen, int ntiles,
+                                              int n, const double* __restrict__ vb, int64_t klen, int ntiles,
                                               T* __restrict__ partials) {
   typedef typename Mma<T>::acc_t acc_t;
   constexpr int NB = TM / 32;       // 16x16 blocks per wave edge
@@ -83,16 +83,25 @@ __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ A, int6
     for (int c = 0; c < NB; ++c) acc[a][c] = acc_t{};
   const double* Ai = A + (int64_t)ti * TM * lda;
   const double* Aj = A + (int64_t)tj * TM * lda;
+  // column c of each operand tile: a column of A, the border column vb
+  // (global column n), or zero padding
   const int ci_lim = n - ti * TM, cj_lim = n - tj * TM;
+  const double* pa[NL];
+  const double* pb[NL];
+#pragma unroll
+  for (int r = 0; r < NL; ++r) {
+    const int c = lc + 16 * r;
+    pa[r] = c < ci_lim ? Ai + (int64_t)c * lda : (c == ci_lim ? vb : nullptr);
+    pb[r] = c < cj_lim ? Aj + (int64_t)c * lda : (c == cj_lim ? vb : nullptr);
+  }
   T ra[NL], rb[NL];
   auto fetch = [&](int64_t k0) {
     const int64_t k = k0 + lk;
     const bool kin = k < kend;
 #pragma unroll
     for (int r = 0; r < NL; ++r) {
-      const int c = lc + 16 * r;
-      ra[r] = (kin && c < ci_lim) ? (T)Ai[k + (int64_t)c * lda] : (T)0;
-      if (!diag) rb[r] = (kin && c < cj_lim) ? (T)Aj[k + (int64_t)c * lda] : (T)0;
+      ra[r] = (kin && pa[r]) ? (T)pa[r][k] : (T)0;
+      if (!diag) rb[r] = (kin && pb[r]) ? (T)pb[r][k] : (T)0;
     }
   };
   auto stash = [&](int buf) {
@@ -144,19 +153,20 @@ __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ A, int6
 }
 
 // Sum the slices of each tile in slice order and write the tile and its
-// mirror image into the full symmetric G (column-major, ldg).  One element
+// mirror image into the full symmetric G (column-major, ldg); with a border
+// column, row n of the bordered product (A^T vb) goes to gv.  One element
 // per thread; the slice values are loaded together, then added in order.
 template <typename T, int TM>
 __global__ __launch_bounds__(256) void k_gram_finalize(const T* __restrict__ partials, int nsplit,
-                                                       int ntiles, int n, double* __restrict__ G,
-                                                       int64_t ldg) {
+                                                       int ntiles, int n, int nc, double* __restrict__ G,
+                                                       int64_t ldg, double* __restrict__ gv) {
   const int tile = blockIdx.y;
   int ti, tj;
   tile_of(tile, ti, tj);
   const int e = blockIdx.x * 256 + threadIdx.x;
   const int row = e / TM, col = e % TM;
   const int i = ti * TM + row, j = tj * TM + col;
-  if (i >= n || j >= n || (ti == tj && row < col)) return;
+  if (i >= nc || j >= nc || (ti == tj && row < col) || (i == n && j == n)) return;
   const T* src = partials + (size_t)tile * (TM * TM) + e;
   const size_t stride = (size_t)ntiles * (TM * TM);
   double s = 0.0;
@@ -169,6 +179,10 @@ __global__ __launch_bounds__(256) void k_gram_finalize(const T* __restrict__ par
     for (int u = 0; u < 8; ++u) s += (double)v[u];
   }
   for (; sp < nsplit; ++sp) s += (double)src[(size_t)sp * stride];
+  if (i == n) {  // border row: j < n
+    gv[j] = s;
+    return;
+  }
   G[i + (int64_t)j * ldg] = s;
   G[j + (int64_t)i * ldg] = s;
 }
@@ -260,51 +274,59 @@ static size_t plan_size(int64_t n, int64_t K, GramCfg c) {
   return (size_t)ntiles * nsplit * tm * tm;
 }
 
-// Partial-tile scratch in doubles, enough for either precision's configuration.
+// Partial-tile scratch in doubles, enough for either precision's
+// configuration, with or without a border column.
 size_t gram_partials_size(int64_t n, int64_t K) {
-  return std::max(plan_size(n, K, gram_cfg(ILS_PREC_FP64, n, K)), plan_size(n, K, gram_cfg(ILS_PREC_MIXED, n, K)));
+  size_t s = 0;
+  for (int64_t nc = n; nc <= n + 1; ++nc)
+    s = std::max({s, plan_size(nc, K, gram_cfg(ILS_PREC_FP64, n, K)), plan_size(nc, K, gram_cfg(ILS_PREC_MIXED, n, K))});
+  return s;
 }
 
 size_t gram_partials_size_cfg(int64_t n, int64_t K, GramCfg c) { return plan_size(n, K, c); }
 
 template <typename T, int TM>
-static void gram_launch(hipStream_t s, int64_t K, int64_t n, const double* A, int64_t lda, T* partials,
-                        double* G, int64_t ldg, hipEvent_t mid, int ntiles, int nsplit, int64_t klen) {
-  hipLaunchKernelGGL((k_gram<T, TM>), dim3(ntiles * nsplit), dim3(256), 0, s, A, lda, K, (int)n, klen,
+static void gram_launch(hipStream_t s, int64_t K, int64_t n, const double* A, int64_t lda, const double* vb,
+                        T* partials, double* G, int64_t ldg, double* gv, hipEvent_t mid, int ntiles, int nsplit,
+                        int64_t klen) {
+  const int nc = (int)n + (vb ? 1 : 0);
+  hipLaunchKernelGGL((k_gram<T, TM>), dim3(ntiles * nsplit), dim3(256), 0, s, A, lda, K, (int)n, vb, klen,
                      ntiles, partials);
   if (mid) (void)hipEventRecord(mid, s);
   hipLaunchKernelGGL((k_gram_finalize<T, TM>), dim3(TM * TM / 256, ntiles), dim3(256), 0, s, partials,
-                     nsplit, ntiles, (int)n, G, ldg);
+                     nsplit, ntiles, (int)n, nc, G, ldg, gv);
 }
 
+// Gram of rows [0, K) of A with the configuration of (n, K); a border column
+// vb (K entries) adds A^T vb, written to gv.
 template <typename T>
-static void gram_run(hipStream_t s, int64_t K, int64_t n, const double* A, int64_t lda, T* partials,
-                     double* G, int64_t ldg, hipEvent_t mid, GramCfg cfg) {
+static void gram_run(hipStream_t s, int64_t K, int64_t n, const double* A, int64_t lda, const double* vb,
+                     T* partials, double* G, int64_t ldg, double* gv, hipEvent_t mid, GramCfg cfg) {
   int tm, ntiles, nsplit;
   int64_t klen;
-  gram_plan_cfg(n, K, cfg, tm, ntiles, nsplit, klen);
+  gram_plan_cfg(n + (vb ? 1 : 0), K, cfg, tm, ntiles, nsplit, klen);
   if (tm == 128)
-    gram_launch<T, 128>(s, K, n, A, lda, partials, G, ldg, mid, ntiles, nsplit, klen);
+    gram_launch<T, 128>(s, K, n, A, lda, vb, partials, G, ldg, gv, mid, ntiles, nsplit, klen);
   else
-    gram_launch<T, 64>(s, K, n, A, lda, partials, G, ldg, mid, ntiles, nsplit, klen);
+    gram_launch<T, 64>(s, K, n, A, lda, vb, partials, G, ldg, gv, mid, ntiles, nsplit, klen);
 }
 
 void launch_gram_cfg(hipStream_t s, int precision, int64_t K, int64_t n, const double* A, int64_t lda,
                      void* partials, double* G, int64_t ldg, GramCfg cfg) {
   if (precision == ILS_PREC_MIXED)
-    gram_run<float>(s, K, n, A, lda, (float*)partials, G, ldg, nullptr, cfg);
+    gram_run<float>(s, K, n, A, lda, nullptr, (float*)partials, G, ldg, nullptr, nullptr, cfg);
   else
-    gram_run<double>(s, K, n, A, lda, (double*)partials, G, ldg, nullptr, cfg);
+    gram_run<double>(s, K, n, A, lda, nullptr, (double*)partials, G, ldg, nullptr, nullptr, cfg);
 }
 
 void launch_gram_f64(hipStream_t s, int64_t K, int64_t n, const double* A, int64_t lda,
-                     double* partials, double* G, int64_t ldg, hipEvent_t mid) {
-  gram_run<double>(s, K, n, A, lda, partials, G, ldg, mid, gram_cfg(ILS_PREC_FP64, n, K));
+                     double* partials, double* G, int64_t ldg, hipEvent_t mid, const double* vb, double* gv) {
+  gram_run<double>(s, K, n, A, lda, vb, partials, G, ldg, gv, mid, gram_cfg(ILS_PREC_FP64, n, K));
 }
 
 void launch_gram_f32(hipStream_t s, int64_t K, int64_t n, const double* A, int64_t lda,
                      float* partials, double* G, int64_t ldg, hipEvent_t mid) {
-  gram_run<float>(s, K, n, A, lda, partials, G, ldg, mid, gram_cfg(ILS_PREC_MIXED, n, K));
+  gram_run<float>(s, K, n, A, lda, nullptr, partials, G, ldg, nullptr, mid, gram_cfg(ILS_PREC_MIXED, n, K));
 }
 
 }  // namespace ils
