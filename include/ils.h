@@ -352,10 +352,13 @@ int ils_tune_clear(void);
 int ils_set_profiling(ils_handle* h, int enable);
 
 /* Durations in ms of the phases of the last profiled ils_sp_solve, written
- * to ms[0 .. count-1] (host): [0] column pass and norms, [1] main Gram kernel
- * for A1^T A1, [2] its split-K reduction, [3] A2^T A2 and right-hand side
- * assembly, [4] block Gauss-Jordan, [5] iteration matrix layout and start
- * vector, [6] outer iterations (including the host's polls of the stop flag).
+ * to ms[0 .. count-1] (host): [0] column pass (correction form, sparse A)
+ * and norms, [1] main Gram kernel (dense paper form: A1^T A1 and A2^T A2 with
+ * the border columns b1, b2 in one launch; otherwise A1^T A1), [2] its
+ * split-K reduction, [3] the other Gram product if separate and right-hand
+ * side assembly, [4] block Gauss-Jordan, [5] iteration matrix layout and
+ * start vector, [6] outer iterations (including the host's polls of the stop
+ * flag).
  * Returns the number of phases written, or a negative ils_status. */
 int ils_get_phase_times(ils_handle* h, double* ms, int count);
 

@@ -34,8 +34,7 @@ EXPORTS = ("ils_create", "ils_destroy", "ils_opts_default", "ils_status_string",
            "ils_ws_adam", "ils_csr_create", "ils_csr_destroy", "ils_sp_solve_csr", "ils_rk_solve_csr",
            "ils_rgs_solve_csr", "ils_csr_gram", "ils_csr_colpass", "ils_csr_residual",
            "ils_csr_export_csc", "ils_tune_gram", "ils_tune_save", "ils_tune_load", "ils_tune_clear")
-PHASES = ("colpass", "gram_a1", "gram_a1_reduce", "gram_a2_rhs", "gauss_jordan", "layout",
-          "iterations")
+PHASES = ("colpass", "gram", "gram_reduce", "rhs", "gauss_jordan", "layout", "iterations")
 
 
 class Opts(C.Structure):

@@ -250,13 +250,12 @@ int ils::sp_solve_op(ils_handle* h, const MatOp& M, const double* b, const doubl
   h->mark(1);
   // [A1^T A1 | A2^T A2 | A^T J b] (paper form) or [A1^T A1 | I] (correction form)
   hipEvent_t mid = h->profile ? h->pev[2] : nullptr;
-  if (bordered)
-    launch_gram_f64(s, p, n, M.A, M.lda, (double*)part, W, ldw, mid, b, g);
+  if (bordered)  // A1^T A1, A1^T b1 and A2^T A2, A2^T b2 in one launch pair
+    launch_gram2_f64(s, n, M.lda, ldw, (double*)part, mid, p, M.A, b, W, g, q, M.A + p, b + p, W + n * ldw, rv);
   else
     mat_gram(s, M, 0, o->precision, part, W, ldw, mid);
   h->mark(3);
   if (bordered) {
-    launch_gram_f64(s, q, n, M.A + p, M.lda, (double*)part, W + n * ldw, ldw, nullptr, b + p, rv);
     launch_border_combine(s, n, g, rv, W, W + n * ldw, ldw, W + 2 * n * ldw, &ds->bits);
     if (o->stop_rule == ILS_STOP_RR) launch_norm2(s, n, g, &ds->scal[0]);
     if (need_h) launch_sub(s, n, W, ldw, W + n * ldw, ldw, H, n);

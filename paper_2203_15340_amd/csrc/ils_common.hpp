@@ -121,6 +121,13 @@ void launch_gram_f64(hipStream_t s, int64_t K, int64_t n, const double* A, int64
                      const double* vb = nullptr, double* gv = nullptr);
 void launch_gram_f32(hipStream_t s, int64_t K, int64_t n, const double* A, int64_t lda,
                      float* partials, double* G, int64_t ldg, hipEvent_t mid = nullptr);
+// Both bordered products [A0 vb0]^T [A0 vb0] and [A1 vb1]^T [A1 vb1] in one
+// launch pair (FP64, part 0's configuration); `partials` must hold
+// gram2_partials_size(n, K0, K1) doubles.
+size_t gram2_partials_size(int64_t n, int64_t K0, int64_t K1);
+void launch_gram2_f64(hipStream_t s, int64_t n, int64_t lda, int64_t ldg, double* partials, hipEvent_t mid,
+                      int64_t K0, const double* A0, const double* vb0, double* G0, double* gv0,
+                      int64_t K1, const double* A1, const double* vb1, double* G1, double* gv1);
 // Gram launch configuration (tile edge 64 or 128, workgroups aimed at) and
 // the tuning table consulted by launch_gram_f64/f32.
 struct GramCfg {

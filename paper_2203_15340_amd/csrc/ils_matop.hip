@@ -20,7 +20,7 @@ int check_op(const MatOp& M, const double* b, const double* x, const ils_opts* o
 
 size_t mat_gram_partials(const MatOp& M) {
   if (M.sp) return 1;
-  return std::max(gram_partials_size(M.n, M.p), gram_partials_size(M.n, M.q));
+  return std::max({gram_partials_size(M.n, M.p), gram_partials_size(M.n, M.q), gram2_partials_size(M.n, M.p, M.q)});
 }
 
 void mat_colpass(hipStream_t s, const MatOp& M, const double* b, double* g, double* cn, int* bits) {

@@ -56,17 +56,46 @@ __device__ inline void tile_of(int tile, int& ti, int& tj) {
 // the A panels of that slice in its L2.  nsplit is a multiple of 8.
 constexpr int kXcds = 8;
 
+// One or two Gram products in one launch (A1^T A1 and A2^T A2 share the tile
+// grid): part 1's workgroups follow part 0's.
+struct GramPart {
+  const double* A;   // first row of the block
+  int64_t K;         // rows
+  const double* vb;  // border column (K entries) or null
+  int64_t klen;      // rows per K-slice
+  int nsplit;        // K-slices (a multiple of kXcds)
+  double* G;         // n x n output (column-major, ldg)
+  double* gv;        // A^T vb output (n entries) when vb is set
+};
+struct GramJob {
+  GramPart part[2];
+  int nparts;
+  int n;             // columns of A
+  int nc;            // n plus the border column, if any
+  int64_t lda, ldg;
+  int ntiles;        // lower-triangle tiles of the nc x nc product
+  int wg1;           // first workgroup of part 1
+  int64_t pbase1;    // part 1's offset in the partial tiles
+};
+
 template <typename T, int TM>
-__global__ __launch_bounds__(256) void k_gram(const double* __restrict__ A, int64_t lda, int64_t K,
-                                              int n, const double* __restrict__ vb, int64_t klen, int ntiles,
-                                              T* __restrict__ partials) {
+__global__ __launch_bounds__(256) void k_gram(GramJob job, T* __restrict__ partials) {
   typedef typename Mma<T>::acc_t acc_t;
   constexpr int NB = TM / 32;       // 16x16 blocks per wave edge
   constexpr int NL = TM / 16;       // loads per thread per operand per stage
   __shared__ T As[2][TM][kGLd];
   __shared__ T Bs[2][TM][kGLd];
-  const int slot = blockIdx.x / kXcds;
-  const int split = (int)(blockIdx.x % kXcds) + kXcds * (slot / ntiles);
+  const bool second = job.nparts == 2 && (int)blockIdx.x >= job.wg1;
+  const int bid = second ? (int)blockIdx.x - job.wg1 : (int)blockIdx.x;
+  const double* A = second ? job.part[1].A : job.part[0].A;
+  const int64_t K = second ? job.part[1].K : job.part[0].K;
+  const double* vb = second ? job.part[1].vb : job.part[0].vb;
+  const int64_t klen = second ? job.part[1].klen : job.part[0].klen;
+  if (second) partials += job.pbase1;
+  const int64_t lda = job.lda;
+  const int n = job.n, ntiles = job.ntiles;
+  const int slot = bid / kXcds;
+  const int split = (int)(bid % kXcds) + kXcds * (slot / ntiles);
   const int tile = slot % ntiles;
   int ti, tj;
   tile_of(tile, ti, tj);
@@ -157,10 +186,15 @@ __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ A, int6
 // column, row n of the bordered product (A^T vb) goes to gv.  One element
 // per thread; the slice values are loaded together, then added in order.
 template <typename T, int TM>
-__global__ __launch_bounds__(256) void k_gram_finalize(const T* __restrict__ partials, int nsplit,
-                                                       int ntiles, int n, int nc, double* __restrict__ G,
-                                                       int64_t ldg, double* __restrict__ gv) {
-  const int tile = blockIdx.y;
+__global__ __launch_bounds__(256) void k_gram_finalize(GramJob job, const T* __restrict__ partials) {
+  const bool second = (int)blockIdx.y >= job.ntiles;
+  const int tile = second ? (int)blockIdx.y - job.ntiles : (int)blockIdx.y;
+  const int nsplit = second ? job.part[1].nsplit : job.part[0].nsplit;
+  double* G = second ? job.part[1].G : job.part[0].G;
+  double* gv = second ? job.part[1].gv : job.part[0].gv;
+  if (second) partials += job.pbase1;
+  const int ntiles = job.ntiles, n = job.n, nc = job.nc;
+  const int64_t ldg = job.ldg;
   int ti, tj;
   tile_of(tile, ti, tj);
   const int e = blockIdx.x * 256 + threadIdx.x;
@@ -247,24 +281,43 @@ void gram_set_cfg_bucket(int precision, int n_bucket, int k_bucket, GramCfg c) {
   g_cfg[((uint32_t)precision << 16) | ((uint32_t)n_bucket << 8) | (uint32_t)k_bucket] = c;
 }
 
-static void gram_plan_cfg(int64_t n, int64_t K, GramCfg cfg, int& tm, int& ntiles, int& nsplit, int64_t& klen) {
-  tm = cfg.tile;
-  const int nt = (int)((n + tm - 1) / tm);
-  ntiles = nt * (nt + 1) / 2;
+// K-split of one part: about cfg.workgroups workgroups over the tiles, at
+// least 256 rows per slice, whole slices per XCD.
+static void split_plan(int64_t K, int ntiles, int64_t target, int& nsplit, int64_t& klen) {
   if (K <= 0) {
     nsplit = kXcds;
     klen = kGK;
     return;
   }
-  const int64_t target = cfg.workgroups;
   int64_t want = (target + ntiles - 1) / ntiles;
-  int64_t maxs = (K + 255) / 256;               // at least 256 rows per slice
+  int64_t maxs = (K + 255) / 256;
   if (want > maxs) want = maxs;
   if (want < 1) want = 1;
-  want = (want + kXcds - 1) / kXcds * kXcds;  // whole K-slices per XCD
+  want = (want + kXcds - 1) / kXcds * kXcds;
   klen = (K + want - 1) / want;
   klen = (klen + kGK - 1) / kGK * kGK;
   nsplit = (int)want;  // trailing slices may be empty: they add zeros
+}
+
+static void gram_plan_cfg(int64_t nc, int64_t K, GramCfg cfg, int& tm, int& ntiles, int& nsplit, int64_t& klen) {
+  tm = cfg.tile;
+  const int nt = (int)((nc + tm - 1) / tm);
+  ntiles = nt * (nt + 1) / 2;
+  split_plan(K, ntiles, cfg.workgroups, nsplit, klen);
+}
+
+// Second part of a two-part launch: slices of about part 0's length.
+static void second_plan(int64_t K1, int64_t klen0, int& nsplit, int64_t& klen) {
+  if (K1 <= 0) {
+    nsplit = kXcds;
+    klen = kGK;
+    return;
+  }
+  int64_t want = (K1 + klen0 - 1) / klen0;
+  want = (want + kXcds - 1) / kXcds * kXcds;
+  klen = (K1 + want - 1) / want;
+  klen = (klen + kGK - 1) / kGK * kGK;
+  nsplit = (int)want;
 }
 
 static size_t plan_size(int64_t n, int64_t K, GramCfg c) {
@@ -283,32 +336,55 @@ size_t gram_partials_size(int64_t n, int64_t K) {
   return s;
 }
 
+size_t gram2_partials_size(int64_t n, int64_t K0, int64_t K1) {
+  int tm, ntiles, ns0, ns1;
+  int64_t kl0, kl1;
+  gram_plan_cfg(n + 1, K0, gram_cfg(ILS_PREC_FP64, n, K0), tm, ntiles, ns0, kl0);
+  second_plan(K1, kl0, ns1, kl1);
+  return std::max((size_t)ntiles * (ns0 + ns1) * tm * tm, gram_partials_size(n, K0));
+}
+
 size_t gram_partials_size_cfg(int64_t n, int64_t K, GramCfg c) { return plan_size(n, K, c); }
 
 template <typename T, int TM>
-static void gram_launch(hipStream_t s, int64_t K, int64_t n, const double* A, int64_t lda, const double* vb,
-                        T* partials, double* G, int64_t ldg, double* gv, hipEvent_t mid, int ntiles, int nsplit,
-                        int64_t klen) {
-  const int nc = (int)n + (vb ? 1 : 0);
-  hipLaunchKernelGGL((k_gram<T, TM>), dim3(ntiles * nsplit), dim3(256), 0, s, A, lda, K, (int)n, vb, klen,
-                     ntiles, partials);
+static void gram_launch(hipStream_t s, const GramJob& job, T* partials, hipEvent_t mid) {
+  const int wgs = job.ntiles * (job.part[0].nsplit + (job.nparts == 2 ? job.part[1].nsplit : 0));
+  hipLaunchKernelGGL((k_gram<T, TM>), dim3(wgs), dim3(256), 0, s, job, partials);
   if (mid) (void)hipEventRecord(mid, s);
-  hipLaunchKernelGGL((k_gram_finalize<T, TM>), dim3(TM * TM / 256, ntiles), dim3(256), 0, s, partials,
-                     nsplit, ntiles, (int)n, nc, G, ldg, gv);
+  hipLaunchKernelGGL((k_gram_finalize<T, TM>), dim3(TM * TM / 256, job.ntiles * job.nparts), dim3(256), 0, s,
+                     job, (const T*)partials);
 }
 
 // Gram of rows [0, K) of A with the configuration of (n, K); a border column
-// vb (K entries) adds A^T vb, written to gv.
+// vb (K entries) adds A^T vb, written to gv.  With a second block (K1 rows
+// at A1, border vb1) both products come from one launch pair.
 template <typename T>
 static void gram_run(hipStream_t s, int64_t K, int64_t n, const double* A, int64_t lda, const double* vb,
-                     T* partials, double* G, int64_t ldg, double* gv, hipEvent_t mid, GramCfg cfg) {
-  int tm, ntiles, nsplit;
-  int64_t klen;
-  gram_plan_cfg(n + (vb ? 1 : 0), K, cfg, tm, ntiles, nsplit, klen);
+                     T* partials, double* G, int64_t ldg, double* gv, hipEvent_t mid, GramCfg cfg,
+                     int64_t K1 = -1, const double* A1 = nullptr, const double* vb1 = nullptr,
+                     double* G1 = nullptr, double* gv1 = nullptr) {
+  GramJob job;
+  job.n = (int)n;
+  job.nc = (int)n + (vb ? 1 : 0);
+  job.lda = lda;
+  job.ldg = ldg;
+  int tm;
+  gram_plan_cfg(job.nc, K, cfg, tm, job.ntiles, job.part[0].nsplit, job.part[0].klen);
+  job.part[0] = GramPart{A, K, vb, job.part[0].klen, job.part[0].nsplit, G, gv};
+  job.nparts = K1 >= 0 ? 2 : 1;
+  job.wg1 = job.ntiles * job.part[0].nsplit;
+  job.pbase1 = (int64_t)job.ntiles * job.part[0].nsplit * tm * tm;
+  job.part[1] = job.part[0];
+  if (job.nparts == 2) {
+    int ns1;
+    int64_t kl1;
+    second_plan(K1, job.part[0].klen, ns1, kl1);
+    job.part[1] = GramPart{A1, K1, vb1, kl1, ns1, G1, gv1};
+  }
   if (tm == 128)
-    gram_launch<T, 128>(s, K, n, A, lda, vb, partials, G, ldg, gv, mid, ntiles, nsplit, klen);
+    gram_launch<T, 128>(s, job, partials, mid);
   else
-    gram_launch<T, 64>(s, K, n, A, lda, vb, partials, G, ldg, gv, mid, ntiles, nsplit, klen);
+    gram_launch<T, 64>(s, job, partials, mid);
 }
 
 void launch_gram_cfg(hipStream_t s, int precision, int64_t K, int64_t n, const double* A, int64_t lda,
@@ -322,6 +398,13 @@ void launch_gram_cfg(hipStream_t s, int precision, int64_t K, int64_t n, const d
 void launch_gram_f64(hipStream_t s, int64_t K, int64_t n, const double* A, int64_t lda,
                      double* partials, double* G, int64_t ldg, hipEvent_t mid, const double* vb, double* gv) {
   gram_run<double>(s, K, n, A, lda, vb, partials, G, ldg, gv, mid, gram_cfg(ILS_PREC_FP64, n, K));
+}
+
+void launch_gram2_f64(hipStream_t s, int64_t n, int64_t lda, int64_t ldg, double* partials, hipEvent_t mid,
+                      int64_t K0, const double* A0, const double* vb0, double* G0, double* gv0,
+                      int64_t K1, const double* A1, const double* vb1, double* G1, double* gv1) {
+  gram_run<double>(s, K0, n, A0, lda, vb0, partials, G0, ldg, gv0, mid, gram_cfg(ILS_PREC_FP64, n, K0), K1, A1,
+                   vb1, G1, gv1);
 }
 
 void launch_gram_f32(hipStream_t s, int64_t K, int64_t n, const double* A, int64_t lda,

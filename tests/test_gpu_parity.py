@@ -235,6 +235,29 @@ def test_sp_error_codes():
     assert info.status == rinfo.status
 
 
+@pytest.mark.parametrize("where", ["b1", "b2", "A1", "A2"])
+@pytest.mark.parametrize("val", [np.nan, np.inf])
+@pytest.mark.parametrize("form", [ils.FORM_PAPER, ils.FORM_CORRECTION])
+def test_sp_nonfinite_inputs(where, val, form):
+    """A non-finite entry anywhere in A or b gives ERR_NONFINITE and leaves x
+    untouched, in both forms (the paper form finds it through the bordered
+    Gram products, the correction form through the column pass)."""
+    P = W.dense_ils(70, 30, 20, ratio=0.5, seed=4)
+    A, b = P.A.copy(), P.b.copy()
+    if where == "b1":
+        b[5] = val
+    elif where == "b2":
+        b[P.p + 3] = val
+    elif where == "A1":
+        A[11, 7] = val
+    else:
+        A[P.p + 2, 19] = val
+    out = torch.full((P.n,), 7.0, dtype=torch.float64, device=DEV)
+    _, info = ils.sp_solve(devA(A), dev(b), P.p, out=out, form=form)
+    assert info.status == ils.ERR_NONFINITE
+    assert torch.all(out == 7.0)
+
+
 # ----------------------------------------------------------------- SP-RK-RGS (Algorithm 2)
 @pytest.mark.parametrize("form", [ils.FORM_PAPER, ils.FORM_CORRECTION])
 def test_rk_fixed_schedule_matches_oracle(prob, form):
