@@ -11,10 +11,11 @@
 //   k_gj_pivot : R = D^{-1} W[K, J] for every trailing 16-column strip J on
 //                the FP64 matrix cores, with D^{-1} already inverted; R
 //                replaces W[K, J].
-//   k_gj_update: W[I, J] -= W[I, K] R[K, J] for every 64-row tile I != K.
-//                The workgroup that updates the next pivot block (K+1, K+1)
-//                runs first and then inverts it, so the next step's pivot
-//                kernel finds D^{-1} ready (one block of lookahead).
+//   k_gj_update: W[I, J] -= W[I, K] R[K, J] for every 64-row tile I != K,
+//                about one workgroup per CU streaming its tiles.  Workgroup 0
+//                updates the next pivot block (K+1, K+1) alone and then
+//                inverts it, so the next step's pivot kernel finds D^{-1}
+//                ready (one block of lookahead).
 // The first pivot block is inverted by k_gj_inv0.  Columns left of the
 // trailing strips are never read again.
 #include "ils_common.hpp"
@@ -103,109 +104,162 @@ __global__ __launch_bounds__(kGjThreads) void k_gj_pivot(double* __restrict__ W,
   }
 }
 
-// W[I, J] -= W[I, K] R[K, J].  The MFMA computes the transposed tile
-// C^T[j][i] = sum_k R[k][j] W[i][k] so that a lane's four outputs run down a
-// column of W (coalesced column-major stores).  All global loads of the tile
-// are issued before their values are used.  Workgroup 0 is the tile of the
-// next pivot block; it inverts the updated block into dinv_next.
+// W[I, J] -= W[I, K] R[K, J] over the 64 x 64 tiles (I, J), I != K.  The
+// MFMA computes the transposed tile C^T[j][i] = sum_k R[k][j] W[i][k] so that
+// a lane's four outputs run down a column of W (coalesced column-major
+// stores).  Workgroup 0 takes the tile of the next pivot block alone and
+// then inverts the updated block into dinv_next (one block of lookahead).
+// The other workgroups (about one per CU) walk the remaining tiles with a
+// stride; the loads of a workgroup's next tile are in flight while the
+// matrix cores work on the current one, so the pass over W streams instead
+// of running load, multiply and store phases in lock step.
+constexpr int kUpdWgs = 256;
+
+struct UpdTile {
+  double wv[16], rv[16], cv[16];  // W[I, K] panel, R[K, J] panel, the tile itself
+};
+
 __global__ __launch_bounds__(kGjThreads) void k_gj_update(double* __restrict__ W, int64_t ldw, int64_t n,
                                                           int64_t k0, int nb, int64_t c0, int64_t ncols,
-                                                          int nstrips, double* __restrict__ dinv_next,
-                                                          int* bits) {
+                                                          int nstrips, int row_tiles,
+                                                          double* __restrict__ dinv_next, int* bits) {
   __shared__ double Ws[kNB][kNB + 1];  // Ws[i][k] = W[I0 + i, k0 + k]
   __shared__ double Rs[kNB][kNB + 1];  // Rs[j][k] = W[k0 + k, J0 + j]
   __shared__ InvBlk inv;
   if (*(volatile int*)bits) return;
-  // workgroup 0 <-> the tile (next pivot rows, first strip)
-  const int next_rt = (int)(k0 / kNB) + 1;
+  const int kt = (int)(k0 / kNB);
   const bool has_next = k0 + kNB < n;
-  int lin = blockIdx.x;
-  const int look = next_rt * nstrips;
-  if (has_next) {
-    if (lin == 0) lin = look;
-    else if (lin == look) lin = 0;
-  }
-  const int64_t cs = c0 + (int64_t)(lin % nstrips) * kNB;
-  const int64_t rs = (int64_t)(lin / nstrips) * kNB;
-  if (rs == k0) return;  // pivot rows already hold R
-  const bool lookahead = has_next && lin == look;
-  {
-    double wv[16], rv[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int e = threadIdx.x + q * kGjThreads, lo = e & (kNB - 1), hi = e >> 6;
-      wv[q] = (rs + lo < n && hi < nb) ? W[rs + lo + (k0 + hi) * ldw] : 0.0;
-      rv[q] = (lo < nb && cs + hi < ncols) ? W[k0 + lo + (cs + hi) * ldw] : 0.0;
-    }
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int e = threadIdx.x + q * kGjThreads, lo = e & (kNB - 1), hi = e >> 6;
-      Ws[lo][hi] = wv[q];
-      Rs[hi][lo] = rv[q];
-    }
-  }
-  __syncthreads();
+  // tile list: the non-pivot row tiles in order, nstrips tiles each; the
+  // lookahead tile (kt + 1, strip 0) sits at list position kt * nstrips and
+  // is swapped with position 0
+  const int ntile = (row_tiles - 1) * nstrips;
+  const int pla = kt * nstrips;
+  auto tile_at = [&](int L, int64_t& rs, int64_t& cs) {
+    if (has_next) L = L == 0 ? pla : (L == pla ? 0 : L);
+    const int rt = L / nstrips;
+    rs = (int64_t)(rt >= kt ? rt + 1 : rt) * kNB;
+    cs = c0 + (int64_t)(L % nstrips) * kNB;
+  };
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int jr = (w >> 1) * 32, ic = (w & 1) * 32;
   const int lr = lane & 15;
-  double cur[2][2][4];
+  auto load = [&](int64_t rs, int64_t cs, UpdTile& T) {
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+    for (int q = 0; q < 16; ++q) {
+      const int e = threadIdx.x + q * kGjThreads, lo = e & (kNB - 1), hi = e >> 6;
+      T.wv[q] = (rs + lo < n && hi < nb) ? W[rs + lo + (k0 + hi) * ldw] : 0.0;
+      T.rv[q] = (lo < nb && cs + hi < ncols) ? W[k0 + lo + (cs + hi) * ldw] : 0.0;
+    }
 #pragma unroll
-    for (int c = 0; c < 2; ++c)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int j = jr + a * 16 + (lane >> 4) + 4 * v, i = ic + c * 16 + lr;
-        cur[a][c][v] = (rs + i < n && cs + j < ncols) ? W[rs + i + (cs + j) * ldw] : 0.0;
-      }
-  v4d acc[2][2];
+      for (int c = 0; c < 2; ++c)
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+        for (int v = 0; v < 4; ++v) {
+          const int j = jr + a * 16 + (lane >> 4) + 4 * v, i = ic + c * 16 + lr;
+          T.cv[(a * 2 + c) * 4 + v] = (rs + i < n && cs + j < ncols) ? W[rs + i + (cs + j) * ldw] : 0.0;
+        }
+  };
+  auto stash = [&](const UpdTile& T) {
 #pragma unroll
-    for (int c = 0; c < 2; ++c) acc[a][c] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int q = 0; q < 16; ++q) {
+      const int e = threadIdx.x + q * kGjThreads, lo = e & (kNB - 1), hi = e >> 6;
+      Ws[lo][hi] = T.wv[q];
+      Rs[hi][lo] = T.rv[q];
+    }
+  };
+  // C = tile - W[I, K] R[K, J]; with keep, the result stays in cv
+  auto multiply_store = [&](int64_t rs, int64_t cs, UpdTile& T) {
+    v4d acc[2][2];
 #pragma unroll
-  for (int kk = 0; kk < kNB; kk += 4) {
-    const int kr = kk + (lane >> 4);
-    const double a0 = Rs[jr + lr][kr], a1 = Rs[jr + 16 + lr][kr];
-    const double b0 = Ws[ic + lr][kr], b1 = Ws[ic + 16 + lr][kr];
-    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
-  }
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+      for (int c = 0; c < 2; ++c) acc[a][c] = v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int c = 0; c < 2; ++c)
+    for (int kk = 0; kk < kNB; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      const double a0 = Rs[jr + lr][kr], a1 = Rs[jr + 16 + lr][kr];
+      const double b0 = Ws[ic + lr][kr], b1 = Ws[ic + 16 + lr][kr];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int j = jr + a * 16 + (lane >> 4) + 4 * v, i = ic + c * 16 + lr;
-        const double val = cur[a][c][v] - acc[a][c][v];
-        cur[a][c][v] = val;
-        if (rs + i < n && cs + j < ncols) W[rs + i + (cs + j) * ldw] = val;
-      }
-  if (!lookahead) return;
-  // invert the freshly updated next pivot block (identity outside it)
-  const int nbn = (int)(n - rs < kNB ? n - rs : kNB);
-  __syncthreads();  // everyone is done reading Ws
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+      for (int c = 0; c < 2; ++c)
 #pragma unroll
-    for (int c = 0; c < 2; ++c)
+        for (int v = 0; v < 4; ++v) {
+          const int j = jr + a * 16 + (lane >> 4) + 4 * v, i = ic + c * 16 + lr;
+          const double val = T.cv[(a * 2 + c) * 4 + v] - acc[a][c][v];
+          T.cv[(a * 2 + c) * 4 + v] = val;
+          if (rs + i < n && cs + j < ncols) W[rs + i + (cs + j) * ldw] = val;
+        }
+  };
+  if (has_next && blockIdx.x == 0) {
+    // the next pivot block: update, then invert (identity outside it)
+    int64_t rs, cs;
+    tile_at(0, rs, cs);
+    UpdTile T;
+    load(rs, cs, T);
+    stash(T);
+    __syncthreads();
+    multiply_store(rs, cs, T);
+    const int nbn = (int)(n - rs < kNB ? n - rs : kNB);
+    __syncthreads();  // everyone is done reading Ws
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int j = jr + a * 16 + (lane >> 4) + 4 * v, i = ic + c * 16 + lr;
-        Ws[i][j] = (i < nbn && j < nbn) ? cur[a][c][v] : (i == j ? 1.0 : 0.0);
-      }
-  __syncthreads();
-  if (!invert64_blk(&Ws[0][0], &Rs[0][0], inv)) {
-    if (threadIdx.x == 0) atomicOr(bits, kBitNotSpd);
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int j = jr + a * 16 + (lane >> 4) + 4 * v, i = ic + c * 16 + lr;
+          Ws[i][j] = (i < nbn && j < nbn) ? T.cv[(a * 2 + c) * 4 + v] : (i == j ? 1.0 : 0.0);
+        }
+    __syncthreads();
+    if (!invert64_blk(&Ws[0][0], &Rs[0][0], inv)) {
+      if (threadIdx.x == 0) atomicOr(bits, kBitNotSpd);
+      return;
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int e = threadIdx.x + q * kGjThreads;
+      dinv_next[e] = Ws[e >> 6][e & (kNB - 1)];
+    }
     return;
   }
-#pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int e = threadIdx.x + q * kGjThreads;
-    dinv_next[e] = Ws[e >> 6][e & (kNB - 1)];
+  // the other tiles, two register sets in turn
+  // workgroup b >= first takes list positions b, b + stride, ...
+  const int first = has_next ? 1 : 0;
+  const int stride = (int)gridDim.x - first;
+  int L = (int)blockIdx.x;
+  if (L >= ntile) return;
+  UpdTile X, Y;
+  int64_t rx, cx, ry, cy;
+  tile_at(L, rx, cx);
+  load(rx, cx, X);
+  while (true) {
+    stash(X);
+    const int L1 = L + stride;
+    if (L1 < ntile) {
+      tile_at(L1, ry, cy);
+      load(ry, cy, Y);
+    }
+    __syncthreads();
+    multiply_store(rx, cx, X);
+    __syncthreads();  // Ws, Rs free again
+    if (L1 >= ntile) break;
+    stash(Y);
+    L = L1 + stride;
+    if (L < ntile) {
+      tile_at(L, rx, cx);
+      load(rx, cx, X);
+    }
+    __syncthreads();
+    multiply_store(ry, cy, Y);
+    __syncthreads();
+    if (L >= ntile) break;
   }
 }
 
@@ -227,8 +281,12 @@ void launch_gj(hipStream_t s, int64_t n, int64_t nrhs, double* W, int64_t ldw, d
     const int pstrips = (int)((ncols - c0 + kPivCols - 1) / kPivCols);
     hipLaunchKernelGGL(k_gj_pivot, dim3(pstrips), dim3(kGjThreads), 0, s, W, ldw, k0, nb, c0, ncols,
                        (const double*)dcur, (const int*)bits);
-    hipLaunchKernelGGL(k_gj_update, dim3(strips * row_tiles), dim3(kGjThreads), 0, s, W, ldw, n, k0, nb,
-                       c0, ncols, strips, dnext, bits);
+    const int ntile = (row_tiles - 1) * strips;
+    if (ntile > 0) {
+      const int wgs = ntile < kUpdWgs ? ntile : kUpdWgs;
+      hipLaunchKernelGGL(k_gj_update, dim3(wgs), dim3(kGjThreads), 0, s, W, ldw, n, k0, nb, c0, ncols, strips,
+                         row_tiles, dnext, bits);
+    }
   }
 }
 
