@@ -168,8 +168,9 @@ __global__ __launch_bounds__(kGjThreads) void k_gj_update(double* __restrict__ W
       Rs[hi][lo] = T.rv[q];
     }
   };
-  // C = tile - W[I, K] R[K, J]; with keep, the result stays in cv
-  auto multiply_store = [&](int64_t rs, int64_t cs, UpdTile& T) {
+  // C = tile - W[I, K] R[K, J], kept in cv; columns j >= jmin of the tile
+  // are written to W
+  auto multiply_store = [&](int64_t rs, int64_t cs, UpdTile& T, int jmin) {
     v4d acc[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -194,19 +195,21 @@ __global__ __launch_bounds__(kGjThreads) void k_gj_update(double* __restrict__ W
           const int j = jr + a * 16 + (lane >> 4) + 4 * v, i = ic + c * 16 + lr;
           const double val = T.cv[(a * 2 + c) * 4 + v] - acc[a][c][v];
           T.cv[(a * 2 + c) * 4 + v] = val;
-          if (rs + i < n && cs + j < ncols) W[rs + i + (cs + j) * ldw] = val;
+          if (j >= jmin && rs + i < n && cs + j < ncols) W[rs + i + (cs + j) * ldw] = val;
         }
   };
   if (has_next && blockIdx.x == 0) {
-    // the next pivot block: update, then invert (identity outside it)
+    // the next pivot block: update, then invert (identity outside it); no
+    // later step reads the block itself, only its inverse, so only the
+    // tile's columns right of it (a short last block) go back to W
     int64_t rs, cs;
     tile_at(0, rs, cs);
+    const int nbn = (int)(n - rs < kNB ? n - rs : kNB);
     UpdTile T;
     load(rs, cs, T);
     stash(T);
     __syncthreads();
-    multiply_store(rs, cs, T);
-    const int nbn = (int)(n - rs < kNB ? n - rs : kNB);
+    multiply_store(rs, cs, T, nbn);
     __syncthreads();  // everyone is done reading Ws
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -247,7 +250,7 @@ __global__ __launch_bounds__(kGjThreads) void k_gj_update(double* __restrict__ W
       load(ry, cy, Y);
     }
     __syncthreads();
-    multiply_store(rx, cx, X);
+    multiply_store(rx, cx, X, 0);
     __syncthreads();  // Ws, Rs free again
     if (L1 >= ntile) break;
     stash(Y);
@@ -257,7 +260,7 @@ __global__ __launch_bounds__(kGjThreads) void k_gj_update(double* __restrict__ W
       load(rx, cx, X);
     }
     __syncthreads();
-    multiply_store(ry, cy, Y);
+    multiply_store(ry, cy, Y, 0);
     __syncthreads();
     if (L >= ntile) break;
   }
