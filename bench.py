@@ -29,6 +29,7 @@ PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 (vector = matrix)
 PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gram_fp64_20000x1000_traffic.json")
+TUNE_FILE = os.path.join(ROOT, "paper_2203_15340_amd", "tune", "gram_mi355x.json")
 GRAM_SRC = os.path.join(ROOT, "paper_2203_15340_amd", "csrc", "k_gram.hip")
 
 
@@ -39,6 +40,22 @@ def log(msg):
 def kernel_hash():
     with open(GRAM_SRC, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def tuned_entry(path, precision, n, K):
+    """The entry of a saved Gram launch table for (precision, n, K)."""
+    def bucket(x):
+        b = 0
+        while (1 << b) < x:
+            b += 1
+        return b
+    with open(path) as f:
+        for e in json.load(f)["entries"]:
+            if (e["kernel"] == "gram" and e["precision"] == precision and e["n_bucket"] == bucket(n)
+                    and e["k_bucket"] == bucket(K)):
+                return {"kernel": "gram", "precision": precision, "n": n, "K": K, "tile": e["tile"],
+                        "workgroups": e["workgroups"], "source": "file"}
+    return None
 
 
 def measured_traffic(tuned):
@@ -326,6 +343,9 @@ def main():
     ap.add_argument("--no-warm-start", action="store_true", help="skip the learned warm start")
     ap.add_argument("--no-sparse", action="store_true", help="skip the sparse workload")
     ap.add_argument("--no-tune", action="store_true", help="keep the default Gram configuration")
+    ap.add_argument("--tune", choices=("file", "live", "none"), default="file",
+                    help="Gram launch table: the committed MI355X table (file), a fresh sweep "
+                         "(live) or the built-in defaults (none)")
     ap.add_argument("--paper-tables", action="store_true",
                     help="also run the paper's own family at the paper's sizes (several GB, minutes)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -359,11 +379,17 @@ def main():
         log("calibration copy: 256 MiB read + 256 MiB written")
         del src, dst
     tuned = None
-    if not args.no_tune:
+    mode = "none" if args.no_tune else args.tune
+    if mode == "live":
         tuned = ils.tune_gram(A, 0, P.p, precision=ils.PREC_FP64, reps=5)
         ils.tune_gram(A, 0, P.p, precision=ils.PREC_MIXED, reps=5)
         ils.tune_gram(A, P.p, P.m, precision=ils.PREC_FP64, reps=5)  # A2^T A2
+        tuned["source"] = "live"
         log(f"autotuned A1 Gram: {tuned}")
+    elif mode == "file":
+        ils.tune_load(TUNE_FILE)
+        tuned = tuned_entry(TUNE_FILE, ils.PREC_FP64, P.n, P.p)
+        log(f"Gram launch table {TUNE_FILE}: A1 {tuned}")
     ils.set_profiling(True)
     log(f"warmup {args.warmup}")
     for _ in range(args.warmup):
