@@ -332,6 +332,43 @@ def bench_paper_tables(ils, W, np, torch):
     return out
 
 
+def probe_peaks(torch):
+    """What this box achieves with vendor kernels, next to the published
+    peaks: a 1 GiB device-to-device copy (HBM read + write) and an FP64
+    8192^3 matrix product (the platform BLAS).  Context for the roofline
+    fractions; the solver does not use either."""
+    out = {}
+    src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1.0)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / 10
+    out["hbm_copy_GB_per_s"] = 2 * src.numel() * 8 / (ms * 1e-3) / 1e9
+    del src, dst
+    a = torch.randn(8192, 8192, dtype=torch.float64, device="cuda")
+    b = torch.randn(8192, 8192, dtype=torch.float64, device="cuda")
+    c = a @ b
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(3):
+        c = a @ b
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / 3
+    out["fp64_gemm_TFLOP_per_s"] = 2 * 8192 ** 3 / (ms * 1e-3) / 1e12
+    out["note"] = "torch copy_ and FP64 matmul (platform BLAS) on the same GPU"
+    del a, b, c
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -348,6 +385,7 @@ def main():
                          "(live) or the built-in defaults (none)")
     ap.add_argument("--paper-tables", action="store_true",
                     help="also run the paper's own family at the paper's sizes (several GB, minutes)")
+    ap.add_argument("--no-peaks", action="store_true", help="skip the copy and FP64 GEMM peak probes")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 256 MiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -450,6 +488,12 @@ def main():
     if not args.no_sparse:
         sparse = bench_sparse(ils, W, np, torch)
     paper_tables = bench_paper_tables(ils, W, np, torch) if args.paper_tables else None
+    peaks = None
+    if not args.no_peaks:
+        log("peak probes")
+        peaks = probe_peaks(torch)
+        peaks["gram_frac_of_fp64_gemm"] = achieved / peaks["fp64_gemm_TFLOP_per_s"]
+        log(f"peaks: {peaks}")
 
     line = {
         "metric": "ILS solves/s to rel.err 1e-6, plain FP64 SP vs chosen form; % HBM/MFMA peak",
@@ -481,6 +525,7 @@ def main():
         "warm_start": warm,
         "sparse": sparse,
         "paper_tables": paper_tables,
+        "peaks_measured": peaks,
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")

@@ -393,13 +393,118 @@ __global__ __launch_bounds__(kScdThreads) void k_scd_inner(
   if (tid == 0) *steps_done += (t < count ? t : count);
 }
 
+// The same inner steps with r and diag(G1) held in LDS for n <= kScdMaxN:
+// one barrier per step (the wave partials are double-buffered; with norm
+// sampling the owner of r_j publishes it before the barrier), and only the
+// G1 column is read from global memory.  Sums, argmax and update are taken
+// in the same order as k_scd_inner, so both give the same iterates.
+__global__ __launch_bounds__(kScdThreads) void k_scd_inner_lds(
+    const double* __restrict__ G1, int64_t ldg, int64_t n, double* __restrict__ r,
+    double* __restrict__ beta, const uint32_t* __restrict__ mask, int64_t mask_words,
+    const int* __restrict__ jpre, int norm_mode, int64_t count, int check, double itol2,
+    const double* tn2, int* inner_done, int64_t* steps_done, const int* outer_done) {
+  if (*(volatile const int*)inner_done || *(volatile const int*)outer_done) return;
+  __shared__ double rs[kScdMaxN];
+  __shared__ double dg[kScdMaxN];
+  __shared__ double red_n[2][kScdThreads / kWave];
+  __shared__ double red_v[2][kScdThreads / kWave];
+  __shared__ double red_r[2][kScdThreads / kWave];
+  __shared__ int red_i[2][kScdThreads / kWave];
+  __shared__ double rj_pub[2];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int64_t sidx = tid; sidx < n; sidx += kScdThreads) {
+    rs[sidx] = r[sidx];
+    dg[sidx] = G1[sidx * ldg + sidx];
+  }
+  __syncthreads();
+  const double stop2 = itol2 * (*tn2);
+  int64_t t = 0;
+  for (; t <= count; ++t) {
+    const int par = (int)(t & 1);
+    const uint32_t* mrow = mask + t * mask_words;
+    const int jn = (norm_mode && t < count) ? jpre[t] : -1;
+    double nrm = 0.0, bv = -1.0, br = 0.0;
+    int bi = 0x7FFFFFFF;
+    for (int64_t sidx = tid; sidx < n; sidx += kScdThreads) {
+      const double rv = rs[sidx];
+      nrm += rv * rv;
+      if (sidx == jn) rj_pub[par] = rv;
+      if (!norm_mode && t < count && ((mrow[sidx >> 5] >> (sidx & 31)) & 1u)) {
+        const double av = fabs(rv);
+        if (better(av, (int)sidx, bv, bi)) {
+          bv = av;
+          br = rv;
+          bi = (int)sidx;
+        }
+      }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      nrm += __shfl_xor(nrm, off, kWave);
+      const double ov = __shfl_xor(bv, off, kWave), orr = __shfl_xor(br, off, kWave);
+      const int oi = __shfl_xor(bi, off, kWave);
+      if (better(ov, oi, bv, bi)) {
+        bv = ov;
+        br = orr;
+        bi = oi;
+      }
+    }
+    if (lane == 0) {
+      red_n[par][wv] = nrm;
+      red_v[par][wv] = bv;
+      red_r[par][wv] = br;
+      red_i[par][wv] = bi;
+    }
+    __syncthreads();
+    nrm = red_n[par][0];
+    bv = red_v[par][0];
+    br = red_r[par][0];
+    bi = red_i[par][0];
+    for (int q = 1; q < kScdThreads / kWave; ++q) {
+      nrm += red_n[par][q];
+      if (better(red_v[par][q], red_i[par][q], bv, bi)) {
+        bv = red_v[par][q];
+        br = red_r[par][q];
+        bi = red_i[par][q];
+      }
+    }
+    if (check && nrm <= stop2) {
+      if (tid == 0) *inner_done = 1;
+      break;
+    }
+    if (t == count) break;
+    int j;
+    double rj;
+    if (norm_mode) {
+      j = jn;
+      rj = (j >= 0 && j < n) ? rj_pub[par] : 0.0;
+    } else {
+      j = bi;
+      rj = br;
+    }
+    if (j < 0 || j >= n) break;  // no finite candidate: the outer update flags it
+    const double gam = rj / dg[j];
+    const double* col = G1 + (int64_t)j * ldg;
+    for (int64_t sidx = tid; sidx < n; sidx += kScdThreads) rs[sidx] -= gam * col[sidx];
+    if (tid == 0) beta[j] += gam;
+  }
+  __syncthreads();
+  for (int64_t sidx = tid; sidx < n; sidx += kScdThreads) r[sidx] = rs[sidx];
+  if (tid == 0) *steps_done += (t < count ? t : count);
+}
+
 void launch_scd_inner(hipStream_t st, const double* G1, int64_t ldg, int64_t n, double* r, double* beta,
                       const uint32_t* mask, int64_t mask_words, const int* jpre, int norm_mode,
                       int64_t count, int check, double itol2, const double* tn2, int* inner_done,
                       int64_t* steps_done, const int* outer_done) {
-  hipLaunchKernelGGL(k_scd_inner, dim3(1), dim3(kScdThreads), 0, st, G1, ldg, n, r, beta, mask,
-                     mask_words, jpre, norm_mode, count, check, itol2, tn2, inner_done, steps_done,
-                     outer_done);
+  if (n <= kScdMaxN)
+    hipLaunchKernelGGL(k_scd_inner_lds, dim3(1), dim3(kScdThreads), 0, st, G1, ldg, n, r, beta, mask,
+                       mask_words, jpre, norm_mode, count, check, itol2, tn2, inner_done, steps_done,
+                       outer_done);
+  else
+    hipLaunchKernelGGL(k_scd_inner, dim3(1), dim3(kScdThreads), 0, st, G1, ldg, n, r, beta, mask,
+                       mask_words, jpre, norm_mode, count, check, itol2, tn2, inner_done, steps_done,
+                       outer_done);
 }
 
 // ------------------------------------------------------------------ outer helpers
