@@ -418,18 +418,37 @@ __global__ __launch_bounds__(kScdThreads) void k_scd_inner_lds(
   }
   __syncthreads();
   const double stop2 = itol2 * (*tn2);
+  // the mask words of this thread's entries for the current step, loaded
+  // one step ahead (they do not depend on r)
+  constexpr int kPer = kScdMaxN / kScdThreads;
+  uint32_t mw[kPer], mnext[kPer];
+  int jnext = -1;
+  auto fetch_mask = [&](int64_t tt) {
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int64_t sidx = tid + (int64_t)u * kScdThreads;
+      mnext[u] = (!norm_mode && tt < count && sidx < n) ? mask[tt * mask_words + (sidx >> 5)] : 0u;
+    }
+    jnext = (norm_mode && tt < count) ? jpre[tt] : -1;
+  };
+  fetch_mask(0);
   int64_t t = 0;
   for (; t <= count; ++t) {
     const int par = (int)(t & 1);
-    const uint32_t* mrow = mask + t * mask_words;
-    const int jn = (norm_mode && t < count) ? jpre[t] : -1;
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) mw[u] = mnext[u];
+    const int jn = jnext;
+    fetch_mask(t + 1);
     double nrm = 0.0, bv = -1.0, br = 0.0;
     int bi = 0x7FFFFFFF;
-    for (int64_t sidx = tid; sidx < n; sidx += kScdThreads) {
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int64_t sidx = tid + (int64_t)u * kScdThreads;
+      if (sidx >= n) break;
       const double rv = rs[sidx];
       nrm += rv * rv;
       if (sidx == jn) rj_pub[par] = rv;
-      if (!norm_mode && t < count && ((mrow[sidx >> 5] >> (sidx & 31)) & 1u)) {
+      if (!norm_mode && t < count && ((mw[u] >> (sidx & 31)) & 1u)) {
         const double av = fabs(rv);
         if (better(av, (int)sidx, bv, bi)) {
           bv = av;
