@@ -8,7 +8,7 @@
 //      accumulation in the mixed form), and A2^T A2 in the paper form;
 //   3. block Gauss-Jordan on [A1^T A1 | A2^T A2 | g] (paper form, giving B, c
 //      of Alg. 1) or [A1^T A1 | I] (correction form, giving P), 64-wide blocks,
-//      pivot blocks inverted in registers;
+//      pivot blocks inverted by 16 x 16 blocks (invert64_blk);
 //   4. outer steps x_{k+1} = B x_k + c, or x_{k+1} = x_k + P A^T J (b - A x_k)
 //      with the residual in FP64 (iterative refinement in the mixed form),
 //      with the stop test of the single-problem solver.
@@ -41,8 +41,7 @@ struct Smem {
     } g32;
     double vec[2 * kNB * (kNB + 1)];  // iteration phase: t (m), x_k (n)
   } u;
-  double rowbuf[2][kRowBuf];
-  double colbuf[2][kNB];
+  InvBlk inv;
   double red[2][NT / kWave];
   int id;
 };
@@ -192,14 +191,8 @@ __device__ __attribute__((noinline)) bool wg_gauss_jordan(double* W, int64_t ldw
       }
     }
     __syncthreads();
-    const int r = t >> 2, g = t & 3;
-    double a[16];
-#pragma unroll
-    for (int v = 0; v < 16; ++v) a[v] = s.u.gj.T0[r][16 * g + v];
-    if (!invert64(a, r, g, s.rowbuf, s.colbuf)) return false;
-    __syncthreads();
-#pragma unroll
-    for (int v = 0; v < 16; ++v) s.u.gj.T0[r][16 * g + v] = a[v];  // D^{-1}, row-major
+    // T0 <- D^{-1} (row-major); T1 serves as the second inversion buffer
+    if (!invert64_blk(&s.u.gj.T0[0][0], &s.u.gj.T1[0][0], s.inv)) return false;
     // pivot rows: R = D^{-1} X for every trailing strip (R^T formed so stores run down columns)
     for (int cs = k0 + nb; cs < ncols; cs += kNB) {
       __syncthreads();
