@@ -109,10 +109,10 @@ __global__ __launch_bounds__(kGjThreads) void k_gj_pivot(double* __restrict__ W,
 // a lane's four outputs run down a column of W (coalesced column-major
 // stores).  Workgroup 0 takes the tile of the next pivot block alone and
 // then inverts the updated block into dinv_next (one block of lookahead).
-// The other workgroups (about one per CU) walk the remaining tiles with a
-// stride; the loads of a workgroup's next tile are in flight while the
-// matrix cores work on the current one, so the pass over W streams instead
-// of running load, multiply and store phases in lock step.
+// The other workgroups (about one per CU) each walk a contiguous run of the
+// remaining tiles; the loads of a workgroup's next tile are in flight while
+// the matrix cores work on the current one, so the pass over W streams
+// instead of running load, multiply and store phases in lock step.
 constexpr int kUpdWgs = 256;
 
 struct UpdTile {
@@ -143,11 +143,13 @@ __global__ __launch_bounds__(kGjThreads) void k_gj_update(double* __restrict__ W
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int jr = (w >> 1) * 32, ic = (w & 1) * 32;
   const int lr = lane & 15;
-  auto load = [&](int64_t rs, int64_t cs, UpdTile& T) {
+  // with_w: also the W[I, K] panel (skipped when the previous tile had the
+  // same row block, whose panel is still in LDS)
+  auto load = [&](int64_t rs, int64_t cs, UpdTile& T, bool with_w) {
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int e = threadIdx.x + q * kGjThreads, lo = e & (kNB - 1), hi = e >> 6;
-      T.wv[q] = (rs + lo < n && hi < nb) ? W[rs + lo + (k0 + hi) * ldw] : 0.0;
+      if (with_w) T.wv[q] = (rs + lo < n && hi < nb) ? W[rs + lo + (k0 + hi) * ldw] : 0.0;
       T.rv[q] = (lo < nb && cs + hi < ncols) ? W[k0 + lo + (cs + hi) * ldw] : 0.0;
     }
 #pragma unroll
@@ -160,11 +162,11 @@ __global__ __launch_bounds__(kGjThreads) void k_gj_update(double* __restrict__ W
           T.cv[(a * 2 + c) * 4 + v] = (rs + i < n && cs + j < ncols) ? W[rs + i + (cs + j) * ldw] : 0.0;
         }
   };
-  auto stash = [&](const UpdTile& T) {
+  auto stash = [&](const UpdTile& T, bool with_w) {
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int e = threadIdx.x + q * kGjThreads, lo = e & (kNB - 1), hi = e >> 6;
-      Ws[lo][hi] = T.wv[q];
+      if (with_w) Ws[lo][hi] = T.wv[q];
       Rs[hi][lo] = T.rv[q];
     }
   };
@@ -206,8 +208,8 @@ __global__ __launch_bounds__(kGjThreads) void k_gj_update(double* __restrict__ W
     tile_at(0, rs, cs);
     const int nbn = (int)(n - rs < kNB ? n - rs : kNB);
     UpdTile T;
-    load(rs, cs, T);
-    stash(T);
+    load(rs, cs, T, true);
+    stash(T, true);
     __syncthreads();
     multiply_store(rs, cs, T, nbn);
     __syncthreads();  // everyone is done reading Ws
@@ -232,37 +234,44 @@ __global__ __launch_bounds__(kGjThreads) void k_gj_update(double* __restrict__ W
     }
     return;
   }
-  // the other tiles, two register sets in turn
-  // workgroup b >= first takes list positions b, b + stride, ...
+  // the other tiles: workgroup b >= first takes a contiguous run of list
+  // positions (mostly one row block, so the W[I, K] panel is loaded once per
+  // row), two register sets in turn
   const int first = has_next ? 1 : 0;
-  const int stride = (int)gridDim.x - first;
-  int L = (int)blockIdx.x;
-  if (L >= ntile) return;
+  const int nw = (int)gridDim.x - first;
+  if (nw <= 0) return;
+  const int cnt = ntile - first;
+  const int chunk = (cnt + nw - 1) / nw;
+  int L = first + ((int)blockIdx.x - first) * chunk;
+  const int Lend = L + chunk < ntile ? L + chunk : ntile;
+  if (L >= Lend) return;
   UpdTile X, Y;
-  int64_t rx, cx, ry, cy;
+  int64_t rx, cx, ry, cy, wrow = -1;
   tile_at(L, rx, cx);
-  load(rx, cx, X);
+  load(rx, cx, X, true);
   while (true) {
-    stash(X);
-    const int L1 = L + stride;
-    if (L1 < ntile) {
+    stash(X, rx != wrow);
+    wrow = rx;
+    const int L1 = L + 1;
+    if (L1 < Lend) {
       tile_at(L1, ry, cy);
-      load(ry, cy, Y);
+      load(ry, cy, Y, ry != rx);
     }
     __syncthreads();
     multiply_store(rx, cx, X, 0);
     __syncthreads();  // Ws, Rs free again
-    if (L1 >= ntile) break;
-    stash(Y);
-    L = L1 + stride;
-    if (L < ntile) {
+    if (L1 >= Lend) break;
+    stash(Y, ry != wrow);
+    wrow = ry;
+    L = L1 + 1;
+    if (L < Lend) {
       tile_at(L, rx, cx);
-      load(rx, cx, X);
+      load(rx, cx, X, rx != ry);
     }
     __syncthreads();
     multiply_store(ry, cy, Y, 0);
     __syncthreads();
-    if (L >= ntile) break;
+    if (L >= Lend) break;
   }
 }
 
