@@ -96,7 +96,8 @@ __device__ inline double block_sum2(double v, Smem& s, int which) {
 // are issued before the matrix-core work on the current one.  One workgroup
 // streams a whole problem alone, so loads in flight, not bandwidth, set the
 // rate.
-template <typename T>
+// (OCC: one copy per kernel register budget, see k_batched)
+template <typename T, int OCC>
 __device__ __attribute__((noinline)) void wg_gram(const double* __restrict__ A, int64_t lda, int K, int n, double* W, int64_t ldw,
                         Smem& s) {
   typedef typename Mma<T>::acc_t acc_t;
@@ -171,6 +172,7 @@ __device__ __attribute__((noinline)) void wg_gram(const double* __restrict__ A, 
 
 // Block Gauss-Jordan on W = [G | R] (n x ncols), 64-wide blocks, inside one
 // workgroup.  Returns false when a pivot block is not positive definite.
+template <int OCC>
 __device__ __attribute__((noinline)) bool wg_gauss_jordan(double* W, int64_t ldw, int n, int ncols, Smem& s) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, lr = lane & 15;
   const int hq = (w >> 1) * 32, lq = (w & 1) * 32;
@@ -310,6 +312,7 @@ __device__ __attribute__((noinline)) bool wg_gauss_jordan(double* W, int64_t ldw
 }
 
 // t = b - A x (x staged in LDS), then r = A^T J t; t lives in LDS.
+template <int OCC>
 __device__ __attribute__((noinline)) void wg_residual(const double* __restrict__ A, int64_t lda, int p, int q, int n,
                             const double* __restrict__ b, const double* xs, double* ts, double* r) {
   const int m = p + q, t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -335,7 +338,7 @@ __device__ __attribute__((noinline)) void wg_residual(const double* __restrict__
   __syncthreads();
 }
 
-template <typename T>
+template <typename T, int OCC>
 __device__ void solve_one(const BatchArgs& a, const BatchProblem& P, double* slot, Smem& s,
                           BatchResult& out) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -389,10 +392,10 @@ __device__ void solve_one(const BatchArgs& a, const BatchProblem& P, double* slo
     xr2 = block_sum2(xr2, s, 1);
   }
   // 2. [A1^T A1 | A2^T A2 | g] or [A1^T A1 | I]
-  wg_gram<T>(P.A, lda, p, n, W, ldw, s);
+  wg_gram<T, OCC>(P.A, lda, p, n, W, ldw, s);
   int nrhs;
   if (paper) {
-    wg_gram<double>(P.A + p, lda, q, n, W + (int64_t)n * ldw, ldw, s);
+    wg_gram<double, OCC>(P.A + p, lda, q, n, W + (int64_t)n * ldw, ldw, s);
     for (int j = t; j < n; j += NT) W[j + (int64_t)2 * n * ldw] = g[j];
     nrhs = n + 1;
   } else {
@@ -404,7 +407,7 @@ __device__ void solve_one(const BatchArgs& a, const BatchProblem& P, double* slo
   }
   __syncthreads();
   // 3. elimination
-  if (!wg_gauss_jordan(W, ldw, n, n + nrhs, s)) {
+  if (!wg_gauss_jordan<OCC>(W, ldw, n, n + nrhs, s)) {
     out.status = ILS_ERR_NOT_SPD;
     return;
   }
@@ -425,7 +428,7 @@ __device__ void solve_one(const BatchArgs& a, const BatchProblem& P, double* slo
     if (need_r) {
       for (int j = t; j < n; j += NT) xs[j] = xk[j];
       __syncthreads();
-      wg_residual(P.A, lda, p, q, n, P.b, xs, ts, r);
+      wg_residual<OCC>(P.A, lda, p, q, n, P.b, xs, ts, r);
     }
     double mp = 0.0;
     for (int j = t; j < n; j += NT) {
@@ -469,8 +472,12 @@ __device__ void solve_one(const BatchArgs& a, const BatchProblem& P, double* slo
   out.metric = metric;
 }
 
-template <typename T>
-__global__ __launch_bounds__(NT) void k_batched(BatchArgs a) {
+// OCC = workgroups per CU the register budget is cut for: 2 for the
+// correction form, whose outer steps stream A (two resident workgroups hide
+// more memory latency), 1 for the paper form, whose Gram and elimination
+// would spill at that budget.
+template <typename T, int OCC>
+__global__ __launch_bounds__(NT, OCC) void k_batched(BatchArgs a) {
   __shared__ Smem s;
   double* slot = a.work + (int64_t)blockIdx.x * a.slot_doubles;
   for (;;) {
@@ -482,7 +489,7 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a) {
     const int idx = a.order[id];
     BatchResult res;
     res.status = ILS_OK;
-    solve_one<T>(a, a.probs[idx], slot, s, res);
+    solve_one<T, OCC>(a, a.probs[idx], slot, s, res);
     if (threadIdx.x == 0) a.res[idx] = res;
     __syncthreads();
   }
@@ -499,10 +506,13 @@ __global__ __launch_bounds__(NT) void k_batched(BatchArgs a) {
 }  // namespace
 
 void launch_batched(hipStream_t s, const BatchArgs& a, int workgroups) {
-  if (a.precision == ILS_PREC_MIXED)
-    hipLaunchKernelGGL(k_batched<float>, dim3(workgroups), dim3(NT), 0, s, a);
+  const bool corr = a.form == ILS_FORM_CORRECTION;
+  if (a.precision == ILS_PREC_MIXED)  // mixed implies the correction form
+    hipLaunchKernelGGL((k_batched<float, 2>), dim3(workgroups), dim3(NT), 0, s, a);
+  else if (corr)
+    hipLaunchKernelGGL((k_batched<double, 2>), dim3(workgroups), dim3(NT), 0, s, a);
   else
-    hipLaunchKernelGGL(k_batched<double>, dim3(workgroups), dim3(NT), 0, s, a);
+    hipLaunchKernelGGL((k_batched<double, 1>), dim3(workgroups), dim3(NT), 0, s, a);
 }
 
 }  // namespace ils
