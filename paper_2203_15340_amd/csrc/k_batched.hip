@@ -32,7 +32,7 @@ struct Smem {
       double T1[kNB][kNB + 1];
     } gj;
     struct {
-      double As[kNB][kNB + 1];  // As[column][k] of the current 64-row stage
+      double As[kNB][kNB + 1];  // As[column][k] of the current 32-row stage
       double Bs[kNB][kNB + 1];
     } g64;
     struct {
@@ -90,20 +90,22 @@ __device__ inline double block_sum2(double v, Smem& s, int which) {
 }
 
 // G = A[0:K, :]^T A[0:K, :] (n x n, full) into W (ldw), one 64 x 64 lower tile
-// at a time.  Each tile streams K in stages of 64 rows: a thread holds 16
-// values of each operand panel in flight (one 512-byte column segment per
-// wave per load), then the stage goes through LDS and the next stage's loads
-// are issued before the matrix-core work on the current one.  One workgroup
-// streams a whole problem alone, so loads in flight, not bandwidth, set the
-// rate.
-// (OCC: one copy per kernel register budget, see k_batched)
-template <typename T, int OCC>
+// at a time.  Each tile streams K in stages of 32 rows: a thread holds 8
+// values of each operand panel in flight (one 256-byte column segment per
+// half wave per load), then the stage goes through LDS and the next stage's
+// loads are issued before the matrix-core work on the current one.  One
+// workgroup streams a whole problem, so loads in flight, not bandwidth, set
+// the rate; the second workgroup on the CU covers its waits.
+template <typename T>
 __device__ __attribute__((noinline)) void wg_gram(const double* __restrict__ A, int64_t lda, int K, int n, double* W, int64_t ldw,
                         Smem& s) {
   typedef typename Mma<T>::acc_t acc_t;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wr = (w >> 1) * 32, wc = (w & 1) * 32, lr = lane & 15;
-  const int lk = t & 63, lc = t >> 6;
+  // 32-row stages (8 loads per operand per thread): two workgroups share a
+  // CU, so registers are scarce and the other workgroup hides latency
+  constexpr int SR = 32, NLD = SR / 4, CG = NT / SR;
+  const int lk = t % SR, lc = t / SR;
   const int nt = (n + kNB - 1) / kNB;
   T(*As)[kNB + 1] = stage_a<T>(s);
   T(*Bs)[kNB + 1] = stage_b<T>(s);
@@ -118,30 +120,30 @@ __device__ __attribute__((noinline)) void wg_gram(const double* __restrict__ A, 
       for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int c = 0; c < 2; ++c) acc[a][c] = acc_t{};
-      T ra[16], rb[16];
+      T ra[NLD], rb[NLD];
       auto fetch = [&](int k0) {
         const int k = k0 + lk;
         const bool kin = k < K;
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-          const int c = lc + 4 * q;
+        for (int q = 0; q < NLD; ++q) {
+          const int c = lc + CG * q;
           ra[q] = (kin && c < ci) ? (T)Ai[k + (int64_t)c * lda] : (T)0;
           if (!diag) rb[q] = (kin && c < cj) ? (T)Aj[k + (int64_t)c * lda] : (T)0;
         }
       };
       if (K > 0) fetch(0);
-      for (int k0 = 0; k0 < K; k0 += kNB) {
+      for (int k0 = 0; k0 < K; k0 += SR) {
         __syncthreads();  // LDS free (previous stage, tile or phase)
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-          As[lc + 4 * q][lk] = ra[q];
-          if (!diag) Bs[lc + 4 * q][lk] = rb[q];
+        for (int q = 0; q < NLD; ++q) {
+          As[lc + CG * q][lk] = ra[q];
+          if (!diag) Bs[lc + CG * q][lk] = rb[q];
         }
         __syncthreads();
-        if (k0 + kNB < K) fetch(k0 + kNB);
+        if (k0 + SR < K) fetch(k0 + SR);
         T(*Bp)[kNB + 1] = diag ? As : Bs;
 #pragma unroll
-        for (int kk = 0; kk < kNB; kk += 4) {
+        for (int kk = 0; kk < SR; kk += 4) {
           const int kr = kk + (lane >> 4);
           const T a0 = As[wr + lr][kr], a1 = As[wr + 16 + lr][kr];
           const T b0 = Bp[wc + lr][kr], b1 = Bp[wc + 16 + lr][kr];
@@ -172,7 +174,6 @@ __device__ __attribute__((noinline)) void wg_gram(const double* __restrict__ A, 
 
 // Block Gauss-Jordan on W = [G | R] (n x ncols), 64-wide blocks, inside one
 // workgroup.  Returns false when a pivot block is not positive definite.
-template <int OCC>
 __device__ __attribute__((noinline)) bool wg_gauss_jordan(double* W, int64_t ldw, int n, int ncols, Smem& s) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, lr = lane & 15;
   const int hq = (w >> 1) * 32, lq = (w & 1) * 32;
@@ -312,7 +313,6 @@ __device__ __attribute__((noinline)) bool wg_gauss_jordan(double* W, int64_t ldw
 }
 
 // t = b - A x (x staged in LDS), then r = A^T J t; t lives in LDS.
-template <int OCC>
 __device__ __attribute__((noinline)) void wg_residual(const double* __restrict__ A, int64_t lda, int p, int q, int n,
                             const double* __restrict__ b, const double* xs, double* ts, double* r) {
   const int m = p + q, t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -338,7 +338,7 @@ __device__ __attribute__((noinline)) void wg_residual(const double* __restrict__
   __syncthreads();
 }
 
-template <typename T, int OCC>
+template <typename T>
 __device__ void solve_one(const BatchArgs& a, const BatchProblem& P, double* slot, Smem& s,
                           BatchResult& out) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -392,10 +392,10 @@ __device__ void solve_one(const BatchArgs& a, const BatchProblem& P, double* slo
     xr2 = block_sum2(xr2, s, 1);
   }
   // 2. [A1^T A1 | A2^T A2 | g] or [A1^T A1 | I]
-  wg_gram<T, OCC>(P.A, lda, p, n, W, ldw, s);
+  wg_gram<T>(P.A, lda, p, n, W, ldw, s);
   int nrhs;
   if (paper) {
-    wg_gram<double, OCC>(P.A + p, lda, q, n, W + (int64_t)n * ldw, ldw, s);
+    wg_gram<double>(P.A + p, lda, q, n, W + (int64_t)n * ldw, ldw, s);
     for (int j = t; j < n; j += NT) W[j + (int64_t)2 * n * ldw] = g[j];
     nrhs = n + 1;
   } else {
@@ -407,7 +407,7 @@ __device__ void solve_one(const BatchArgs& a, const BatchProblem& P, double* slo
   }
   __syncthreads();
   // 3. elimination
-  if (!wg_gauss_jordan<OCC>(W, ldw, n, n + nrhs, s)) {
+  if (!wg_gauss_jordan(W, ldw, n, n + nrhs, s)) {
     out.status = ILS_ERR_NOT_SPD;
     return;
   }
@@ -428,7 +428,7 @@ __device__ void solve_one(const BatchArgs& a, const BatchProblem& P, double* slo
     if (need_r) {
       for (int j = t; j < n; j += NT) xs[j] = xk[j];
       __syncthreads();
-      wg_residual<OCC>(P.A, lda, p, q, n, P.b, xs, ts, r);
+      wg_residual(P.A, lda, p, q, n, P.b, xs, ts, r);
     }
     double mp = 0.0;
     for (int j = t; j < n; j += NT) {
@@ -472,12 +472,10 @@ __device__ void solve_one(const BatchArgs& a, const BatchProblem& P, double* slo
   out.metric = metric;
 }
 
-// OCC = workgroups per CU the register budget is cut for: 2 for the
-// correction form, whose outer steps stream A (two resident workgroups hide
-// more memory latency), 1 for the paper form, whose Gram and elimination
-// would spill at that budget.
-template <typename T, int OCC>
-__global__ __launch_bounds__(NT, OCC) void k_batched(BatchArgs a) {
+// Two workgroups per CU: the register budget is cut to fit them (the helper
+// functions spill a little at entry), and each hides the other's latency.
+template <typename T>
+__global__ __launch_bounds__(NT, 2) void k_batched(BatchArgs a) {
   __shared__ Smem s;
   double* slot = a.work + (int64_t)blockIdx.x * a.slot_doubles;
   for (;;) {
@@ -489,7 +487,7 @@ __global__ __launch_bounds__(NT, OCC) void k_batched(BatchArgs a) {
     const int idx = a.order[id];
     BatchResult res;
     res.status = ILS_OK;
-    solve_one<T, OCC>(a, a.probs[idx], slot, s, res);
+    solve_one<T>(a, a.probs[idx], slot, s, res);
     if (threadIdx.x == 0) a.res[idx] = res;
     __syncthreads();
   }
@@ -506,13 +504,10 @@ __global__ __launch_bounds__(NT, OCC) void k_batched(BatchArgs a) {
 }  // namespace
 
 void launch_batched(hipStream_t s, const BatchArgs& a, int workgroups) {
-  const bool corr = a.form == ILS_FORM_CORRECTION;
-  if (a.precision == ILS_PREC_MIXED)  // mixed implies the correction form
-    hipLaunchKernelGGL((k_batched<float, 2>), dim3(workgroups), dim3(NT), 0, s, a);
-  else if (corr)
-    hipLaunchKernelGGL((k_batched<double, 2>), dim3(workgroups), dim3(NT), 0, s, a);
+  if (a.precision == ILS_PREC_MIXED)
+    hipLaunchKernelGGL(k_batched<float>, dim3(workgroups), dim3(NT), 0, s, a);
   else
-    hipLaunchKernelGGL((k_batched<double, 1>), dim3(workgroups), dim3(NT), 0, s, a);
+    hipLaunchKernelGGL(k_batched<double>, dim3(workgroups), dim3(NT), 0, s, a);
 }
 
 }  // namespace ils
