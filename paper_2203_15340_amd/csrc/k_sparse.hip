@@ -292,9 +292,10 @@ void launch_csr_residual(hipStream_t s, const ils_csr& A, const double* b, const
 // One workgroup per column j of G = A_part^T A_part (lower triangle k >= j,
 // mirrored): for every entry a_ij of column j in the part, add a_ij * a_ik
 // for the entries a_ik (k >= j) of CSR row i into an LDS accumulator of
-// length n.  Each wavefront owns a private accumulator and takes every
-// `copies`-th entry of the column in row order; the copies are added in a
-// fixed order, so the result does not depend on scheduling.
+// length n.  Each wavefront owns a private accumulator and takes 64 entries
+// of the column at a time, one CSR row per lane (LDS atomics; lanes that hit
+// the same k in one instruction are applied by the LDS in a fixed order);
+// the copies are added in a fixed order.
 __global__ void k_sparse_gram(int64_t n, int second, const int64_t* __restrict__ rowptr,
                               const int32_t* __restrict__ colidx, const double* __restrict__ val,
                               const int64_t* __restrict__ colptr, const int32_t* __restrict__ rowidx,
@@ -309,11 +310,14 @@ __global__ void k_sparse_gram(int64_t n, int second, const int64_t* __restrict__
   const int64_t base = colptr[j], L = colptr[j + 1] - base, l1 = a1len[j];
   const int64_t e0 = second ? l1 : 0, e1 = second ? L : l1;
   double* my = acc + (int64_t)w * n;
-  for (int64_t e = e0 + w; e < e1; e += copies) {
-    const int64_t i = rowidx[base + e];
-    const double a = cval[base + e];
-    const int64_t r1 = rowptr[i + 1];
-    for (int64_t f = rowptr[i] + lane; f < r1; f += 64) {
+  // lane l of wave w walks CSR row i of column entry e = e0 + 64 (w + copies t) + l;
+  // the 64 rows of one step load their index ranges together
+  for (int64_t e = e0 + (int64_t)w * 64 + lane; e - lane < e1; e += (int64_t)copies * 64) {
+    const bool live = e < e1;
+    const int64_t i = live ? rowidx[base + e] : 0;
+    const double a = live ? cval[base + e] : 0.0;
+    const int64_t f0 = live ? rowptr[i] : 0, f1 = live ? rowptr[i + 1] : 0;
+    for (int64_t f = f0; f < f1; ++f) {
       const int k = colidx[f];
       if (k >= j) atomicAdd(&my[k], a * val[f]);
     }

@@ -82,6 +82,8 @@ def test_gram_parts(sp):
             continue
         assert np.linalg.norm(G - ref) <= 1e-13 * np.linalg.norm(ref)
         np.testing.assert_array_equal(G, G.T)
+        for _ in range(3):  # run to run, bit for bit
+            np.testing.assert_array_equal(host(S.gram(part)).view(np.uint64), G.view(np.uint64))
 
 
 @pytest.mark.parametrize("form", ["paper", "correction"])
