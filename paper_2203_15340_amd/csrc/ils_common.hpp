@@ -36,6 +36,16 @@ struct LoopState {
   unsigned int arrive3;// last-block counter of the blocked RK-RGS steps
 };
 
+// Pointers loaded from memory or passed to out-of-line functions are generic,
+// and accesses through them compile to flat instructions, which count against
+// both the vector-memory and the LDS wait counters (a wait for an LDS read then
+// also waits for every load in flight).  Recasting a pointer known to address
+// device memory to the global address space gives global_* instructions.
+template <typename T>
+__device__ inline __attribute__((address_space(1))) T* glb(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
 // ---------------------------------------------------------------- reductions
 // Butterfly sum over the 64 lanes of a wavefront.  The pairing order is
 // fixed, so results are reproducible run to run.

@@ -46,6 +46,11 @@ struct Smem {
   int id;
 };
 
+// One LDS block per workgroup, at file scope so that the out-of-line helper
+// functions address it as LDS (ds_* instructions) rather than through
+// generic pointers.
+__shared__ Smem bsm;
+
 template <typename T>
 struct Mma;
 template <>
@@ -97,8 +102,11 @@ __device__ inline double block_sum2(double v, Smem& s, int which) {
 // workgroup streams a whole problem, so loads in flight, not bandwidth, set
 // the rate; the second workgroup on the CU covers its waits.
 template <typename T>
-__device__ __attribute__((noinline)) void wg_gram(const double* __restrict__ A, int64_t lda, int K, int n, double* W, int64_t ldw,
-                        Smem& s) {
+__device__ __attribute__((noinline)) void wg_gram(const double* A_, int64_t lda, int K, int n, double* W_,
+                                                 int64_t ldw) {
+  Smem& s = bsm;
+  const auto A = glb(A_);
+  const auto W = glb(W_);
   typedef typename Mma<T>::acc_t acc_t;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wr = (w >> 1) * 32, wc = (w & 1) * 32, lr = lane & 15;
@@ -112,8 +120,8 @@ __device__ __attribute__((noinline)) void wg_gram(const double* __restrict__ A, 
   for (int ti = 0; ti < nt; ++ti) {
     for (int tj = 0; tj <= ti; ++tj) {
       const bool diag = ti == tj;
-      const double* Ai = A + (int64_t)ti * kNB * lda;
-      const double* Aj = A + (int64_t)tj * kNB * lda;
+      const auto Ai = A + (int64_t)ti * kNB * lda;
+      const auto Aj = A + (int64_t)tj * kNB * lda;
       const int ci = n - ti * kNB, cj = n - tj * kNB;
       acc_t acc[2][2];
 #pragma unroll
@@ -174,7 +182,9 @@ __device__ __attribute__((noinline)) void wg_gram(const double* __restrict__ A, 
 
 // Block Gauss-Jordan on W = [G | R] (n x ncols), 64-wide blocks, inside one
 // workgroup.  Returns false when a pivot block is not positive definite.
-__device__ __attribute__((noinline)) bool wg_gauss_jordan(double* W, int64_t ldw, int n, int ncols, Smem& s) {
+__device__ __attribute__((noinline)) bool wg_gauss_jordan(double* W_, int64_t ldw, int n, int ncols) {
+  Smem& s = bsm;
+  const auto W = glb(W_);
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, lr = lane & 15;
   const int hq = (w >> 1) * 32, lq = (w & 1) * 32;
   for (int k0 = 0; k0 < n; k0 += kNB) {
@@ -313,19 +323,25 @@ __device__ __attribute__((noinline)) bool wg_gauss_jordan(double* W, int64_t ldw
 }
 
 // t = b - A x (x staged in LDS), then r = A^T J t; t lives in LDS.
-__device__ __attribute__((noinline)) void wg_residual(const double* __restrict__ A, int64_t lda, int p, int q, int n,
-                            const double* __restrict__ b, const double* xs, double* ts, double* r) {
+constexpr int kXsOff = 4096;  // x_k's offset in the LDS vector area
+__device__ __attribute__((noinline)) void wg_residual(const double* A_, int64_t lda, int p, int q, int n,
+                                                     const double* b_, double* r_) {
+  const auto A = glb(A_);
+  const auto b = glb(b_);
+  const auto r = glb(r_);
+  const double* xs = bsm.u.vec + kXsOff;
+  double* ts = bsm.u.vec;
   const int m = p + q, t = threadIdx.x, lane = t & 63, w = t >> 6;
   for (int i = t; i < m; i += NT) {
     double acc = 0.0;
-    const double* ai = A + i;
+    const auto ai = A + i;
 #pragma unroll 8
     for (int j = 0; j < n; ++j) acc += ai[(int64_t)j * lda] * xs[j];
     ts[i] = b[i] - acc;
   }
   __syncthreads();
   for (int j = w; j < n; j += NT / kWave) {
-    const double* col = A + (int64_t)j * lda;
+    const auto col = A + (int64_t)j * lda;
     double s1 = 0.0, s2 = 0.0;
 #pragma unroll 8
     for (int i = lane; i < p; i += kWave) s1 += col[i] * ts[i];
@@ -339,8 +355,8 @@ __device__ __attribute__((noinline)) void wg_residual(const double* __restrict__
 }
 
 template <typename T>
-__device__ void solve_one(const BatchArgs& a, const BatchProblem& P, double* slot, Smem& s,
-                          BatchResult& out) {
+__device__ void solve_one(const BatchArgs& a, const BatchProblem& P, double* slot, BatchResult& out) {
+  Smem& s = bsm;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int n = (int)P.n, p = (int)P.p, q = (int)P.q, m = p + q;
   const int64_t lda = P.lda, ldw = a.ldw;
@@ -356,13 +372,13 @@ __device__ void solve_one(const BatchArgs& a, const BatchProblem& P, double* slo
   bool ok = true;
   double* bs = s.u.vec;
   for (int i = t; i < m; i += NT) {
-    const double bv = P.b[i];
+    const double bv = glb(P.b)[i];
     bs[i] = bv;
     ok &= isfinite(bv);
   }
   __syncthreads();
   for (int j = w; j < n; j += NT / kWave) {
-    const double* col = P.A + (int64_t)j * lda;
+    const auto col = glb(P.A) + (int64_t)j * lda;
     double s1 = 0.0, s2 = 0.0;
 #pragma unroll 8
     for (int i = lane; i < p; i += kWave) {
@@ -388,14 +404,14 @@ __device__ void solve_one(const BatchArgs& a, const BatchProblem& P, double* slo
   for (int j = t; j < n; j += NT) gn2 += g[j] * g[j];
   gn2 = block_sum2(gn2, s, 0);
   if (a.stop_rule == ILS_STOP_XREF) {
-    for (int j = t; j < n; j += NT) xr2 += P.x_ref[j] * P.x_ref[j];
+    for (int j = t; j < n; j += NT) xr2 += glb(P.x_ref)[j] * glb(P.x_ref)[j];
     xr2 = block_sum2(xr2, s, 1);
   }
   // 2. [A1^T A1 | A2^T A2 | g] or [A1^T A1 | I]
-  wg_gram<T>(P.A, lda, p, n, W, ldw, s);
+  wg_gram<T>(P.A, lda, p, n, W, ldw);
   int nrhs;
   if (paper) {
-    wg_gram<double>(P.A + p, lda, q, n, W + (int64_t)n * ldw, ldw, s);
+    wg_gram<double>(P.A + p, lda, q, n, W + (int64_t)n * ldw, ldw);
     for (int j = t; j < n; j += NT) W[j + (int64_t)2 * n * ldw] = g[j];
     nrhs = n + 1;
   } else {
@@ -407,16 +423,15 @@ __device__ void solve_one(const BatchArgs& a, const BatchProblem& P, double* slo
   }
   __syncthreads();
   // 3. elimination
-  if (!wg_gauss_jordan(W, ldw, n, n + nrhs, s)) {
+  if (!wg_gauss_jordan(W, ldw, n, n + nrhs)) {
     out.status = ILS_ERR_NOT_SPD;
     return;
   }
   const double* M = W + (int64_t)n * ldw;  // B (paper) or P (correction)
   const double* c = W + (int64_t)2 * n * ldw;
   // 4. outer steps
-  double* ts = s.u.vec;          // m entries
-  double* xs = s.u.vec + 4096;   // n entries (x_k staged for the residual)
-  for (int j = t; j < n; j += NT) xa[j] = P.x0 ? P.x0[j] : 0.0;
+  double* xs = s.u.vec + kXsOff;  // n entries (x_k staged for the residual)
+  for (int j = t; j < n; j += NT) xa[j] = P.x0 ? glb(P.x0)[j] : 0.0;
   __syncthreads();
   double* xk = xa;
   double* xn = xb;
@@ -428,12 +443,12 @@ __device__ void solve_one(const BatchArgs& a, const BatchProblem& P, double* slo
     if (need_r) {
       for (int j = t; j < n; j += NT) xs[j] = xk[j];
       __syncthreads();
-      wg_residual(P.A, lda, p, q, n, P.b, xs, ts, r);
+      wg_residual(P.A, lda, p, q, n, P.b, r);
     }
     double mp = 0.0;
     for (int j = t; j < n; j += NT) {
       if (a.stop_rule == ILS_STOP_XREF) {
-        const double d = xk[j] - P.x_ref[j];
+        const double d = xk[j] - glb(P.x_ref)[j];
         mp += d * d;
       } else if (a.stop_rule == ILS_STOP_RR) {
         mp += r[j] * r[j];
@@ -466,7 +481,7 @@ __device__ void solve_one(const BatchArgs& a, const BatchProblem& P, double* slo
       break;
     }
   }
-  for (int j = t; j < n; j += NT) P.x[j] = xk[j];
+  for (int j = t; j < n; j += NT) glb(P.x)[j] = xk[j];
   out.status = status;
   out.iters = k;
   out.metric = metric;
@@ -476,7 +491,7 @@ __device__ void solve_one(const BatchArgs& a, const BatchProblem& P, double* slo
 // functions spill a little at entry), and each hides the other's latency.
 template <typename T>
 __global__ __launch_bounds__(NT, 2) void k_batched(BatchArgs a) {
-  __shared__ Smem s;
+  Smem& s = bsm;
   double* slot = a.work + (int64_t)blockIdx.x * a.slot_doubles;
   for (;;) {
     if (threadIdx.x == 0) s.id = (int)atomicAdd(&a.queue[0], 1u);
@@ -487,7 +502,7 @@ __global__ __launch_bounds__(NT, 2) void k_batched(BatchArgs a) {
     const int idx = a.order[id];
     BatchResult res;
     res.status = ILS_OK;
-    solve_one<T>(a, a.probs[idx], slot, s, res);
+    solve_one<T>(a, a.probs[idx], slot, res);
     if (threadIdx.x == 0) a.res[idx] = res;
     __syncthreads();
   }

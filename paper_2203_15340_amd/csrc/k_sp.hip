@@ -24,8 +24,9 @@ constexpr int kSpRows = 4;
 // lane partials are added by a fixed butterfly.
 constexpr int kDotDepth = 16;
 
-__device__ inline double dot_row(const double* __restrict__ row, const double* __restrict__ v,
-                                 int64_t n, int lane) {
+__device__ inline double dot_row(const double* row_, const double* v_, int64_t n, int lane) {
+  const auto row = glb(row_);
+  const auto v = glb(v_);
   double s = 0.0;
   for (int64_t j0 = 0; j0 < n; j0 += kDotDepth * kWave) {
     double rv[kDotDepth], vv[kDotDepth];
