@@ -193,6 +193,7 @@ int ils::finish_info(ils_handle* h, int64_t n, double* x, const ils_opts* o, int
 int ils::setup_status(const LoopState& s) {
   if (s.bits & kBitNonfinite) return ILS_ERR_NONFINITE;
   if (s.bits & kBitNotSpd) return ILS_ERR_NOT_SPD;
+  if (s.bits & kBitStall) return ILS_ERR_HIP;
   return ILS_OK;
 }
 
@@ -232,7 +233,7 @@ int ils::sp_solve_op(ils_handle* h, const MatOp& M, const double* b, const doubl
       (st = h->need(kBufR, sizeof(double) * n, (void**)&rv)) ||
       (st = h->need(kBufSPart, sizeof(double) * 2 * nblk, (void**)&spart)) ||
       (st = h->need(kBufSBad, sizeof(int) * 2 * nblk, (void**)&sbad)) ||
-      (st = h->need(kBufDinv, sizeof(double) * gj_dinv_size(), (void**)&dinv)))
+      (st = h->need(kBufDinv, gj_scratch_bytes(n, n + nrhs), (void**)&dinv)))
     return fail(info, st);
 
   HIPCHK(hipMemsetAsync(h->st, 0, sizeof(LoopState), s));
@@ -378,7 +379,7 @@ extern "C" int ils_spd_solve(ils_handle* h, int64_t n, int64_t nrhs, const doubl
   double *W, *dinv;
   int st;
   if ((st = h->need(kBufW, sizeof(double) * n * (n + nrhs), (void**)&W)) ||
-      (st = h->need(kBufDinv, sizeof(double) * gj_dinv_size(), (void**)&dinv)))
+      (st = h->need(kBufDinv, gj_scratch_bytes(n, n + nrhs), (void**)&dinv)))
     return st;
   HIPCHK(hipMemsetAsync(h->st, 0, sizeof(LoopState), h->stream));
   launch_copy_cols(h->stream, n, n, G, ldg, W, n);

@@ -17,6 +17,7 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 enum : int {
   kBitNonfinite = 1,  // NaN/Inf in A or b
   kBitNotSpd = 2,     // a Gauss-Jordan pivot block is not positive definite
+  kBitStall = 4,      // a dataflow kernel's bounded wait ran out (never expected)
 };
 
 // Device-side state of an outer loop (one per handle).
@@ -167,9 +168,9 @@ void launch_sub(hipStream_t s, int64_t n, const double* X, int64_t ldx, const do
                 double* Z, int64_t ldz);
 
 // Block Gauss-Jordan on W = [G | R] (n x (n + nrhs), column-major, ldw);
-// dinv is scratch of gj_dinv_size() doubles.
-size_t gj_dinv_size();
-void launch_gj(hipStream_t s, int64_t n, int64_t nrhs, double* W, int64_t ldw, double* dinv, int* bits);
+// scratch is gj_scratch_bytes(n, n + nrhs) bytes of device memory.
+size_t gj_scratch_bytes(int64_t n, int64_t ncols);
+void launch_gj(hipStream_t s, int64_t n, int64_t nrhs, double* W, int64_t ldw, void* scratch, int* bits);
 
 // SP outer step kernels (k_sp.hip).
 struct SpStepArgs {

@@ -66,7 +66,7 @@ extern "C" int ils_sp_solve_multi(ils_handle* h, int64_t p, int64_t q, int64_t n
       (st = h->need(kBufMDen, sizeof(double) * nrhs, (void**)&den)) ||
       (st = h->need(kBufMBt, sizeof(double) * n * n, (void**)&Bt)) ||
       (st = h->need(kBufPart, part_bytes, &part)) ||
-      (st = h->need(kBufDinv, sizeof(double) * gj_dinv_size(), (void**)&dinv)))
+      (st = h->need(kBufDinv, gj_scratch_bytes(n, 2 * n + nrhs), (void**)&dinv)))
     return fail_multi(info, st);
 
   LoopState* ds = h->st;
@@ -168,6 +168,7 @@ extern "C" int ils_sp_solve_multi(ils_handle* h, int64_t p, int64_t q, int64_t n
       if ((st = read_state(h))) return fail_multi(info, st);
       const LoopState& hs = *h->st_host;
       if (hs.bits & kBitNotSpd) return fail_multi(info, ILS_ERR_NOT_SPD);
+      if (hs.bits & kBitStall) return fail_multi(info, ILS_ERR_HIP);
       if (hs.bits & kBitNonfinite) {
         status = ILS_ERR_NONFINITE;
         break;

@@ -233,7 +233,7 @@ int ils::rgs_solve_op(ils_handle* h, const MatOp& M, const double* b, const doub
       (st = h->need(kBufW1, sizeof(double) * n, (void**)&r)) ||
       (st = h->need(kBufIdx, sizeof(int) * 2 * chunk, (void**)&alpha_buf)) ||
       (st = h->need(kBufMask, sizeof(uint32_t) * words * chunk, (void**)&mask)) ||
-      (st = h->need(kBufDinv, sizeof(double) * gj_dinv_size(), (void**)&dinv)))
+      (st = h->need(kBufDinv, gj_scratch_bytes(n, n), (void**)&dinv)))
     return fail_info(info, st);
   jpre = alpha_buf + chunk;
   if ((st = common_setup(h, M, b, x0, o, nullptr, c))) return fail_info(info, st);

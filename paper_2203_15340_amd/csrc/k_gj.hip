@@ -18,6 +18,11 @@
 //                ready (one block of lookahead).
 // The first pivot block is inverted by k_gj_inv0.  Columns left of the
 // trailing strips are never read again.
+//
+// Up to kFlowMaxRows block rows (n <= 2048) the same items run as one
+// dataflow launch instead (k_gj_flow below): no step waits for the whole
+// previous step, only for the tiles it reads, so the chain of pivot-block
+// inversions is the critical path rather than one launch pair per step.
 #include "ils_common.hpp"
 #include "ils_blocks.hpp"
 
@@ -275,11 +280,424 @@ __global__ __launch_bounds__(kGjThreads) void k_gj_update(double* __restrict__ W
   }
 }
 
-size_t gj_dinv_size() { return 2 * kNB * kNB; }
+// ------------------------------------------------------------- dataflow form
+// For n up to kFlowMaxRows blocks the whole elimination is one persistent
+// launch: workgroups take work items from a ticket counter and each item
+// waits, by polling counters in device memory, only for the items whose
+// output it reads.  Items of step k (pivot block K = block row k):
+//   L_k        (k + 1 < R) update the next pivot block (k+1, k+1) with step
+//              k's pivot rows, formed here from D_k^{-1}, and invert it;
+//              the chain L_0 -> L_1 -> ... is the critical path;
+//   P(k, j)    R_j = D_k^{-1} W[K, j] in place, for every trailing strip j;
+//   U(k, i, j) W[i, j] -= W[i, K] R_j for every row block i != k.
+// Strips are the 64-column blocks of W (the last pivot block may be short,
+// then its strip also holds right-hand-side columns).  Counters:
+//   cnt[k][j]   items of step k that have written strip j (R of them, R - 1
+//               for strip k+1, whose row k+1 belongs to L_k),
+//   pdone[k][j] P(k, j) done,  dflag[k] D_k^{-1} published,
+//   lflag[k]    L_k has read W[K, k+1], which P(k, k+1) then overwrites.
+// Tickets are issued in step order (within a step: L_k, the P items, then the
+// U items strip by strip), and an item only waits for items with smaller
+// tickets, which are held by running workgroups; so every wait ends.  A
+// bounded spin still raises kBitStall rather than hanging if one did not.
+constexpr int kFlowMaxRows = 32;
+constexpr int kFlowOcc = 1;  // workgroups per CU
+constexpr int kFlowWgs = 256 * kFlowOcc;
+constexpr int kSpinLimit = 1 << 22;
 
-void launch_gj(hipStream_t s, int64_t n, int64_t nrhs, double* W, int64_t ldw, double* dinv, int* bits) {
+struct GjFlow {
+  double* W;
+  int64_t ldw, n, ncols;
+  int R, S;
+  double* dinv;  // R blocks of 64 x 64, row-major
+  int* cnt;      // R x S
+  int* pdone;    // R x S
+  int* dflag;    // R
+  int* lflag;    // R
+  unsigned* ticket;
+  int* bits;
+};
+
+struct FlowStep {
+  int nb, j0, nP, nI;
+  int64_t c0;
+  bool hasL;
+};
+
+__device__ inline FlowStep flow_step(const GjFlow& a, int k) {
+  FlowStep f;
+  const int64_t k0 = (int64_t)k * kNB;
+  f.nb = (int)(a.n - k0 < kNB ? a.n - k0 : kNB);
+  f.c0 = k0 + f.nb;
+  f.j0 = (int)(f.c0 / kNB);
+  f.hasL = k + 1 < a.R;
+  f.nP = f.c0 < a.ncols ? a.S - f.j0 : 0;
+  const int nU = f.nP > 0 ? (a.R - 1) * f.nP - (f.hasL ? 1 : 0) : 0;
+  f.nI = (f.hasL ? 1 : 0) + f.nP + nU;
+  return f;
+}
+
+// writers of strip j at step k (see above)
+__device__ inline int flow_target(const GjFlow& a, int k, int j) {
+  return (k + 1 < a.R && j == k + 1) ? a.R - 1 : a.R;
+}
+
+// Thread 0 polls until *p >= target; false if the bits were raised meanwhile.
+__device__ inline bool flow_wait(const int* p, int target, int* bits) {
+  for (int spin = 0;; ++spin) {
+    if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) return true;
+    if (__hip_atomic_load(bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+    if (spin >= kSpinLimit) {
+      atomicOr(bits, kBitStall);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
+
+// W and the inverses are read and written inside the launch with device-scope
+// relaxed atomic loads and stores: those bypass the non-coherent caches
+// (each XCD has its own L2), so no cache write-back or invalidation is needed
+// around a hand-over.  A producer waits until its stores are acknowledged
+// (vmcnt 0), then one thread counts.
+__device__ inline double ald(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void ast(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void wait_stores() {
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's stores have completed
+}
+__device__ inline void flow_signal(int* p) {
+  wait_stores();
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_fetch_add(p, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ __launch_bounds__(kGjThreads, kFlowOcc) void k_gj_flow(GjFlow a) {
+  __shared__ double As[kNB][kNB + 1];  // A operand: As[i][k]
+  __shared__ double Bs[kNB][kNB + 1];  // B operand: Bs[j][k]
+  __shared__ InvBlk inv;
+  __shared__ int s_tk, s_ok;
+  if (__hip_atomic_load(a.bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int jr = (w >> 1) * 32, ic = (w & 1) * 32, lr = lane & 15;
+  double* W = a.W;
+  const int64_t ldw = a.ldw, n = a.n, ncols = a.ncols;
+  // 64 x 64 block of W at (r0, c0) into registers (e = t + 256 q: row e & 63,
+  // column e >> 6); rows >= rmax, columns outside [cmin, cmax) and columns
+  // >= c0 + kmax read as zero
+  auto load_tile = [&](double (&v)[16], int64_t r0, int64_t c0, int64_t rmax, int64_t cmin, int64_t cmax) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int e = t + q * kGjThreads, lo = e & (kNB - 1), hi = e >> 6;
+      const int64_t r = r0 + lo, c = c0 + hi;
+      v[q] = (r < rmax && c >= cmin && c < cmax) ? ald(W + r + c * ldw) : 0.0;
+    }
+  };
+  // the same block in the product's output layout (C^T lanes)
+  auto load_out = [&](double (&v)[16], int64_t r0, int64_t c0, int64_t rmax, int64_t cmin, int64_t cmax) {
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int j = jr + x * 16 + (lane >> 4) + 4 * u, i = ic + y * 16 + lr;
+          const int64_t r = r0 + i, c = c0 + j;
+          v[(x * 2 + y) * 4 + u] = (r < rmax && c >= cmin && c < cmax) ? ald(W + r + c * ldw) : 0.0;
+        }
+  };
+  auto store_out = [&](const double (&v)[16], int64_t r0, int64_t c0, int64_t rmax, int64_t cmin, int64_t cmax) {
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int j = jr + x * 16 + (lane >> 4) + 4 * u, i = ic + y * 16 + lr;
+          const int64_t r = r0 + i, c = c0 + j;
+          if (r < rmax && c >= cmin && c < cmax) ast(W + r + c * ldw, v[(x * 2 + y) * 4 + u]);
+        }
+  };
+  // tile (A operand) As[i][k] = v(i, k); (B operand) Bs[j][k] = v(k, j)
+  auto stash_a = [&](const double (&v)[16]) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int e = t + q * kGjThreads;
+      As[e & (kNB - 1)][e >> 6] = v[q];
+    }
+  };
+  auto stash_b = [&](const double (&v)[16]) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int e = t + q * kGjThreads;
+      Bs[e >> 6][e & (kNB - 1)] = v[q];
+    }
+  };
+  auto stash_dinv = [&](const double* D) {
+    double v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) v[q] = ald(D + t + q * kGjThreads);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int e = t + q * kGjThreads;
+      As[e >> 6][e & (kNB - 1)] = v[q];
+    }
+  };
+  // acc (output layout) = A B over the full 64-deep contraction
+  auto product = [&](double (&acc)[16]) {
+    v4d c4[2][2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) c4[x][y] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < kNB; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      const double b0 = Bs[jr + lr][kr], b1 = Bs[jr + 16 + lr][kr];
+      const double a0 = As[ic + lr][kr], a1 = As[ic + 16 + lr][kr];
+      c4[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, a0, c4[0][0], 0, 0, 0);
+      c4[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, a1, c4[0][1], 0, 0, 0);
+      c4[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, a0, c4[1][0], 0, 0, 0);
+      c4[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, a1, c4[1][1], 0, 0, 0);
+    }
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[(x * 2 + y) * 4 + u] = c4[x][y][u];
+  };
+  // thread 0 runs the waits; every thread learns the outcome
+  auto finish_wait = [&](bool ok) {
+    if (t == 0) s_ok = ok;
+    __syncthreads();
+    const bool r = s_ok;
+    return r;
+  };
+
+  int k = 0;
+  int base = 0;
+  FlowStep f = flow_step(a, 0);
+  for (;;) {
+    __syncthreads();  // LDS of the previous item free
+    if (t == 0) s_tk = (int)atomicAdd(a.ticket, 1u);
+    __syncthreads();
+    const int tk = s_tk;
+    while (k < a.R && tk >= base + f.nI) {
+      base += f.nI;
+      ++k;
+      if (k < a.R) f = flow_step(a, k);
+    }
+    if (k >= a.R) break;
+    int u = tk - base;
+    const int64_t k0 = (int64_t)k * kNB;
+    const int R = a.R;
+    if (f.hasL && u == 0) {
+      // ---- L_k: D_{k+1} = W[k+1, k+1] - W[k+1, K] D_k^{-1} W[K, k+1], inverted
+      const int64_t k1 = k0 + kNB;
+      const int nbn = (int)(n - k1 < kNB ? n - k1 : kNB);
+      bool ok = true;
+      if (t == 0 && k >= 1) {
+        ok = flow_wait(a.cnt + (k - 1) * a.S + k, flow_target(a, k - 1, k), a.bits) &&
+             flow_wait(a.cnt + (k - 1) * a.S + k + 1, flow_target(a, k - 1, k + 1), a.bits);
+      }
+      if (!finish_wait(ok)) continue;
+      double xv[16], mv[16], cv[16];
+      load_tile(xv, k0, k1, k0 + kNB, k1, ncols);  // X = W[K, k+1]
+      load_tile(mv, k1, k0, n, k0, k0 + kNB);      // M = W[k+1, K]
+      load_out(cv, k1, k1, n, k1, ncols);          // C = W[k+1, k+1]
+      stash_b(xv);                                 // X has been read
+      __syncthreads();
+      if (t == 0) {
+        __hip_atomic_fetch_add(a.lflag + k, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = flow_wait(a.dflag + k, 1, a.bits);
+      }
+      if (!finish_wait(ok)) continue;
+      stash_dinv(a.dinv + (int64_t)k * kNB * kNB);
+      __syncthreads();
+      double acc[16];
+      product(acc);  // R = D_k^{-1} X
+      __syncthreads();
+      stash_a(mv);
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int j = jr + x * 16 + (lane >> 4) + 4 * q, i = ic + y * 16 + lr;
+            Bs[j][i] = acc[(x * 2 + y) * 4 + q];
+          }
+      __syncthreads();
+      product(acc);  // M R
+#pragma unroll
+      for (int q = 0; q < 16; ++q) cv[q] -= acc[q];
+      // right-hand-side columns sharing the short last block's strip
+      store_out(cv, k1, k1, n, k1 + nbn, ncols);
+      __syncthreads();
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int j = jr + x * 16 + (lane >> 4) + 4 * q, i = ic + y * 16 + lr;
+            As[i][j] = (i < nbn && j < nbn) ? cv[(x * 2 + y) * 4 + q] : (i == j ? 1.0 : 0.0);
+          }
+      __syncthreads();
+      if (!invert64_blk(&As[0][0], &Bs[0][0], inv)) {
+        if (t == 0) atomicOr(a.bits, kBitNotSpd);
+        continue;
+      }
+      double* dn = a.dinv + (int64_t)(k + 1) * kNB * kNB;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int e = t + q * kGjThreads;
+        ast(dn + e, As[e >> 6][e & (kNB - 1)]);
+      }
+      flow_signal(a.dflag + k + 1);
+      continue;
+    }
+    if (f.hasL) --u;
+    if (u < f.nP) {
+      // ---- P(k, j): R_j = D_k^{-1} W[K, j]
+      const int j = f.j0 + u;
+      const int64_t cj = (int64_t)j * kNB;
+      bool ok = true;
+      if (t == 0) {
+        ok = flow_wait(a.dflag + k, 1, a.bits);
+        if (ok && k >= 1) ok = flow_wait(a.cnt + (k - 1) * a.S + j, flow_target(a, k - 1, j), a.bits);
+        if (ok && f.hasL && j == k + 1) ok = flow_wait(a.lflag + k, 1, a.bits);
+      }
+      if (!finish_wait(ok)) continue;
+      double xv[16];
+      load_tile(xv, k0, cj, k0 + f.nb, f.c0, ncols);
+      stash_dinv(a.dinv + (int64_t)k * kNB * kNB);
+      stash_b(xv);
+      __syncthreads();
+      double acc[16];
+      product(acc);
+      store_out(acc, k0, cj, k0 + f.nb, f.c0, ncols);
+      flow_signal(a.pdone + k * a.S + j);
+      if (t == 0) __hip_atomic_fetch_add(a.cnt + k * a.S + j, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      continue;
+    }
+    u -= f.nP;
+    // ---- U(k, i, j): W[i, j] -= W[i, K] R_j
+    int i, j;
+    if (f.hasL) {
+      if (u < R - 2) {
+        j = k + 1;
+        i = u < k ? u : u + 2;
+      } else {
+        u -= R - 2;
+        j = k + 2 + u / (R - 1);
+        const int r = u % (R - 1);
+        i = r < k ? r : r + 1;
+      }
+    } else {
+      j = f.j0 + u / (R - 1);
+      const int r = u % (R - 1);
+      i = r < k ? r : r + 1;
+    }
+    const int64_t ri = (int64_t)i * kNB, cj = (int64_t)j * kNB;
+    bool ok = true;
+    if (t == 0) {
+      ok = flow_wait(a.pdone + k * a.S + j, 1, a.bits);
+      if (ok && k >= 1) ok = flow_wait(a.cnt + (k - 1) * a.S + k, flow_target(a, k - 1, k), a.bits);
+    }
+    if (!finish_wait(ok)) continue;
+    double mv[16], rv[16], cv[16];
+    load_tile(mv, ri, k0, n, k0, k0 + f.nb);
+    load_tile(rv, k0, cj, k0 + f.nb, f.c0, ncols);
+    load_out(cv, ri, cj, n, f.c0, ncols);
+    stash_a(mv);
+    stash_b(rv);
+    __syncthreads();
+    double acc[16];
+    product(acc);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) cv[q] -= acc[q];
+    store_out(cv, ri, cj, n, f.c0, ncols);
+    flow_signal(a.cnt + k * a.S + j);
+  }
+}
+
+// D_0 = W[0:nb, 0:nb] inverted into dinv block 0 (as k_gj_inv0), and the
+// flow counters cleared, before the dataflow launch.
+__global__ __launch_bounds__(kGjThreads) void k_gj_flow_init(GjFlow a) {
+  __shared__ double Ds[kNB][kLds];
+  __shared__ double Es[kNB][kLds];
+  __shared__ InvBlk inv;
+  const int t = threadIdx.x;
+  const int64_t nint = 2 * (int64_t)a.R * a.S + 2 * a.R + 1;  // cnt, pdone, dflag, lflag, ticket
+  for (int64_t e = t; e < nint; e += kGjThreads) a.cnt[e] = 0;
+  if (__hip_atomic_load(a.bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+  const int nb = (int)(a.n < kNB ? a.n : kNB);
+  double dv[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = t + q * kGjThreads, r = e & (kNB - 1), c = e >> 6;
+    dv[q] = (r < nb && c < nb) ? a.W[r + (int64_t)c * a.ldw] : (r == c ? 1.0 : 0.0);
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = t + q * kGjThreads;
+    Ds[e & (kNB - 1)][e >> 6] = dv[q];
+  }
+  __syncthreads();
+  if (!invert64_blk(&Ds[0][0], &Es[0][0], inv)) {
+    if (t == 0) atomicOr(a.bits, kBitNotSpd);
+    return;
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = t + q * kGjThreads;
+    a.dinv[e] = Ds[e >> 6][e & (kNB - 1)];
+  }
+  __syncthreads();
+  if (t == 0) a.dflag[0] = 1;
+}
+
+static bool flow_fits(int64_t n) { return (n + kNB - 1) / kNB <= kFlowMaxRows; }
+
+size_t gj_scratch_bytes(int64_t n, int64_t ncols) {
+  size_t b = sizeof(double) * 2 * kNB * kNB;  // the step-by-step form
+  if (flow_fits(n)) {
+    const int64_t R = (n + kNB - 1) / kNB, S = (ncols + kNB - 1) / kNB;
+    const size_t f = sizeof(double) * R * kNB * kNB + sizeof(int) * (2 * R * S + 2 * R + 1);
+    if (f > b) b = f;
+  }
+  return b;
+}
+
+
+void launch_gj(hipStream_t s, int64_t n, int64_t nrhs, double* W, int64_t ldw, void* scratch, int* bits) {
   const int64_t ncols = n + nrhs;
   const int row_tiles = (int)((n + kNB - 1) / kNB);
+  if (flow_fits(n) && ncols > n) {
+    GjFlow a;
+    a.W = W;
+    a.ldw = ldw;
+    a.n = n;
+    a.ncols = ncols;
+    a.R = row_tiles;
+    a.S = (int)((ncols + kNB - 1) / kNB);
+    a.dinv = (double*)scratch;
+    a.cnt = (int*)(a.dinv + (int64_t)a.R * kNB * kNB);
+    a.pdone = a.cnt + a.R * a.S;
+    a.dflag = a.pdone + a.R * a.S;
+    a.lflag = a.dflag + a.R;
+    a.ticket = (unsigned*)(a.lflag + a.R);
+    a.bits = bits;
+    hipLaunchKernelGGL(k_gj_flow_init, dim3(1), dim3(kGjThreads), 0, s, a);
+    hipLaunchKernelGGL(k_gj_flow, dim3(kFlowWgs), dim3(kGjThreads), 0, s, a);
+    return;
+  }
+  double* dinv = (double*)scratch;
   hipLaunchKernelGGL(k_gj_inv0, dim3(1), dim3(kGjThreads), 0, s, (const double*)W, ldw,
                      (int)(n < kNB ? n : kNB), dinv, bits);
   int step = 0;

@@ -100,9 +100,12 @@ def test_spd_solve(prob):
     assert rel(host(X), np.linalg.solve(G1, R)) < 1e-12
 
 
-@pytest.mark.parametrize("n,nrhs", [(1, 1), (63, 2), (64, 64), (65, 1), (128, 129), (129, 64), (300, 301)])
+@pytest.mark.parametrize("n,nrhs", [(1, 1), (63, 2), (64, 64), (65, 1), (128, 129), (129, 64), (300, 301),
+                                    (960, 1), (1000, 1001), (2047, 3), (2048, 2049), (2049, 2)])
 def test_spd_solve_block_edges(n, nrhs):
-    # block edges of the 64-wide Gauss-Jordan: one block, exact multiples, ragged tails
+    # block edges of the 64-wide Gauss-Jordan: one block, exact multiples, ragged tails;
+    # up to 32 block rows the elimination is one dataflow launch, above it one
+    # launch pair per block step (2048 / 2049)
     rng = np.random.default_rng(n)
     X = rng.standard_normal((3 * n + 5, n))
     G = X.T @ X
@@ -110,6 +113,19 @@ def test_spd_solve_block_edges(n, nrhs):
     rc, Y = ils.spd_solve(devA(G), devA(R))
     assert rc == ils.OK
     assert rel(host(Y), np.linalg.solve(G, R)) < 1e-11
+
+
+def test_spd_solve_repeated_sizes():
+    # the dataflow elimination clears its counters on every call; alternate sizes
+    # so that a stale counter or a short scratch buffer would show
+    for n, nrhs in ((1000, 1001), (130, 5), (1000, 1001), (700, 2)):
+        rng = np.random.default_rng(n + nrhs)
+        X = rng.standard_normal((2 * n + 7, n))
+        G = X.T @ X
+        R = rng.standard_normal((n, nrhs))
+        rc, Y = ils.spd_solve(devA(G), devA(R))
+        assert rc == ils.OK
+        assert rel(host(Y), np.linalg.solve(G, R)) < 1e-11
 
 
 @pytest.mark.parametrize("bad", [0, 63, 64, 100, 129])
