@@ -324,6 +324,7 @@ __device__ __attribute__((noinline)) bool wg_gauss_jordan(double* W_, int64_t ld
 
 // t = b - A x (x staged in LDS), then r = A^T J t; t lives in LDS.
 constexpr int kXsOff = 4096;  // x_k's offset in the LDS vector area
+constexpr int kVsOff = 4608;  // the outer product's vector (n <= 256 entries)
 __device__ __attribute__((noinline)) void wg_residual(const double* A_, int64_t lda, int p, int q, int n,
                                                      const double* b_, double* r_) {
   const auto A = glb(A_);
@@ -431,6 +432,7 @@ __device__ void solve_one(const BatchArgs& a, const BatchProblem& P, double* slo
   const double* c = W + (int64_t)2 * n * ldw;
   // 4. outer steps
   double* xs = s.u.vec + kXsOff;  // n entries (x_k staged for the residual)
+  double* vs = s.u.vec + kVsOff;  // n entries (the vector of the outer step's product)
   for (int j = t; j < n; j += NT) xa[j] = P.x0 ? glb(P.x0)[j] : 0.0;
   __syncthreads();
   double* xk = xa;
@@ -462,11 +464,22 @@ __device__ void solve_one(const BatchArgs& a, const BatchProblem& P, double* slo
       break;
     }
     bool bad = false;
-    for (int i = t; i < n; i += NT) {
-      double acc = 0.0;
+    {
       const double* v = paper ? xk : r;
-#pragma unroll 8
-      for (int j = 0; j < n; ++j) acc += M[i + (int64_t)j * ldw] * v[j];
+      for (int j = t; j < n; j += NT) vs[j] = v[j];
+    }
+    __syncthreads();
+    for (int i = t; i < n; i += NT) {
+      // sixteen loads of the row in flight, then the products in order
+      double acc = 0.0;
+      for (int j0 = 0; j0 < n; j0 += 16) {
+        double mv[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) mv[u] = M[i + (int64_t)(j0 + u < n ? j0 + u : n - 1) * ldw];
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          if (j0 + u < n) acc += mv[u] * vs[j0 + u];
+      }
       const double xi = paper ? acc + c[i] : xk[i] + acc;
       xn[i] = xi;
       bad |= !isfinite(xi);
