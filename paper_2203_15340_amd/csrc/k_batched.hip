@@ -3,9 +3,11 @@
 // Each workgroup takes problems from an atomic queue (largest first) and
 // solves each one alone, keeping its working matrices in a private slot of
 // device memory (L2-resident at these sizes):
-//   1. column pass: g = A1^T b1 - A2^T b2 (Alg. 1 step 4), non-finite scan;
-//   2. Gram A1^T A1 on the matrix cores (FP64, or FP32 inputs with FP32
-//      accumulation in the mixed form), and A2^T A2 in the paper form;
+//   1.-2. paper form: the Gram products of the bordered blocks [A1 b1] and
+//      [A2 b2] on the matrix cores, which give A1^T A1, A2^T A2 and
+//      g = A1^T b1 - A2^T b2 (Alg. 1 steps 2-4) in one read of A; correction
+//      form: a column pass for g and the non-finite scan, then A1^T A1 (FP64,
+//      or FP32 inputs with FP32 accumulation in the mixed form);
 //   3. block Gauss-Jordan on [A1^T A1 | A2^T A2 | g] (paper form, giving B, c
 //      of Alg. 1) or [A1^T A1 | I] (correction form, giving P), 64-wide blocks,
 //      pivot blocks inverted by 16 x 16 blocks (invert64_blk);
@@ -95,7 +97,8 @@ __device__ inline double block_sum2(double v, Smem& s, int which) {
 }
 
 // G = A[0:K, :]^T A[0:K, :] (n x n, full) into W (ldw), one 64 x 64 lower tile
-// at a time.  Each tile streams K in stages of 32 rows: a thread holds 8
+// at a time.  With a border column vb (K entries) the product is that of
+// [A vb], whose border row A^T vb goes to gv (n entries).  Each tile streams K in stages of 32 rows: a thread holds 8
 // values of each operand panel in flight (one 256-byte column segment per
 // half wave per load), then the stage goes through LDS and the next stage's
 // loads are issued before the matrix-core work on the current one.  One
@@ -103,10 +106,13 @@ __device__ inline double block_sum2(double v, Smem& s, int which) {
 // the rate; the second workgroup on the CU covers its waits.
 template <typename T>
 __device__ __attribute__((noinline)) void wg_gram(const double* A_, int64_t lda, int K, int n, double* W_,
-                                                 int64_t ldw) {
+                                                 int64_t ldw, const double* vb_, double* gv_) {
   Smem& s = bsm;
   const auto A = glb(A_);
   const auto W = glb(W_);
+  const auto vb = glb(vb_);
+  const auto gv = glb(gv_);
+  const bool border = vb_ != nullptr;
   typedef typename Mma<T>::acc_t acc_t;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wr = (w >> 1) * 32, wc = (w & 1) * 32, lr = lane & 15;
@@ -114,7 +120,7 @@ __device__ __attribute__((noinline)) void wg_gram(const double* A_, int64_t lda,
   // CU, so registers are scarce and the other workgroup hides latency
   constexpr int SR = 32, NLD = SR / 4, CG = NT / SR;
   const int lk = t % SR, lc = t / SR;
-  const int nt = (n + kNB - 1) / kNB;
+  const int nt = (n + (border ? 1 : 0) + kNB - 1) / kNB;
   T(*As)[kNB + 1] = stage_a<T>(s);
   T(*Bs)[kNB + 1] = stage_b<T>(s);
   for (int ti = 0; ti < nt; ++ti) {
@@ -135,7 +141,9 @@ __device__ __attribute__((noinline)) void wg_gram(const double* A_, int64_t lda,
 #pragma unroll
         for (int q = 0; q < NLD; ++q) {
           const int c = lc + CG * q;
-          ra[q] = (kin && c < ci) ? (T)Ai[k + (int64_t)c * lda] : (T)0;
+          // column n of the bordered matrix is vb (it can only fall in a
+          // diagonal tile's column range when tj < ti, never in Aj's)
+          ra[q] = !kin ? (T)0 : c < ci ? (T)Ai[k + (int64_t)c * lda] : (border && c == ci) ? (T)vb[k] : (T)0;
           if (!diag) rb[q] = (kin && c < cj) ? (T)Aj[k + (int64_t)c * lda] : (T)0;
         }
       };
@@ -169,10 +177,12 @@ __device__ __attribute__((noinline)) void wg_gram(const double* A_, int64_t lda,
           for (int v = 0; v < 4; ++v) {
             const int i = ti * kNB + wr + a * 16 + Mma<T>::row(lane, v);
             const int j = tj * kNB + wc + c * 16 + lr;
+            const double val = (double)acc[a][c][v];
             if (i < n && j < n) {
-              const double val = (double)acc[a][c][v];
               W[i + (int64_t)j * ldw] = val;
               if (!diag) W[j + (int64_t)i * ldw] = val;
+            } else if (border && i == n && j < n) {
+              gv[j] = val;
             }
           }
     }
@@ -369,33 +379,52 @@ __device__ void solve_one(const BatchArgs& a, const BatchProblem& P, double* slo
   double* r = xb + a.nmax;
   out.iters = 0;
   out.metric = 0.0;
-  // 1. column pass (b staged in LDS; A columns read eight loads deep)
+  // 1. A^T J b and the screen for non-finite input.  Paper form: from the
+  // Gram products of the bordered blocks [A1 b1] and [A2 b2], whose border
+  // rows hold A1^T b1 and A2^T b2, so A is read once; a non-finite entry of A
+  // or b then shows in a Gram diagonal or in g.  Correction form: a column
+  // pass (b staged in LDS).
   bool ok = true;
-  double* bs = s.u.vec;
-  for (int i = t; i < m; i += NT) {
-    const double bv = glb(P.b)[i];
-    bs[i] = bv;
-    ok &= isfinite(bv);
-  }
-  __syncthreads();
-  for (int j = w; j < n; j += NT / kWave) {
-    const auto col = glb(P.A) + (int64_t)j * lda;
-    double s1 = 0.0, s2 = 0.0;
-#pragma unroll 8
-    for (int i = lane; i < p; i += kWave) {
-      const double av = col[i];
-      s1 += av * bs[i];
-      ok &= isfinite(av);
+  int nrhs;
+  if (paper) {
+    // 2. [A1^T A1 | A2^T A2 | g]
+    wg_gram<double>(P.A, lda, p, n, W, ldw, P.b, g);
+    wg_gram<double>(P.A + p, lda, q, n, W + (int64_t)n * ldw, ldw, P.b + p, xb);
+    for (int j = t; j < n; j += NT) {
+      const double gj = g[j] - xb[j];
+      g[j] = gj;
+      W[j + (int64_t)2 * n * ldw] = gj;
+      ok &= isfinite(gj) && isfinite(W[j + (int64_t)j * ldw]) && isfinite(W[j + (int64_t)(n + j) * ldw]);
     }
-#pragma unroll 8
-    for (int i = p + lane; i < m; i += kWave) {
-      const double av = col[i];
-      s2 += av * bs[i];
-      ok &= isfinite(av);
+    nrhs = n + 1;
+  } else {
+    double* bs = s.u.vec;
+    for (int i = t; i < m; i += NT) {
+      const double bv = glb(P.b)[i];
+      bs[i] = bv;
+      ok &= isfinite(bv);
     }
-    s1 = wave_sum(s1);
-    s2 = wave_sum(s2);
-    if (lane == 0) g[j] = s1 - s2;
+    __syncthreads();
+    for (int j = w; j < n; j += NT / kWave) {
+      const auto col = glb(P.A) + (int64_t)j * lda;
+      double s1 = 0.0, s2 = 0.0;
+#pragma unroll 8
+      for (int i = lane; i < p; i += kWave) {
+        const double av = col[i];
+        s1 += av * bs[i];
+        ok &= isfinite(av);
+      }
+#pragma unroll 8
+      for (int i = p + lane; i < m; i += kWave) {
+        const double av = col[i];
+        s2 += av * bs[i];
+        ok &= isfinite(av);
+      }
+      s1 = wave_sum(s1);
+      s2 = wave_sum(s2);
+      if (lane == 0) g[j] = s1 - s2;
+    }
+    nrhs = n;
   }
   if (__syncthreads_or(!ok)) {
     out.status = ILS_ERR_NONFINITE;
@@ -408,19 +437,13 @@ __device__ void solve_one(const BatchArgs& a, const BatchProblem& P, double* slo
     for (int j = t; j < n; j += NT) xr2 += glb(P.x_ref)[j] * glb(P.x_ref)[j];
     xr2 = block_sum2(xr2, s, 1);
   }
-  // 2. [A1^T A1 | A2^T A2 | g] or [A1^T A1 | I]
-  wg_gram<T>(P.A, lda, p, n, W, ldw);
-  int nrhs;
-  if (paper) {
-    wg_gram<double>(P.A + p, lda, q, n, W + (int64_t)n * ldw, ldw);
-    for (int j = t; j < n; j += NT) W[j + (int64_t)2 * n * ldw] = g[j];
-    nrhs = n + 1;
-  } else {
+  if (!paper) {
+    // 2. [A1^T A1 | I]
+    wg_gram<T>(P.A, lda, p, n, W, ldw, nullptr, nullptr);
     for (int e = t; e < n * n; e += NT) {
       const int i = e % n, j = e / n;
       W[i + (int64_t)(n + j) * ldw] = (i == j) ? 1.0 : 0.0;
     }
-    nrhs = n;
   }
   __syncthreads();
   // 3. elimination

@@ -123,3 +123,29 @@ def test_batched_errors():
     big = W.dense_ils(600, 10, 257, ratio=0.5, seed=1)
     _, infos, rc = ils.sp_solve_batched([(devA(big.A), dev(big.b), big.p)])
     assert rc == ils.ERR_ARG
+
+
+@pytest.mark.parametrize("form", [ils.FORM_PAPER, ils.FORM_CORRECTION])
+@pytest.mark.parametrize("where", ["A1", "A2", "b1", "b2"])
+@pytest.mark.parametrize("val", [np.nan, np.inf, -np.inf])
+def test_batched_nonfinite_inputs(form, where, val):
+    # paper form: caught through the bordered Gram products (a Gram diagonal or
+    # A^T J b turns non-finite); correction form: by the column pass
+    P = W.dense_ils(60, 30, 20, ratio=0.5, seed=4)
+    A, b = P.A.copy(), P.b.copy()
+    if where == "A1":
+        A[7, 3] = val
+    elif where == "A2":
+        A[P.p + 5, 11] = val
+    elif where == "b1":
+        b[2] = val
+    else:
+        b[P.p + 1] = val
+    out_good = torch.empty(P.n, dtype=torch.float64, device="cuda")
+    out_bad = torch.full((P.n,), 5.0, dtype=torch.float64, device="cuda")
+    xs, infos, rc = ils.sp_solve_batched([(devA(P.A), dev(P.b), P.p), (devA(A), dev(b), P.p)],
+                                         outs=[out_good, out_bad], form=form)
+    assert infos[0].status == ils.OK
+    assert infos[1].status == ils.ERR_NONFINITE
+    assert rc == ils.ERR_NONFINITE
+    assert torch.all(out_bad == 5.0)
