@@ -343,23 +343,43 @@ __device__ __attribute__((noinline)) void wg_residual(const double* A_, int64_t 
   const double* xs = bsm.u.vec + kXsOff;
   double* ts = bsm.u.vec;
   const int m = p + q, t = threadIdx.x, lane = t & 63, w = t >> 6;
+  // loads are gathered in batches of RB before their products, in order, so
+  // that a batch is in flight at once (entries past the end read as zero)
+  constexpr int RB = 16, CB = 8;
   for (int i = t; i < m; i += NT) {
     double acc = 0.0;
     const auto ai = A + i;
-#pragma unroll 8
-    for (int j = 0; j < n; ++j) acc += ai[(int64_t)j * lda] * xs[j];
+    for (int j0 = 0; j0 < n; j0 += RB) {
+      double av[RB];
+#pragma unroll
+      for (int u = 0; u < RB; ++u) av[u] = j0 + u < n ? ai[(int64_t)(j0 + u) * lda] : 0.0;
+#pragma unroll
+      for (int u = 0; u < RB; ++u)
+        if (j0 + u < n) acc += av[u] * xs[j0 + u];
+    }
     ts[i] = b[i] - acc;
   }
   __syncthreads();
+  auto colsum = [&](auto col, int lo, int hi) {
+    double sacc = 0.0;
+    for (int i0 = lo + lane; i0 < hi; i0 += CB * kWave) {
+      double av[CB];
+#pragma unroll
+      for (int u = 0; u < CB; ++u) {
+        const int i = i0 + u * kWave;
+        av[u] = i < hi ? col[i] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < CB; ++u) {
+        const int i = i0 + u * kWave;
+        if (i < hi) sacc += av[u] * ts[i];
+      }
+    }
+    return wave_sum(sacc);
+  };
   for (int j = w; j < n; j += NT / kWave) {
     const auto col = A + (int64_t)j * lda;
-    double s1 = 0.0, s2 = 0.0;
-#pragma unroll 8
-    for (int i = lane; i < p; i += kWave) s1 += col[i] * ts[i];
-#pragma unroll 8
-    for (int i = p + lane; i < m; i += kWave) s2 += col[i] * ts[i];
-    s1 = wave_sum(s1);
-    s2 = wave_sum(s2);
+    const double s1 = colsum(col, 0, p), s2 = colsum(col, p, m);
     if (lane == 0) r[j] = s1 - s2;
   }
   __syncthreads();
@@ -405,23 +425,29 @@ __device__ void solve_one(const BatchArgs& a, const BatchProblem& P, double* slo
       ok &= isfinite(bv);
     }
     __syncthreads();
+    // eight loads of a column in flight, then their products in order
+    auto colsum = [&](auto col, int lo, int hi) {
+      constexpr int CB = 8;
+      double sacc = 0.0;
+      for (int i0 = lo + lane; i0 < hi; i0 += CB * kWave) {
+        double av[CB];
+#pragma unroll
+        for (int u = 0; u < CB; ++u) {
+          const int i = i0 + u * kWave;
+          av[u] = i < hi ? col[i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < CB; ++u) {
+          const int i = i0 + u * kWave;
+          if (i < hi) sacc += av[u] * bs[i];
+          ok &= isfinite(av[u]);
+        }
+      }
+      return wave_sum(sacc);
+    };
     for (int j = w; j < n; j += NT / kWave) {
       const auto col = glb(P.A) + (int64_t)j * lda;
-      double s1 = 0.0, s2 = 0.0;
-#pragma unroll 8
-      for (int i = lane; i < p; i += kWave) {
-        const double av = col[i];
-        s1 += av * bs[i];
-        ok &= isfinite(av);
-      }
-#pragma unroll 8
-      for (int i = p + lane; i < m; i += kWave) {
-        const double av = col[i];
-        s2 += av * bs[i];
-        ok &= isfinite(av);
-      }
-      s1 = wave_sum(s1);
-      s2 = wave_sum(s2);
+      const double s1 = colsum(col, 0, p), s2 = colsum(col, p, m);
       if (lane == 0) g[j] = s1 - s2;
     }
     nrhs = n;
