@@ -376,6 +376,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the non-headline forms")
+    ap.add_argument("--forms", default="",
+                    help="comma-separated subset of the non-headline forms to time (default: all)")
     ap.add_argument("--no-batched", action="store_true", help="skip the 4096-problem batch")
     ap.add_argument("--no-warm-start", action="store_true", help="skip the learned warm start")
     ap.add_argument("--no-sparse", action="store_true", help="skip the sparse workload")
@@ -469,13 +471,18 @@ def main():
         log("other forms")
         forms["sp_fp64_paper"] = {"solves_per_s": value, "ms": ms, "outer": infos[-1].outer_iters,
                                   "rel_err": infos[-1].rel_err}
-        forms["sp_fp64_correction"] = time_form(ils.sp_solve, 5, form=ils.FORM_CORRECTION, **kw)
-        forms["sp_mixed_correction"] = time_form(ils.sp_solve, 5, form=ils.FORM_CORRECTION,
-                                                 precision=ils.PREC_MIXED, **kw)
-        forms["sp_scd_correction"] = time_form(ils.rgs_solve, 1, form=ils.FORM_CORRECTION, **kw)
-        forms["sp_rk_rgs_correction"] = time_form(ils.rk_solve, 1, form=ils.FORM_CORRECTION, **kw)
-        forms["sp_rk_rgs_mixed_correction"] = time_form(ils.rk_solve, 1, form=ils.FORM_CORRECTION,
-                                                        precision=ils.PREC_MIXED, **kw)
+        table = {
+            "sp_fp64_correction": (ils.sp_solve, 5, dict(form=ils.FORM_CORRECTION)),
+            "sp_mixed_correction": (ils.sp_solve, 5, dict(form=ils.FORM_CORRECTION, precision=ils.PREC_MIXED)),
+            "sp_scd_correction": (ils.rgs_solve, 1, dict(form=ils.FORM_CORRECTION)),
+            "sp_rk_rgs_correction": (ils.rk_solve, 1, dict(form=ils.FORM_CORRECTION)),
+            "sp_rk_rgs_mixed_correction": (ils.rk_solve, 1, dict(form=ils.FORM_CORRECTION,
+                                                                 precision=ils.PREC_MIXED)),
+        }
+        pick = [f for f in args.forms.split(",") if f] or list(table)
+        for name in pick:
+            fn, reps, extra = table[name]
+            forms[name] = time_form(fn, reps, **extra, **kw)
         ils.set_profiling(True)
 
     batched = None
