@@ -134,20 +134,13 @@ __device__ inline void blk_row(const double* cur, double* nxt, const double* P, 
 // into B0; B1 is a second buffer of the same shape.  All 256 threads call it
 // after a barrier that makes B0 complete; returns false in every thread when
 // a pivot is not > 0 (the matrix is not positive definite).
-__device__ __attribute__((always_inline)) inline bool invert64_blk(double* B0, double* B1, InvBlk& S) {
+// The block steps of invert64_blk, given the inverse of B0's (0,0) block
+// already in B1's (0,0) block and S.bad set (a caller that forms B0 itself can
+// invert that first block while the rest is still being formed).
+__device__ __attribute__((always_inline)) inline bool invert64_steps(double* B0, double* B1, InvBlk& S) {
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int li = lane & 15, lg = lane >> 4;
   const v4d zero = {0.0, 0.0, 0.0, 0.0};
-  if (w == 0) {
-    double a[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) a[c] = B0[li * kLds + 4 * lg + c];
-    const bool ok = leaf_inv16(a, lane);
-#pragma unroll
-    for (int c = 0; c < 4; ++c) B1[li * kLds + 4 * lg + c] = a[c];
-    if (lane == 0) S.bad = ok ? 0 : 1;
-  }
-  __syncthreads();
 #pragma unroll 1
   for (int K = 0; K < 4; ++K) {
     double* cur = (K & 1) ? B1 : B0;
@@ -194,6 +187,22 @@ __device__ __attribute__((always_inline)) inline bool invert64_blk(double* B0, d
     __syncthreads();
   }
   return S.bad == 0;
+}
+
+__device__ __attribute__((always_inline)) inline bool invert64_blk(double* B0, double* B1, InvBlk& S) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  if (w == 0) {
+    double a[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) a[c] = B0[li * kLds + 4 * lg + c];
+    const bool ok = leaf_inv16(a, lane);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) B1[li * kLds + 4 * lg + c] = a[c];
+    if (lane == 0) S.bad = ok ? 0 : 1;
+  }
+  __syncthreads();
+  return invert64_steps(B0, B1, S);
 }
 
 }  // namespace ils

@@ -378,6 +378,7 @@ __device__ inline void flow_signal(int* p) {
 __global__ __launch_bounds__(kGjThreads, kFlowOcc) void k_gj_flow(GjFlow a) {
   __shared__ double As[kNB][kNB + 1];  // A operand: As[i][k]
   __shared__ double Bs[kNB][kNB + 1];  // B operand: Bs[j][k]
+  __shared__ double Ds[kNB][kNB + 1];  // L_k: the next pivot block, then its inverse
   __shared__ InvBlk inv;
   __shared__ int s_tk, s_ok;
   if (__hip_atomic_load(a.bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
@@ -530,25 +531,79 @@ __global__ __launch_bounds__(kGjThreads, kFlowOcc) void k_gj_flow(GjFlow a) {
           for (int q = 0; q < 4; ++q) {
             const int j = jr + x * 16 + (lane >> 4) + 4 * q, i = ic + y * 16 + lr;
             Bs[j][i] = acc[(x * 2 + y) * 4 + q];
+            Ds[i][j] = cv[(x * 2 + y) * 4 + q];  // C, row-major
           }
       __syncthreads();
-      product(acc);  // M R
+      bool inv_ok;
+      double(*Dinv)[kNB + 1];
+      if (nbn == kNB) {
+        // D = C - M R is symmetric: its lower 16 x 16 blocks are formed and
+        // mirrored, and wave 0 takes block (0, 0) alone and inverts it while
+        // waves 1-3 form the other nine
+        const int li = lane & 15, lg = lane >> 4;
+        auto block_d = [&](int bi, int bj) {
+          v4d d = ld16(&Ds[16 * bi][16 * bj], kLds, lane);
 #pragma unroll
-      for (int q = 0; q < 16; ++q) cv[q] -= acc[q];
-      // right-hand-side columns sharing the short last block's strip
-      store_out(cv, k1, k1, n, k1 + nbn, ncols);
-      __syncthreads();
-#pragma unroll
-      for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int y = 0; y < 2; ++y)
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int j = jr + x * 16 + (lane >> 4) + 4 * q, i = ic + y * 16 + lr;
-            As[i][j] = (i < nbn && j < nbn) ? cv[(x * 2 + y) * 4 + q] : (i == j ? 1.0 : 0.0);
+          for (int kk = 0; kk < kNB; kk += 4) {
+            const int kr = kk + lg;
+            d = __builtin_amdgcn_mfma_f64_16x16x4f64(-As[16 * bi + li][kr], Bs[16 * bj + li][kr], d, 0, 0, 0);
           }
-      __syncthreads();
-      if (!invert64_blk(&As[0][0], &Bs[0][0], inv)) {
+          return d;
+        };
+        if (w == 0) {
+          st16(&Ds[0][0], kLds, block_d(0, 0), lane);
+          __threadfence_block();
+          double av[4];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) av[c] = Ds[li][4 * lg + c];
+          const bool okl = leaf_inv16(av, lane);
+#pragma unroll
+          for (int c = 0; c < 4; ++c) inv.x[li][4 * lg + c] = av[c];
+          if (lane == 0) inv.bad = okl ? 0 : 1;
+        } else {
+          // (1,0) (1,1) (2,0) | (2,1) (2,2) (3,0) | (3,1) (3,2) (3,3)
+#pragma unroll
+          for (int q = 0; q < 3; ++q) {
+            const int e = 3 * (w - 1) + q;
+            const int bi = e < 2 ? 1 : (e < 5 ? 2 : 3);
+            const int bj = e - (bi == 1 ? 0 : (bi == 2 ? 2 : 5));
+            const v4d d = block_d(bi, bj);
+            st16(&Ds[16 * bi][16 * bj], kLds, d, lane);
+            if (bi != bj) {
+#pragma unroll
+              for (int u = 0; u < 4; ++u) Ds[16 * bj + li][16 * bi + lg + 4 * u] = d[u];
+            }
+          }
+        }
+        __syncthreads();
+        if (w == 0) {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) Bs[li][4 * lg + c] = inv.x[li][4 * lg + c];
+        }
+        __syncthreads();
+        inv_ok = invert64_steps(&Ds[0][0], &Bs[0][0], inv);
+        Dinv = Ds;
+      } else {
+        product(acc);  // M R
+#pragma unroll
+        for (int q = 0; q < 16; ++q) cv[q] -= acc[q];
+        // right-hand-side columns sharing the short last block's strip
+        store_out(cv, k1, k1, n, k1 + nbn, ncols);
+        __syncthreads();
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int j = jr + x * 16 + (lane >> 4) + 4 * q, i = ic + y * 16 + lr;
+              As[i][j] = (i < nbn && j < nbn) ? cv[(x * 2 + y) * 4 + q] : (i == j ? 1.0 : 0.0);
+            }
+        __syncthreads();
+        inv_ok = invert64_blk(&As[0][0], &Bs[0][0], inv);
+        Dinv = As;
+      }
+      if (!inv_ok) {
         if (t == 0) atomicOr(a.bits, kBitNotSpd);
         continue;
       }
@@ -556,7 +611,7 @@ __global__ __launch_bounds__(kGjThreads, kFlowOcc) void k_gj_flow(GjFlow a) {
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         const int e = t + q * kGjThreads;
-        ast(dn + e, As[e >> 6][e & (kNB - 1)]);
+        ast(dn + e, Dinv[e >> 6][e & (kNB - 1)]);
       }
       flow_signal(a.dflag + k + 1);
       continue;
