@@ -30,7 +30,10 @@
  * ILS_ERR_NO_CONVERGENCE x holds the last iterate, which may be passed back
  * as x0 to resume: each method converges from any start (Thm 2.1, 3.2, 4.1).
  * ILS_ERR_NONFINITE is also returned when an iterate becomes non-finite; x
- * then holds that iterate.
+ * then holds that iterate.  ILS_ERR_HIP reports a failed HIP call, and also a
+ * device-side wait of the one-launch elimination (n <= 2048) that ran out of
+ * its bounded spin, which does not happen in normal operation; x is then left
+ * untouched.
  */
 #ifndef ILS_H
 #define ILS_H
