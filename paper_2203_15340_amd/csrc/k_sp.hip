@@ -24,6 +24,40 @@ constexpr int kSpRows = 4;
 // lane partials are added by a fixed butterfly.
 constexpr int kDotDepth = 16;
 
+// The first round's loads alone, so a caller can issue them early, and the
+// rest of dot_row from there (the same sums in the same order).
+__device__ inline void dot_first(const double* row_, const double* v_, int64_t n, int lane,
+                                 double (&rv)[kDotDepth], double (&vv)[kDotDepth]) {
+  const auto row = glb(row_);
+  const auto v = glb(v_);
+#pragma unroll
+  for (int u = 0; u < kDotDepth; ++u) {
+    const int64_t j = lane + u * kWave;
+    rv[u] = j < n ? row[j] : 0.0;
+    vv[u] = j < n ? v[j] : 0.0;
+  }
+}
+__device__ inline double dot_rest(const double* row_, const double* v_, int64_t n, int lane,
+                                  const double (&rv0)[kDotDepth], const double (&vv0)[kDotDepth]) {
+  const auto row = glb(row_);
+  const auto v = glb(v_);
+  double s = 0.0;
+#pragma unroll
+  for (int u = 0; u < kDotDepth; ++u) s = fma(rv0[u], vv0[u], s);
+  for (int64_t j0 = kDotDepth * kWave; j0 < n; j0 += kDotDepth * kWave) {
+    double rv[kDotDepth], vv[kDotDepth];
+#pragma unroll
+    for (int u = 0; u < kDotDepth; ++u) {
+      const int64_t j = j0 + lane + u * kWave;
+      rv[u] = j < n ? row[j] : 0.0;
+      vv[u] = j < n ? v[j] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kDotDepth; ++u) s = fma(rv[u], vv[u], s);
+  }
+  return wave_sum(s);
+}
+
 __device__ inline double dot_row(const double* row_, const double* v_, int64_t n, int lane) {
   const auto row = glb(row_);
   const auto v = glb(v_);
@@ -47,6 +81,15 @@ __global__ __launch_bounds__(256) void k_sp_step(SpStepArgs a, int64_t k) {
   if (*(volatile int*)&st->done || *(volatile int*)&st->bits) return;
   __shared__ double tred[256 / kWave];
   const unsigned nblk = gridDim.x;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * kSpRows + w;
+  const double* xk = (k & 1) ? a.xbuf1 : a.xbuf0;
+  const double* row = a.Mrow + i * a.ldm;
+  const double* v = (a.form == ILS_FORM_PAPER) ? xk : a.r;
+  // this step's row loads go out first; their latency overlaps the stopping
+  // test of the previous step
+  double rv0[kDotDepth], vv0[kDotDepth];
+  if (i < a.n) dot_first(row, v, a.n, lane, rv0, vv0);
   if (k >= 1) {
     // stopping test for x_{k-1} from the partials of launch k - 1: strided
     // per thread, then the block tree (the same order in every workgroup)
@@ -79,7 +122,6 @@ __global__ __launch_bounds__(256) void k_sp_step(SpStepArgs a, int64_t k) {
     if (done) {
       // the returned iterate goes straight to the caller's x
       const double* xs = (iters & 1) ? a.xbuf1 : a.xbuf0;
-      const int64_t i = (int64_t)blockIdx.x * kSpRows + (threadIdx.x >> 6);
       if ((threadIdx.x & 63) == 0 && i < a.n) a.x_out[i] = xs[i];
       if (blockIdx.x == 0 && threadIdx.x == 0) {
         st->metric = metric;
@@ -90,17 +132,12 @@ __global__ __launch_bounds__(256) void k_sp_step(SpStepArgs a, int64_t k) {
       return;
     }
   }
-  const double* xk = (k & 1) ? a.xbuf1 : a.xbuf0;
   double* xn = (k & 1) ? a.xbuf0 : a.xbuf1;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t i = (int64_t)blockIdx.x * kSpRows + w;
   double mp = 0.0;
   int bad = 0;
   if (i < a.n) {
-    const double* row = a.Mrow + i * a.ldm;
-    const double* v = (a.form == ILS_FORM_PAPER) ? xk : a.r;
-    const double xi = (a.form == ILS_FORM_PAPER) ? dot_row(row, v, a.n, lane) + a.c[i]
-                                                 : xk[i] + dot_row(row, v, a.n, lane);
+    const double dot = dot_rest(row, v, a.n, lane, rv0, vv0);
+    const double xi = (a.form == ILS_FORM_PAPER) ? dot + a.c[i] : xk[i] + dot;
     if (a.stop_rule == ILS_STOP_XREF) {
       const double d = xk[i] - a.x_ref[i];
       mp = d * d;
