@@ -271,7 +271,7 @@ int ils::sp_solve_op(ils_handle* h, const MatOp& M, const double* b, const doubl
   launch_gj(s, n, nrhs, W, ldw, dinv, &ds->bits);
   h->mark(5);
   launch_transpose(s, n, n, W + n * ldw, ldw, Mrow, n);
-  launch_fill_vec(s, n, x0, xb0);
+  if (!paper) launch_fill_vec(s, n, x0, xb0);  // the paper form's step 0 reads x0 itself
   h->mark(6);
 
   SpStepArgs a;
@@ -286,6 +286,7 @@ int ils::sp_solve_op(ils_handle* h, const MatOp& M, const double* b, const doubl
   a.xbuf0 = xb0;
   a.xbuf1 = xb1;
   a.x_out = x;
+  a.x0 = x0;
   a.r = rv;
   a.partials = spart;
   a.nonfinite_part = sbad;

@@ -185,6 +185,7 @@ struct SpStepArgs {
   double* xbuf0;
   double* xbuf1;
   double* x_out;        // the caller's x, written when the loop finishes
+  const double* x0;     // paper form: the caller's x0 (null: zero), read by step 0
   const double* r;      // correction form: residual at x_k (n)
   double* partials;     // per-block metric partials, two sets of sp_step_blocks(n)
   int* nonfinite_part;  // per-block flags, two sets

@@ -34,7 +34,7 @@ __device__ inline void dot_first(const double* row_, const double* v_, int64_t n
   for (int u = 0; u < kDotDepth; ++u) {
     const int64_t j = lane + u * kWave;
     rv[u] = j < n ? row[j] : 0.0;
-    vv[u] = j < n ? v[j] : 0.0;
+    vv[u] = (v_ && j < n) ? v[j] : 0.0;  // v_ null: the zero vector
   }
 }
 __device__ inline double dot_rest(const double* row_, const double* v_, int64_t n, int lane,
@@ -50,7 +50,7 @@ __device__ inline double dot_rest(const double* row_, const double* v_, int64_t 
     for (int u = 0; u < kDotDepth; ++u) {
       const int64_t j = j0 + lane + u * kWave;
       rv[u] = j < n ? row[j] : 0.0;
-      vv[u] = j < n ? v[j] : 0.0;
+      vv[u] = (v_ && j < n) ? v[j] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < kDotDepth; ++u) s = fma(rv[u], vv[u], s);
@@ -83,7 +83,10 @@ __global__ __launch_bounds__(256) void k_sp_step(SpStepArgs a, int64_t k) {
   const unsigned nblk = gridDim.x;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t i = (int64_t)blockIdx.x * kSpRows + w;
-  const double* xk = (k & 1) ? a.xbuf1 : a.xbuf0;
+  // paper form, step 0: x_0 is read from the caller's x0 (null: zero) and
+  // copied to the first buffer here, so no separate fill launch is needed
+  const bool first = k == 0 && a.form == ILS_FORM_PAPER;
+  const double* xk = first ? a.x0 : ((k & 1) ? a.xbuf1 : a.xbuf0);
   const double* row = a.Mrow + i * a.ldm;
   const double* v = (a.form == ILS_FORM_PAPER) ? xk : a.r;
   // this step's row loads go out first; their latency overlaps the stopping
@@ -137,14 +140,16 @@ __global__ __launch_bounds__(256) void k_sp_step(SpStepArgs a, int64_t k) {
   int bad = 0;
   if (i < a.n) {
     const double dot = dot_rest(row, v, a.n, lane, rv0, vv0);
-    const double xi = (a.form == ILS_FORM_PAPER) ? dot + a.c[i] : xk[i] + dot;
+    const double xki = xk ? xk[i] : 0.0;
+    if (first && lane == 0) a.xbuf0[i] = xki;
+    const double xi = (a.form == ILS_FORM_PAPER) ? dot + a.c[i] : xki + dot;
     if (a.stop_rule == ILS_STOP_XREF) {
-      const double d = xk[i] - a.x_ref[i];
+      const double d = xki - a.x_ref[i];
       mp = d * d;
     } else if (a.stop_rule == ILS_STOP_RR) {
       // (A^T J b - A^T J A x_k)_i in the paper form (A^T J A symmetric), r_k in
       // the correction form
-      const double ri = (a.form == ILS_FORM_PAPER) ? a.g[i] - dot_row(a.H + i * a.ldh, xk, a.n, lane)
+      const double ri = (a.form == ILS_FORM_PAPER) ? a.g[i] - (xk ? dot_row(a.H + i * a.ldh, xk, a.n, lane) : 0.0)
                                                    : a.r[i];
       mp = ri * ri;
     }
