@@ -31,7 +31,7 @@ extern "C" int ils_tune_gram(ils_handle* h, int64_t K, int64_t n, const double* 
   HIPCHK(hipSetDevice(h->device));
   hipStream_t s = h->stream;
   const int tiles[2] = {64, 128};
-  const int targets[6] = {256, 512, 1024, 2048, 4096, 8192};
+  const int targets[10] = {256, 512, 1024, 1536, 2048, 3072, 4096, 5120, 6144, 8192};
   size_t part_max = 0;
   for (int t : tiles)
     for (int w : targets) part_max = std::max(part_max, gram_partials_size_cfg(n, K, GramCfg{t, w}));
