@@ -256,9 +256,8 @@ int ils::sp_solve_op(ils_handle* h, const MatOp& M, const double* b, const doubl
   else
     mat_gram(s, M, 0, o->precision, part, W, ldw, mid);
   h->mark(3);
+  GjCombine pre{g, rv, W + 2 * n * ldw};  // bordered: A^T J b formed by the elimination's first kernel
   if (bordered) {
-    launch_border_combine(s, n, g, rv, W, W + n * ldw, ldw, W + 2 * n * ldw, &ds->bits);
-    if (o->stop_rule == ILS_STOP_RR) launch_norm2(s, n, g, &ds->scal[0]);
     if (need_h) launch_sub(s, n, W, ldw, W + n * ldw, ldw, H, n);
   } else if (paper) {
     mat_gram(s, M, 1, ILS_PREC_FP64, part, W + n * ldw, ldw);
@@ -268,7 +267,8 @@ int ils::sp_solve_op(ils_handle* h, const MatOp& M, const double* b, const doubl
     launch_eye(s, n, W + n * ldw, ldw);
   }
   h->mark(4);
-  launch_gj(s, n, nrhs, W, ldw, dinv, &ds->bits);
+  launch_gj(s, n, nrhs, W, ldw, dinv, &ds->bits, bordered ? &pre : nullptr);
+  if (bordered && o->stop_rule == ILS_STOP_RR) launch_norm2(s, n, g, &ds->scal[0]);
   h->mark(5);
   launch_transpose(s, n, n, W + n * ldw, ldw, Mrow, n);
   if (!paper) launch_fill_vec(s, n, x0, xb0);  // the paper form's step 0 reads x0 itself

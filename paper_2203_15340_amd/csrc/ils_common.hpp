@@ -168,9 +168,18 @@ void launch_sub(hipStream_t s, int64_t n, const double* X, int64_t ldx, const do
                 double* Z, int64_t ldz);
 
 // Block Gauss-Jordan on W = [G | R] (n x (n + nrhs), column-major, ldw);
-// scratch is gj_scratch_bytes(n, n + nrhs) bytes of device memory.
+// scratch is gj_scratch_bytes(n, n + nrhs) bytes of device memory.  With pre,
+// the elimination first forms one right-hand-side column from the bordered
+// Gram products, exactly as launch_border_combine with G1 = W and G2 = W + n ldw
+// (the one-launch form does it in its first kernel).
+struct GjCombine {
+  double* g;         // A1^T b1 in, A^T J b out (n)
+  const double* g2;  // A2^T b2 (n)
+  double* gcol;      // the column of W that receives A^T J b
+};
 size_t gj_scratch_bytes(int64_t n, int64_t ncols);
-void launch_gj(hipStream_t s, int64_t n, int64_t nrhs, double* W, int64_t ldw, void* scratch, int* bits);
+void launch_gj(hipStream_t s, int64_t n, int64_t nrhs, double* W, int64_t ldw, void* scratch, int* bits,
+               const GjCombine* pre = nullptr);
 
 // SP outer step kernels (k_sp.hip).
 struct SpStepArgs {

@@ -316,6 +316,7 @@ struct GjFlow {
   int* lflag;    // R
   unsigned* ticket;
   int* bits;
+  GjCombine pre;  // optional right-hand-side column formed first (see launch_gj)
 };
 
 struct FlowStep {
@@ -690,6 +691,21 @@ __global__ __launch_bounds__(kGjThreads) void k_gj_flow_init(GjFlow a) {
   const int t = threadIdx.x;
   const int64_t nint = 2 * (int64_t)a.R * a.S + 2 * a.R + 1;  // cnt, pdone, dflag, lflag, ticket
   for (int64_t e = t; e < nint; e += kGjThreads) a.cnt[e] = 0;
+  if (a.pre.g) {
+    // the right-hand-side column g = g1 - g2 and the screen of g and of the
+    // diagonals of the two Gram blocks (columns 0..n-1 and n..2n-1 of W)
+    int bad = 0;
+    for (int64_t j = t; j < a.n; j += kGjThreads) {
+      const double v = a.pre.g[j] - a.pre.g2[j];
+      a.pre.g[j] = v;
+      a.pre.gcol[j] = v;
+      bad |= !isfinite(v) || !isfinite(a.W[j + j * a.ldw]) || !isfinite(a.W[j + (a.n + j) * a.ldw]);
+    }
+    if (__syncthreads_or(bad)) {
+      if (t == 0) atomicOr(a.bits, kBitNonfinite);
+      return;
+    }
+  }
   if (__hip_atomic_load(a.bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
   const int nb = (int)(a.n < kNB ? a.n : kNB);
   double dv[16];
@@ -730,7 +746,8 @@ size_t gj_scratch_bytes(int64_t n, int64_t ncols) {
 }
 
 
-void launch_gj(hipStream_t s, int64_t n, int64_t nrhs, double* W, int64_t ldw, void* scratch, int* bits) {
+void launch_gj(hipStream_t s, int64_t n, int64_t nrhs, double* W, int64_t ldw, void* scratch, int* bits,
+               const GjCombine* pre) {
   const int64_t ncols = n + nrhs;
   const int row_tiles = (int)((n + kNB - 1) / kNB);
   if (flow_fits(n) && ncols > n) {
@@ -748,10 +765,12 @@ void launch_gj(hipStream_t s, int64_t n, int64_t nrhs, double* W, int64_t ldw, v
     a.lflag = a.dflag + a.R;
     a.ticket = (unsigned*)(a.lflag + a.R);
     a.bits = bits;
+    a.pre = pre ? *pre : GjCombine{nullptr, nullptr, nullptr};
     hipLaunchKernelGGL(k_gj_flow_init, dim3(1), dim3(kGjThreads), 0, s, a);
     hipLaunchKernelGGL(k_gj_flow, dim3(kFlowWgs), dim3(kGjThreads), 0, s, a);
     return;
   }
+  if (pre) launch_border_combine(s, n, pre->g, pre->g2, W, W + n * ldw, ldw, pre->gcol, bits);
   double* dinv = (double*)scratch;
   hipLaunchKernelGGL(k_gj_inv0, dim3(1), dim3(kGjThreads), 0, s, (const double*)W, ldw,
                      (int)(n < kNB ? n : kNB), dinv, bits);
