@@ -107,7 +107,10 @@ typedef struct {
   int64_t inner_iters;   /* randomized methods: inner steps over all outer steps */
   double rr;             /* RR at the returned x when stop_rule == ILS_STOP_RR, else NaN */
   double rel_err;        /* ||x - x_ref|| / ||x_ref|| when x_ref is given, else -1 */
-  double device_ms;      /* time between the first and last queued kernel */
+  double device_ms;      /* device time from the first to the last queued kernel:
+                          * measured while phase timing is on
+                          * (ils_set_profiling), else 0; the batched solver
+                          * always measures it */
 } ils_info;
 
 typedef struct ils_handle ils_handle;
@@ -349,20 +352,31 @@ int ils_tune_clear(void);
 
 /* ---- instrumentation ---- */
 
-/* Turn phase timing of ils_sp_solve on (enable != 0) or off.  When on, the
- * library records HIP events between the phases of each solve on the
- * handle's stream; kernel work is unchanged. */
-int ils_set_profiling(ils_handle* h, int enable);
+/* Phase timing of ils_sp_solve: the library records HIP events on the
+ * handle's stream, between the phases of each solve (ILS_PROFILE_PHASES) or
+ * only around the main Gram kernel (ILS_PROFILE_GRAM).  Kernel work is
+ * unchanged, but each event costs a few microseconds of device time, so the
+ * second mode is the one to keep on while timing whole solves.  Returns
+ * ILS_ERR_ARG for another mode. */
+enum {
+  ILS_PROFILE_OFF = 0,
+  ILS_PROFILE_PHASES = 1,
+  ILS_PROFILE_GRAM = 2
+};
+int ils_set_profiling(ils_handle* h, int mode);
 
 /* Durations in ms of the phases of the last profiled ils_sp_solve, written
- * to ms[0 .. count-1] (host): [0] column pass (correction form, sparse A)
+ * to ms[0 .. count-1] (host; under ILS_PROFILE_GRAM only [1] is measured and
+ * the others are NaN): [0] column pass (correction form, sparse A)
  * and norms, [1] main Gram kernel (dense paper form: A1^T A1 and A2^T A2 with
- * the border columns b1, b2 in one launch; otherwise A1^T A1), [2] its
- * split-K reduction, [3] the other Gram product if separate and right-hand
+ * the border columns b1, b2 in one launch, queued first; otherwise A1^T A1),
+ * [2] its split-K reduction (dense paper form: also the loop-state reset and
+ * the norms), [3] the other Gram product if separate and right-hand
  * side assembly, [4] block Gauss-Jordan, [5] iteration matrix layout and
  * start vector, [6] outer iterations (including the host's polls of the stop
  * flag).
- * Returns the number of phases written, or a negative ils_status. */
+ * Returns the number of phases written, or a negative ils_status
+ * (ILS_ERR_ARG when profiling is off). */
 int ils_get_phase_times(ils_handle* h, double* ms, int count);
 
 #ifdef __cplusplus

@@ -152,9 +152,17 @@ _handles = {}
 def handle(device=None):
     """Library handle bound to `device` and torch's current stream there."""
     torch = _torch()
+    dev = None
+    if device is not None:
+        dev = device.index if isinstance(device, torch.device) else torch.device(device).index
+    if dev is not None and _handles:
+        # repeated calls: the raw current stream and one lookup (host time
+        # here is time the device waits for the first kernel of a solve)
+        h = _handles.get((dev, torch._C._cuda_getCurrentRawStream(dev)))
+        if h is not None:
+            return h
     if not torch.cuda.is_available():
         raise ILSError("no GPU visible: the ILS library runs only on the GPU")
-    dev = None if device is None else torch.device(device).index
     if dev is None:
         dev = torch.cuda.current_device()
     stream = torch.cuda.current_stream(dev).cuda_stream
@@ -194,11 +202,18 @@ def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
 
 
+_opts_default = None
+
+
 def make_opts(tol=1e-6, stop_rule=STOP_RR, form=FORM_PAPER, precision=PREC_FP64,
               sampling=SAMPLE_UNIFORM, x_ref=None, max_outer=20000, max_inner=-1, inner_tol=-1.0,
               inner_check=-1, seed=0, stream_offset=0, alpha=0):
-    o = Opts()
-    load_library().ils_opts_default(C.byref(o))
+    global _opts_default
+    if _opts_default is None:
+        d = Opts()
+        load_library().ils_opts_default(C.byref(d))
+        _opts_default = bytes(d)
+    o = Opts.from_buffer_copy(_opts_default)
     o.tol, o.stop_rule, o.form, o.precision, o.sampling = tol, stop_rule, form, precision, sampling
     o.x_ref = None if x_ref is None else x_ref.data_ptr()
     o.max_outer, o.max_inner, o.inner_tol, o.inner_check = max_outer, max_inner, inner_tol, inner_check
@@ -351,12 +366,21 @@ def scd_subsets(seed, outer, t0, count, n, alpha_opt=0, device="cuda"):
     return alpha, mask
 
 
-def set_profiling(enable=True, device=None):
-    _rc(load_library().ils_set_profiling(handle(device), int(bool(enable))), "ils_set_profiling")
+PROFILE_OFF, PROFILE_PHASES, PROFILE_GRAM = 0, 1, 2
+
+
+def set_profiling(mode=PROFILE_PHASES, device=None):
+    """Phase events of sp_solve: PROFILE_PHASES (every phase), PROFILE_GRAM
+    (the main Gram kernel only, the cheap one to leave on while timing) or
+    PROFILE_OFF; True / False mean PROFILE_PHASES / PROFILE_OFF."""
+    if mode is True or mode is False:
+        mode = PROFILE_PHASES if mode else PROFILE_OFF
+    _rc(load_library().ils_set_profiling(handle(device), int(mode)), "ils_set_profiling")
 
 
 def phase_times(device=None):
-    """Phase durations (ms) of the last profiled sp_solve, keyed by PHASES."""
+    """Phase durations (ms) of the last profiled sp_solve, keyed by PHASES
+    (NaN for the phases PROFILE_GRAM does not time)."""
     buf = (C.c_double * len(PHASES))()
     n = load_library().ils_get_phase_times(handle(device), buf, len(PHASES))
     if n < 0:

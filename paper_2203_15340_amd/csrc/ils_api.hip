@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 
 #include "ils_common.hpp"
 #include "ils_runtime.hpp"
@@ -185,7 +186,7 @@ int ils::finish_info(ils_handle* h, int64_t n, double* x, const ils_opts* o, int
     info->rel_err = v;
   }
   float ms = 0.0f;
-  if (hipEventElapsedTime(&ms, h->ev0, h->ev1) == hipSuccess) info->device_ms = ms;
+  info->device_ms = (h->timing() && hipEventElapsedTime(&ms, h->ev0, h->ev1) == hipSuccess) ? ms : 0.0;
   return status;
 }
 
@@ -197,10 +198,22 @@ int ils::setup_status(const LoopState& s) {
   return ILS_OK;
 }
 
+// Wait for the handle's stream: poll it for up to 20 ms, then block.  A
+// blocking wait sleeps and is woken well after the work ends, time the
+// device then spends idle before the caller's next solve reaches it.
+static int stream_wait(hipStream_t s) {
+  const auto t0 = std::chrono::steady_clock::now();
+  while (std::chrono::steady_clock::now() - t0 < std::chrono::milliseconds(20)) {
+    const hipError_t e = hipStreamQuery(s);
+    if (e == hipSuccess) return ILS_OK;
+    if (e != hipErrorNotReady) return ILS_ERR_HIP;
+  }
+  return hipStreamSynchronize(s) == hipSuccess ? ILS_OK : ILS_ERR_HIP;
+}
+
 int ils::read_state(ils_handle* h) {
   HIPCHK(hipMemcpyAsync(h->st_host, h->st, sizeof(LoopState), hipMemcpyDeviceToHost, h->stream));
-  HIPCHK(hipStreamSynchronize(h->stream));
-  return ILS_OK;
+  return stream_wait(h->stream);
 }
 
 // ------------------------------------------------------------------ SP
@@ -236,25 +249,30 @@ int ils::sp_solve_op(ils_handle* h, const MatOp& M, const double* b, const doubl
       (st = h->need(kBufDinv, gj_scratch_bytes(n, n + nrhs), (void**)&dinv)))
     return fail(info, st);
 
-  HIPCHK(hipMemsetAsync(h->st, 0, sizeof(LoopState), s));
-  HIPCHK(hipEventRecord(h->ev0, s));
+  if (h->timing()) HIPCHK(hipEventRecord(h->ev0, s));
   h->mark(0);
   LoopState* ds = h->st;
   // dense paper form: A^T J b = A1^T b1 - A2^T b2 comes from the Gram
-  // products of the bordered blocks [A1 b1] and [A2 b2], so A is read once
+  // products of the bordered blocks [A1 b1] and [A2 b2], so A is read once.
+  // That launch pair touches no loop state, so it goes first: the device
+  // starts on it while the host queues the rest of the solve.
   const bool bordered = paper && !M.sp;
+  hipEvent_t mid = h->gram_end_event();
+  if (bordered) {  // A1^T A1, A1^T b1 and A2^T A2, A2^T b2 in one launch pair
+    h->mark(1);
+    launch_gram2_f64(s, n, M.lda, ldw, (double*)part, mid, p, M.A, b, W, g, q, M.A + p, b + p, W + n * ldw, rv);
+  }
+  HIPCHK(hipMemsetAsync(h->st, 0, sizeof(LoopState), s));
   if (!bordered) {
     mat_colpass(s, M, b, g, nullptr, &ds->bits);
     if (o->stop_rule == ILS_STOP_RR) launch_norm2(s, n, g, &ds->scal[0]);
   }
   if (o->stop_rule == ILS_STOP_XREF) launch_norm2(s, n, o->x_ref, &ds->scal[1]);
-  h->mark(1);
   // [A1^T A1 | A2^T A2 | A^T J b] (paper form) or [A1^T A1 | I] (correction form)
-  hipEvent_t mid = h->profile ? h->pev[2] : nullptr;
-  if (bordered)  // A1^T A1, A1^T b1 and A2^T A2, A2^T b2 in one launch pair
-    launch_gram2_f64(s, n, M.lda, ldw, (double*)part, mid, p, M.A, b, W, g, q, M.A + p, b + p, W + n * ldw, rv);
-  else
+  if (!bordered) {
+    h->mark(1);
     mat_gram(s, M, 0, o->precision, part, W, ldw, mid);
+  }
   h->mark(3);
   GjCombine pre{g, rv, W + 2 * n * ldw};  // bordered: A^T J b formed by the elimination's first kernel
   if (bordered) {
@@ -305,7 +323,7 @@ int ils::sp_solve_op(ils_handle* h, const MatOp& M, const double* b, const doubl
       if (!paper && k <= o->max_outer) mat_residual(s, M, b, k & 1 ? xb1 : xb0, tv, rv, &ds->done);
       launch_sp_step(s, a, k);
     }
-    HIPCHK(hipEventRecord(h->ev1, s));
+    if (h->timing()) HIPCHK(hipEventRecord(h->ev1, s));
     if ((st = read_state(h))) return fail(info, st);
     if (h->st_host->done || h->st_host->bits || k > o->max_outer + 1) break;
     chunk = std::min<int64_t>(chunk * 2, 64);
@@ -392,21 +410,23 @@ extern "C" int ils_spd_solve(ils_handle* h, int64_t n, int64_t nrhs, const doubl
 }
 
 // ------------------------------------------------------------------ instrumentation
-extern "C" int ils_set_profiling(ils_handle* h, int enable) {
-  if (!h) return ILS_ERR_ARG;
-  h->profile = enable != 0;
+extern "C" int ils_set_profiling(ils_handle* h, int mode) {
+  if (!h || mode < ILS_PROFILE_OFF || mode > ILS_PROFILE_GRAM) return ILS_ERR_ARG;
+  h->profile = mode;
   return ILS_OK;
 }
 
 extern "C" int ils_get_phase_times(ils_handle* h, double* ms, int count) {
   if (!h || !ms || count < 0) return ILS_ERR_ARG;
+  if (h->profile == ILS_PROFILE_OFF) return ILS_ERR_ARG;
   HIPCHK(hipSetDevice(h->device));
-  HIPCHK(hipEventSynchronize(h->pev[ils_handle::kPhases]));
+  const bool all = h->profile == ILS_PROFILE_PHASES;
+  HIPCHK(hipEventSynchronize(h->pev[all ? ils_handle::kPhases : 2]));
   const int nph = count < ils_handle::kPhases ? count : ils_handle::kPhases;
   for (int i = 0; i < nph; ++i) {
     float v = 0.0f;
-    HIPCHK(hipEventElapsedTime(&v, h->pev[i], h->pev[i + 1]));
-    ms[i] = v;
+    if (all || i == 1) HIPCHK(hipEventElapsedTime(&v, h->pev[i], h->pev[i + 1]));
+    ms[i] = (all || i == 1) ? (double)v : NAN;
   }
   return nph;
 }

@@ -71,7 +71,7 @@ extern "C" int ils_sp_solve_multi(ils_handle* h, int64_t p, int64_t q, int64_t n
 
   LoopState* ds = h->st;
   HIPCHK(hipMemsetAsync(ds, 0, sizeof(LoopState), s));
-  HIPCHK(hipEventRecord(h->ev0, s));
+  if (h->timing()) HIPCHK(hipEventRecord(h->ev0, s));
   launch_gram_f64(s, p, n, A, lda, (double*)part, W, ldw);
   launch_gram_f64(s, q, n, A + p, lda, (double*)part, W + n * ldw, ldw);
   if (rr) launch_sub(s, n, W, ldw, W + n * ldw, ldw, H, n);
@@ -164,7 +164,7 @@ extern "C" int ils_sp_solve_multi(ils_handle* h, int64_t p, int64_t q, int64_t n
       launch_multi_metric(s, ma, k);
     }
     if (!fixed || k == 0) {
-      HIPCHK(hipEventRecord(h->ev1, s));
+      if (h->timing()) HIPCHK(hipEventRecord(h->ev1, s));
       if ((st = read_state(h))) return fail_multi(info, st);
       const LoopState& hs = *h->st_host;
       if (hs.bits & kBitNotSpd) return fail_multi(info, ILS_ERR_NOT_SPD);
@@ -186,7 +186,7 @@ extern "C" int ils_sp_solve_multi(ils_handle* h, int64_t p, int64_t q, int64_t n
     std::swap(cur, nxt);
   }
   launch_mat_copy(s, n, nrhs, cur, n, X, ldx);
-  HIPCHK(hipEventRecord(h->ev1, s));
+  if (h->timing()) HIPCHK(hipEventRecord(h->ev1, s));
   HIPCHK(hipGetLastError());
 
   std::vector<int> hact(nrhs);
@@ -238,7 +238,7 @@ extern "C" int ils_sp_solve_multi(ils_handle* h, int64_t p, int64_t q, int64_t n
     info->inner_iters = 0;
     info->rr = rr ? worst_rr : NAN;
     float ms = 0.0f;
-    info->device_ms = hipEventElapsedTime(&ms, h->ev0, h->ev1) == hipSuccess ? ms : 0.0;
+    info->device_ms = (h->timing() && hipEventElapsedTime(&ms, h->ev0, h->ev1) == hipSuccess) ? ms : 0.0;
   }
   return status;
 }

@@ -67,7 +67,7 @@ static int common_setup(ils_handle* h, const MatOp& M, const double* b, const do
     return st;
   if (!paper) c.G2 = nullptr;
   HIPCHK(hipMemsetAsync(h->st, 0, sizeof(LoopState), s));
-  HIPCHK(hipEventRecord(h->ev0, s));
+  if (h->timing()) HIPCHK(hipEventRecord(h->ev0, s));
   mat_colpass(s, M, b, c.g, cn, &h->st->bits);
   if (o->stop_rule == ILS_STOP_RR) launch_norm2(s, n, c.g, &h->st->scal[0]);
   if (o->stop_rule == ILS_STOP_XREF) launch_norm2(s, n, o->x_ref, &h->st->scal[1]);
@@ -99,7 +99,7 @@ static int outer_begin(ils_handle* h, const MatOp& M, const double* b, const ils
 
 static int finish(ils_handle* h, int64_t n, double* x, const ils_opts* o, Common& c, int64_t inner_total,
                   ils_info* info) {
-  HIPCHK(hipEventRecord(h->ev1, h->stream));
+  if (h->timing()) HIPCHK(hipEventRecord(h->ev1, h->stream));
   int st = read_state(h);
   if (st) return fail_info(info, st);
   const LoopState& hs = *h->st_host;

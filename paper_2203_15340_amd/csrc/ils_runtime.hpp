@@ -65,7 +65,7 @@ struct ils_handle {
   ils::LoopState* st_host = nullptr;  // pinned host mirror
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   static constexpr int kPhases = 7;
-  bool profile = false;
+  int profile = ILS_PROFILE_OFF;  // ILS_PROFILE_*
   hipEvent_t pev[kPhases + 1] = {};
   // SP outer launches queued before the first look at the loop state: the
   // previous solve's count plus the deciding launch (a guess; too few costs a
@@ -79,8 +79,16 @@ struct ils_handle {
   hipGraphExec_t bexec = nullptr;
   std::vector<char> bkey;
   void mark(int i) {
-    if (profile) (void)hipEventRecord(pev[i], stream);
+    if (profile == ILS_PROFILE_PHASES || (profile == ILS_PROFILE_GRAM && i == 1))
+      (void)hipEventRecord(pev[i], stream);
   }
+  // the event that closes the main Gram kernel (recorded between it and its
+  // split-K reduction), or null when not profiling
+  hipEvent_t gram_end_event() const { return profile != ILS_PROFILE_OFF ? pev[2] : nullptr; }
+  // ils_info::device_ms of the single-problem solvers is measured only while
+  // phase timing is on: an event record costs host time at the start of a
+  // solve, while the device waits for its first kernel
+  bool timing() const { return profile != ILS_PROFILE_OFF; }
   ~ils_handle();
   int need(int slot, size_t bytes, void** out);
 };

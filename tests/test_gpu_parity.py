@@ -217,6 +217,31 @@ def test_sp_x0_and_resume(prob):
     assert rel(host(x2), ref2) < 1e-10
 
 
+def test_sp_profiling_modes(prob):
+    """Phase events change no result; each mode times what it promises."""
+    P, A, b, xs = prob
+    kw = dict(stop_rule=ils.STOP_XREF, x_ref=xs, tol=1e-10)
+    try:
+        ils.set_profiling(ils.PROFILE_OFF)
+        x0, _ = ils.sp_solve(A, b, P.p, **kw)
+        with pytest.raises(ils.ILSError):
+            ils.phase_times()
+        ils.set_profiling(ils.PROFILE_GRAM)
+        x1, _ = ils.sp_solve(A, b, P.p, **kw)
+        ph = ils.phase_times()
+        assert ph["gram"] > 0.0
+        assert all(np.isnan(v) for k, v in ph.items() if k != "gram")
+        ils.set_profiling(ils.PROFILE_PHASES)
+        x2, _ = ils.sp_solve(A, b, P.p, **kw)
+        ph = ils.phase_times()
+        assert all(np.isfinite(v) and v >= 0.0 for v in ph.values()) and ph["gram"] > 0.0
+        with pytest.raises(ils.ILSError):
+            ils.set_profiling(3)
+        assert np.array_equal(host(x0), host(x1)) and np.array_equal(host(x0), host(x2))
+    finally:
+        ils.set_profiling(ils.PROFILE_OFF)
+
+
 def test_sp_mixed_reaches_x_ils(prob):
     P, A, b, xs = prob
     x, info = ils.sp_solve(A, b, P.p, precision=ils.PREC_MIXED, form=ils.FORM_CORRECTION,
