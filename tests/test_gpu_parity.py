@@ -91,6 +91,20 @@ def test_residual(prob):
     assert rel(host(r), ref) < 1e-12
 
 
+@pytest.mark.parametrize("shape", [(1100, 60, 1024), (1200, 90, 1025), (40, 0, 1), (37, 5, 30)],
+                         ids=["one_pass_max_n", "two_pass", "n1", "ragged_rows"])
+def test_residual_paths(shape):
+    """Both residual paths (one pass over A up to n = 1024, two passes above),
+    a single column, and fewer 16-row blocks than workgroups with a ragged
+    last block."""
+    p, q, n = shape
+    P = W.dense_ils(p, q, n, ratio=0.5, seed=p + q + n)
+    x = np.random.default_rng(2).standard_normal(n)
+    r = ils.residual(devA(P.A), dev(P.b), P.p, dev(x))
+    ref = O.residual(P.A, P.b, P.p, x)
+    assert rel(host(r), ref) < 1e-12
+
+
 def test_spd_solve(prob):
     P, A, b, _ = prob
     G1 = O.gram(P.A, 0, P.p)
