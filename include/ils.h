@@ -367,11 +367,11 @@ int ils_set_profiling(ils_handle* h, int mode);
 
 /* Durations in ms of the phases of the last profiled ils_sp_solve, written
  * to ms[0 .. count-1] (host; under ILS_PROFILE_GRAM only [1] is measured and
- * the others are NaN): [0] column pass (correction form, sparse A)
- * and norms, [1] main Gram kernel (dense paper form: A1^T A1 and A2^T A2 with
- * the border columns b1, b2 in one launch, queued first; otherwise A1^T A1),
- * [2] its split-K reduction (dense paper form: also the loop-state reset and
- * the norms), [3] the other Gram product if separate and right-hand
+ * the others are NaN): [0] solve start to the main Gram kernel (nothing:
+ * that launch is queued first), [1] main Gram kernel (dense paper form:
+ * A1^T A1 and A2^T A2 with the border columns b1, b2 in one launch;
+ * otherwise A1^T A1), [2] its split-K reduction, the loop-state reset, the
+ * column pass (correction form, sparse A) and the norms, [3] the other Gram product if separate and right-hand
  * side assembly, [4] block Gauss-Jordan, [5] iteration matrix layout and
  * start vector, [6] outer iterations (including the host's polls of the stop
  * flag).

@@ -254,25 +254,21 @@ int ils::sp_solve_op(ils_handle* h, const MatOp& M, const double* b, const doubl
   LoopState* ds = h->st;
   // dense paper form: A^T J b = A1^T b1 - A2^T b2 comes from the Gram
   // products of the bordered blocks [A1 b1] and [A2 b2], so A is read once.
-  // That launch pair touches no loop state, so it goes first: the device
-  // starts on it while the host queues the rest of the solve.
+  // The Gram launch touches no loop state, so it goes first in every form:
+  // the device starts on it while the host queues the rest of the solve.
   const bool bordered = paper && !M.sp;
   hipEvent_t mid = h->gram_end_event();
-  if (bordered) {  // A1^T A1, A1^T b1 and A2^T A2, A2^T b2 in one launch pair
-    h->mark(1);
+  h->mark(1);
+  if (bordered)  // A1^T A1, A1^T b1 and A2^T A2, A2^T b2 in one launch pair
     launch_gram2_f64(s, n, M.lda, ldw, (double*)part, mid, p, M.A, b, W, g, q, M.A + p, b + p, W + n * ldw, rv);
-  }
+  else  // A1^T A1 for [A1^T A1 | A2^T A2 | A^T J b] or [A1^T A1 | I]
+    mat_gram(s, M, 0, o->precision, part, W, ldw, mid);
   HIPCHK(hipMemsetAsync(h->st, 0, sizeof(LoopState), s));
   if (!bordered) {
     mat_colpass(s, M, b, g, nullptr, &ds->bits);
     if (o->stop_rule == ILS_STOP_RR) launch_norm2(s, n, g, &ds->scal[0]);
   }
   if (o->stop_rule == ILS_STOP_XREF) launch_norm2(s, n, o->x_ref, &ds->scal[1]);
-  // [A1^T A1 | A2^T A2 | A^T J b] (paper form) or [A1^T A1 | I] (correction form)
-  if (!bordered) {
-    h->mark(1);
-    mat_gram(s, M, 0, o->precision, part, W, ldw, mid);
-  }
   h->mark(3);
   GjCombine pre{g, rv, W + 2 * n * ldw};  // bordered: A^T J b formed by the elimination's first kernel
   if (bordered) {
