@@ -337,50 +337,62 @@ constexpr int kXsOff = 4096;  // x_k's offset in the LDS vector area
 constexpr int kVsOff = 4608;  // the outer product's vector (n <= 256 entries)
 __device__ __attribute__((noinline)) void wg_residual(const double* A_, int64_t lda, int p, int q, int n,
                                                      const double* b_, double* r_) {
+  // One pass over A: the workgroup takes blocks of 16 rows; thread
+  // (k = t % 16, g = t / 16) holds row k of the block at columns g, g + 16,
+  // ... (n <= 256: 16 values), t_k = b_k - (A x)_k is formed with the other 15
+  // column groups through LDS, and J_kk t_k A_kc is added to the thread's
+  // column sums, which a 16-lane butterfly adds at the end.
+  constexpr int R = 16, G = NT / R, PER = 16;
   const auto A = glb(A_);
   const auto b = glb(b_);
   const auto r = glb(r_);
   const double* xs = bsm.u.vec + kXsOff;
-  double* ts = bsm.u.vec;
+  double* red = bsm.u.vec;           // [NT / kWave][R]
+  double* tk = bsm.u.vec + 4 * R;    // [R]
   const int m = p + q, t = threadIdx.x, lane = t & 63, w = t >> 6;
-  // loads are gathered in batches of RB before their products, in order, so
-  // that a batch is in flight at once (entries past the end read as zero)
-  constexpr int RB = 16, CB = 8;
-  for (int i = t; i < m; i += NT) {
-    double acc = 0.0;
-    const auto ai = A + i;
-    for (int j0 = 0; j0 < n; j0 += RB) {
-      double av[RB];
+  const int k = t & (R - 1), g = t / R;
+  double acc[PER];
 #pragma unroll
-      for (int u = 0; u < RB; ++u) av[u] = j0 + u < n ? ai[(int64_t)(j0 + u) * lda] : 0.0;
+  for (int u = 0; u < PER; ++u) acc[u] = 0.0;
+  for (int i0 = 0; i0 < m; i0 += R) {
+    const int i = i0 + k;
+    double av[PER];
 #pragma unroll
-      for (int u = 0; u < RB; ++u)
-        if (j0 + u < n) acc += av[u] * xs[j0 + u];
+    for (int u = 0; u < PER; ++u) {
+      const int c = g + G * u;
+      av[u] = (i < m && c < n) ? A[i + (int64_t)c * lda] : 0.0;
     }
-    ts[i] = b[i] - acc;
+    const double bi = (t < R && i < m) ? b[i] : 0.0;
+    double sdot = 0.0;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) sdot = fma(av[u], (g + G * u < n) ? xs[g + G * u] : 0.0, sdot);
+    sdot += __shfl_xor(sdot, 16);
+    sdot += __shfl_xor(sdot, 32);
+    if (lane < R) red[w * R + k] = sdot;
+    __syncthreads();
+    if (t < R) {
+      const double tot = ((red[t] + red[R + t]) + red[2 * R + t]) + red[3 * R + t];
+      double tv = 0.0;
+      if (i < m) {
+        tv = bi - tot;
+        if (i >= p) tv = -tv;  // J = diag(I_p, -I_q)
+      }
+      tk[t] = tv;
+    }
+    __syncthreads();
+    const double tj = tk[k];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) acc[u] = fma(tj, av[u], acc[u]);
   }
-  __syncthreads();
-  auto colsum = [&](auto col, int lo, int hi) {
-    double sacc = 0.0;
-    for (int i0 = lo + lane; i0 < hi; i0 += CB * kWave) {
-      double av[CB];
 #pragma unroll
-      for (int u = 0; u < CB; ++u) {
-        const int i = i0 + u * kWave;
-        av[u] = i < hi ? col[i] : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < CB; ++u) {
-        const int i = i0 + u * kWave;
-        if (i < hi) sacc += av[u] * ts[i];
-      }
-    }
-    return wave_sum(sacc);
-  };
-  for (int j = w; j < n; j += NT / kWave) {
-    const auto col = A + (int64_t)j * lda;
-    const double s1 = colsum(col, 0, p), s2 = colsum(col, p, m);
-    if (lane == 0) r[j] = s1 - s2;
+  for (int u = 0; u < PER; ++u) {
+    double v = acc[u];
+    v += __shfl_xor(v, 1);
+    v += __shfl_xor(v, 2);
+    v += __shfl_xor(v, 4);
+    v += __shfl_xor(v, 8);
+    const int c = g + G * u;
+    if (k == 0 && c < n) r[c] = v;
   }
   __syncthreads();
 }
