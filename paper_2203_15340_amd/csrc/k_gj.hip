@@ -689,24 +689,8 @@ __global__ __launch_bounds__(kGjThreads) void k_gj_flow_init(GjFlow a) {
   __shared__ double Es[kNB][kLds];
   __shared__ InvBlk inv;
   const int t = threadIdx.x;
-  const int64_t nint = 2 * (int64_t)a.R * a.S + 2 * a.R + 1;  // cnt, pdone, dflag, lflag, ticket
-  for (int64_t e = t; e < nint; e += kGjThreads) a.cnt[e] = 0;
-  if (a.pre.g) {
-    // the right-hand-side column g = g1 - g2 and the screen of g and of the
-    // diagonals of the two Gram blocks (columns 0..n-1 and n..2n-1 of W)
-    int bad = 0;
-    for (int64_t j = t; j < a.n; j += kGjThreads) {
-      const double v = a.pre.g[j] - a.pre.g2[j];
-      a.pre.g[j] = v;
-      a.pre.gcol[j] = v;
-      bad |= !isfinite(v) || !isfinite(a.W[j + j * a.ldw]) || !isfinite(a.W[j + (a.n + j) * a.ldw]);
-    }
-    if (__syncthreads_or(bad)) {
-      if (t == 0) atomicOr(a.bits, kBitNonfinite);
-      return;
-    }
-  }
-  if (__hip_atomic_load(a.bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+  // the first pivot block's loads go out first (columns 0..63: untouched by
+  // the right-hand-side column written below)
   const int nb = (int)(a.n < kNB ? a.n : kNB);
   double dv[16];
 #pragma unroll
@@ -714,6 +698,41 @@ __global__ __launch_bounds__(kGjThreads) void k_gj_flow_init(GjFlow a) {
     const int e = t + q * kGjThreads, r = e & (kNB - 1), c = e >> 6;
     dv[q] = (r < nb && c < nb) ? a.W[r + (int64_t)c * a.ldw] : (r == c ? 1.0 : 0.0);
   }
+  const int64_t nint = 2 * (int64_t)a.R * a.S + 2 * a.R + 1;  // cnt, pdone, dflag, lflag, ticket
+  for (int64_t e = t; e < nint; e += kGjThreads) a.cnt[e] = 0;
+  if (a.pre.g) {
+    // the right-hand-side column g = g1 - g2 and the screen of g and of the
+    // diagonals of the two Gram blocks (columns 0..n-1 and n..2n-1 of W); the
+    // one-launch form has n <= kFlowMaxRows * 64, so each thread's entries
+    // are loaded in one batch
+    constexpr int kPer = kFlowMaxRows * kNB / kGjThreads;
+    double g1[kPer], g2[kPer], d1[kPer], d2[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int64_t j = t + (int64_t)u * kGjThreads;
+      const bool in = j < a.n;
+      g1[u] = in ? a.pre.g[j] : 0.0;
+      g2[u] = in ? a.pre.g2[j] : 0.0;
+      d1[u] = in ? a.W[j + j * a.ldw] : 0.0;
+      d2[u] = in ? a.W[j + (a.n + j) * a.ldw] : 0.0;
+    }
+    int bad = 0;
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int64_t j = t + (int64_t)u * kGjThreads;
+      if (j < a.n) {
+        const double v = g1[u] - g2[u];
+        a.pre.g[j] = v;
+        a.pre.gcol[j] = v;
+        bad |= !isfinite(v) || !isfinite(d1[u]) || !isfinite(d2[u]);
+      }
+    }
+    if (__syncthreads_or(bad)) {
+      if (t == 0) atomicOr(a.bits, kBitNonfinite);
+      return;
+    }
+  }
+  if (__hip_atomic_load(a.bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
     const int e = t + q * kGjThreads;
