@@ -93,6 +93,34 @@ def cpu_baseline(P):
                       f"{info.outer_iters} outer iterations"}
 
 
+def bench_ratio09(ils, W, np, torch):
+    """The headline problem with A2 scaled to ||A2|| = 0.9 sigma_min(A1) (the
+    same A1 and x*, slower outer convergence): the SP forms, FP64 and mixed."""
+    log("ratio 0.9 variant")
+    P = W.large(ratio=0.9, seed=1)
+    A = torch.from_numpy(np.ascontiguousarray(P.A.T)).cuda().t()
+    b = torch.from_numpy(P.b).cuda()
+    xs = torch.from_numpy(P.x_star).cuda()
+    x = torch.empty(P.n, dtype=torch.float64, device="cuda")
+    kw = dict(stop_rule=ils.STOP_XREF, x_ref=xs, tol=1e-6)
+    out = {"workload": "dense ILS, A1 18000x1000 + A2 2000x1000 Gaussian, ||A2|| = 0.9 sigma_min(A1), "
+                       "b = A x* + 1e-8 noise, to ||x-x*||/||x*|| < 1e-6"}
+    for name, reps, extra in (("sp_fp64_paper", 20, {}),
+                              ("sp_fp64_correction", 5, dict(form=ils.FORM_CORRECTION)),
+                              ("sp_mixed_correction", 5, dict(form=ils.FORM_CORRECTION, precision=ils.PREC_MIXED))):
+        ils.sp_solve(A, b, P.p, out=x, **kw, **extra)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            _, inf = ils.sp_solve(A, b, P.p, out=x, **kw, **extra)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t) / reps
+        out[name] = {"solves_per_s": 1.0 / el, "ms": el * 1e3, "outer": inf.outer_iters,
+                     "rel_err": inf.rel_err, "status": inf.status}
+    log(f"ratio 0.9: {out}")
+    return out
+
+
 def bench_batched(ils, W, np, torch, count=4096, single_sample=256):
     """4096 independent problems, n ~ U{32..256}, p = 4n, q = n/2, solved to
     rel.err 1e-6 in one persistent launch (graph replay) vs one ils_sp_solve
@@ -500,6 +528,8 @@ def main():
             forms[name] = time_form(fn, reps, **extra, **kw)
         ils.set_profiling(True)
 
+    ratio09 = None if args.no_forms else bench_ratio09(ils, W, np, torch)
+
     batched = None
     if not args.no_batched:
         batched = bench_batched(ils, W, np, torch)
@@ -543,6 +573,7 @@ def main():
                      "flops_per_launch": gram_flops, "avg_launch_ms": gram_avg},
         "phases_ms": ph,
         "forms": forms,
+        "ratio_0_9": ratio09,
         "batched": batched,
         "warm_start": warm,
         "sparse": sparse,

@@ -59,6 +59,24 @@ def test_headline_correction_form_matches_oracle(big):
     assert np.linalg.norm(xh - ref) / np.linalg.norm(ref) < 1e-10
 
 
+def test_headline_ratio_09_matches_oracle():
+    """The slower-converging variant of the same problem (||A2|| = 0.9
+    sigma_min(A1)): same outer count as the oracle, iterates to 1e-10."""
+    P = W.large(ratio=0.9, seed=1)
+    A = torch.from_numpy(np.ascontiguousarray(P.A.T)).cuda().t()
+    b, xs = torch.from_numpy(P.b).cuda(), torch.from_numpy(P.x_star).cuda()
+    ils.tune_load(TUNE)
+    try:
+        x, info = ils.sp_solve(A, b, P.p, stop_rule=ils.STOP_XREF, x_ref=xs, tol=1e-6)
+    finally:
+        ils.tune_clear()
+    ref, rinfo = O.sp_solve(P.A, P.b, P.p, stop_rule=O.STOP_XREF, x_ref=P.x_star, tol=1e-6)
+    assert info.status == ils.OK and rinfo.status == O.OK
+    assert info.outer_iters == rinfo.outer_iters
+    xh = x.cpu().numpy()
+    assert np.linalg.norm(xh - ref) / np.linalg.norm(ref) < 1e-10
+
+
 def _sample_pairs(n, rng, count=48):
     # tile edges (64-column tiles), the last column, and random pairs
     edges = [0, 1, 63, 64, 127, 128, 511, 512, 959, 960, n - 2, n - 1]
