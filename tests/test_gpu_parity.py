@@ -115,14 +115,20 @@ def test_spd_solve(prob):
 
 
 @pytest.mark.parametrize("n,nrhs", [(1, 1), (63, 2), (64, 64), (65, 1), (128, 129), (129, 64), (300, 301),
-                                    (960, 1), (1000, 1001), (2047, 3), (2048, 2049), (2049, 2)])
+                                    (960, 1), (1000, 1001), (2047, 3), (2048, 2049), (2049, 2),
+                                    (4096, 3), (4097, 2)])
 def test_spd_solve_block_edges(n, nrhs):
     # block edges of the 64-wide Gauss-Jordan: one block, exact multiples, ragged tails;
     # up to 32 block rows the elimination is one dataflow launch, above it one
-    # launch pair per block step (2048 / 2049)
+    # launch pair per block step (2048 / 2049); 4096 and 4097 are the large
+    # step-by-step cases
     rng = np.random.default_rng(n)
-    X = rng.standard_normal((3 * n + 5, n))
-    G = X.T @ X
+    if n <= 2048:
+        X = rng.standard_normal((3 * n + 5, n))
+        G = X.T @ X
+    else:  # a nearly square X, shifted to keep G as well conditioned as above
+        X = rng.standard_normal((n + 5, n))
+        G = X.T @ X + n * np.eye(n)
     R = rng.standard_normal((n, nrhs))
     rc, Y = ils.spd_solve(devA(G), devA(R))
     assert rc == ils.OK
