@@ -71,7 +71,11 @@ enum {
 enum {
   ILS_PREC_FP64 = 0,  /* every step in FP64 */
   ILS_PREC_MIXED = 1  /* A1^T A1 and the inner sweeps in FP32, residual and
-                         update in FP64; needs ILS_FORM_CORRECTION */
+                         update in FP64; needs ILS_FORM_CORRECTION.  SP: FP32
+                         Gram of A1, FP64 elimination.  SP-RK-RGS: FP32 copy
+                         of A1, FP32 w and s.  SP-SCD: FP32 A1^T A1 and FP32
+                         residual r in the coordinate steps (beta FP64).
+                         Dense A only. */
 };
 
 /* SP-SCD column choice (Alg. 5 and Remark 4.1). */
@@ -147,7 +151,12 @@ int ils_rk_solve(ils_handle* h, int64_t p, int64_t q, int64_t n, const double* A
 
 /* SP-SCD, Algorithm 5: each outer step runs coordinate descent on
  * A1^T A1 beta = bhat from beta = 0, taking at step t the coordinate of
- * largest |residual| within a uniformly random subset of size alpha_t. */
+ * largest |residual| within a uniformly random subset of size alpha_t.
+ * Random subsets (ILS_SAMPLE_UNIFORM with alpha < n) need n <= 4096; the
+ * greedy choice (alpha >= n) and SP-RCD (alpha = 1, ILS_SAMPLE_NORM) take any
+ * n.  ILS_PREC_MIXED (with ILS_FORM_CORRECTION): A1^T A1 is formed in FP32
+ * and the coordinate steps keep it and the inner residual in FP32 with FP32
+ * sums; the outer residual A^T J (b - A x_k) and x stay FP64. */
 int ils_rgs_solve(ils_handle* h, int64_t p, int64_t q, int64_t n, const double* A, int64_t lda,
                   const double* b, const double* x0, double* x, const ils_opts* opts,
                   ils_info* info /* host */);

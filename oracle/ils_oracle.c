@@ -233,20 +233,34 @@ double ora_rr(int64_t p, int64_t q, int64_t n, const double* A, int64_t lda,
 /* Cholesky G = L L^T (L lower, column-major n x n, strict upper set to 0).
  * Returns ORA_ERR_NOT_SPD on a pivot that is not > 0 (NaN included). */
 int ora_cholesky(int64_t n, const double* G, double* L) {
-  memset(L, 0, sizeof(double) * (size_t)n * (size_t)n);
-  for (int64_t j = 0; j < n; ++j) {
+  /* column-by-column (left-looking) Cholesky.  The rows of L are kept in a
+     row-major copy R (R[i n + k] = L_ik) so that the inner products over k
+     read contiguous memory; the sums are the same, in the same order. */
+  double* R = (double*)calloc((size_t)n * (size_t)n, sizeof(double));
+  int st = ORA_OK;
+  for (int64_t j = 0; j < n && st == ORA_OK; ++j) {
+    const double* Rj = R + (size_t)j * n;
     double d = G[(size_t)j * n + j];
-    for (int64_t k = 0; k < j; ++k) d -= L[(size_t)k * n + j] * L[(size_t)k * n + j];
-    if (!(d > 0.0)) return ORA_ERR_NOT_SPD;
+    for (int64_t k = 0; k < j; ++k) d -= Rj[k] * Rj[k];
+    if (!(d > 0.0)) { st = ORA_ERR_NOT_SPD; break; }
     double ljj = sqrt(d);
-    L[(size_t)j * n + j] = ljj;
+    R[(size_t)j * n + j] = ljj;
+    /* the entries below the diagonal of column j are independent of each other */
+#pragma omp parallel for schedule(static) if (n - j > 256)
     for (int64_t i = j + 1; i < n; ++i) {
+      const double* Ri = R + (size_t)i * n;
       double s = G[(size_t)j * n + i];
-      for (int64_t k = 0; k < j; ++k) s -= L[(size_t)k * n + i] * L[(size_t)k * n + j];
-      L[(size_t)j * n + i] = s / ljj;
+      for (int64_t k = 0; k < j; ++k) s -= Ri[k] * Rj[k];
+      R[(size_t)i * n + j] = s / ljj;
     }
   }
-  return ORA_OK;
+  if (st == ORA_OK) {
+    memset(L, 0, sizeof(double) * (size_t)n * (size_t)n);
+    for (int64_t j = 0; j < n; ++j)
+      for (int64_t i = j; i < n; ++i) L[(size_t)j * n + i] = R[(size_t)i * n + j];
+  }
+  free(R);
+  return st;
 }
 
 /* x = (L L^T)^{-1} rhs by forward then backward substitution. */

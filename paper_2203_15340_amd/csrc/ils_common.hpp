@@ -22,7 +22,7 @@ enum : int {
 
 // Device-side state of an outer loop (one per handle).
 struct LoopState {
-  int done;           // 0 running, 1 finished
+  int done;           // 0 running, else finished (SP step: deciding launch + 1)
   int status;         // ils_status of the finished loop
   int64_t iters;      // outer updates performed when done
   double metric;      // stop quantity at the final iterate

@@ -236,6 +236,12 @@ int ils::rgs_solve_op(ils_handle* h, const MatOp& M, const double* b, const doub
       (st = h->need(kBufDinv, gj_scratch_bytes(n, n), (void**)&dinv)))
     return fail_info(info, st);
   jpre = alpha_buf + chunk;
+  // mixed precision: the inner sweeps read an FP32 A1^T A1 and keep r in FP32
+  const bool mixed = o->precision == ILS_PREC_MIXED;
+  float *G1f = nullptr, *rf = nullptr;
+  if (mixed && ((st = h->need(kBufA1f32, sizeof(float) * n * n, (void**)&G1f)) ||
+                (st = h->need(kBufA1f, sizeof(float) * n, (void**)&rf))))
+    return fail_info(info, st);
   if ((st = common_setup(h, M, b, x0, o, nullptr, c))) return fail_info(info, st);
   mat_gram(s, M, 0, o->precision, c.part, G1, n);
   // positive definiteness of A1^T A1 (the elimination is only a test here)
@@ -243,20 +249,26 @@ int ils::rgs_solve_op(ils_handle* h, const MatOp& M, const double* b, const doub
   launch_gj(s, n, 0, W, n, dinv, &h->st->bits);
   launch_diag(s, n, G1, n, diag);
   launch_prefix(s, n, diag, 1, prefix);
+  if (mixed) launch_to_f32(s, n, n, G1, n, G1f);  // FP32 sums already: exact
   int64_t inner_total = 0;
   for (int64_t k = 0;; ++k) {
     int over = 0;
     if ((st = outer_begin(h, M, b, o, c, k, &over))) return fail_info(info, st);
     if (over) break;
-    launch_fill_vec(s, n, c.tgt, r);
+    if (mixed) launch_to_f32(s, n, 1, c.tgt, n, rf);
+    else launch_fill_vec(s, n, c.tgt, r);
     HIPCHK(hipMemsetAsync(beta, 0, sizeof(double) * n, s));
     int64_t t = 0;
     while (true) {
       const int64_t cnt = std::min(chunk, max_inner - t);
       launch_scd_draw(s, o->seed, (uint64_t)k + o->stream_offset, t, cnt, n, o->alpha, norm_mode, prefix,
                       alpha_buf, jpre, mask, words);
-      launch_scd_inner(s, G1, n, n, r, beta, mask, words, jpre, norm_mode, cnt, !fixed, itol * itol,
-                       &h->st->scal[2], &h->st->inner_done, &h->st->steps, &h->st->done);
+      if (mixed)
+        launch_scd_inner_f32(s, G1f, n, n, rf, beta, mask, words, jpre, norm_mode, cnt, !fixed, itol * itol,
+                             &h->st->scal[2], &h->st->inner_done, &h->st->steps, &h->st->done);
+      else
+        launch_scd_inner(s, G1, n, n, r, beta, mask, words, jpre, norm_mode, cnt, !fixed, itol * itol,
+                         &h->st->scal[2], &h->st->inner_done, &h->st->steps, &h->st->done);
       t += cnt;
       if ((st = read_state(h))) return fail_info(info, st);
       if (h->st_host->inner_done || t >= max_inner || h->st_host->done) break;

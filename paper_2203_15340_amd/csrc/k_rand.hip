@@ -292,31 +292,32 @@ void launch_rk_check_f32(hipStream_t st, const double* A1, int64_t lda, int64_t 
 }
 
 // ------------------------------------------------------------------ SCD inner
-// One workgroup runs up to `count` inner steps of Alg. 5 (steps 7-11):
-// before each step it forms ||r||^2 (stop test) and, over the members of
-// tau_t, the entry of largest |r| (smallest index on ties) in one block
-// reduction, then r -= r_j / G1_jj * G1_(j) and beta_j += r_j / G1_jj.
-constexpr int kScdThreads = 1024;
+// Inner steps of Alg. 5 (steps 7-11): before each step ||r||^2 (stop test)
+// and, over the members of tau_t, the entry of largest |r| (smallest index on
+// ties); then r -= r_j / G1_jj * G1_(j) and beta_j += r_j / G1_jj.  With
+// norm-weighted sampling (SP-RCD) the pre-drawn index is the only member.
+// T is the precision of G1 and r (double; float under mixed precision, where
+// the sums are FP32 too); beta is always FP64.
 
-struct ArgMax {
-  double v;   // |r_s|
-  double r;   // r_s
-  int idx;
-};
-
+// The better of two candidates (|r|, index): larger |r|, then smaller index.
 __device__ inline bool better(double v, int i, double bv, int bi) {
   return v > bv || (v == bv && i < bi);
 }
 
+// Global-memory form for n > kScdMaxN (greedy or norm-weighted choice only):
+// one workgroup, r in global memory.
+constexpr int kScdThreads = 1024;
+
+template <typename T>
 __global__ __launch_bounds__(kScdThreads) void k_scd_inner(
-    const double* __restrict__ G1, int64_t ldg, int64_t n, double* __restrict__ r,
+    const T* __restrict__ G1, int64_t ldg, int64_t n, T* __restrict__ r,
     double* __restrict__ beta, const uint32_t* __restrict__ mask, int64_t mask_words,
     const int* __restrict__ jpre, int norm_mode, int64_t count, int check, double itol2,
     const double* tn2, int* inner_done, int64_t* steps_done, const int* outer_done) {
   if (*(volatile const int*)inner_done || *(volatile const int*)outer_done) return;
-  __shared__ double red_n[2][kScdThreads / kWave];
+  __shared__ T red_n[2][kScdThreads / kWave];
   __shared__ double red_v[2][kScdThreads / kWave];
-  __shared__ double red_r[2][kScdThreads / kWave];
+  __shared__ T red_r[2][kScdThreads / kWave];
   __shared__ int red_i[2][kScdThreads / kWave];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const double stop2 = itol2 * (*tn2);
@@ -324,13 +325,17 @@ __global__ __launch_bounds__(kScdThreads) void k_scd_inner(
   for (; t <= count; ++t) {
     const int par = (int)(t & 1);
     const uint32_t* mrow = mask + t * mask_words;
-    double nrm = 0.0, bv = -1.0, br = 0.0;
+    const int jn = (norm_mode && t < count) ? jpre[t] : -1;
+    T nrm = 0;
+    double bv = -1.0;
+    T br = 0;
     int bi = 0x7FFFFFFF;
     for (int64_t sidx = tid; sidx < n; sidx += kScdThreads) {
-      const double rv = r[sidx];
+      const T rv = r[sidx];
       nrm += rv * rv;
-      if (!norm_mode && t < count && ((mrow[sidx >> 5] >> (sidx & 31)) & 1u)) {
-        const double av = fabs(rv);
+      const bool member = t < count && (norm_mode ? sidx == jn : ((mrow[sidx >> 5] >> (sidx & 31)) & 1u));
+      if (member) {
+        const double av = norm_mode ? 0.0 : fabs((double)rv);
         if (better(av, (int)sidx, bv, bi)) {
           bv = av;
           br = rv;
@@ -342,7 +347,8 @@ __global__ __launch_bounds__(kScdThreads) void k_scd_inner(
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
       nrm += __shfl_xor(nrm, off, kWave);
-      const double ov = __shfl_xor(bv, off, kWave), orr = __shfl_xor(br, off, kWave);
+      const double ov = __shfl_xor(bv, off, kWave);
+      const T orr = __shfl_xor(br, off, kWave);
       const int oi = __shfl_xor(bi, off, kWave);
       if (better(ov, oi, bv, bi)) {
         bv = ov;
@@ -369,98 +375,96 @@ __global__ __launch_bounds__(kScdThreads) void k_scd_inner(
         bi = red_i[par][q];
       }
     }
-    if (check && nrm <= stop2) {
+    if (check && (double)nrm <= stop2) {
       if (tid == 0) *inner_done = 1;
       break;
     }
     if (t == count) break;
-    int j;
-    double rj;
-    if (norm_mode) {
-      j = jpre[t];
-      rj = r[j];  // each thread reads r_j; only updates below write r
-    } else {
-      j = bi;
-      rj = br;
-    }
+    const int j = bi;
     if (j < 0 || j >= n) break;  // no finite candidate: the outer update flags it
-    __syncthreads();  // everyone has read r_j before it is overwritten
-    const double gam = rj / G1[(int64_t)j * ldg + j];
-    const double* col = G1 + (int64_t)j * ldg;
+    __syncthreads();  // everyone has read r before it is overwritten
+    const T gam = br / G1[(int64_t)j * ldg + j];
+    const T* col = G1 + (int64_t)j * ldg;
     for (int64_t sidx = tid; sidx < n; sidx += kScdThreads) r[sidx] -= gam * col[sidx];
-    if (tid == 0) beta[j] += gam;
+    if (tid == 0) beta[j] += (double)gam;
   }
   if (tid == 0) *steps_done += (t < count ? t : count);
 }
 
-// The same inner steps with r and diag(G1) held in LDS for n <= kScdMaxN:
-// one barrier per step (the wave partials are double-buffered; with norm
-// sampling the owner of r_j publishes it before the barrier), and only the
-// G1 column is read from global memory.  Sums, argmax and update are taken
-// in the same order as k_scd_inner, so both give the same iterates.
-__global__ __launch_bounds__(kScdThreads) void k_scd_inner_lds(
-    const double* __restrict__ G1, int64_t ldg, int64_t n, double* __restrict__ r,
+// Register form for n <= kScdMaxN.  256 threads; thread th owns the E
+// consecutive entries [th E, th E + E) of r in registers (E = 4, 8 or 16 for
+// n up to 1024, 2048, 4096) and the matching E bits of the step's subset
+// mask, fetched one step ahead (the subsets do not depend on r).  A step is:
+// the thread's own sum of squares and best member, a butterfly over the
+// wave, one barrier, the four wave partials combined in wave order; then
+// G1_jj from LDS and the thread's E entries of the column G1_(j) from global
+// memory, and the update.  beta lives in LDS for the launch.  Sums, argmax
+// and update follow the same definitions as the global-memory form.
+constexpr int kScdRegThreads = 256;
+constexpr int kScdRegWaves = kScdRegThreads / kWave;
+
+template <typename T, int E>
+__global__ __launch_bounds__(kScdRegThreads) void k_scd_inner_reg(
+    const T* __restrict__ G1, int64_t ldg, int64_t n, T* __restrict__ r,
     double* __restrict__ beta, const uint32_t* __restrict__ mask, int64_t mask_words,
     const int* __restrict__ jpre, int norm_mode, int64_t count, int check, double itol2,
     const double* tn2, int* inner_done, int64_t* steps_done, const int* outer_done) {
   if (*(volatile const int*)inner_done || *(volatile const int*)outer_done) return;
-  __shared__ double rs[kScdMaxN];
-  __shared__ double dg[kScdMaxN];
-  __shared__ double red_n[2][kScdThreads / kWave];
-  __shared__ double red_v[2][kScdThreads / kWave];
-  __shared__ double red_r[2][kScdThreads / kWave];
-  __shared__ int red_i[2][kScdThreads / kWave];
-  __shared__ double rj_pub[2];
+  __shared__ T dg[kScdMaxN];
+  __shared__ double bs[kScdMaxN];
+  __shared__ T red_n[2][kScdRegWaves];
+  __shared__ double red_v[2][kScdRegWaves];
+  __shared__ T red_r[2][kScdRegWaves];
+  __shared__ int red_i[2][kScdRegWaves];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  for (int64_t sidx = tid; sidx < n; sidx += kScdThreads) {
-    rs[sidx] = r[sidx];
-    dg[sidx] = G1[sidx * ldg + sidx];
+  const auto gG = glb(G1);
+  const int64_t s0 = (int64_t)tid * E;
+  T rr[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) rr[e] = (s0 + e < n) ? r[s0 + e] : (T)0;
+  for (int64_t i = tid; i < n; i += kScdRegThreads) {
+    dg[i] = gG[i * ldg + i];
+    bs[i] = beta[i];
   }
   __syncthreads();
   const double stop2 = itol2 * (*tn2);
-  // the mask words of this thread's entries for the current step, loaded
-  // one step ahead (they do not depend on r)
-  constexpr int kPer = kScdMaxN / kScdThreads;
-  uint32_t mw[kPer], mnext[kPer];
-  int jnext = -1;
-  auto fetch_mask = [&](int64_t tt) {
-#pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-      const int64_t sidx = tid + (int64_t)u * kScdThreads;
-      mnext[u] = (!norm_mode && tt < count && sidx < n) ? mask[tt * mask_words + (sidx >> 5)] : 0u;
-    }
-    jnext = (norm_mode && tt < count) ? jpre[tt] : -1;
+  // this thread's E subset bits for step tt (E divides 32, so one word)
+  auto fetch_bits = [&](int64_t tt) -> uint32_t {
+    if (norm_mode || tt >= count || s0 >= n) return 0u;
+    const uint32_t wd = mask[tt * mask_words + (s0 >> 5)];
+    return E == 32 ? wd : (wd >> (s0 & 31)) & ((1u << E) - 1u);
   };
-  fetch_mask(0);
+  uint32_t bits_next = fetch_bits(0);
+  int jn_next = (norm_mode && count > 0) ? jpre[0] : -1;
   int64_t t = 0;
   for (; t <= count; ++t) {
     const int par = (int)(t & 1);
-#pragma unroll
-    for (int u = 0; u < kPer; ++u) mw[u] = mnext[u];
-    const int jn = jnext;
-    fetch_mask(t + 1);
-    double nrm = 0.0, bv = -1.0, br = 0.0;
+    const uint32_t bits = bits_next;
+    const int jn = jn_next;
+    bits_next = fetch_bits(t + 1);
+    jn_next = (norm_mode && t + 1 < count) ? jpre[t + 1] : -1;
+    T nrm = 0;
+    double bv = -1.0;
+    T br = 0;
     int bi = 0x7FFFFFFF;
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-      const int64_t sidx = tid + (int64_t)u * kScdThreads;
-      if (sidx >= n) break;
-      const double rv = rs[sidx];
-      nrm += rv * rv;
-      if (sidx == jn) rj_pub[par] = rv;
-      if (!norm_mode && t < count && ((mw[u] >> (sidx & 31)) & 1u)) {
-        const double av = fabs(rv);
-        if (better(av, (int)sidx, bv, bi)) {
+    for (int e = 0; e < E; ++e) {
+      nrm += rr[e] * rr[e];
+      const bool member = t < count && s0 + e < n && (norm_mode ? s0 + e == jn : ((bits >> e) & 1u));
+      if (member) {
+        const double av = norm_mode ? 0.0 : fabs((double)rr[e]);
+        if (better(av, (int)(s0 + e), bv, bi)) {
           bv = av;
-          br = rv;
-          bi = (int)sidx;
+          br = rr[e];
+          bi = (int)(s0 + e);
         }
       }
     }
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
       nrm += __shfl_xor(nrm, off, kWave);
-      const double ov = __shfl_xor(bv, off, kWave), orr = __shfl_xor(br, off, kWave);
+      const double ov = __shfl_xor(bv, off, kWave);
+      const T orr = __shfl_xor(br, off, kWave);
       const int oi = __shfl_xor(bi, off, kWave);
       if (better(ov, oi, bv, bi)) {
         bv = ov;
@@ -479,7 +483,8 @@ __global__ __launch_bounds__(kScdThreads) void k_scd_inner_lds(
     bv = red_v[par][0];
     br = red_r[par][0];
     bi = red_i[par][0];
-    for (int q = 1; q < kScdThreads / kWave; ++q) {
+#pragma unroll
+    for (int q = 1; q < kScdRegWaves; ++q) {
       nrm += red_n[par][q];
       if (better(red_v[par][q], red_i[par][q], bv, bi)) {
         bv = red_v[par][q];
@@ -487,43 +492,67 @@ __global__ __launch_bounds__(kScdThreads) void k_scd_inner_lds(
         bi = red_i[par][q];
       }
     }
-    if (check && nrm <= stop2) {
+    if (check && (double)nrm <= stop2) {
       if (tid == 0) *inner_done = 1;
       break;
     }
     if (t == count) break;
-    int j;
-    double rj;
-    if (norm_mode) {
-      j = jn;
-      rj = (j >= 0 && j < n) ? rj_pub[par] : 0.0;
-    } else {
-      j = bi;
-      rj = br;
-    }
+    const int j = bi;
     if (j < 0 || j >= n) break;  // no finite candidate: the outer update flags it
-    const double gam = rj / dg[j];
-    const double* col = G1 + (int64_t)j * ldg;
-    for (int64_t sidx = tid; sidx < n; sidx += kScdThreads) rs[sidx] -= gam * col[sidx];
-    if (tid == 0) beta[j] += gam;
+    const auto col = gG + (int64_t)j * ldg;
+    T cv[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) cv[e] = (s0 + e < n) ? col[s0 + e] : (T)0;
+    const T gam = br / dg[j];
+#pragma unroll
+    for (int e = 0; e < E; ++e) rr[e] -= gam * cv[e];
+    if (tid == 0) bs[j] += (double)gam;
   }
   __syncthreads();
-  for (int64_t sidx = tid; sidx < n; sidx += kScdThreads) r[sidx] = rs[sidx];
+#pragma unroll
+  for (int e = 0; e < E; ++e)
+    if (s0 + e < n) r[s0 + e] = rr[e];
+  for (int64_t i = tid; i < n; i += kScdRegThreads) beta[i] = bs[i];
   if (tid == 0) *steps_done += (t < count ? t : count);
 }
+
+template <typename T>
+static void scd_inner_run(hipStream_t st, const T* G1, int64_t ldg, int64_t n, T* r, double* beta,
+                          const uint32_t* mask, int64_t mask_words, const int* jpre, int norm_mode,
+                          int64_t count, int check, double itol2, const double* tn2, int* inner_done,
+                          int64_t* steps_done, const int* outer_done) {
+#define ILS_SCD_REG(E)                                                                                     \
+  hipLaunchKernelGGL((k_scd_inner_reg<T, E>), dim3(1), dim3(kScdRegThreads), 0, st, G1, ldg, n, r, beta, \
+                     mask, mask_words, jpre, norm_mode, count, check, itol2, tn2, inner_done, steps_done,  \
+                     outer_done)
+  if (n <= 4 * kScdRegThreads)
+    ILS_SCD_REG(4);
+  else if (n <= 8 * kScdRegThreads)
+    ILS_SCD_REG(8);
+  else if (n <= kScdMaxN)
+    ILS_SCD_REG(16);
+  else
+    hipLaunchKernelGGL((k_scd_inner<T>), dim3(1), dim3(kScdThreads), 0, st, G1, ldg, n, r, beta, mask,
+                       mask_words, jpre, norm_mode, count, check, itol2, tn2, inner_done, steps_done,
+                       outer_done);
+#undef ILS_SCD_REG
+}
+static_assert(16 * kScdRegThreads == kScdMaxN, "register form covers n <= kScdMaxN");
 
 void launch_scd_inner(hipStream_t st, const double* G1, int64_t ldg, int64_t n, double* r, double* beta,
                       const uint32_t* mask, int64_t mask_words, const int* jpre, int norm_mode,
                       int64_t count, int check, double itol2, const double* tn2, int* inner_done,
                       int64_t* steps_done, const int* outer_done) {
-  if (n <= kScdMaxN)
-    hipLaunchKernelGGL(k_scd_inner_lds, dim3(1), dim3(kScdThreads), 0, st, G1, ldg, n, r, beta, mask,
-                       mask_words, jpre, norm_mode, count, check, itol2, tn2, inner_done, steps_done,
-                       outer_done);
-  else
-    hipLaunchKernelGGL(k_scd_inner, dim3(1), dim3(kScdThreads), 0, st, G1, ldg, n, r, beta, mask,
-                       mask_words, jpre, norm_mode, count, check, itol2, tn2, inner_done, steps_done,
-                       outer_done);
+  scd_inner_run<double>(st, G1, ldg, n, r, beta, mask, mask_words, jpre, norm_mode, count, check, itol2, tn2,
+                        inner_done, steps_done, outer_done);
+}
+
+void launch_scd_inner_f32(hipStream_t st, const float* G1, int64_t ldg, int64_t n, float* r, double* beta,
+                          const uint32_t* mask, int64_t mask_words, const int* jpre, int norm_mode,
+                          int64_t count, int check, double itol2, const double* tn2, int* inner_done,
+                          int64_t* steps_done, const int* outer_done) {
+  scd_inner_run<float>(st, G1, ldg, n, r, beta, mask, mask_words, jpre, norm_mode, count, check, itol2, tn2,
+                       inner_done, steps_done, outer_done);
 }
 
 // ------------------------------------------------------------------ outer helpers

@@ -42,6 +42,11 @@ void launch_scd_inner(hipStream_t st, const double* G1, int64_t ldg, int64_t n, 
                       const uint32_t* mask, int64_t mask_words, const int* jpre, int norm_mode,
                       int64_t count, int check, double itol2, const double* tn2, int* inner_done,
                       int64_t* steps_done, const int* outer_done);
+// The same steps with G1 and r in FP32 (mixed precision; beta stays FP64).
+void launch_scd_inner_f32(hipStream_t st, const float* G1, int64_t ldg, int64_t n, float* r, double* beta,
+                          const uint32_t* mask, int64_t mask_words, const int* jpre, int norm_mode,
+                          int64_t count, int check, double itol2, const double* tn2, int* inner_done,
+                          int64_t* steps_done, const int* outer_done);
 void launch_symv_add(hipStream_t s, int64_t n, const double* G, int64_t ldg, const double* x,
                      const double* g, double* y, const int* skip);
 void launch_outer_test(hipStream_t s, int64_t n, const double* xk, const double* x_ref, const double* rk,

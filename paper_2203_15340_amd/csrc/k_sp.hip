@@ -12,7 +12,10 @@
 // order, so all reach the same decision without atomics or fences, and
 // workgroup 0 records it in LoopState; the deciding launch also copies the
 // returned iterate into the caller's x.  The host queues several steps ahead;
-// a launch that finds the loop finished returns at once.
+// a launch that finds the loop finished by an EARLIER launch returns at once.
+// LoopState::done holds the deciding launch's index + 1, so a workgroup of the
+// deciding launch itself that starts after workgroup 0's store is visible
+// still takes the decision and writes its rows of x.
 #include "ils_common.hpp"
 
 namespace ils {
@@ -81,7 +84,8 @@ __device__ inline double dot_row(const double* row_, const double* v_, int64_t n
 
 __global__ __launch_bounds__(kSpThreads) void k_sp_step(SpStepArgs a, int64_t k) {
   LoopState* st = a.st;
-  if (*(volatile int*)&st->done || *(volatile int*)&st->bits) return;
+  const int decided = *(volatile int*)&st->done;  // 0, or deciding launch + 1
+  if ((decided != 0 && (int64_t)decided <= k) || *(volatile int*)&st->bits) return;
   __shared__ double tred[kSpThreads / kWave];
   const unsigned nblk = gridDim.x;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -133,7 +137,7 @@ __global__ __launch_bounds__(kSpThreads) void k_sp_step(SpStepArgs a, int64_t k)
         st->metric = metric;
         st->status = status;
         st->iters = iters;
-        st->done = 1;
+        st->done = (int)(k < INT_MAX - 1 ? k + 1 : INT_MAX);
       }
       return;
     }

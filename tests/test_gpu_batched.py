@@ -6,6 +6,7 @@ import pytest
 
 import oracle as O
 import workloads as W
+from checks import assert_close
 
 torch = pytest.importorskip("torch")
 import paper_2203_15340_amd as ils  # noqa: E402
@@ -47,7 +48,7 @@ def test_batched_fp64_iterates_match_oracle(batch, form, prec):
         for P, x, inf in zip(probs, xs, infos):
             ref, _ = O.sp_solve(P.A, P.b, P.p, stop_rule=O.STOP_FIXED, max_outer=k, form=form)
             assert inf.status == ils.OK and inf.outer_iters == k
-            assert rel(x.cpu().numpy(), ref) < 1e-10, (P.n, k)
+            assert_close(x.cpu().numpy(), ref, 1e-10, what=str(((P.n, k),)))
 
 
 def test_batched_xref_stop_matches_single(batch):
@@ -58,7 +59,7 @@ def test_batched_xref_stop_matches_single(batch):
         ref, rinfo = O.sp_solve(P.A, P.b, P.p, stop_rule=O.STOP_XREF, x_ref=P.x_star, tol=1e-10)
         assert inf.outer_iters == rinfo.outer_iters
         assert inf.rel_err < 1e-10
-        assert rel(x.cpu().numpy(), ref) < 1e-10
+        assert_close(x.cpu().numpy(), ref, 1e-10)
 
 
 def test_batched_rr_stop_matches_oracle(batch):
@@ -68,7 +69,7 @@ def test_batched_rr_stop_matches_oracle(batch):
     for P, x, inf in zip(probs, xs, infos):
         ref, rinfo = O.sp_solve(P.A, P.b, P.p, tol=1e-12)
         assert inf.outer_iters == rinfo.outer_iters
-        assert rel(x.cpu().numpy(), ref) < 1e-10
+        assert_close(x.cpu().numpy(), ref, 1e-10)
 
 
 def test_batched_mixed_reaches_x_ils(batch):
@@ -78,7 +79,7 @@ def test_batched_mixed_reaches_x_ils(batch):
     assert rc == ils.OK
     for P, x, inf in zip(probs, xs, infos):
         st, ref = O.normal_solve(P.A, P.b, P.p)
-        assert rel(x.cpu().numpy(), ref) < 1e-6, P.n
+        assert_close(x.cpu().numpy(), ref, 1e-6, what=str((P.n,)))
 
 
 def test_batched_graph_replays_and_changed_inputs(batch):

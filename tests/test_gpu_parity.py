@@ -10,6 +10,7 @@ import pytest
 
 import oracle as O
 import workloads as W
+from checks import assert_close
 
 torch = pytest.importorskip("torch")
 import paper_2203_15340_amd as ils  # noqa: E402
@@ -102,7 +103,7 @@ def test_residual_paths(shape):
     x = np.random.default_rng(2).standard_normal(n)
     r = ils.residual(devA(P.A), dev(P.b), P.p, dev(x))
     ref = O.residual(P.A, P.b, P.p, x)
-    assert rel(host(r), ref) < 1e-12
+    assert_close(host(r), ref, 1e-12)
 
 
 def test_spd_solve(prob):
@@ -111,7 +112,7 @@ def test_spd_solve(prob):
     R = np.random.default_rng(2).standard_normal((P.n, P.n + 3))
     rc, X = ils.spd_solve(devA(G1), devA(R))
     assert rc == ils.OK
-    assert rel(host(X), np.linalg.solve(G1, R)) < 1e-12
+    assert_close(host(X), np.linalg.solve(G1, R), 1e-12)
 
 
 @pytest.mark.parametrize("n,nrhs", [(1, 1), (63, 2), (64, 64), (65, 1), (128, 129), (129, 64), (300, 301),
@@ -132,7 +133,7 @@ def test_spd_solve_block_edges(n, nrhs):
     R = rng.standard_normal((n, nrhs))
     rc, Y = ils.spd_solve(devA(G), devA(R))
     assert rc == ils.OK
-    assert rel(host(Y), np.linalg.solve(G, R)) < 1e-11
+    assert_close(host(Y), np.linalg.solve(G, R), 1e-11)
 
 
 def test_spd_solve_repeated_sizes():
@@ -145,7 +146,7 @@ def test_spd_solve_repeated_sizes():
         R = rng.standard_normal((n, nrhs))
         rc, Y = ils.spd_solve(devA(G), devA(R))
         assert rc == ils.OK
-        assert rel(host(Y), np.linalg.solve(G, R)) < 1e-11
+        assert_close(host(Y), np.linalg.solve(G, R), 1e-11)
 
 
 @pytest.mark.parametrize("bad", [0, 63, 64, 100, 129])
@@ -199,7 +200,7 @@ def test_sp_iterates_match_oracle(prob, form):
         ref, rinfo = O.sp_solve(P.A, P.b, P.p, stop_rule=O.STOP_FIXED, max_outer=k, form=form,
                                 variant=O.SP_EXPLICIT)
         assert info.status == ils.OK and info.outer_iters == k
-        assert rel(host(x), ref) < 1e-10
+        assert_close(host(x), ref, 1e-10)
 
 
 def test_sp_converged_parity(prob):
@@ -207,7 +208,7 @@ def test_sp_converged_parity(prob):
     x, info = ils.sp_solve(A, b, P.p, stop_rule=ils.STOP_XREF, x_ref=xs, tol=1e-12)
     ref, rinfo = O.sp_solve(P.A, P.b, P.p, stop_rule=O.STOP_XREF, x_ref=P.x_star, tol=1e-12)
     assert info.status == ils.OK and info.outer_iters == rinfo.outer_iters
-    assert rel(host(x), ref) < 1e-10
+    assert_close(host(x), ref, 1e-10)
     assert info.rel_err < 1e-12
 
 
@@ -222,7 +223,7 @@ def test_sp_rr_stop_matches_oracle(prob):
         assert info.rr == pytest.approx(rinfo.rr, rel=1e-6)
     else:
         assert info.rr < 1e-24
-    assert rel(host(x), ref) < 1e-10
+    assert_close(host(x), ref, 1e-10)
 
 
 def test_sp_x0_and_resume(prob):
@@ -230,11 +231,11 @@ def test_sp_x0_and_resume(prob):
     x0 = np.random.default_rng(9).standard_normal(P.n)
     x, info = ils.sp_solve(A, b, P.p, x0=dev(x0), stop_rule=ils.STOP_FIXED, max_outer=3)
     ref, _ = O.sp_solve(P.A, P.b, P.p, x0=x0, stop_rule=O.STOP_FIXED, max_outer=3)
-    assert rel(host(x), ref) < 1e-10
+    assert_close(host(x), ref, 1e-10)
     # resuming from the returned iterate continues the same sequence
     x2, _ = ils.sp_solve(A, b, P.p, x0=x, stop_rule=ils.STOP_FIXED, max_outer=2)
     ref2, _ = O.sp_solve(P.A, P.b, P.p, x0=x0, stop_rule=O.STOP_FIXED, max_outer=5)
-    assert rel(host(x2), ref2) < 1e-10
+    assert_close(host(x2), ref2, 1e-10)
 
 
 def test_sp_profiling_modes(prob):
@@ -268,7 +269,7 @@ def test_sp_mixed_reaches_x_ils(prob):
                            stop_rule=ils.STOP_XREF, x_ref=xs, tol=1e-8)
     assert info.status == ils.OK
     st, ref = O.normal_solve(P.A, P.b, P.p)
-    assert rel(host(x), ref) < 1e-6
+    assert_close(host(x), ref, 1e-6)
 
 
 def test_sp_error_codes():
@@ -328,7 +329,7 @@ def test_rk_fixed_schedule_matches_oracle(prob, form):
     ref, rinfo = O.rk_solve(P.A, P.b, P.p, stop_rule=O.STOP_FIXED, max_outer=2, max_inner=700,
                             seed=5, form=form)
     assert info.status == ils.OK and info.inner_iters == rinfo.inner_iters == 1400
-    assert rel(host(x), ref) < 1e-10
+    assert_close(host(x), ref, 1e-10)
 
 
 def test_rk_converged_parity():
@@ -340,7 +341,7 @@ def test_rk_converged_parity():
     assert info.status == ils.OK and rinfo.status == O.OK
     assert info.outer_iters == rinfo.outer_iters
     assert info.inner_iters == rinfo.inner_iters
-    assert rel(host(x), ref) < 1e-10
+    assert_close(host(x), ref, 1e-10)
 
 
 # ----------------------------------------------------------------- SP-SCD (Algorithm 5)
@@ -354,7 +355,7 @@ def test_scd_fixed_schedule_matches_oracle(prob, alpha, sampling, form):
     x, info = ils.rgs_solve(A, b, P.p, **kw)
     ref, rinfo = O.rgs_solve(P.A, P.b, P.p, **kw)
     assert info.status == ils.OK and info.inner_iters == rinfo.inner_iters == 600
-    assert rel(host(x), ref) < 1e-10
+    assert_close(host(x), ref, 1e-10)
 
 
 @pytest.mark.parametrize("form", [ils.FORM_PAPER, ils.FORM_CORRECTION])
@@ -368,7 +369,7 @@ def test_scd_converged_parity(form):
     assert info.status == ils.OK and rinfo.status == O.OK
     assert info.outer_iters == rinfo.outer_iters
     assert abs(info.inner_iters - rinfo.inner_iters) <= 2 * info.outer_iters
-    assert rel(host(x), ref) < 1e-10
+    assert_close(host(x), ref, 1e-10)
 
 
 def test_scd_mixed_reaches_x_ils():
@@ -377,7 +378,7 @@ def test_scd_mixed_reaches_x_ils():
     x, info = ils.rgs_solve(A, b, P.p, precision=ils.PREC_MIXED, form=ils.FORM_CORRECTION,
                             stop_rule=ils.STOP_XREF, x_ref=xs, tol=1e-8, seed=1)
     assert info.status == ils.OK
-    assert rel(host(x), P.x_star) < 1e-6
+    assert_close(host(x), P.x_star, 1e-6)
 
 
 @pytest.mark.parametrize("shape", [(500, 100, 50), (700, 90, 150)])
@@ -391,7 +392,7 @@ def test_rk_mixed_reaches_x_ils(shape):
     assert info.status == ils.OK
     st, x_ils = O.normal_solve(P.A, P.b, P.p)
     assert st == O.OK
-    assert rel(host(x), x_ils) < 1e-6
+    assert_close(host(x), x_ils, 1e-6)
     _, info = ils.rk_solve(A, b, P.p, precision=ils.PREC_MIXED, form=ils.FORM_PAPER)
     assert info.status == ils.ERR_ARG
 
