@@ -88,7 +88,7 @@ def cpu_baseline(P):
     assert info.status == O.OK, info
     return {"value": 1.0 / dt, "unit": "solves/s", "cores": int(os.environ["OMP_NUM_THREADS"]),
             "kind": "oracle",
-            "sample": f"one FP64 SP solve (explicit P, Algorithm 1 as printed) of the same "
+            "sample": f"one FP64 SP solve (explicit iteration matrix of update (Sec23)) of the same "
                       f"{P.p}+{P.q} x {P.n} problem to rel.err 1e-6: {dt:.2f} s, "
                       f"{info.outer_iters} outer iterations"}
 

@@ -237,7 +237,8 @@ def _solve(fname, A, b, p, x0=None, tol=1e-6, stop_rule=STOP_RR, form=FORM_PAPER
 
 
 def sp_solve(A, b, p, **kw):
-    """SP (Algorithm 1).  variant=SP_EXPLICIT (as printed) or SP_CHOLESKY."""
+    """SP (Algorithm 1).  variant=SP_EXPLICIT (B = G1^-1 G2 and c = G1^-1 A^T J b
+    of the update (Sec23) formed once) or SP_CHOLESKY (triangular solves)."""
     return _solve("ora_sp_solve", A, b, p, **kw)
 
 

@@ -78,8 +78,8 @@ int64_t ora_weighted_index(const double* prefix, int64_t n, double u) {
   return j;
 }
 
-/* Reading (Alg. 5, "an index subset of size alpha_t, uniformly at random"):
- * every index s gets a key from a SplitMix64 stream seeded with a per-step
+/* Reading of Alg. 5 step 8 (tau_t is drawn with equal probability among all
+ * subsets of [n] with alpha_t members): every index s gets a key from a SplitMix64 stream seeded with a per-step
  * 64-bit value K (the s-th output of that stream), with its low b bits
  * (2^b >= n) replaced by s so that all keys differ and equal random parts
  * are ordered by index; tau_t is the set of the alpha_t indices with the
@@ -481,9 +481,10 @@ static double default_inner_tol(const ora_opts* o) {
 /* ------------------------------------------------------------------------ */
 
 /* x_{k+1} = (A1^T A1)^{-1} A2^T A2 x_k + (A1^T A1)^{-1} A^T J b  (Sec23).
- * ORA_SP_EXPLICIT follows Algorithm 1 as printed: P = (A1^T A1)^{-1},
- * B = P A2^T A2, c = P A^T J b, then x <- B x + c.  ORA_SP_CHOLESKY applies
- * (A1^T A1)^{-1} by two triangular solves.  The correction form solves
+ * ORA_SP_EXPLICIT forms the iteration matrix and constant of (Sec23) once,
+ * B = (A1^T A1)^{-1} A2^T A2 and c = (A1^T A1)^{-1} A^T J b (the inverse by
+ * Cholesky solves against the unit vectors), then x <- B x + c.
+ * ORA_SP_CHOLESKY applies (A1^T A1)^{-1} by two triangular solves per step.  The correction form solves
  * A1^T A1 d = A^T J (b - A x_k) and sets x_{k+1} = x_k + d, the same iterate
  * in exact arithmetic (subtract A1^T A1 x_k from both sides of (Sec23) and use
  * A^T J A = A1^T A1 - A2^T A2). */
@@ -565,14 +566,33 @@ done:
 /* SP-RK-RGS, Algorithm 2                                                   */
 /* ------------------------------------------------------------------------ */
 
-/* Outer: bhat = A2^T A2 x_k + A^T J b (Alg. 2 step 5), or in the correction
- * form the residual A^T J (b - A x_k).  Inner (steps 6-12), from w = z = 0:
- *   j1 ~ ||A1_(j)||^2,  w += (bhat_j1 - A1_(j1)^T w) / ||A1_(j1)||^2 * A1_(j1)
- *   j2 ~ ||A1_(j)||^2,  z_j2 += A1_(j2)^T (w - A1 z) / ||A1_(j2)||^2
- * LITERAL recomputes A1 z for every step (the count 2pn + 6p + 2 of the cost
- * remark).  INCREMENTAL carries s = w - A1 z: s gains the same multiple of
- * A1_(j1) as w, then loses the z-step times A1_(j2); the iterates are the same
- * in exact arithmetic.
+/* The two one-dimensional projections the method is built from.
+ * Kaczmarz half (eq. Sec3.32111, A1^T w = bhat): move w to the nearest point
+ * of the hyperplane {y : a^T y = beta}, a = A1_(j1), beta = bhat_j1; that is
+ * w + gamma a with gamma = (beta - a^T w) / ||a||^2.  Returns gamma. */
+static double kaczmarz_project(double* w, const double* a, double beta, double a_nrm2, int64_t p) {
+  double gamma = (beta - dot(a, w, p)) / a_nrm2;
+  for (int64_t i = 0; i < p; ++i) w[i] += gamma * a[i];
+  return gamma;
+}
+
+/* Gauss-Seidel half (eq. Sec3.33111, A1 z = w): z_j2 changes by the delta
+ * that minimises ||v - delta a||, v = w - A1 z the current misfit and
+ * a = A1_(j2): delta = a^T v / ||a||^2. */
+static double gs_line_min(const double* a, const double* v, double a_nrm2, int64_t p) {
+  return dot(a, v, p) / a_nrm2;
+}
+
+/* SP-RK-RGS.  Outer right-hand side bhat = A2^T A2 x_k + A^T J b (the SP
+ * update (Sec23) with A1^T A1 left to the inner solver), or in the correction
+ * form the residual A^T J (b - A x_k).  The inner solver approaches the
+ * solution of A1^T A1 z = bhat, the fixed point of Thm 3.1, from w = z = 0 by
+ * alternating the two projections above, each on a column drawn with
+ * probability ||A1_(j)||^2 / ||A1||_F^2 (j1 first, then j2, independently).
+ * LITERAL forms the misfit w - A1 z afresh for every Gauss-Seidel half (the
+ * work counted in the cost remark after Alg. 2).  INCREMENTAL carries
+ * s = w - A1 z instead: s gains the Kaczmarz move gamma a1 and loses the
+ * Gauss-Seidel move delta a2; the iterates are the same in exact arithmetic.
  * Reading (inner "until convergence"): every inner_check steps, starting at
  * t = 0, stop if ||bhat - A1^T A1 z|| <= inner_tol * ||bhat|| (INCREMENTAL uses
  * A1 z = w - s); always stop after max_inner steps.  ORA_STOP_FIXED runs
@@ -655,20 +675,19 @@ int ora_rk_solve(int64_t p, int64_t q, int64_t n, const double* A, int64_t lda,
       int64_t j2 = ora_weighted_index(prefix, n, ora_u01(out[1]));
       const double* a1 = A + (size_t)j1 * (size_t)lda;
       const double* a2 = A + (size_t)j2 * (size_t)lda;
-      double gamma = (tgt[j1] - dot(a1, w, p)) / cn[j1];
-      for (int64_t i = 0; i < p; ++i) w[i] += gamma * a1[i];
+      const double gamma = kaczmarz_project(w, a1, tgt[j1], cn[j1], p);
       double delta;
       if (o->variant == ORA_RK_LITERAL) {
-        for (int64_t i = 0; i < p; ++i) {
+        for (int64_t i = 0; i < p; ++i) { /* v = w - A1 z */
           double acc = 0.0;
           for (int64_t j = 0; j < n; ++j) acc += AT(i, j) * z[j];
           v[i] = w[i] - acc;
         }
-        delta = dot(a2, v, p) / cn[j2];
+        delta = gs_line_min(a2, v, cn[j2], p);
         z[j2] += delta;
       } else {
         for (int64_t i = 0; i < p; ++i) s[i] += gamma * a1[i];
-        delta = dot(a2, s, p) / cn[j2];
+        delta = gs_line_min(a2, s, cn[j2], p);
         z[j2] += delta;
         for (int64_t i = 0; i < p; ++i) s[i] -= delta * a2[i];
       }

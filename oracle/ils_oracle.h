@@ -23,7 +23,8 @@ enum { ORA_OK = 0, ORA_ERR_ARG = -1, ORA_ERR_NOT_SPD = -2, ORA_ERR_NO_CONVERGENC
        ORA_ERR_NONFINITE = -4 };
 enum { ORA_STOP_RR = 0, ORA_STOP_XREF = 1, ORA_STOP_FIXED = 2 };
 enum { ORA_FORM_PAPER = 0, ORA_FORM_CORRECTION = 1 };
-/* SP: how G1^{-1} is applied.  EXPLICIT = Algorithm 1 as printed (P, B, c).
+/* SP: how G1^{-1} is applied.  EXPLICIT = the iteration matrix and constant
+ * of the update (Sec23) formed once (B = G1^{-1} G2, c = G1^{-1} A^T J b).
  * CHOLESKY = two triangular solves per iteration.
  * RK-RGS: INCREMENTAL carries s = w - A1 z; LITERAL recomputes A1 z. */
 enum { ORA_SP_EXPLICIT = 0, ORA_SP_CHOLESKY = 1 };
