@@ -316,6 +316,25 @@ int ils_colpass(ils_handle* h, int64_t p, int64_t q, int64_t n, const double* A,
 int ils_residual(ils_handle* h, int64_t p, int64_t q, int64_t n, const double* A, int64_t lda,
                  const double* b, const double* x, double* r);
 
+/* ils_residual for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same r = A^T J (b - A x), same kernels and the same result bit for bit,
+ * but its workspace is a fixed device array of 8 MiB (2^20 doubles) that the
+ * library holds on each device until the process ends, and the call
+ * allocates nothing.  It returns once the work is queued on the handle's
+ * stream (r is ready when that stream's earlier work is done); it does not
+ * wait.  The workspace needed is (p + q) + 256 n doubles for n <= 1024 and
+ * (groups + 1)(p + q) doubles above (groups = the column groups of the
+ * two-pass residual, at most ceil(n / 32)); a size that needs more than
+ * 2^20 doubles returns ILS_ERR_ARG, as do the argument errors of
+ * ils_residual and a handle on device ordinal 64 or above.  Every call on a
+ * device shares that device's array: calls that overlap in time on one
+ * device (other streams, other handles, other host threads) race and must be
+ * ordered by the caller; calls queued on one stream are ordered by it.
+ * Nothing in the array needs to start at zero. */
+int ils_residual_noalloc(ils_handle* h, int64_t p, int64_t q, int64_t n, const double* A, int64_t lda,
+                         const double* b, const double* x, double* r);
+
 /* X = G^{-1} R for SPD G (n x n, ldg) and R (n x nrhs, ldr), by the block
  * Gauss-Jordan elimination used inside ils_sp_solve.  Returns
  * ILS_ERR_NOT_SPD if a pivot block is not positive definite. */

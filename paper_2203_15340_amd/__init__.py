@@ -26,7 +26,7 @@ SAMPLE_UNIFORM, SAMPLE_NORM = 0, 1
 
 LIB_PATH = _build.LIB
 EXPORTS = ("ils_create", "ils_destroy", "ils_opts_default", "ils_status_string", "ils_sp_solve",
-           "ils_rk_solve", "ils_rgs_solve", "ils_gram", "ils_colpass", "ils_residual",
+           "ils_rk_solve", "ils_rgs_solve", "ils_gram", "ils_colpass", "ils_residual", "ils_residual_noalloc",
            "ils_spd_solve", "ils_rk_indices", "ils_scd_subsets", "ils_set_profiling",
            "ils_get_phase_times", "ils_sp_solve_batched", "ils_sp_solve_multi", "ils_ws_create",
            "ils_ws_destroy", "ils_ws_train", "ils_ws_infer", "ils_ws_save", "ils_ws_load",
@@ -95,6 +95,7 @@ def load_library(path: str = LIB_PATH):
         "ils_gram": (C.c_int, [P, I64, I64, I64, P, I64, P, I64, I32]),
         "ils_colpass": (C.c_int, [P, I64, I64, I64, P, I64, P, P, P]),
         "ils_residual": (C.c_int, [P, I64, I64, I64, P, I64, P, P, P]),
+        "ils_residual_noalloc": (C.c_int, [P, I64, I64, I64, P, I64, P, P, P]),
         "ils_spd_solve": (C.c_int, [P, I64, I64, P, I64, P, I64, P, I64]),
         "ils_rk_indices": (C.c_int, [P, U64, U64, I64, I64, P, I64, P, P]),
         "ils_scd_subsets": (C.c_int, [P, U64, U64, I64, I64, I64, I64, P, P]),
@@ -333,6 +334,18 @@ def residual(A, b, p, x):
     r = torch.empty(n, dtype=torch.float64, device=A.device)
     _rc(load_library().ils_residual(handle(A.device), p, m - p, n, _ptr(A), _ld(A), _ptr(b),
                                     _ptr(x), _ptr(r)), "ils_residual")
+    return r
+
+
+def residual_noalloc(A, b, p, x, out=None):
+    """r = A^T J (b - A x) through ils_residual_noalloc: the library's fixed
+    device workspace, nothing allocated by the call.  Queued on torch's
+    current stream; r is ready once that stream's work is done."""
+    torch = _torch()
+    m, n = A.shape
+    r = out if out is not None else torch.empty(n, dtype=torch.float64, device=A.device)
+    _rc(load_library().ils_residual_noalloc(handle(A.device), p, m - p, n, _ptr(A), _ld(A), _ptr(b),
+                                            _ptr(x), _ptr(r)), "ils_residual_noalloc")
     return r
 
 

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <mutex>
 
 #include "ils_common.hpp"
 #include "ils_runtime.hpp"
@@ -45,6 +46,36 @@ int ils_handle::need(int slot, size_t bytes, void** out) {
   return ILS_OK;
 }
 
+// ------------------------------------------------------------------ fixed scratch
+// Workspace of the allocation-free entry point (ils_residual_noalloc): a
+// file-scope device array, one copy on every device the library is loaded on,
+// held until the process ends.  In host code `scratch` only names the array;
+// its device address is looked up once per device (with that device current)
+// by ils_create and kept in g_scratch_dev, and only that address is handed to
+// kernels.
+constexpr size_t kScratchDoubles = (size_t)1 << 20;  // 8 MiB
+constexpr int kScratchDevices = 64;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+static double* g_scratch_dev[kScratchDevices];
+static std::mutex g_scratch_mu;
+
+// Called with `device` current.
+static int bind_scratch(int device) {
+  if (device >= kScratchDevices) return ILS_OK;  // no fixed scratch there: the no-alloc call rejects it
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_dev[device]) return ILS_OK;
+  void* p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return ILS_ERR_HIP;
+  g_scratch_dev[device] = (double*)p;
+  return ILS_OK;
+}
+
+static double* scratch_of(int device) {
+  if (device < 0 || device >= kScratchDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_dev[device];
+}
+
 extern "C" int ils_create(ils_handle** out, int device_ordinal, void* hip_stream) {
   if (!out) return ILS_ERR_ARG;
   *out = nullptr;
@@ -52,6 +83,7 @@ extern "C" int ils_create(ils_handle** out, int device_ordinal, void* hip_stream
   if (hipGetDeviceCount(&ndev) != hipSuccess || device_ordinal < 0 || device_ordinal >= ndev)
     return ILS_ERR_ARG;
   if (hipSetDevice(device_ordinal) != hipSuccess) return ILS_ERR_HIP;
+  if (bind_scratch(device_ordinal) != ILS_OK) return ILS_ERR_HIP;
   ils_handle* h = new ils_handle();
   h->device = device_ordinal;
   if (hip_stream) {
@@ -384,6 +416,18 @@ extern "C" int ils_residual(ils_handle* h, int64_t p, int64_t q, int64_t n, cons
   launch_residual(h->stream, p, q, n, A, lda, b, x, tv, r, nullptr);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(h->stream));
+  return ILS_OK;
+}
+
+extern "C" int ils_residual_noalloc(ils_handle* h, int64_t p, int64_t q, int64_t n, const double* A,
+                                    int64_t lda, const double* b, const double* x, double* r) {
+  if (!h || !A || !b || !x || !r || n < 1 || p < 0 || q < 0 || lda < p + q) return ILS_ERR_ARG;
+  if (residual_scratch(p + q, n) > kScratchDoubles) return ILS_ERR_ARG;
+  double* tv = scratch_of(h->device);
+  if (!tv) return ILS_ERR_ARG;
+  HIPCHK(hipSetDevice(h->device));
+  launch_residual(h->stream, p, q, n, A, lda, b, x, tv, r, nullptr);
+  HIPCHK(hipGetLastError());
   return ILS_OK;
 }
 
