@@ -11,7 +11,7 @@ for B and c, and the outer iterations with their stop tests.
 Printed as one JSON line.  Besides the headline FP64 SP number it reports
 the other forms on the same problem, the dominant kernel (the MFMA Gram
 A1^T A1) against the FP64 matrix peak, and the CPU oracle timed on this
-host's cores on one solve of the same workload.
+host's cores on the same workload (all cores and one thread).
 """
 import argparse
 import gc
@@ -77,20 +77,56 @@ def measured_traffic(tuned):
     return t.get("bytes_per_launch")
 
 
-def cpu_baseline(P):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(P, reps=3, one_thread_budget_s=12.0):
+    """The oracle's FP64 SP on the host cores, same problem and stop rule as
+    the GPU line: both of its variants (explicit iteration matrix of the
+    update (Sec23), and triangular solves with the Cholesky factor) on all
+    cores, median of `reps` runs each; then the faster variant on one thread
+    (median of `reps` runs, or a single run when one takes longer than
+    `one_thread_budget_s`, which keeps the whole baseline near 30 s)."""
+    import numpy as np
+
     import oracle as O
-    threads = len(os.sched_getaffinity(0))
-    os.environ.setdefault("OMP_NUM_THREADS", str(threads))
-    t0 = time.perf_counter()
-    x, info = O.sp_solve(P.A, P.b, P.p, stop_rule=O.STOP_XREF, x_ref=P.x_star, tol=1e-6,
-                         variant=O.SP_EXPLICIT)
-    dt = time.perf_counter() - t0
-    assert info.status == O.OK, info
-    return {"value": 1.0 / dt, "unit": "solves/s", "cores": int(os.environ["OMP_NUM_THREADS"]),
-            "kind": "oracle",
-            "sample": f"one FP64 SP solve (explicit iteration matrix of update (Sec23)) of the same "
-                      f"{P.p}+{P.q} x {P.n} problem to rel.err 1e-6: {dt:.2f} s, "
-                      f"{info.outer_iters} outer iterations"}
+    allc = len(os.sched_getaffinity(0))
+
+    def timed(variant, threads, count):
+        O.set_threads(threads)
+        ts = []
+        for _ in range(count):
+            t0 = time.perf_counter()
+            _, info = O.sp_solve(P.A, P.b, P.p, stop_rule=O.STOP_XREF, x_ref=P.x_star, tol=1e-6,
+                                 variant=variant)
+            ts.append(time.perf_counter() - t0)
+            assert info.status == O.OK, info
+            if threads == 1 and ts[0] > one_thread_budget_s:
+                break
+        med = float(np.median(ts))
+        return {"threads": threads, "runs": len(ts), "median_s": med, "solves_per_s": 1.0 / med,
+                "times_s": [round(t, 4) for t in ts], "outer": int(info.outer_iters)}
+
+    runs = {"explicit_all_cores": timed(O.SP_EXPLICIT, allc, reps),
+            "cholesky_all_cores": timed(O.SP_CHOLESKY, allc, reps)}
+    fast = min(("explicit", "cholesky"), key=lambda v: runs[v + "_all_cores"]["median_s"])
+    runs[fast + "_1_thread"] = timed(O.SP_EXPLICIT if fast == "explicit" else O.SP_CHOLESKY, 1, reps)
+    O.set_threads(allc)
+    best = runs[fast + "_all_cores"]
+    return {"value": best["solves_per_s"], "unit": "solves/s", "cores": allc, "kind": "oracle",
+            "cpu": cpu_model(),
+            "sample": f"FP64 SP solves of the same {P.p}+{P.q} x {P.n} problem to rel.err 1e-6 "
+                      f"({best['outer']} outer iterations); value = the faster oracle variant "
+                      f"({fast}) on {allc} threads, median of {best['runs']} runs; every run in 'runs'",
+            "runs": runs}
 
 
 def bench_ratio09(ils, W, np, torch):

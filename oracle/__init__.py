@@ -68,6 +68,8 @@ def lib():
             "ora_gram": (None, [I64, I64, I64, P, I64, P]),
             "ora_atjb": (None, [I64, I64, I64, P, I64, P, P]),
             "ora_residual": (None, [I64, I64, I64, P, I64, P, P, P]),
+            "ora_set_threads": (None, [C.c_int]),
+            "ora_max_threads": (C.c_int, []),
             "ora_rr": (D, [I64, I64, I64, P, I64, P, P]),
             "ora_cholesky": (C.c_int, [I64, P, P]),
             "ora_chol_solve": (None, [I64, P, P, P]),
@@ -165,6 +167,15 @@ def atjb(A, b, p):
     g = np.zeros(n)
     lib().ora_atjb(p, m - p, n, _ptr(A), m, _ptr(_c(b)), _ptr(g))
     return g
+
+
+def set_threads(t):
+    """OpenMP threads of the oracle's parallel loops (results do not depend on it)."""
+    lib().ora_set_threads(int(t))
+
+
+def max_threads():
+    return int(lib().ora_max_threads())
 
 
 def residual(A, b, p, x):

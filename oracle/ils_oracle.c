@@ -12,6 +12,7 @@
 #include "ils_oracle.h"
 
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -808,3 +809,9 @@ done:
   free(beta); free(r); free(keys); free(member);
   return st;
 }
+
+/* Worker threads of the OpenMP loops (timing runs of the oracle only; the
+ * results do not depend on the count: every parallel loop writes disjoint
+ * entries and each entry's sum runs in index order). */
+void ora_set_threads(int t) { omp_set_num_threads(t > 0 ? t : 1); }
+int ora_max_threads(void) { return omp_get_max_threads(); }

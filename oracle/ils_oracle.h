@@ -114,6 +114,11 @@ double ora_bf16_round(double x);
 void ora_csr_to_csc(int64_t m, int64_t n, int64_t p, const int64_t* rowptr, const int32_t* colidx,
                     const double* val, int64_t* colptr, int32_t* rowidx, double* cval, int32_t* a1len);
 
+/* OpenMP worker threads for later calls (timing only; results are the same
+ * for any count). */
+void ora_set_threads(int t);
+int ora_max_threads(void);
+
 #ifdef __cplusplus
 }
 #endif

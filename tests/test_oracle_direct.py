@@ -107,3 +107,21 @@ def test_spd_invariant_of_generated_instances(tiny):
     assert lam.min() > -1e-12
     assert lam.max() <= tiny.ratio ** 2 * (1 + 1e-10)
     assert np.linalg.eigvalsh(G1 - G2).min() > 0
+
+
+def test_thread_count_does_not_change_results():
+    """The oracle's parallel loops write disjoint entries with sums in index
+    order, so its results are the same bits for any OpenMP thread count."""
+    import oracle as O
+    import workloads as W
+    P = W.dense_ils(700, 90, 150, seed=21)
+    outs = []
+    try:
+        for t in (1, 3, 8):
+            O.set_threads(t)
+            x, info = O.sp_solve(P.A, P.b, P.p, stop_rule=O.STOP_FIXED, max_outer=4, variant=O.SP_CHOLESKY)
+            outs.append((x, O.gram(P.A, 0, P.p)))
+    finally:
+        O.set_threads(max(1, len(__import__("os").sched_getaffinity(0))))
+    for x, G in outs[1:]:
+        assert np.array_equal(x, outs[0][0]) and np.array_equal(G, outs[0][1])
