@@ -55,8 +55,15 @@ def tuned_entry(path, precision, n, K):
             if (e["kernel"] == "gram" and e["precision"] == precision and e["n_bucket"] == bucket(n)
                     and e["k_bucket"] == bucket(K)):
                 return {"kernel": "gram", "precision": precision, "n": n, "K": K, "tile": e["tile"],
-                        "workgroups": e["workgroups"], "source": "file"}
+                        "workgroups": e["workgroups"], "kind": e.get("kind", 0), "source": "file"}
     return None
+
+
+def gram_kernel_name(tuned):
+    what = "A1^T A1, A2^T A2 and border columns b1, b2 in one launch, FP64 MFMA"
+    if tuned is not None and tuned.get("kind", 0) == 1:
+        return f"k_gram_pers ({what}; resident grid, operands loaded straight into LDS)"
+    return f"k_gram<double, 64> ({what}; split-K grid)"
 
 
 def measured_traffic(tuned):
@@ -72,7 +79,8 @@ def measured_traffic(tuned):
         return None
     cfg = t.get("config")
     if tuned is not None and (cfg is None or cfg.get("tile") != tuned["tile"]
-                              or cfg.get("workgroups") != tuned["workgroups"]):
+                              or cfg.get("workgroups") != tuned["workgroups"]
+                              or cfg.get("kind", 0) != tuned.get("kind", 0)):
         return None
     return t.get("bytes_per_launch")
 
@@ -603,7 +611,7 @@ def main():
                    "outer_iters": infos[-1].outer_iters, "rel_err": infos[-1].rel_err},
         "autotune": tuned,
         "roofline": {"bound": "mfma",
-                     "kernel": "k_gram<double> (A1^T A1, A2^T A2 and border columns b1, b2, FP64 MFMA)",
+                     "kernel": gram_kernel_name(tuned),
                      "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
                      "flops_per_launch": gram_flops, "avg_launch_ms": gram_avg},

@@ -318,8 +318,9 @@ int ils_residual(ils_handle* h, int64_t p, int64_t q, int64_t n, const double* A
 
 /* ils_residual for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
- * the same r = A^T J (b - A x), same kernels and the same result bit for bit,
- * but its workspace is a fixed device array of 8 MiB (2^20 doubles) that the
+ * the same r = A^T J (b - A x) with the default launch choice (the same bits
+ * as ils_residual unless the tuning table holds a residual entry for the
+ * shape), but its workspace is a fixed device array of 8 MiB (2^20 doubles) that the
  * library holds on each device until the process ends, and the call
  * allocates nothing.  It returns once the work is queued on the handle's
  * stream (r is ready when that stream's earlier work is done); it does not
@@ -353,18 +354,35 @@ int ils_scd_subsets(ils_handle* h, uint64_t seed, uint64_t outer, int64_t t0, in
 
 /* ---- autotuning ---- */
 
-enum { ILS_TUNE_GRAM = 0 };
+enum { ILS_TUNE_GRAM = 0, ILS_TUNE_BATCHED = 1, ILS_TUNE_RESIDUAL = 2 };
+enum { ILS_GRAM_SPLITK = 0, ILS_GRAM_PERSISTENT = 1 };
+enum { ILS_BATCH_LARGEST_FIRST = 0, ILS_BATCH_AS_GIVEN = 1 };
+enum { ILS_RESID_AUTO = 0, ILS_RESID_TWO_PASS = 1 };
+/* One launch choice; the fields mean, per kernel:
+ *   ILS_TUNE_GRAM     n columns, K rows; tile 64 or 128; workgroups aimed at
+ *                     (ILS_GRAM_SPLITK, sets the K-split) or resident per CU
+ *                     (ILS_GRAM_PERSISTENT); kind ILS_GRAM_*.
+ *   ILS_TUNE_BATCHED  n = largest n of the batch, K = batch size; tile = rows
+ *                     of A per LDS stage of the Gram products (16, 32, 64);
+ *                     workgroups = resident per CU (1 or 2); kind = order the
+ *                     problems are taken in (ILS_BATCH_*); reserved = form.
+ *   ILS_TUNE_RESIDUAL n columns, K = p + q rows; tile 16 (rows per block);
+ *                     workgroups of the one-pass kernel; kind ILS_RESID_*
+ *                     (ILS_RESID_AUTO: one pass over A for n <= 1024). */
 typedef struct {
   int32_t kernel;       /* ILS_TUNE_* */
   int32_t precision;    /* ILS_PREC_* */
   int64_t n, K;         /* shape the sweep ran on */
-  int32_t tile;         /* tile edge, 64 or 128 */
-  int32_t workgroups;   /* workgroups aimed at (sets the K-split) */
+  int32_t tile;
+  int32_t workgroups;
   double ms;            /* mean time of one launch */
+  int32_t kind;
+  int32_t reserved;
 } ils_tune_entry;
 
-/* Time every launch configuration of the Gram kernel (tile edge 64 / 128 x
- * 256 .. 8192 workgroups) on G = A[0:K, :]^T A[0:K, :] (reps launches each,
+/* Time every launch configuration of the Gram kernel (split-K: tile edge
+ * 64 / 128 x 256 .. 8192 workgroups; FP64 also the persistent kind, used
+ * where A is 16-byte aligned with an even lda) on G = A[0:K, :]^T A[0:K, :] (reps launches each,
  * after one warm-up; the matrix is only read) and keep the fastest for the
  * bucket (precision, ceil(log2 n), ceil(log2 K)) in the process-wide table
  * that all Gram launches consult (every solver, every handle).  *best (host,
@@ -372,6 +390,21 @@ typedef struct {
  * default configuration only by the order of the K-split additions. */
 int ils_tune_gram(ils_handle* h, int64_t K, int64_t n, const double* A, int64_t lda, int32_t precision,
                   int32_t reps, ils_tune_entry* best /* host */);
+/* The batched solver's launch choices (Gram stage rows 16 / 32 / 64 x 1 or 2
+ * resident workgroups per CU x largest-first or given order), each timed on
+ * the caller's batch with ils_sp_solve_batched's options (one warm-up and
+ * `reps` timed launches; every launch solves the batch, so each problem's x
+ * receives its solution); the fastest is kept for the bucket (precision,
+ * form, ceil(log2 largest n), ceil(log2 batch)).  Results of later batched
+ * solves differ from other choices only in the order of the Gram sums. */
+int ils_tune_batched(ils_handle* h, int64_t batch, const ils_problem* probs, const ils_opts* opts, int32_t reps,
+                     ils_tune_entry* best /* host */);
+/* The residual A^T J (b - A x)'s launch choices (one pass over A with 128,
+ * 256, 512 or 1024 workgroups for n <= 1024; two passes), timed on the
+ * caller's A, b, x (only read); the fastest is kept for the bucket
+ * (ceil(log2 n), ceil(log2 (p + q))). */
+int ils_tune_residual(ils_handle* h, int64_t p, int64_t q, int64_t n, const double* A, int64_t lda,
+                      const double* b, const double* x, int32_t reps, ils_tune_entry* best /* host */);
 /* Save / load the table as JSON (host path); load adds to the table and
  * rejects malformed files with ILS_ERR_ARG.  Clear restores the defaults. */
 int ils_tune_save(const char* path);

@@ -23,6 +23,9 @@ STOP_RR, STOP_XREF, STOP_FIXED = 0, 1, 2
 FORM_PAPER, FORM_CORRECTION = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
 SAMPLE_UNIFORM, SAMPLE_NORM = 0, 1
+GRAM_SPLITK, GRAM_PERSISTENT = 0, 1
+BATCH_LARGEST_FIRST, BATCH_AS_GIVEN = 0, 1
+RESID_AUTO, RESID_TWO_PASS = 0, 1
 
 LIB_PATH = _build.LIB
 EXPORTS = ("ils_create", "ils_destroy", "ils_opts_default", "ils_status_string", "ils_sp_solve",
@@ -33,7 +36,7 @@ EXPORTS = ("ils_create", "ils_destroy", "ils_opts_default", "ils_status_string",
            "ils_ws_nparams", "ils_ws_get_params", "ils_ws_set_params", "ils_ws_forward", "ils_ws_grad",
            "ils_ws_adam", "ils_csr_create", "ils_csr_destroy", "ils_sp_solve_csr", "ils_rk_solve_csr",
            "ils_rgs_solve_csr", "ils_csr_gram", "ils_csr_colpass", "ils_csr_residual",
-           "ils_csr_export_csc", "ils_tune_gram", "ils_tune_save", "ils_tune_load", "ils_tune_clear")
+           "ils_csr_export_csc", "ils_tune_gram", "ils_tune_batched", "ils_tune_residual", "ils_tune_save", "ils_tune_load", "ils_tune_clear")
 PHASES = ("colpass", "gram", "gram_reduce", "rhs", "gauss_jordan", "layout", "iterations")
 
 
@@ -126,6 +129,8 @@ def load_library(path: str = LIB_PATH):
         "ils_csr_residual": (C.c_int, [P, P, P, P, P]),
         "ils_csr_export_csc": (C.c_int, [P, P, P, P, P]),
         "ils_tune_gram": (C.c_int, [P, I64, I64, P, I64, I32, I32, P]),
+        "ils_tune_batched": (C.c_int, [P, I64, P, P, I32, P]),
+        "ils_tune_residual": (C.c_int, [P, I64, I64, I64, P, I64, P, P, I32, P]),
         "ils_tune_save": (C.c_int, [C.c_char_p]),
         "ils_tune_load": (C.c_int, [C.c_char_p]),
         "ils_tune_clear": (C.c_int, []),
@@ -625,7 +630,8 @@ class SparseA:
 
 class _TuneEntry(C.Structure):
     _fields_ = [("kernel", C.c_int32), ("precision", C.c_int32), ("n", C.c_int64), ("K", C.c_int64),
-                ("tile", C.c_int32), ("workgroups", C.c_int32), ("ms", C.c_double)]
+                ("tile", C.c_int32), ("workgroups", C.c_int32), ("ms", C.c_double),
+                ("kind", C.c_int32), ("reserved", C.c_int32)]
 
 
 def tune_gram(A, r0, r1, precision=PREC_FP64, reps=5):
@@ -636,7 +642,34 @@ def tune_gram(A, r0, r1, precision=PREC_FP64, reps=5):
                                      C.c_void_p(A.data_ptr() + 8 * r0), _ld(A), precision, reps,
                                      C.byref(e)), "ils_tune_gram")
     return {"kernel": "gram", "precision": int(e.precision), "n": int(e.n), "K": int(e.K),
-            "tile": int(e.tile), "workgroups": int(e.workgroups), "ms": float(e.ms)}
+            "tile": int(e.tile), "workgroups": int(e.workgroups), "ms": float(e.ms), "kind": int(e.kind)}
+
+
+def _entry(e):
+    names = {0: "gram", 1: "batched", 2: "residual"}
+    return {"kernel": names[int(e.kernel)], "precision": int(e.precision), "n": int(e.n), "K": int(e.K),
+            "tile": int(e.tile), "workgroups": int(e.workgroups), "ms": float(e.ms), "kind": int(e.kind),
+            "reserved": int(e.reserved)}
+
+
+def tune_batched(batch, reps=3, **kw):
+    """Sweep the batched solver's launch choices on a Batch (its problems are
+    solved by every timed launch); the fastest becomes the choice for that
+    bucket."""
+    e = _TuneEntry()
+    o = make_opts(**kw)
+    _rc(load_library().ils_tune_batched(handle(batch.device), len(batch.arr), batch.arr, C.byref(o), reps,
+                                        C.byref(e)), "ils_tune_batched")
+    return _entry(e)
+
+
+def tune_residual(A, b, p, x, reps=10):
+    """Sweep the residual's launch choices on (A, b, x) (only read)."""
+    m, n = A.shape
+    e = _TuneEntry()
+    _rc(load_library().ils_tune_residual(handle(A.device), p, m - p, n, _ptr(A), _ld(A), _ptr(b), _ptr(x), reps,
+                                         C.byref(e)), "ils_tune_residual")
+    return _entry(e)
 
 
 def tune_save(path):

@@ -422,11 +422,13 @@ extern "C" int ils_residual(ils_handle* h, int64_t p, int64_t q, int64_t n, cons
 extern "C" int ils_residual_noalloc(ils_handle* h, int64_t p, int64_t q, int64_t n, const double* A,
                                     int64_t lda, const double* b, const double* x, double* r) {
   if (!h || !A || !b || !x || !r || n < 1 || p < 0 || q < 0 || lda < p + q) return ILS_ERR_ARG;
-  if (residual_scratch(p + q, n) > kScratchDoubles) return ILS_ERR_ARG;
+  // the default launch choice (not the tuning table's), so the workspace
+  // bound stated in ils.h holds
+  if (residual_scratch_cfg(p + q, n, ResidCfg{}) > kScratchDoubles) return ILS_ERR_ARG;
   double* tv = scratch_of(h->device);
   if (!tv) return ILS_ERR_ARG;
   HIPCHK(hipSetDevice(h->device));
-  launch_residual(h->stream, p, q, n, A, lda, b, x, tv, r, nullptr);
+  launch_residual_cfg(h->stream, p, q, n, A, lda, b, x, tv, r, nullptr, ResidCfg{});
   HIPCHK(hipGetLastError());
   return ILS_OK;
 }

@@ -23,7 +23,7 @@ namespace {
 
 struct GraphKey {
   int64_t batch;
-  int workgroups, precision, form, stop_rule;
+  int workgroups, stage_rows, precision, form, stop_rule;
   double tol;
   int64_t max_outer, slot_doubles, ldw, nmax;
   const void *probs, *order, *res, *work, *queue;
@@ -41,8 +41,20 @@ int ensure_pinned(ils_handle* h, size_t bytes) {
 
 }  // namespace
 
+namespace ils {
+// The batched solve with the launch choices of `force` (tuning) or of the
+// process-wide table.
+int batched_solve(ils_handle* h, int64_t batch, const ils_problem* probs, const ils_opts* o, ils_info* infos,
+                  const BatchCfg* force);
+}  // namespace ils
+
 extern "C" int ils_sp_solve_batched(ils_handle* h, int64_t batch, const ils_problem* probs,
                                     const ils_opts* o, ils_info* infos) {
+  return batched_solve(h, batch, probs, o, infos, nullptr);
+}
+
+int ils::batched_solve(ils_handle* h, int64_t batch, const ils_problem* probs, const ils_opts* o, ils_info* infos,
+                       const BatchCfg* force) {
   if (!h || batch < 1 || batch > (1 << 30) || !probs || !o || !infos) return ILS_ERR_ARG;
   // per-problem checks with the single-problem rules
   int64_t nmax = 1;
@@ -67,7 +79,8 @@ extern "C" int ils_sp_solve_batched(ils_handle* h, int64_t batch, const ils_prob
   hipStream_t s = h->stream;
   int cus = 0;
   HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device));
-  const int workgroups = (int)std::min<int64_t>(batch, 2 * (int64_t)cus);
+  const BatchCfg bc = force ? *force : batched_cfg(o->precision, o->form, nmax, batch);
+  const int workgroups = (int)std::min<int64_t>(batch, (int64_t)bc.wpc * cus);
   const int64_t ldw = nmax;
   const int64_t w_doubles = ldw * (2 * nmax + 1);
   const int64_t slot_doubles = (w_doubles + 4 * nmax + 31) / 32 * 32;
@@ -94,7 +107,7 @@ extern "C" int ils_sp_solve_batched(ils_handle* h, int64_t batch, const ils_prob
   const size_t up_bytes = desc_bytes + order_bytes;
   if (h->batch_uploaded.size() != sizeof(ils_problem) * batch ||
       memcmp(h->batch_uploaded.data(), probs, sizeof(ils_problem) * batch) != 0 ||
-      h->bkey.empty()) {
+      h->bkey.empty() || h->batch_order != bc.order) {
     if ((st = ensure_pinned(h, up_bytes))) return st;
     HIPCHK(hipStreamSynchronize(s));  // the staging area may still feed an earlier copy
     BatchProblem* hp = (BatchProblem*)h->pinned;
@@ -111,9 +124,11 @@ extern "C" int ils_sp_solve_batched(ils_handle* h, int64_t batch, const ils_prob
     }
     std::vector<int> order(batch);
     std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int x, int y) { return probs[x].n * probs[x].n * (probs[x].p + probs[x].n) >
-                                                probs[y].n * probs[y].n * (probs[y].p + probs[y].n); });
+    if (bc.order == kBatchOrderLargest)
+      std::stable_sort(order.begin(), order.end(),
+                       [&](int x, int y) { return probs[x].n * probs[x].n * (probs[x].p + probs[x].n) >
+                                                  probs[y].n * probs[y].n * (probs[y].p + probs[y].n); });
+    h->batch_order = bc.order;
     memcpy((char*)h->pinned + desc_bytes, order.data(), order_bytes);
     HIPCHK(hipMemcpyAsync(dprobs, hp, desc_bytes, hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(dorder, (char*)h->pinned + desc_bytes, order_bytes, hipMemcpyHostToDevice, s));
@@ -141,6 +156,7 @@ extern "C" int ils_sp_solve_batched(ils_handle* h, int64_t batch, const ils_prob
   memset(&key, 0, sizeof(key));
   key.batch = batch;
   key.workgroups = workgroups;
+  key.stage_rows = bc.stage_rows;
   key.precision = o->precision;
   key.form = o->form;
   key.stop_rule = o->stop_rule;
@@ -163,7 +179,7 @@ extern "C" int ils_sp_solve_batched(ils_handle* h, int64_t batch, const ils_prob
     h->bkey.clear();
     HIPCHK(hipStreamSynchronize(s));
     HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
-    launch_batched(s, a, workgroups);
+    launch_batched(s, a, workgroups, bc.stage_rows);
     HIPCHK(hipStreamEndCapture(s, &h->bgraph));
     HIPCHK(hipGraphInstantiate(&h->bexec, h->bgraph, nullptr, nullptr, 0));
     h->bkey.assign((const char*)&key, (const char*)&key + sizeof(key));

@@ -119,9 +119,24 @@ void launch_colpass(hipStream_t s, int64_t p, int64_t q, int64_t n, const double
 // in the first m).  Skipped when *done != 0.
 void launch_border_combine(hipStream_t s, int64_t n, double* g, const double* g2, const double* G1,
                            const double* G2, int64_t ldg, double* gcol, int* bits);
+// Residual launch choice: kResidAuto takes the one-pass kernel for n <= 1024
+// with `wgs` workgroups, kResidTwoPass always the row pass + column pass.
+// The table (autotuner) supplies it per (log2 n, log2 m); the scratch a
+// caller allocates with residual_scratch covers the table's and the default
+// choice.
+enum { kResidAuto = 0, kResidTwoPass = 1 };
+constexpr int kResidDefaultWgs = 256;
+struct ResidCfg {
+  int path = kResidAuto;
+  int wgs = kResidDefaultWgs;
+};
+ResidCfg residual_cfg(int64_t n, int64_t m);
 size_t residual_scratch(int64_t m, int64_t n);
+size_t residual_scratch_cfg(int64_t m, int64_t n, ResidCfg c);
 void launch_residual(hipStream_t s, int64_t p, int64_t q, int64_t n, const double* A, int64_t lda,
                      const double* b, const double* x, double* t, double* r, const int* done);
+void launch_residual_cfg(hipStream_t s, int64_t p, int64_t q, int64_t n, const double* A, int64_t lda,
+                         const double* b, const double* x, double* t, double* r, const int* done, ResidCfg c);
 // Gram of rows [0, K) of A (A already offset to the first row).  `partials`
 // must hold gram_partials_size(n, K) doubles.
 size_t gram_partials_size(int64_t n, int64_t K);
@@ -139,11 +154,17 @@ size_t gram2_partials_size(int64_t n, int64_t K0, int64_t K1);
 void launch_gram2_f64(hipStream_t s, int64_t n, int64_t lda, int64_t ldg, double* partials, hipEvent_t mid,
                       int64_t K0, const double* A0, const double* vb0, double* G0, double* gv0,
                       int64_t K1, const double* A1, const double* vb1, double* G1, double* gv1);
-// Gram launch configuration (tile edge 64 or 128, workgroups aimed at) and
-// the tuning table consulted by launch_gram_f64/f32.
+// Gram launch configuration and the tuning table consulted by
+// launch_gram_f64/f32.  kind kGramSplitK: tile edge 64 or 128 and the
+// workgroups aimed at (which set the K-split); kind kGramPersistent (FP64):
+// the resident 64-tile kernel with direct global-to-LDS loads (tile 64,
+// workgroups = per CU).
+enum { kGramSplitK = 0, kGramPersistent = 1 };
+constexpr int kGramPersistentWpc = 4;  // resident workgroups per CU of the persistent kind
 struct GramCfg {
   int tile;
   int workgroups;
+  int kind = kGramSplitK;
 };
 struct GramCfgEntry {
   int precision, n_bucket, k_bucket;

@@ -75,6 +75,7 @@ struct ils_handle {
   void* pinned = nullptr;
   size_t pinned_cap = 0;
   std::vector<char> batch_uploaded;
+  int batch_order = -1;  // processing-order policy of the uploaded order array
   hipGraph_t bgraph = nullptr;
   hipGraphExec_t bexec = nullptr;
   std::vector<char> bkey;

@@ -104,7 +104,7 @@ __device__ inline double block_sum2(double v, Smem& s, int which) {
 // loads are issued before the matrix-core work on the current one.  One
 // workgroup streams a whole problem, so loads in flight, not bandwidth, set
 // the rate; the second workgroup on the CU covers its waits.
-template <typename T>
+template <typename T, int SR>
 __device__ __attribute__((noinline)) void wg_gram(const double* A_, int64_t lda, int K, int n, double* W_,
                                                  int64_t ldw, const double* vb_, double* gv_) {
   Smem& s = bsm;
@@ -116,9 +116,11 @@ __device__ __attribute__((noinline)) void wg_gram(const double* A_, int64_t lda,
   typedef typename Mma<T>::acc_t acc_t;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wr = (w >> 1) * 32, wc = (w & 1) * 32, lr = lane & 15;
-  // 32-row stages (8 loads per operand per thread): two workgroups share a
-  // CU, so registers are scarce and the other workgroup hides latency
-  constexpr int SR = 32, NLD = SR / 4, CG = NT / SR;
+  // SR-row stages (SR / 4 loads per operand per thread; 32 by default: two
+  // workgroups share a CU, so registers are scarce and the other workgroup
+  // hides latency; the autotuner may pick 16 or 64)
+  static_assert(SR == 16 || SR == 32 || SR == 64, "stage rows");
+  constexpr int NLD = SR / 4, CG = NT / SR;
   const int lk = t % SR, lc = t / SR;
   const int nt = (n + (border ? 1 : 0) + kNB - 1) / kNB;
   T(*As)[kNB + 1] = stage_a<T>(s);
@@ -397,7 +399,7 @@ __device__ __attribute__((noinline)) void wg_residual(const double* A_, int64_t 
   __syncthreads();
 }
 
-template <typename T>
+template <typename T, int SR>
 __device__ void solve_one(const BatchArgs& a, const BatchProblem& P, double* slot, BatchResult& out) {
   Smem& s = bsm;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -420,8 +422,8 @@ __device__ void solve_one(const BatchArgs& a, const BatchProblem& P, double* slo
   int nrhs;
   if (paper) {
     // 2. [A1^T A1 | A2^T A2 | g]
-    wg_gram<double>(P.A, lda, p, n, W, ldw, P.b, g);
-    wg_gram<double>(P.A + p, lda, q, n, W + (int64_t)n * ldw, ldw, P.b + p, xb);
+    wg_gram<double, SR>(P.A, lda, p, n, W, ldw, P.b, g);
+    wg_gram<double, SR>(P.A + p, lda, q, n, W + (int64_t)n * ldw, ldw, P.b + p, xb);
     for (int j = t; j < n; j += NT) {
       const double gj = g[j] - xb[j];
       g[j] = gj;
@@ -477,7 +479,7 @@ __device__ void solve_one(const BatchArgs& a, const BatchProblem& P, double* slo
   }
   if (!paper) {
     // 2. [A1^T A1 | I]
-    wg_gram<T>(P.A, lda, p, n, W, ldw, nullptr, nullptr);
+    wg_gram<T, SR>(P.A, lda, p, n, W, ldw, nullptr, nullptr);
     for (int e = t; e < n * n; e += NT) {
       const int i = e % n, j = e / n;
       W[i + (int64_t)(n + j) * ldw] = (i == j) ? 1.0 : 0.0;
@@ -563,7 +565,7 @@ __device__ void solve_one(const BatchArgs& a, const BatchProblem& P, double* slo
 
 // Two workgroups per CU: the register budget is cut to fit them (the helper
 // functions spill a little at entry), and each hides the other's latency.
-template <typename T>
+template <typename T, int SR>
 __global__ __launch_bounds__(NT, 2) void k_batched(BatchArgs a) {
   Smem& s = bsm;
   double* slot = a.work + (int64_t)blockIdx.x * a.slot_doubles;
@@ -576,7 +578,7 @@ __global__ __launch_bounds__(NT, 2) void k_batched(BatchArgs a) {
     const int idx = a.order[id];
     BatchResult res;
     res.status = ILS_OK;
-    solve_one<T>(a, a.probs[idx], slot, res);
+    solve_one<T, SR>(a, a.probs[idx], slot, res);
     if (threadIdx.x == 0) a.res[idx] = res;
     __syncthreads();
   }
@@ -592,11 +594,21 @@ __global__ __launch_bounds__(NT, 2) void k_batched(BatchArgs a) {
 
 }  // namespace
 
-void launch_batched(hipStream_t s, const BatchArgs& a, int workgroups) {
+template <int SR>
+static void launch_sr(hipStream_t s, const BatchArgs& a, int workgroups) {
   if (a.precision == ILS_PREC_MIXED)
-    hipLaunchKernelGGL(k_batched<float>, dim3(workgroups), dim3(NT), 0, s, a);
+    hipLaunchKernelGGL((k_batched<float, SR>), dim3(workgroups), dim3(NT), 0, s, a);
   else
-    hipLaunchKernelGGL(k_batched<double>, dim3(workgroups), dim3(NT), 0, s, a);
+    hipLaunchKernelGGL((k_batched<double, SR>), dim3(workgroups), dim3(NT), 0, s, a);
+}
+
+void launch_batched(hipStream_t s, const BatchArgs& a, int workgroups, int stage_rows) {
+  if (stage_rows == 16)
+    launch_sr<16>(s, a, workgroups);
+  else if (stage_rows == 64)
+    launch_sr<64>(s, a, workgroups);
+  else
+    launch_sr<32>(s, a, workgroups);
 }
 
 }  // namespace ils

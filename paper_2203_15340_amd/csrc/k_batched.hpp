@@ -42,6 +42,18 @@ struct BatchArgs {
   int64_t max_outer;
 };
 
-void launch_batched(hipStream_t s, const BatchArgs& a, int workgroups);
+// stage_rows: rows of A per LDS stage of the Gram products (16, 32 or 64).
+void launch_batched(hipStream_t s, const BatchArgs& a, int workgroups, int stage_rows);
+
+// Launch choices of the batched solver, per (precision, form, n bucket,
+// batch-size bucket): Gram stage rows, resident workgroups per CU (1 or 2)
+// and the order problems are taken in (largest first, or as given).
+enum { kBatchOrderLargest = 0, kBatchOrderGiven = 1 };
+struct BatchCfg {
+  int stage_rows = 32;
+  int wpc = 2;
+  int order = kBatchOrderLargest;
+};
+BatchCfg batched_cfg(int precision, int form, int64_t nmax, int64_t batch);
 
 }  // namespace ils

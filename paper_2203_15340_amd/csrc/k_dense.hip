@@ -128,17 +128,24 @@ constexpr int kR1Rows = 16;
 constexpr int kR1Groups = kR1Threads / kR1Rows;  // 64 column groups
 constexpr int kR1Per = 16;                       // columns per thread
 constexpr int64_t kR1MaxN = (int64_t)kR1Groups * kR1Per;
-constexpr int kR1Wgs = 256;  // one per CU
+constexpr int kR1Wgs = kResidDefaultWgs;  // one per CU
 
-static int r1_wgs(int64_t m) {
+static int r1_wgs(int64_t m, int wgs) {
   const int64_t nblk = (m + kR1Rows - 1) / kR1Rows;
-  return (int)(nblk < kR1Wgs ? (nblk > 0 ? nblk : 1) : kR1Wgs);
+  return (int)(nblk < wgs ? (nblk > 0 ? nblk : 1) : wgs);
+}
+
+static bool one_pass(int64_t n, ResidCfg c) { return n <= kR1MaxN && c.path == kResidAuto; }
+
+size_t residual_scratch_cfg(int64_t m, int64_t n, ResidCfg c) {
+  const size_t two = (size_t)(resid_groups(m, n) + 1) * (size_t)(m > 0 ? m : 1);
+  const size_t one = (size_t)(m > 0 ? m : 1) + (size_t)(c.wgs > 0 ? c.wgs : kR1Wgs) * (size_t)(n > 0 ? n : 1);
+  return one_pass(n, c) ? (two > one ? two : one) : two;
 }
 
 size_t residual_scratch(int64_t m, int64_t n) {
-  const size_t two = (size_t)(resid_groups(m, n) + 1) * (size_t)(m > 0 ? m : 1);
-  const size_t one = (size_t)(m > 0 ? m : 1) + (size_t)kR1Wgs * (size_t)(n > 0 ? n : 1);
-  return n <= kR1MaxN ? (two > one ? two : one) : two;
+  const size_t a = residual_scratch_cfg(m, n, ResidCfg{}), b = residual_scratch_cfg(m, n, residual_cfg(n, m));
+  return a > b ? a : b;
 }
 
 __global__ __launch_bounds__(kR1Threads) void k_resid_1pass(const double* __restrict__ A, int64_t lda,
@@ -303,9 +310,14 @@ __global__ __launch_bounds__(kColThreads) void k_resid_cols(const double* __rest
 
 void launch_residual(hipStream_t s, int64_t p, int64_t q, int64_t n, const double* A, int64_t lda,
                      const double* b, const double* x, double* t, double* r, const int* done) {
+  launch_residual_cfg(s, p, q, n, A, lda, b, x, t, r, done, residual_cfg(n, p + q));
+}
+
+void launch_residual_cfg(hipStream_t s, int64_t p, int64_t q, int64_t n, const double* A, int64_t lda,
+                         const double* b, const double* x, double* t, double* r, const int* done, ResidCfg c) {
   const int64_t m = p + q;
-  if (n <= kR1MaxN) {
-    const int nwg = r1_wgs(m);
+  if (one_pass(n, c)) {
+    const int nwg = r1_wgs(m, c.wgs > 0 ? c.wgs : kR1Wgs);
     double* part = t + (m > 0 ? m : 1);
     hipLaunchKernelGGL(k_resid_1pass, dim3((unsigned)nwg), dim3(kR1Threads), 0, s, A, lda, p, m, n, b, x, part,
                        done);

@@ -4,6 +4,8 @@
 #include <algorithm>
 #include <map>
 #include <mutex>
+#include <tuple>
+#include <type_traits>
 #include <vector>
 
 #include "ils_common.hpp"
@@ -221,6 +223,394 @@ __global__ __launch_bounds__(256) void k_gram_finalize(GramJob job, const T* __r
   G[j + (int64_t)i * ldg] = s;
 }
 
+// ------------------------------------------------------------------ persistent Gram (FP64)
+// The same lower 64 x 64 tiles, but a fixed grid of kPersWpc workgroups per CU
+// that stays resident.  The rows of A are cut into one range per XCD (the
+// grid's workgroups are dealt to the XCDs round-robin, so workgroup b runs on
+// XCD b % 8 and all tiles of a range share that XCD's L2).  Inside a range,
+// workgroup j of the XCD first takes the whole range for tiles j, j + W, ...
+// (the q = T / W main tiles per workgroup; all workgroups walk the rows in
+// step, so each stage of the panels is fetched into the L2 once and shared),
+// then an equal contiguous share of the (tile, 16-row stage) pairs of the
+// L = T - q W leftover tiles, tile-major.  Every workgroup does the same
+// number of stages, with no tail of partly filled rounds.
+//
+// Operand panels go from global memory straight into LDS
+// (global_load_lds_dwordx4: each lane moves 16 bytes, a wave 1 KB, with no
+// register staging and no LDS store instructions), two stages in flight.  A
+// stage holds, per operand, 64 column slots of 16 rows = 8 chunks of two rows;
+// the chunk of rows (2q, 2q + 1) of slot s sits at position q ^ ((s >> 1) & 7),
+// so the 16 lanes of an MFMA operand read (16 slots, one row) hit 16 distinct
+// bank groups.  A stage that does not start on an even row or is shorter than
+// 16 rows (a range end, the A1/A2 boundary) goes through registers into the
+// same layout.  Needs A and the border column 16-byte aligned and an even lda.
+//
+// Each share (tile, XCD range, part) writes one partial tile; the reduction
+// kernel adds, per tile and part, the shares of XCD 0..7 in row order.
+constexpr int kPersWpc = kGramPersistentWpc;  // resident workgroups per CU (32 KB of LDS each)
+constexpr int kPersRS = 16;  // rows per stage
+constexpr int kPersMaxShares = 64;  // shares per (leftover tile, XCD) the reduction lists
+
+struct GramPJob {
+  const double* A;   // row 0 of the rows [0, M)
+  int64_t lda;
+  const double* vb;  // border column (M entries) or null
+  int64_t M, p;      // rows; part 0 = rows [0, p), part 1 = rows [p, M)
+  int n, nc, T;      // columns, bordered columns, lower tiles
+  int W;             // workgroups per XCD
+  int q, L;          // main tiles per workgroup (T / W) and the leftover tiles (T - q W)
+  int cmax;          // shares per (leftover tile, XCD) at most
+  double* partials;  // (kXcds + 1) * (q W + L cmax) partial tiles
+  double *G0, *gv0, *G1, *gv1;
+  int64_t ldg;
+};
+
+__device__ __host__ inline void pers_range(int64_t M, int x, int64_t& r0, int64_t& r1) {
+  r0 = (M * x / kXcds) / kPersRS * kPersRS;
+  r1 = x == kXcds - 1 ? M : (M * (x + 1) / kXcds) / kPersRS * kPersRS;
+}
+// Partial-tile block of XCD range x for `part`: the range itself, except the
+// part-1 shares of the one range that holds rows on both sides of p, which
+// go to block kXcds.
+__device__ __host__ inline int pers_vx(int x, int part, int64_t r0, int64_t r1, int64_t p) {
+  return (part == 1 && r0 < p && p < r1) ? kXcds : x;
+}
+// first workgroup (of W) whose share of TS stages contains stage u
+__device__ __host__ inline int pers_first(int64_t u, int64_t TS, int W) {
+  return (int)(((u + 1) * W - 1) / TS);
+}
+
+// Partial-tile index of the share of main tile t (t < q W) in block vx, and
+// of share c of leftover tile lt in block vx.
+__device__ __host__ inline size_t pers_slot_main(int vx, int t, int q, int W) {
+  return (size_t)vx * q * W + t;
+}
+__device__ __host__ inline size_t pers_slot_left(int vx, int lt, int c, int q, int W, int L, int cmax) {
+  return (size_t)(kXcds + 1) * q * W + ((size_t)vx * L + lt) * cmax + c;
+}
+
+static __device__ const double g_zero16[16] = {0.0};
+
+// s_waitcnt with a vector-memory limit only (vmcnt low bits 3:0, high bits
+// 15:14; expcnt 6:4 and lgkmcnt 11:8 left at their maxima)
+#define ILS_WAIT_VM(N) __builtin_amdgcn_s_waitcnt(((N) & 0xF) | (((N) >> 4) << 14) | (0x7 << 4) | (0xF << 8))
+
+__device__ inline int pers_swz(int s) { return (s >> 1) & 7; }
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPersWpc)))
+void k_gram_pers(GramPJob job) {
+  __shared__ __attribute__((aligned(16))) double L[2][2][64 * kPersRS];  // [stage][operand][slot * 16 + row]
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  const int lr = lane & 15;
+  const int x = (int)(blockIdx.x % kXcds), j = (int)(blockIdx.x / kXcds);
+  int64_t r0, r1;
+  pers_range(job.M, x, r0, r1);
+  const int64_t S = (r1 - r0 + kPersRS - 1) / kPersRS;
+  if (S == 0) return;
+  const int64_t LS = (int64_t)job.L * S;
+  // main tiles over the whole range, then this workgroup's leftover stages
+  const int64_t u0 = (int64_t)j * LS / job.W, u1 = (int64_t)(j + 1) * LS / job.W;
+  const double* A = job.A;
+  const int64_t lda = job.lda;
+  const int n = job.n;
+
+  int mi = 0;
+  for (int64_t u = u0; mi < job.q || u < u1;) {
+    int tile, c = 0;
+    int64_t klo, khi;
+    const bool main = mi < job.q;
+    if (main) {
+      tile = j + mi * job.W;
+      klo = r0;
+      khi = r1;
+      ++mi;
+    } else {
+      const int lt = (int)(u / S);
+      const int64_t send = u1 < (int64_t)(lt + 1) * S ? u1 : (int64_t)(lt + 1) * S;
+      c = j - pers_first((int64_t)lt * S, LS, job.W);
+      tile = job.q * job.W + lt;
+      klo = r0 + (u - (int64_t)lt * S) * kPersRS;
+      khi = r0 + (send - (int64_t)lt * S) * kPersRS < r1 ? r0 + (send - (int64_t)lt * S) * kPersRS : r1;
+      u = send;
+    }
+    int ti, tj;
+    tile_of(tile, ti, tj);
+    const bool diag = ti == tj;
+    for (int part = 0; part < 2; ++part) {
+      const int64_t kbeg = part ? (klo > job.p ? klo : job.p) : klo;
+      const int64_t kend = part ? khi : (khi < job.p ? khi : job.p);
+      if (kbeg >= kend) continue;
+      v4d acc[2][2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int cc = 0; cc < 2; ++cc) acc[a][cc] = v4d{};
+      auto compute = [&](int buf) {
+        const double* La = &L[buf][0][0];
+        const double* Lb = diag ? &L[buf][0][0] : &L[buf][1][0];
+#pragma unroll
+        for (int kk = 0; kk < kPersRS; kk += 4) {
+          const int kr = kk + (lane >> 4);
+          double fa[2], fb[2];
+#pragma unroll
+          for (int a = 0; a < 2; ++a) {
+            const int s = wr + a * 16 + lr;
+            fa[a] = La[s * kPersRS + (((kr >> 1) ^ pers_swz(s)) << 1) + (kr & 1)];
+          }
+#pragma unroll
+          for (int cc = 0; cc < 2; ++cc) {
+            const int s = wc + cc * 16 + lr;
+            fb[cc] = Lb[s * kPersRS + (((kr >> 1) ^ pers_swz(s)) << 1) + (kr & 1)];
+          }
+#pragma unroll
+          for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int cc = 0; cc < 2; ++cc)
+              acc[a][cc] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[cc], acc[a][cc], 0, 0, 0);
+        }
+      };
+      // rows [ka, kb) of buffer 0 through registers (ka..kb within one stage), the rest zero
+      auto reg_stage = [&](int64_t ka, int64_t kb) {
+        __syncthreads();
+        for (int id = t; id < 2 * 64 * (kPersRS / 2); id += 256) {
+          const int op = id / (64 * (kPersRS / 2)), s = (id / (kPersRS / 2)) % 64, q = id % (kPersRS / 2);
+          if (op == 1 && diag) continue;
+          const int col = (op ? tj : ti) * 64 + s;
+          const double* cp = col < n ? A + (int64_t)col * lda : (col == n ? job.vb : nullptr);
+          const int64_t r = ka + 2 * q;
+          double v0 = 0.0, v1 = 0.0;
+          if (cp) {
+            if (r < kb) v0 = cp[r];
+            if (r + 1 < kb) v1 = cp[r + 1];
+          }
+          double* d = &L[0][op][s * kPersRS + ((q ^ pers_swz(s)) << 1)];
+          d[0] = v0;
+          d[1] = v1;
+        }
+        __syncthreads();
+        compute(0);
+      };
+      int64_t ka = kbeg;
+      if (ka & 1) {  // odd first row: one row through registers, then even rows
+        reg_stage(ka, ka + 1);
+        ++ka;
+      }
+      const int64_t nfull = (kend - ka) / kPersRS;
+      if (nfull > 0) {
+        // this lane's sources: load i of operand op fills slots (2w + i) * 8 + lane / 8, chunk lane % 8
+        const double* src[2][2];
+        int64_t step[2][2];
+#pragma unroll
+        for (int op = 0; op < 2; ++op)
+#pragma unroll
+          for (int i = 0; i < 2; ++i) {
+            const int s = (2 * w + i) * 8 + (lane >> 3);
+            const int sig = (lane & 7) ^ pers_swz(s);
+            const int col = (op ? tj : ti) * 64 + s;
+            if (col < n) {
+              src[op][i] = A + (int64_t)col * lda + ka + 2 * sig;
+              step[op][i] = kPersRS;
+            } else if (col == n && job.vb) {
+              src[op][i] = job.vb + ka + 2 * sig;
+              step[op][i] = kPersRS;
+            } else {
+              src[op][i] = g_zero16 + 2 * sig;
+              step[op][i] = 0;
+            }
+          }
+        auto issue = [&](int64_t st, int buf) {
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+            __builtin_amdgcn_global_load_lds(
+                (const __attribute__((address_space(1))) void*)(src[0][i] + st * step[0][i]),
+                (__attribute__((address_space(3))) void*)&L[buf][0][(2 * w + i) * 128], 16, 0, 0);
+          if (!diag) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+              __builtin_amdgcn_global_load_lds(
+                  (const __attribute__((address_space(1))) void*)(src[1][i] + st * step[1][i]),
+                  (__attribute__((address_space(3))) void*)&L[buf][1][(2 * w + i) * 128], 16, 0, 0);
+          }
+        };
+        __syncthreads();  // buffer 0 may still be read by a register stage
+        issue(0, 0);
+        for (int64_t st = 0; st < nfull; ++st) {
+          // this wave's loads of stage st have landed; after the barrier every
+          // wave's have, and every wave is done reading the other buffer
+          ILS_WAIT_VM(0);
+          __asm__ __volatile__("" ::: "memory");
+          __builtin_amdgcn_s_barrier();
+          __asm__ __volatile__("" ::: "memory");
+          if (st + 1 < nfull) issue(st + 1, (int)((st + 1) & 1));
+          compute((int)(st & 1));
+        }
+      }
+      const int64_t kt = ka + nfull * kPersRS;
+      if (kt < kend) reg_stage(kt, kend);
+      const int vx = pers_vx(x, part, r0, r1, job.p);
+      double* P = job.partials + (main ? pers_slot_main(vx, tile, job.q, job.W)
+                                       : pers_slot_left(vx, tile - job.q * job.W, c, job.q, job.W, job.L, job.cmax)) *
+                                     4096;
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int cc = 0; cc < 2; ++cc)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = wr + a * 16 + Mma<double>::row(lane, v);
+            const int col = wc + cc * 16 + lr;
+            P[row * 64 + col] = acc[a][cc][v];
+          }
+      __syncthreads();  // LDS free for the next share
+    }
+  }
+}
+
+// Per (tile, part): the shares of XCD 0..7 in row order (share index c within
+// an XCD follows the rows).  Wave 0 lists them, one (XCD, c) pair per lane in
+// that order, compacted by ballot; then every thread adds its element.
+__global__ __launch_bounds__(256) void k_gram_pers_fin(GramPJob job) {
+  __shared__ int slots[kXcds * kPersMaxShares];
+  __shared__ int nsl;
+  const int part = (int)blockIdx.y / job.T, tile = (int)blockIdx.y % job.T;
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    const int64_t lo = part ? job.p : 0, hi = part ? job.M : job.p;
+    const bool main = tile < job.q * job.W;
+    const int lt = tile - job.q * job.W;
+    const int per = main ? 1 : job.cmax;  // pairs (XCD, share) per XCD
+    int base = 0;
+    for (int p0 = 0; p0 < kXcds * per; p0 += 64) {
+      const int pair = p0 + lane;
+      const int x = pair / per, c = pair % per;
+      int slot = -1;
+      if (x < kXcds) {
+        int64_t r0, r1;
+        pers_range(job.M, x, r0, r1);
+        const int64_t S = (r1 - r0 + kPersRS - 1) / kPersRS;
+        int64_t klo = r0, khi = r1;
+        bool ok = S > 0;
+        if (ok && !main) {
+          const int64_t LS = (int64_t)job.L * S;
+          const int j = pers_first((int64_t)lt * S, LS, job.W) + c;
+          ok = j < job.W;
+          if (ok) {
+            const int64_t u0 = (int64_t)j * LS / job.W, u1 = (int64_t)(j + 1) * LS / job.W;
+            const int64_t a = u0 > (int64_t)lt * S ? u0 : (int64_t)lt * S;
+            const int64_t b = u1 < (int64_t)(lt + 1) * S ? u1 : (int64_t)(lt + 1) * S;
+            ok = a < b;
+            klo = r0 + (a - (int64_t)lt * S) * kPersRS;
+            khi = r0 + (b - (int64_t)lt * S) * kPersRS;
+            if (khi > r1) khi = r1;
+          }
+        }
+        if (ok && (klo > lo ? klo : lo) < (khi < hi ? khi : hi)) {
+          const int vx = pers_vx(x, part, r0, r1, job.p);
+          slot = (int)(main ? pers_slot_main(vx, tile, job.q, job.W)
+                            : pers_slot_left(vx, lt, c, job.q, job.W, job.L, job.cmax));
+        }
+      }
+      const uint64_t m = __ballot(slot >= 0);
+      if (slot >= 0) slots[base + __popcll(m & ((1ull << lane) - 1))] = slot;
+      base += __popcll(m);
+    }
+    if (lane == 0) nsl = base;
+  }
+  __syncthreads();
+  int ti, tj;
+  tile_of(tile, ti, tj);
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  const int row = e / 64, col = e % 64;
+  const int i = ti * 64 + row, jj = tj * 64 + col;
+  if (i >= job.nc || jj >= job.nc || (ti == tj && row < col) || (i == job.n && jj == job.n)) return;
+  const int cnt = nsl;
+  double sacc = 0.0;
+  int q = 0;
+  for (; q + 8 <= cnt; q += 8) {
+    double v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = job.partials[(size_t)slots[q + k] * 4096 + e];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) sacc += v[k];
+  }
+  for (; q < cnt; ++q) sacc += job.partials[(size_t)slots[q] * 4096 + e];
+  double* G = part ? job.G1 : job.G0;
+  double* gv = part ? job.gv1 : job.gv0;
+  if (i == job.n) {
+    gv[jj] = sacc;
+    return;
+  }
+  G[i + (int64_t)jj * job.ldg] = sacc;
+  G[jj + (int64_t)i * job.ldg] = sacc;
+}
+
+static int device_cus() {
+  static int cache[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (dev < 0 || dev >= 64) return 256;
+  if (!cache[dev]) {
+    int c = 0;
+    if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c < kXcds) c = 256;
+    cache[dev] = c;
+  }
+  return cache[dev];
+}
+
+// Largest number of workgroups sharing one leftover tile within one XCD range.
+static int pers_cmax(int64_t M, int L, int W) {
+  int cm = 1;
+  for (int x = 0; x < kXcds && L > 0; ++x) {
+    int64_t r0, r1;
+    pers_range(M, x, r0, r1);
+    const int64_t S = (r1 - r0 + kPersRS - 1) / kPersRS;
+    const int64_t LS = (int64_t)L * S;
+    if (LS == 0) continue;
+    for (int j = 0; j < W; ++j) {
+      const int64_t u0 = (int64_t)j * LS / W, u1 = (int64_t)(j + 1) * LS / W;
+      for (int64_t u = u0; u < u1;) {
+        const int lt = (int)(u / S);
+        cm = std::max(cm, j - pers_first((int64_t)lt * S, LS, W) + 1);
+        u = std::min(u1, (int64_t)(lt + 1) * S);
+      }
+    }
+  }
+  return cm;
+}
+
+struct PersShape {
+  int T, W, q, L, cmax;
+};
+static PersShape pers_shape(int64_t nc, int64_t M) {
+  static std::mutex mu;
+  static std::map<std::tuple<int64_t, int64_t, int>, int> cache;
+  PersShape sh;
+  const int nt = (int)((nc + 63) / 64);
+  sh.T = nt * (nt + 1) / 2;
+  sh.W = kPersWpc * (device_cus() / kXcds);
+  sh.q = sh.T / sh.W;
+  sh.L = sh.T - sh.q * sh.W;
+  std::lock_guard<std::mutex> lk(mu);
+  auto key = std::make_tuple(nc, M, sh.W);
+  auto it = cache.find(key);
+  if (it == cache.end()) {
+    if (cache.size() > 256) cache.clear();
+    it = cache.emplace(key, pers_cmax(M, sh.L, sh.W)).first;
+  }
+  sh.cmax = it->second;
+  return sh;
+}
+
+static size_t pers_partials(int64_t nc, int64_t M) {
+  const PersShape sh = pers_shape(nc, M);
+  return ((size_t)(kXcds + 1) * ((size_t)sh.q * sh.W + (size_t)sh.L * sh.cmax)) * 4096;
+}
+
+static bool pers_aligned(const double* A, int64_t lda, const double* vb) {
+  return ((uintptr_t)A & 15) == 0 && (lda & 1) == 0 && (!vb || ((uintptr_t)vb & 15) == 0);
+}
+
 // Launch configuration: tile edge and the number of workgroups to aim for
 // (the K-split follows from it).  Defaults: 128-tiles when the matrix is
 // large enough to give them split-K work for every CU (512 workgroups), else
@@ -243,13 +633,28 @@ GramCfg gram_default_cfg(int64_t n) {
   GramCfg c;
   c.tile = n >= 512 ? 128 : 64;
   c.workgroups = c.tile == 128 ? 512 : 1024;
+  c.kind = kGramSplitK;
   return c;
 }
 
+// Without a table entry: the persistent kernel for FP64 products with
+// enough columns and rows to give every resident workgroup several stages,
+// and few enough tiles that splitting the rows per XCD stays cheap.
+static GramCfg auto_cfg(int precision, int64_t n, int64_t K) {
+  if (precision == ILS_PREC_FP64 && n >= 192 && K >= 2048) {
+    const int nt = (int)((n + 1 + 63) / 64);
+    if (nt * (nt + 1) / 2 <= 2 * kPersWpc * (device_cus() / kXcds)) return GramCfg{64, kPersWpc, kGramPersistent};
+  }
+  return gram_default_cfg(n);
+}
+
 GramCfg gram_cfg(int precision, int64_t n, int64_t K) {
-  std::lock_guard<std::mutex> lk(g_cfg_mu);
-  auto it = g_cfg.find(cfg_key(precision, n, K));
-  return it == g_cfg.end() ? gram_default_cfg(n) : it->second;
+  {
+    std::lock_guard<std::mutex> lk(g_cfg_mu);
+    auto it = g_cfg.find(cfg_key(precision, n, K));
+    if (it != g_cfg.end()) return it->second;
+  }
+  return auto_cfg(precision, n, K);
 }
 
 void gram_set_cfg(int precision, int64_t n, int64_t K, GramCfg c) {
@@ -320,11 +725,17 @@ static void second_plan(int64_t K1, int64_t klen0, int& nsplit, int64_t& klen) {
   nsplit = (int)want;
 }
 
+// The split-K configuration behind cfg (a persistent entry falls back to the
+// default split-K launch where the persistent kernel does not apply).
+static GramCfg splitk_of(GramCfg c, int64_t n) { return c.kind == kGramSplitK ? c : gram_default_cfg(n); }
+
 static size_t plan_size(int64_t n, int64_t K, GramCfg c) {
   int tm, ntiles, nsplit;
   int64_t klen;
-  gram_plan_cfg(n, K, c, tm, ntiles, nsplit, klen);
-  return (size_t)ntiles * nsplit * tm * tm;
+  gram_plan_cfg(n, K, splitk_of(c, n), tm, ntiles, nsplit, klen);
+  size_t sz = (size_t)ntiles * nsplit * tm * tm;
+  if (c.kind == kGramPersistent) sz = std::max(sz, pers_partials(n, K));
+  return sz;
 }
 
 // Partial-tile scratch in doubles, enough for either precision's
@@ -339,9 +750,12 @@ size_t gram_partials_size(int64_t n, int64_t K) {
 size_t gram2_partials_size(int64_t n, int64_t K0, int64_t K1) {
   int tm, ntiles, ns0, ns1;
   int64_t kl0, kl1;
-  gram_plan_cfg(n + 1, K0, gram_cfg(ILS_PREC_FP64, n, K0), tm, ntiles, ns0, kl0);
+  const GramCfg c = gram_cfg(ILS_PREC_FP64, n, K0);
+  gram_plan_cfg(n + 1, K0, splitk_of(c, n), tm, ntiles, ns0, kl0);
   second_plan(K1, kl0, ns1, kl1);
-  return std::max((size_t)ntiles * (ns0 + ns1) * tm * tm, gram_partials_size(n, K0));
+  size_t sz = std::max((size_t)ntiles * (ns0 + ns1) * tm * tm, gram_partials_size(n, K0));
+  if (c.kind == kGramPersistent) sz = std::max(sz, pers_partials(n + 1, K0 + std::max<int64_t>(K1, 0)));
+  return sz;
 }
 
 size_t gram_partials_size_cfg(int64_t n, int64_t K, GramCfg c) { return plan_size(n, K, c); }
@@ -363,6 +777,36 @@ static void gram_run(hipStream_t s, int64_t K, int64_t n, const double* A, int64
                      T* partials, double* G, int64_t ldg, double* gv, hipEvent_t mid, GramCfg cfg,
                      int64_t K1 = -1, const double* A1 = nullptr, const double* vb1 = nullptr,
                      double* G1 = nullptr, double* gv1 = nullptr) {
+  if (std::is_same<T, double>::value && cfg.kind == kGramPersistent && pers_aligned(A, lda, vb) &&
+      (K1 < 0 || (A1 == A + K && (vb ? vb1 == vb + K : vb1 == nullptr)))) {
+    GramPJob pj;
+    pj.A = A;
+    pj.lda = lda;
+    pj.vb = vb;
+    pj.M = K + (K1 > 0 ? K1 : 0);
+    pj.p = K;
+    pj.n = (int)n;
+    pj.nc = (int)n + (vb ? 1 : 0);
+    const PersShape sh = pers_shape(pj.nc, pj.M);
+    pj.T = sh.T;
+    pj.W = sh.W;
+    pj.q = sh.q;
+    pj.L = sh.L;
+    pj.cmax = sh.cmax;
+    if (sh.cmax <= kPersMaxShares) {
+      pj.partials = (double*)partials;
+      pj.G0 = G;
+      pj.gv0 = gv;
+      pj.G1 = G1;
+      pj.gv1 = gv1;
+      pj.ldg = ldg;
+      hipLaunchKernelGGL(k_gram_pers, dim3(kXcds * sh.W), dim3(256), 0, s, pj);
+      if (mid) (void)hipEventRecord(mid, s);
+      hipLaunchKernelGGL(k_gram_pers_fin, dim3(64 * 64 / 256, sh.T * (K1 >= 0 ? 2 : 1)), dim3(256), 0, s, pj);
+      return;
+    }
+  }
+  cfg = splitk_of(cfg, n);
   GramJob job;
   job.n = (int)n;
   job.nc = (int)n + (vb ? 1 : 0);

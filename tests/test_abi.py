@@ -31,7 +31,7 @@ def test_struct_layouts():
     # ils_opts: 8 + 4*4 + 8 + 8 + 8 + 8 + 8 + 8 + 8 + 8 bytes, ils_info: 4+4+8*5
     assert C.sizeof(ils.Opts) == 88
     assert C.sizeof(ils._Info) == 48
-    assert C.sizeof(ils._TuneEntry) == 40  # 2 int32, 2 int64, 2 int32, 1 double
+    assert C.sizeof(ils._TuneEntry) == 48  # 2 int32, 2 int64, 2 int32, 1 double, 2 int32
     o = ils.Opts()
     ils.load_library().ils_opts_default(C.byref(o))
     assert o.tol == 1e-6 and o.max_outer == 20000 and o.stop_rule == ils.STOP_RR

@@ -150,3 +150,55 @@ def test_batched_nonfinite_inputs(form, where, val):
     assert infos[1].status == ils.ERR_NONFINITE
     assert rc == ils.ERR_NONFINITE
     assert torch.all(out_bad == 5.0)
+
+
+@pytest.mark.parametrize("sr,wpc,order", [(16, 1, ils.BATCH_AS_GIVEN), (64, 2, ils.BATCH_LARGEST_FIRST)],
+                         ids=["stage16_wpc1_given", "stage64_wpc2_largest"])
+def test_batched_launch_choices_match_oracle(batch, tmp_path, sr, wpc, order):
+    """The launch choices the autotuner may pick (Gram stage rows, resident
+    workgroups per CU, processing order), set through a table file, give the
+    oracle's iterates in both forms."""
+    import json
+    probs, dv, xr = batch
+    nb = max(P.n for P in probs)
+    b = 0
+    while (1 << b) < nb:
+        b += 1
+    kb = 0
+    while (1 << kb) < len(probs):
+        kb += 1
+    f = tmp_path / "t.json"
+    lines = [json.dumps({"kernel": "batched", "precision": 0, "form": form, "n_bucket": b, "k_bucket": kb,
+                         "tile": sr, "workgroups": wpc, "kind": order}) for form in (0, 1)]
+    f.write_text('{"version": 1, "entries": [\n  ' + ",\n  ".join(lines) + "\n]}\n")
+    ils.tune_clear()
+    try:
+        ils.tune_load(f)
+        for form in (ils.FORM_PAPER, ils.FORM_CORRECTION):
+            xs, infos, rc = ils.sp_solve_batched(dv, stop_rule=ils.STOP_FIXED, max_outer=3, form=form)
+            assert rc == ils.OK
+            for P, x, inf in zip(probs, xs, infos):
+                ref, _ = O.sp_solve(P.A, P.b, P.p, stop_rule=O.STOP_FIXED, max_outer=3, form=form)
+                assert inf.status == ils.OK and inf.outer_iters == 3
+                assert_close(x.cpu().numpy(), ref, 1e-10, what=str((P.n, form, sr, wpc, order)))
+    finally:
+        ils.tune_clear()
+
+
+def test_tune_batched_picks_a_valid_choice(batch):
+    probs, dv, xr = batch
+    plan = ils.BatchPlan(dv, x_refs=xr)
+    ils.tune_clear()
+    try:
+        best = ils.tune_batched(plan, reps=2, stop_rule=ils.STOP_XREF, tol=1e-8, form=ils.FORM_CORRECTION,
+                                precision=ils.PREC_MIXED)
+        print(f"[gpu-batched] tuned: {best}", flush=True)
+        assert best["kernel"] == "batched" and best["tile"] in (16, 32, 64) and best["workgroups"] in (1, 2)
+        assert best["kind"] in (ils.BATCH_LARGEST_FIRST, ils.BATCH_AS_GIVEN) and best["ms"] > 0
+        assert plan.solve(stop_rule=ils.STOP_XREF, tol=1e-8, form=ils.FORM_CORRECTION,
+                          precision=ils.PREC_MIXED) == ils.OK
+        for P, x in zip(probs, plan.xs):
+            st, ref = O.normal_solve(P.A, P.b, P.p)
+            assert st == O.OK and rel(x.cpu().numpy(), ref) <= 1e-6
+    finally:
+        ils.tune_clear()

@@ -27,7 +27,11 @@ def test_tuned_gram_matches_oracle(tmp_path, prec):
     try:
         best = ils.tune_gram(A, 0, P.p, precision=prec, reps=3)
         print(f"[gpu-tune] precision {prec}: {best}", flush=True)
-        assert best["tile"] in (64, 128) and 256 <= best["workgroups"] <= 8192 and best["ms"] > 0
+        if best["kind"] == ils.GRAM_PERSISTENT:
+            assert prec == ils.PREC_FP64 and best["tile"] == 64 and best["workgroups"] == 4
+        else:
+            assert best["tile"] in (64, 128) and 256 <= best["workgroups"] <= 8192
+        assert best["ms"] > 0
         G = ils.gram(A, 0, P.p, precision=prec).cpu().numpy()
         ref = O.gram(P.A, 0, P.p)
         if prec == ils.PREC_FP64:
@@ -40,6 +44,7 @@ def test_tuned_gram_matches_oracle(tmp_path, prec):
         entries = json.loads(f.read_text())["entries"]
         assert len(entries) == 1 and entries[0]["tile"] == best["tile"]
         assert entries[0]["workgroups"] == best["workgroups"] and entries[0]["precision"] == prec
+        assert entries[0]["kind"] == best["kind"]
         ils.tune_clear()
         ils.tune_load(f)
         f2 = tmp_path / "tune2.json"
@@ -49,5 +54,39 @@ def test_tuned_gram_matches_oracle(tmp_path, prec):
                                x_ref=torch.from_numpy(P.x_star).cuda(), tol=1e-9,
                                form=ils.FORM_CORRECTION, precision=prec)
         assert info.status == ils.OK and info.rel_err < 1e-9
+    finally:
+        ils.tune_clear()
+
+
+@pytest.mark.parametrize("shape", [(3000, 300, 200), (1500, 200, 1100)], ids=["one_pass_range", "two_pass_only"])
+def test_tune_residual_and_its_choices_match_oracle(tmp_path, shape):
+    """Every residual launch choice gives A^T J (b - A x) to the oracle's
+    value, and the sweep keeps a valid one."""
+    p, q, n = shape
+    P = W.dense_ils(p, q, n, ratio=0.5, seed=9, spectral="eig")
+    A = devA(P.A)
+    b = torch.from_numpy(P.b).cuda()
+    x = np.random.default_rng(3).standard_normal(n)
+    xd = torch.from_numpy(x).cuda()
+    ref = O.residual(P.A, P.b, P.p, x)
+    ils.tune_clear()
+    try:
+        best = ils.tune_residual(A, b, P.p, xd, reps=3)
+        print(f"[gpu-tune] residual {shape}: {best}", flush=True)
+        assert best["kernel"] == "residual" and best["kind"] in (ils.RESID_AUTO, ils.RESID_TWO_PASS)
+        assert 64 <= best["workgroups"] <= 2048 and best["ms"] > 0
+        r = ils.residual(A, b, P.p, xd).cpu().numpy()
+        assert np.linalg.norm(r - ref) <= 1e-12 * np.linalg.norm(ref)
+        nb = int(np.ceil(np.log2(n))) if n > 1 else 0
+        kb = int(np.ceil(np.log2(p + q)))
+        for wg, path in ((128, 0), (512, 0), (1024, 0), (256, 1)):
+            ils.tune_clear()
+            f = tmp_path / f"r{wg}_{path}.json"
+            f.write_text('{"version": 1, "entries": [\n  ' + json.dumps(
+                {"kernel": "residual", "precision": 0, "form": 0, "n_bucket": nb, "k_bucket": kb, "tile": 16,
+                 "workgroups": wg, "kind": path}) + "\n]}\n")
+            ils.tune_load(f)
+            r = ils.residual(A, b, P.p, xd).cpu().numpy()
+            assert np.linalg.norm(r - ref) <= 1e-12 * np.linalg.norm(ref), (wg, path)
     finally:
         ils.tune_clear()
