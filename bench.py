@@ -59,6 +59,26 @@ def tuned_entry(path, precision, n, K):
     return None
 
 
+def batched_launch_entry(form, precision, nmax, count):
+    """The committed table's batched-solver entry for this batch, or the
+    built-in default (stage rows 32, 2 workgroups per CU, largest first)."""
+    def bucket(x):
+        b = 0
+        while (1 << b) < x:
+            b += 1
+        return b
+    try:
+        with open(TUNE_FILE) as f:
+            for e in json.load(f)["entries"]:
+                if (e["kernel"] == "batched" and e["precision"] == precision and e["form"] == form
+                        and e["n_bucket"] == bucket(nmax) and e["k_bucket"] == bucket(count)):
+                    return {"stage_rows": e["tile"], "workgroups_per_cu": e["workgroups"],
+                            "order": "as given" if e["kind"] == 1 else "largest first", "source": "file"}
+    except (OSError, ValueError, KeyError):
+        pass
+    return {"stage_rows": 32, "workgroups_per_cu": 2, "order": "largest first", "source": "default"}
+
+
 def gram_kernel_name(tuned):
     what = "A1^T A1, A2^T A2 and border columns b1, b2 in one launch, FP64 MFMA"
     if tuned is not None and tuned.get("kind", 0) == 1:
@@ -192,7 +212,10 @@ def bench_batched(ils, W, np, torch, count=4096, single_sample=256):
         out[name] = {"solves_per_s": count / el, "ms_per_batch": el * 1e3, "status": rc,
                      "max_rel_err": max(r.rel_err for r in res),
                      "max_outer": max(r.outer_iters for r in res),
-                     "device_ms": res[0].device_ms}
+                     "device_ms": res[0].device_ms,
+                     "launch": batched_launch_entry(extra.get("form", ils.FORM_PAPER),
+                                                    extra.get("precision", ils.PREC_FP64),
+                                                    max(P.n for P in B), count)}
         log(f"batched {name}: {count / el:.0f} solves/s ({el * 1e3:.2f} ms per batch)")
     xs = torch.empty(max(P.n for P in B), dtype=torch.float64, device="cuda")
     ils.sp_solve(*dv[0][:2], dv[0][2], out=xs[:B[0].n], x_ref=xr[0], **kw)
