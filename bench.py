@@ -157,6 +157,30 @@ def cpu_baseline(P, reps=3, one_thread_budget_s=12.0):
             "runs": runs}
 
 
+def time_rk_multi(ils, W, np, torch, P, A, x, nrhs=16):
+    """SP-RK-RGS (correction form) for nrhs right-hand sides sharing the
+    headline A and one index stream: the headline b and nrhs - 1 more with
+    planted solutions (same noise level), to rel.err 1e-6 per column."""
+    rng = np.random.default_rng(77)
+    Xs = np.empty((P.n, nrhs))
+    Xs[:, 0] = P.x_star
+    Xs[:, 1:] = rng.standard_normal((P.n, nrhs - 1))
+    B = P.A @ Xs
+    B[:, 0] = P.b
+    B[:, 1:] += 1e-8 * rng.standard_normal((P.A.shape[0], nrhs - 1))
+    Bd = torch.from_numpy(np.ascontiguousarray(B.T)).cuda().t()
+    xr = torch.from_numpy(np.ascontiguousarray(Xs.T)).cuda().t()
+    kw = dict(stop_rule=ils.STOP_XREF, tol=1e-6, form=ils.FORM_CORRECTION)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    X, inf, iters = ils.rk_solve_multi(A, Bd, P.p, x_ref=xr, **kw)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    log(f"multi-RHS SP-RK-RGS: {nrhs} right-hand sides in {el * 1e3:.1f} ms")
+    return {"solves_per_s": nrhs / el, "ms_per_call": el * 1e3, "nrhs": nrhs, "max_outer": int(max(iters)),
+            "inner": inf.inner_iters, "max_rel_err": inf.rel_err, "status": inf.status}
+
+
 def bench_ratio09(ils, W, np, torch):
     """The headline problem with A2 scaled to ||A2|| = 0.9 sigma_min(A1) (the
     same A1 and x*, slower outer convergence): the SP forms, FP64 and mixed."""
@@ -589,8 +613,12 @@ def main():
             "sp_rk_rgs_mixed_correction": (ils.rk_solve, 1, dict(form=ils.FORM_CORRECTION,
                                                                  precision=ils.PREC_MIXED)),
         }
-        pick = [f for f in args.forms.split(",") if f] or list(table)
+        multi = "sp_rk_rgs_multi16_correction"
+        pick = [f for f in args.forms.split(",") if f] or list(table) + [multi]
         for name in pick:
+            if name == multi:
+                forms[name] = time_rk_multi(ils, W, np, torch, P, A, x, nrhs=16)
+                continue
             fn, reps, extra = table[name]
             forms[name] = time_form(fn, reps, **extra, **kw)
         ils.set_profiling(True)

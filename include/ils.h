@@ -183,6 +183,29 @@ int ils_sp_solve_multi(ils_handle* h, int64_t p, int64_t q, int64_t n, const dou
                        double* X, int64_t ldx, const ils_opts* opts, int64_t* iters /* host */,
                        ils_info* info /* host */);
 
+/* SP-RK-RGS (Algorithm 2) for nrhs right-hand sides B = [b_1 .. b_nrhs] (m x
+ * nrhs, ldb >= p + q) with the same A and one index stream: the column draws
+ * of Alg. 2 steps 8 and 10 depend only on the column norms of A1, so every
+ * right-hand side uses the draws ils_rk_solve makes with the same seed, and
+ * column r of X gets the iterates ils_rk_solve would give for b_r alone.
+ * A block of inner steps gathers its columns of A1 once for all right-hand
+ * sides, which turns the per-step inner products and updates into products
+ * over the block (groups of 16 right-hand sides).  Each column has its own
+ * outer stop test (Sec. 5) at x_k and inner stop test (every inner_check
+ * steps, as in ils_rk_solve); a column that meets its test stops changing
+ * while the others continue.  opts->x_ref, when given, is n x nrhs (leading
+ * dimension n).  X0 (ldx0 >= n) may be NULL (zero start); X is n x nrhs
+ * (ldx >= n).  ILS_PREC_FP64 only (else ILS_ERR_ARG); both forms.
+ * iters (host, nrhs entries, may be NULL) receives each column's outer
+ * count; info->outer_iters and info->rel_err are maxima over columns,
+ * info->inner_iters the inner steps run.  Returns ILS_ERR_NO_CONVERGENCE if
+ * any column is still above tol after max_outer outer steps.  Workspace
+ * grows with (2 p + 6 n) nrhs doubles. */
+int ils_rk_solve_multi(ils_handle* h, int64_t p, int64_t q, int64_t n, const double* A, int64_t lda,
+                       int64_t nrhs, const double* B, int64_t ldb, const double* X0, int64_t ldx0,
+                       double* X, int64_t ldx, const ils_opts* opts, int64_t* iters /* host */,
+                       ils_info* info /* host */);
+
 /* ---- many small problems in one launch ---- */
 
 /* One problem of a batch; all pointers are device pointers (x0 may be NULL,

@@ -31,7 +31,7 @@ LIB_PATH = _build.LIB
 EXPORTS = ("ils_create", "ils_destroy", "ils_opts_default", "ils_status_string", "ils_sp_solve",
            "ils_rk_solve", "ils_rgs_solve", "ils_gram", "ils_colpass", "ils_residual", "ils_residual_noalloc",
            "ils_spd_solve", "ils_rk_indices", "ils_scd_subsets", "ils_set_profiling",
-           "ils_get_phase_times", "ils_sp_solve_batched", "ils_sp_solve_multi", "ils_ws_create",
+           "ils_get_phase_times", "ils_sp_solve_batched", "ils_sp_solve_multi", "ils_rk_solve_multi", "ils_ws_create",
            "ils_ws_destroy", "ils_ws_train", "ils_ws_infer", "ils_ws_save", "ils_ws_load",
            "ils_ws_nparams", "ils_ws_get_params", "ils_ws_set_params", "ils_ws_forward", "ils_ws_grad",
            "ils_ws_adam", "ils_csr_create", "ils_csr_destroy", "ils_sp_solve_csr", "ils_rk_solve_csr",
@@ -106,6 +106,8 @@ def load_library(path: str = LIB_PATH):
         "ils_sp_solve_batched": (C.c_int, [P, I64, P, P, P]),
         "ils_get_phase_times": (C.c_int, [P, P, C.c_int]),
         "ils_sp_solve_multi": (C.c_int, [P, I64, I64, I64, P, I64, I64, P, I64, P, I64, P, I64, P,
+                                         P, P]),
+        "ils_rk_solve_multi": (C.c_int, [P, I64, I64, I64, P, I64, I64, P, I64, P, I64, P, I64, P,
                                          P, P]),
         "ils_ws_create": (C.c_int, [P, I64, I64, I64, P, I64, U64, C.POINTER(P)]),
         "ils_ws_destroy": (C.c_int, [P]),
@@ -295,6 +297,39 @@ def sp_solve_multi(A, B, p, X0=None, out=None, raise_on_error=False, **kw):
                float(info.rel_err), float(info.device_ms))
     if raise_on_error and rc != OK:
         raise ILSError(f"ils_sp_solve_multi: {status_string(rc)}")
+    return X, res, iters
+
+
+def rk_solve_multi(A, B, p, X0=None, out=None, raise_on_error=False, **kw):
+    """SP-RK-RGS for the columns of B (m x nrhs) sharing A and one index
+    stream (column r follows rk_solve on b_r with the same seed).  x_ref,
+    when given, is an (n, nrhs) tensor with leading dimension n.  Returns
+    (X, Info, iters)."""
+    import numpy as np
+    torch = _torch()
+    if A.dim() != 2 or A.dtype != torch.float64 or not A.is_cuda:
+        raise ILSError("A must be a column-major (stride (1, lda)) float64 CUDA tensor")
+    m, n = A.shape
+    nrhs = B.shape[1]
+    _check_mat(B, m, nrhs, "B")
+    _check_mat(X0, n, nrhs, "X0")
+    xr = kw.get("x_ref")
+    if xr is not None:
+        _check_mat(xr, n, nrhs, "x_ref")
+        if nrhs > 1 and xr.stride(1) != n:
+            raise ILSError("x_ref must have leading dimension n")
+    X = out if out is not None else torch.empty((nrhs, n), dtype=torch.float64, device=A.device).t()
+    _check_mat(X, n, nrhs, "out")
+    o = make_opts(**kw)
+    info = _Info()
+    iters = np.zeros(nrhs, dtype=np.int64)
+    rc = load_library().ils_rk_solve_multi(
+        handle(A.device), p, m - p, n, _ptr(A), _ld(A), nrhs, _ptr(B), _ld(B), _ptr(X0),
+        n if X0 is None else _ld(X0), _ptr(X), _ld(X), C.byref(o), iters.ctypes.data, C.byref(info))
+    res = Info(int(rc), int(info.outer_iters), int(info.inner_iters), float(info.rr),
+               float(info.rel_err), float(info.device_ms))
+    if raise_on_error and rc != OK:
+        raise ILSError(f"ils_rk_solve_multi: {status_string(rc)}")
     return X, res, iters
 
 

@@ -46,6 +46,12 @@ enum BufSlot {
   kBufMBt,      // multi-RHS: B^T
   kBufA1f32,    // FP32 copy of A1 (mixed-precision RK-RGS inner sweeps)
   kBufRkb,      // blocked RK-RGS inner steps: slice partials, C, coefficients
+  kBufRmW,      // multi-RHS RK-RGS: w of every right-hand side (p x nrhs)
+  kBufRmS,      // multi-RHS RK-RGS: s (p x nrhs)
+  kBufRmZ,      // multi-RHS RK-RGS: z (n x nrhs)
+  kBufRmT,      // multi-RHS RK-RGS: inner targets (n x nrhs)
+  kBufRmV,      // multi-RHS RK-RGS: w - s of a group (p x kMR), then A1^T of it (n x kMR)
+  kBufRmF,      // multi-RHS RK-RGS: frozen flags, target norms
   kBufCount
 };
 

@@ -38,6 +38,22 @@ void launch_rk_blocks_f32(hipStream_t st, const float* A1, int64_t lda, int64_t 
                           const double* cn, const int* j1, const int* j2, int64_t count, float* w, float* s,
                           double* z, double* scratch, unsigned* arrive, const int* inner_done,
                           const int* outer_done);
+// SP-RK-RGS blocks for up to kMR right-hand sides sharing one index stream
+// (k_rkmulti.hip).  W, S: p x R (ldw), Z, tgt: n x R; frozen: R flags (a
+// frozen right-hand side takes zero coefficients); scratch:
+// rk_multi_scratch(p) doubles; arrive: a zero last-block counter.
+constexpr int kMR = 16;
+size_t rk_multi_scratch(int64_t p);
+void launch_rk_multi_blocks(hipStream_t st, const double* A1, int64_t lda, int64_t p, int R, const double* tgt,
+                            int64_t ldt, const double* cn, const int* j1, const int* j2, int64_t count,
+                            double* W, double* S, int64_t ldw, double* Z, int64_t ldz, const int* frozen,
+                            double* scratch, unsigned* arrive);
+// Inner stop test of every right-hand side of a group: V (p x R) and AtV
+// (n x R) are scratch; sets frozen[r] when ||tgt_r - A1^T (w_r - s_r)||^2 <=
+// itol2 tn2[r].
+void launch_rkm_check(hipStream_t st, const double* A1, int64_t lda, int64_t p, int64_t n, int R, const double* W,
+                      const double* S, int64_t ldw, double* V, double* AtV, const double* tgt, int64_t ldt,
+                      const double* tn2, double itol2, int* frozen);
 void launch_scd_inner(hipStream_t st, const double* G1, int64_t ldg, int64_t n, double* r, double* beta,
                       const uint32_t* mask, int64_t mask_words, const int* jpre, int norm_mode,
                       int64_t count, int check, double itol2, const double* tn2, int* inner_done,
