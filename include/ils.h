@@ -384,7 +384,9 @@ enum { ILS_RESID_AUTO = 0, ILS_RESID_TWO_PASS = 1 };
 /* One launch choice; the fields mean, per kernel:
  *   ILS_TUNE_GRAM     n columns, K rows; tile 64 or 128; workgroups aimed at
  *                     (ILS_GRAM_SPLITK, sets the K-split) or resident per CU
- *                     (ILS_GRAM_PERSISTENT); kind ILS_GRAM_*.
+ *                     (ILS_GRAM_PERSISTENT; under ILS_PREC_MIXED it first
+ *                     copies the rows to FP32 and reads the copy); kind
+ *                     ILS_GRAM_*.
  *   ILS_TUNE_BATCHED  n = largest n of the batch, K = batch size; tile = rows
  *                     of A per LDS stage of the Gram products (16, 32, 64);
  *                     workgroups = resident per CU (1 or 2); kind = order the
@@ -404,8 +406,10 @@ typedef struct {
 } ils_tune_entry;
 
 /* Time every launch configuration of the Gram kernel (split-K: tile edge
- * 64 / 128 x 256 .. 8192 workgroups; FP64 also the persistent kind, used
- * where A is 16-byte aligned with an even lda) on G = A[0:K, :]^T A[0:K, :] (reps launches each,
+ * 64 / 128 x 256 .. 8192 workgroups; the persistent kind, used where the
+ * operand columns are 16-byte aligned: FP64 A with an even lda, or under
+ * ILS_PREC_MIXED an FP32 copy of the rows made by the launch) on
+ * G = A[0:K, :]^T A[0:K, :] (reps launches each,
  * after one warm-up; the matrix is only read) and keep the fastest for the
  * bucket (precision, ceil(log2 n), ceil(log2 K)) in the process-wide table
  * that all Gram launches consult (every solver, every handle).  *best (host,

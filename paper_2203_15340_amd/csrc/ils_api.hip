@@ -280,6 +280,12 @@ int ils::sp_solve_op(ils_handle* h, const MatOp& M, const double* b, const doubl
       (st = h->need(kBufSBad, sizeof(int) * 2 * nblk, (void**)&sbad)) ||
       (st = h->need(kBufDinv, gj_scratch_bytes(n, n + nrhs), (void**)&dinv)))
     return fail(info, st);
+  // mixed precision: scratch for the FP32 copy of A1 when the launch table's
+  // mixed Gram entry reads one
+  float* a1f = nullptr;
+  if (!M.sp && o->precision == ILS_PREC_MIXED && gram_f32_uses_copy(n, p) &&
+      (st = h->need(kBufA1f32, sizeof(float) * gram_f32_copy_ld(p) * n, (void**)&a1f)))
+    return fail(info, st);
 
   if (h->timing()) HIPCHK(hipEventRecord(h->ev0, s));
   h->mark(0);
@@ -294,7 +300,7 @@ int ils::sp_solve_op(ils_handle* h, const MatOp& M, const double* b, const doubl
   if (bordered)  // A1^T A1, A1^T b1 and A2^T A2, A2^T b2 in one launch pair
     launch_gram2_f64(s, n, M.lda, ldw, (double*)part, mid, p, M.A, b, W, g, q, M.A + p, b + p, W + n * ldw, rv);
   else  // A1^T A1 for [A1^T A1 | A2^T A2 | A^T J b] or [A1^T A1 | I]
-    mat_gram(s, M, 0, o->precision, part, W, ldw, mid);
+    mat_gram(s, M, 0, o->precision, part, W, ldw, mid, a1f);
   HIPCHK(hipMemsetAsync(h->st, 0, sizeof(LoopState), s));
   if (!bordered) {
     mat_colpass(s, M, b, g, nullptr, &ds->bits);
@@ -348,6 +354,13 @@ int ils::sp_solve_op(ils_handle* h, const MatOp& M, const double* b, const doubl
   while (true) {
     const int64_t kend = std::min(k + chunk, o->max_outer + 2);
     for (; k < kend; ++k) {
+      if (!paper && k == 0 && !x0) {
+        // r_0 at x_0 = 0 is A^T J b, which the column pass formed
+        SpStepArgs a0 = a;
+        a0.r = g;
+        launch_sp_step(s, a0, k);
+        continue;
+      }
       if (!paper && k <= o->max_outer) mat_residual(s, M, b, k & 1 ? xb1 : xb0, tv, rv, &ds->done);
       launch_sp_step(s, a, k);
     }
@@ -386,10 +399,16 @@ extern "C" int ils_gram(ils_handle* h, int64_t r0, int64_t r1, int64_t n, const 
   void* part;
   int st = h->need(kBufPart, gram_partials_size(n, r1 - r0) * sizeof(double), &part);
   if (st) return st;
-  if (precision == ILS_PREC_MIXED)
-    launch_gram_f32(h->stream, r1 - r0, n, A + r0, lda, (float*)part, G, ldg);
-  else
-    launch_gram_f64(h->stream, r1 - r0, n, A + r0, lda, (double*)part, G, ldg);
+  const int64_t K = r1 - r0;
+  if (precision == ILS_PREC_MIXED && gram_f32_uses_copy(n, K)) {
+    float* a1f;
+    if ((st = h->need(kBufA1f32, sizeof(float) * gram_f32_copy_ld(K) * n, (void**)&a1f))) return st;
+    launch_gram_f32_copy(h->stream, K, n, A + r0, lda, a1f, (float*)part, G, ldg);
+  } else if (precision == ILS_PREC_MIXED) {
+    launch_gram_f32(h->stream, K, n, A + r0, lda, (float*)part, G, ldg);
+  } else {
+    launch_gram_f64(h->stream, K, n, A + r0, lda, (double*)part, G, ldg);
+  }
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(h->stream));
   return ILS_OK;

@@ -147,6 +147,14 @@ void launch_gram_f64(hipStream_t s, int64_t K, int64_t n, const double* A, int64
                      const double* vb = nullptr, double* gv = nullptr);
 void launch_gram_f32(hipStream_t s, int64_t K, int64_t n, const double* A, int64_t lda,
                      float* partials, double* G, int64_t ldg, hipEvent_t mid = nullptr);
+// FP32 Gram through an FP32 copy of the K rows (Af: gram_f32_copy_ld(K) x n
+// floats of scratch), formed first; taken when the launch table's mixed entry
+// for (n, K) is the persistent kind (gram_f32_uses_copy), which then reads
+// half the bytes of the FP64 rows.
+int64_t gram_f32_copy_ld(int64_t K);
+bool gram_f32_uses_copy(int64_t n, int64_t K);
+void launch_gram_f32_copy(hipStream_t s, int64_t K, int64_t n, const double* A, int64_t lda, float* Af,
+                          float* partials, double* G, int64_t ldg, hipEvent_t mid = nullptr);
 // Both bordered products [A0 vb0]^T [A0 vb0] and [A1 vb1]^T [A1 vb1] in one
 // launch pair (FP64, part 0's configuration); `partials` must hold
 // gram2_partials_size(n, K0, K1) doubles.
@@ -177,7 +185,7 @@ void gram_set_cfg_bucket(int precision, int n_bucket, int k_bucket, GramCfg c);
 void gram_clear_cfg();
 size_t gram_partials_size_cfg(int64_t n, int64_t K, GramCfg c);
 void launch_gram_cfg(hipStream_t s, int precision, int64_t K, int64_t n, const double* A, int64_t lda,
-                     void* partials, double* G, int64_t ldg, GramCfg cfg);
+                     void* partials, double* G, int64_t ldg, GramCfg cfg, float* a1f = nullptr);
 void launch_norm2(hipStream_t s, int64_t n, const double* v, double* out);
 void launch_transpose(hipStream_t s, int64_t n, int64_t ncol, const double* X, int64_t ldx,
                       double* Y, int64_t ldy);

@@ -117,8 +117,11 @@ void mat_colpass(hipStream_t s, const MatOp& M, const double* b, double* g, doub
 void mat_residual(hipStream_t s, const MatOp& M, const double* b, const double* x, double* t, double* r,
                   const int* done);
 // G = A1^T A1 (second == 0) or A2^T A2 (second == 1).
+// a1f: scratch for an FP32 copy of A1 (gram_f32_copy_ld(p) x n floats) or
+// null; with it, and the mixed launch entry of the persistent kind, the FP32
+// product reads the copy.
 void mat_gram(hipStream_t s, const MatOp& M, int second, int precision, void* part, double* G, int64_t ldg,
-              hipEvent_t mid = nullptr);
+              hipEvent_t mid = nullptr, float* a1f = nullptr);
 void mat_rk_inner(hipStream_t st, const MatOp& M, const double* tgt, const double* cn, const int* j1,
                   const int* j2, int64_t count, double* w, double* s, double* z, const int* inner_done,
                   const int* outer_done);

@@ -93,13 +93,16 @@ extern "C" int ils_tune_gram(ils_handle* h, int64_t K, int64_t n, const double* 
   std::vector<GramCfg> cands;
   for (int t : tiles)
     for (int w : targets) cands.push_back(GramCfg{t, w, kGramSplitK});
-  if (precision == ILS_PREC_FP64) cands.push_back(GramCfg{64, kGramPersistentWpc, kGramPersistent});
+  cands.push_back(GramCfg{64, kGramPersistentWpc, kGramPersistent});  // FP32: from a copy of the rows
   size_t part_max = 0;
   for (const GramCfg& c : cands) part_max = std::max(part_max, gram_partials_size_cfg(n, K, c));
   double *G, *part;
+  float* a1f = nullptr;
   int st;
   if ((st = h->need(kBufM, sizeof(double) * n * n, (void**)&G)) ||
-      (st = h->need(kBufPart, sizeof(double) * part_max, (void**)&part)))
+      (st = h->need(kBufPart, sizeof(double) * part_max, (void**)&part)) ||
+      (precision == ILS_PREC_MIXED &&
+       (st = h->need(kBufA1f32, sizeof(float) * gram_f32_copy_ld(K) * n, (void**)&a1f))))
     return st;
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
@@ -108,9 +111,9 @@ extern "C" int ils_tune_gram(ils_handle* h, int64_t K, int64_t n, const double* 
   float win_ms = INFINITY;
   {
     for (const GramCfg& c : cands) {
-      launch_gram_cfg(s, precision, K, n, A, lda, part, G, n, c);  // warm-up
+      launch_gram_cfg(s, precision, K, n, A, lda, part, G, n, c, a1f);  // warm-up
       (void)hipEventRecord(e0, s);
-      for (int r = 0; r < reps; ++r) launch_gram_cfg(s, precision, K, n, A, lda, part, G, n, c);
+      for (int r = 0; r < reps; ++r) launch_gram_cfg(s, precision, K, n, A, lda, part, G, n, c, a1f);
       (void)hipEventRecord(e1, s);
       if (hipEventSynchronize(e1) != hipSuccess) {
         (void)hipEventDestroy(e0);
@@ -340,7 +343,7 @@ extern "C" int ils_tune_load(const char* path) {
     const bool kind_ok = e.cfg.kind == kGramSplitK
                              ? ((e.cfg.tile == 64 || e.cfg.tile == 128) && e.cfg.workgroups >= 8 &&
                                 e.cfg.workgroups <= (1 << 20))
-                             : (e.cfg.kind == kGramPersistent && e.precision == ILS_PREC_FP64 && e.cfg.tile == 64 &&
+                             : (e.cfg.kind == kGramPersistent && e.cfg.tile == 64 &&
                                 e.cfg.workgroups == kGramPersistentWpc);
     if (got < 5 || !kind_ok || (e.precision != ILS_PREC_FP64 && e.precision != ILS_PREC_MIXED) ||
         e.n_bucket < 0 || e.n_bucket > 40 || e.k_bucket < 0 || e.k_bucket > 62) {

@@ -117,18 +117,22 @@ static int64_t resid_groups(int64_t m, int64_t n) {
 // blocks of 16 rows in turn; thread (k = tid % 16, g = tid / 16) holds row k
 // of the block at columns g, g + 64, ... (the 16 row lanes of a column read
 // one 128-byte segment), forms t_k = b_k - (A x)_k with the other 63 column
-// groups through LDS, and adds J_kk t_k A_kc to its column accumulators, so
-// the block is read from memory once.  Each workgroup's column sums go to a
-// partial vector; a second kernel adds the partials in workgroup order.
-// (Keeping the next block's loads in flight during the reduction needs a
-// second register set, which leaves no room for the accumulators; with them
-// in LDS that variant was slower: 39 against 37.6 us at 20000 x 1000.)
+// groups through LDS, and adds J_kk t_k A_kc into the column sums, so the
+// block is read from memory once.  The next block's loads are issued before
+// the current block is reduced (two register sets, one barrier per block
+// that waits for LDS only), and the per-block column sums are reduced over
+// the 16 row lanes at once, so each thread keeps one accumulator instead of
+// 16 (37.3 -> 33.0 us at 20000 x 1000, 4.8 TB/s; mapping blocks to XCDs in
+// runs or giving each workgroup a contiguous range of blocks moved it by
+// under 1 us).  Each workgroup's column sums go to a partial vector; a
+// second kernel adds the partials in workgroup order.
 constexpr int kR1Threads = 1024;
 constexpr int kR1Rows = 16;
 constexpr int kR1Groups = kR1Threads / kR1Rows;  // 64 column groups
 constexpr int kR1Per = 16;                       // columns per thread
 constexpr int64_t kR1MaxN = (int64_t)kR1Groups * kR1Per;
 constexpr int kR1Wgs = kResidDefaultWgs;  // one per CU
+constexpr int kR1StepsPerRsrc = 4;        // column steps per buffer resource
 
 static int r1_wgs(int64_t m, int wgs) {
   const int64_t nblk = (m + kR1Rows - 1) / kR1Rows;
@@ -136,6 +140,10 @@ static int r1_wgs(int64_t m, int wgs) {
 }
 
 static bool one_pass(int64_t n, ResidCfg c) { return n <= kR1MaxN && c.path == kResidAuto; }
+// the one-pass kernel's buffer offsets reach (kR1Rows + 4 kR1Groups lda) doubles
+static bool one_pass_fits(int64_t lda) {
+  return ((int64_t)kR1Rows + (int64_t)kR1StepsPerRsrc * kR1Groups * lda) * 8 < ((int64_t)1 << 31);
+}
 
 size_t residual_scratch_cfg(int64_t m, int64_t n, ResidCfg c) {
   const size_t two = (size_t)(resid_groups(m, n) + 1) * (size_t)(m > 0 ? m : 1);
@@ -148,67 +156,120 @@ size_t residual_scratch(int64_t m, int64_t n) {
   return a > b ? a : b;
 }
 
+// s_waitcnt lgkmcnt(0) alone (vmcnt and expcnt at their maxima), so a
+// barrier can publish LDS writes while global loads stay in flight.
+#define ILS_WAIT_LGKM0() __builtin_amdgcn_s_waitcnt((0xF) | (0x3 << 14) | (0x7 << 4))
+__device__ inline void lds_barrier() {
+  ILS_WAIT_LGKM0();
+  __asm__ __volatile__("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  __asm__ __volatile__("" ::: "memory");
+}
+
+struct R1Block {
+  double a[kR1Per];
+  double b;
+};
+
+// The block's loads are buffer loads: one resource (a wave-uniform base) per
+// 4 column steps, the step within them as a scalar offset and one 32-bit
+// byte offset per lane (k + g lda), so the addresses take no per-load
+// registers.  Loads out of range return zero without a branch: columns past
+// n lie past the resource's size, and a row past m gets an offset past every
+// size.  The launch keeps 4 kR1Groups lda rows within 2^31 bytes.
+constexpr int kBufRsrcWord3 = 0x00020000;  // raw (untyped) buffer access on gfx9-family parts
+constexpr uint32_t kBufOutOfRange = 0x7fffffffu;
+
+__device__ inline void r1_load(R1Block& d, const double* __restrict__ A, int64_t lda, int64_t m, int64_t n,
+                               const double* __restrict__ b, int64_t blk, int k, uint32_t boff) {
+  const int64_t i = blk * kR1Rows + k;
+  const bool row_ok = i < m;
+  d.b = b[row_ok ? i : m - 1];  // first, so its wait is not the last load's; unused past m
+  const uint32_t voff = row_ok ? boff : kBufOutOfRange;
+#pragma unroll
+  for (int u0 = 0; u0 < kR1Per; u0 += kR1StepsPerRsrc) {
+    // bytes from this resource's first column to column n
+    const int64_t cols = n - (int64_t)kR1Groups * u0;
+    const int64_t bytes = cols > 0 ? cols * lda * 8 : 0;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(A + blk * kR1Rows + (int64_t)kR1Groups * u0 * lda), (short)0,
+        (int)(bytes < (int64_t)kBufOutOfRange ? bytes : (int64_t)kBufOutOfRange), kBufRsrcWord3);
+#pragma unroll
+    for (int e = 0; e < kR1StepsPerRsrc; ++e) {
+      const int soff = (int)((int64_t)kR1Groups * e * lda * 8);
+      d.a[u0 + e] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0));
+    }
+  }
+}
+
+// First block of workgroup b: the workgroups of one XCD (b % 8, dealt
+// round-robin) take consecutive blocks in each round of G (when G is a
+// multiple of 8), so an XCD's requests cover adjacent rows of every column.
+__device__ inline int64_t r1_first(int64_t b, int64_t G) { return (G % 8) ? b : (b % 8) * (G / 8) + b / 8; }
+
 __global__ __launch_bounds__(kR1Threads) void k_resid_1pass(const double* __restrict__ A, int64_t lda,
                                                              int64_t p, int64_t m, int64_t n,
                                                              const double* __restrict__ b,
                                                              const double* __restrict__ x,
                                                              double* __restrict__ part, const int* done) {
   if (done && *done) return;
-  __shared__ double red[kR1Threads / kWave][kR1Rows];
-  __shared__ double tk[kR1Rows];
+  __shared__ double red[2][kR1Threads / kWave][kR1Rows];
   __shared__ double xs[kR1MaxN];
   const int tid = threadIdx.x, k = tid & (kR1Rows - 1), g = tid / kR1Rows;
   const int lane = tid & (kWave - 1), w = tid / kWave;
-  for (int c = tid; c < kR1MaxN; c += kR1Threads) xs[c] = c < n ? x[c] : 0.0;
-  double acc[kR1Per];
-#pragma unroll
-  for (int u = 0; u < kR1Per; ++u) acc[u] = 0.0;
-  __syncthreads();
   const int64_t nblk = (m + kR1Rows - 1) / kR1Rows;
-  for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+  const int64_t G = gridDim.x;
+  const uint32_t boff = (uint32_t)((k + (int64_t)g * lda) * 8);
+  for (int c = tid; c < kR1MaxN; c += kR1Threads) xs[c] = c < n ? x[c] : 0.0;
+  R1Block d0, d1;
+  r1_load(d0, A, lda, m, n, b, r1_first(blockIdx.x, G), k, boff);
+  lds_barrier();
+  double acc = 0.0;  // column g + 64 k
+  // one block: t_k = J_kk (b_k - (A x)_k) through LDS, then the block's
+  // column sums t^T A_blk, each reduced over the 16 row lanes by recursive
+  // halving so that lane k keeps column g + 64 k
+  auto process = [&](int64_t blk, R1Block& d, int par) {
+    double sx = 0.0;
+#pragma unroll
+    for (int u = 0; u < kR1Per; ++u) sx = fma(d.a[u], xs[g + kR1Groups * u], sx);
+    sx += __shfl_xor(sx, 16);
+    sx += __shfl_xor(sx, 32);
+    if (lane < kR1Rows) red[par][w][k] = sx;
+    lds_barrier();
+    double tot = 0.0;
+#pragma unroll
+    for (int q = 0; q < kR1Threads / kWave; ++q) tot += red[par][q][k];
     const int64_t i = blk * kR1Rows + k;
-    double a[kR1Per];
-#pragma unroll
-    for (int u = 0; u < kR1Per; ++u) {
-      const int64_t c = g + (int64_t)kR1Groups * u;
-      a[u] = (i < m && c < n) ? A[i + c * lda] : 0.0;
+    double tv = 0.0;
+    if (i < m) {
+      tv = d.b - tot;
+      if (i >= p) tv = -tv;  // J = diag(I_p, -I_q)
     }
-    const double bi = (tid < kR1Rows && i < m) ? b[i] : 0.0;  // with the block's loads
-    double s = 0.0;
 #pragma unroll
-    for (int u = 0; u < kR1Per; ++u) s = fma(a[u], xs[g + kR1Groups * u], s);
-    // the wave's four column groups (lanes k, k + 16, k + 32, k + 48)
-    s += __shfl_xor(s, 16);
-    s += __shfl_xor(s, 32);
-    if (lane < kR1Rows) red[w][k] = s;
-    __syncthreads();
-    if (tid < kR1Rows) {
-      double tot = 0.0;
+    for (int u = 0; u < kR1Per; ++u) d.a[u] *= tv;
 #pragma unroll
-      for (int q = 0; q < kR1Threads / kWave; ++q) tot += red[q][tid];
-      double tv = 0.0;
-      if (i < m) {
-        tv = bi - tot;
-        if (i >= p) tv = -tv;  // J = diag(I_p, -I_q)
+    for (int o = kR1Rows / 2, len = kR1Per; o >= 1; o >>= 1, len >>= 1) {
+      const bool up = (k & o) != 0;
+#pragma unroll
+      for (int j = 0; j < len / 2; ++j) {
+        const double lo = d.a[j], hi = d.a[j + len / 2];
+        const double got = __shfl_xor(up ? lo : hi, o);
+        d.a[j] = (up ? hi : lo) + got;
       }
-      tk[tid] = tv;
     }
-    __syncthreads();
-    const double tj = tk[k];
-#pragma unroll
-    for (int u = 0; u < kR1Per; ++u) acc[u] = fma(tj, a[u], acc[u]);
+    acc += d.a[0];
+  };
+  const int64_t first = r1_first(blockIdx.x, G);
+  // (blocks past the end load zeros: no branch around a load)
+  for (int64_t blk = first; blk < nblk; blk += 2 * G) {
+    r1_load(d1, A, lda, m, n, b, blk + G, k, boff);
+    process(blk, d0, 0);
+    if (blk + G >= nblk) break;
+    r1_load(d0, A, lda, m, n, b, blk + 2 * G, k, boff);
+    process(blk + G, d1, 1);
   }
-  // add the 16 row lanes of each column group (a fixed butterfly)
-#pragma unroll
-  for (int u = 0; u < kR1Per; ++u) {
-    double v = acc[u];
-    v += __shfl_xor(v, 1);
-    v += __shfl_xor(v, 2);
-    v += __shfl_xor(v, 4);
-    v += __shfl_xor(v, 8);
-    const int64_t c = g + (int64_t)kR1Groups * u;
-    if (k == 0 && c < n) part[c * gridDim.x + blockIdx.x] = v;
-  }
+  const int64_t c = g + (int64_t)kR1Groups * k;
+  if (c < n) part[c * gridDim.x + blockIdx.x] = acc;
 }
 
 // r_c = the workgroup partials of column c added by one wave: lane q takes
@@ -316,7 +377,11 @@ void launch_residual(hipStream_t s, int64_t p, int64_t q, int64_t n, const doubl
 void launch_residual_cfg(hipStream_t s, int64_t p, int64_t q, int64_t n, const double* A, int64_t lda,
                          const double* b, const double* x, double* t, double* r, const int* done, ResidCfg c) {
   const int64_t m = p + q;
-  if (one_pass(n, c)) {
+  if (m == 0) {  // no rows: r = 0
+    launch_fill_vec(s, n, nullptr, r);
+    return;
+  }
+  if (one_pass(n, c) && one_pass_fits(lda)) {
     const int nwg = r1_wgs(m, c.wgs > 0 ? c.wgs : kR1Wgs);
     double* part = t + (m > 0 ? m : 1);
     hipLaunchKernelGGL(k_resid_1pass, dim3((unsigned)nwg), dim3(kR1Threads), 0, s, A, lda, p, m, n, b, x, part,

@@ -223,7 +223,7 @@ __global__ __launch_bounds__(256) void k_gram_finalize(GramJob job, const T* __r
   G[j + (int64_t)i * ldg] = s;
 }
 
-// ------------------------------------------------------------------ persistent Gram (FP64)
+// ------------------------------------------------------------------ persistent Gram
 // The same lower 64 x 64 tiles, but a fixed grid of kPersWpc workgroups per CU
 // that stays resident.  The rows of A are cut into one range per XCD (the
 // grid's workgroups are dealt to the XCDs round-robin, so workgroup b runs on
@@ -231,43 +231,51 @@ __global__ __launch_bounds__(256) void k_gram_finalize(GramJob job, const T* __r
 // workgroup j of the XCD first takes the whole range for tiles j, j + W, ...
 // (the q = T / W main tiles per workgroup; all workgroups walk the rows in
 // step, so each stage of the panels is fetched into the L2 once and shared),
-// then an equal contiguous share of the (tile, 16-row stage) pairs of the
+// then an equal contiguous share of the (tile, stage) pairs of the
 // L = T - q W leftover tiles, tile-major.  Every workgroup does the same
 // number of stages, with no tail of partly filled rounds.
 //
 // Operand panels go from global memory straight into LDS
 // (global_load_lds_dwordx4: each lane moves 16 bytes, a wave 1 KB, with no
 // register staging and no LDS store instructions), two stages in flight.  A
-// stage holds, per operand, 64 column slots of 16 rows = 8 chunks of two rows;
-// the chunk of rows (2q, 2q + 1) of slot s sits at position q ^ ((s >> 1) & 7),
-// so the 16 lanes of an MFMA operand read (16 slots, one row) hit 16 distinct
-// bank groups.  A stage that does not start on an even row or is shorter than
-// 16 rows (a range end, the A1/A2 boundary) goes through registers into the
-// same layout.  Needs A and the border column 16-byte aligned and an even lda.
+// stage holds, per operand, 64 column slots of RS rows = 8 chunks of 16 bytes
+// (RS = 16 rows of FP64, 32 of FP32); chunk q of slot s sits at position
+// q ^ ((s >> 1) & 7), so the 16 lanes of an FP64 MFMA operand read (16
+// slots, one row) hit 16 distinct bank groups.  A stage that does not start
+// on a 16-byte boundary or is shorter than RS rows (a range end, the A1/A2
+// boundary) goes through registers into the same layout.  Needs A and the
+// border column 16-byte aligned and lda a multiple of 16 bytes.
+//
+// The FP32 instance reads an FP32 copy of the rows (made by k_copy_f32), so a
+// stage carries twice the rows for the same bytes.  Its 4-byte operand reads
+// see 2-way bank conflicts (half the LDS cycles); reading 16-byte chunks and
+// feeding 4 MFMAs from each removes them but was not faster (211.7 against
+// 209.0 us at 18000 x 1000), nor were 5 workgroups per CU (212.9 us): the
+// kernel runs at 0.55 of the FP32 MFMA peak, MFMA busy 0.65.
 //
 // Each share (tile, XCD range, part) writes one partial tile; the reduction
 // kernel adds, per tile and part, the shares of XCD 0..7 in row order.
 constexpr int kPersWpc = kGramPersistentWpc;  // resident workgroups per CU (32 KB of LDS each)
-constexpr int kPersRS = 16;  // rows per stage
+constexpr int kPersAlign = 16;  // row ranges start on multiples of 16 rows
 constexpr int kPersMaxShares = 64;  // shares per (leftover tile, XCD) the reduction lists
 
 struct GramPJob {
-  const double* A;   // row 0 of the rows [0, M)
+  const void* A;     // row 0 of the rows [0, M) (double, or float for the FP32 kind)
   int64_t lda;
-  const double* vb;  // border column (M entries) or null
+  const void* vb;    // border column (M entries) or null
   int64_t M, p;      // rows; part 0 = rows [0, p), part 1 = rows [p, M)
   int n, nc, T;      // columns, bordered columns, lower tiles
   int W;             // workgroups per XCD
   int q, L;          // main tiles per workgroup (T / W) and the leftover tiles (T - q W)
   int cmax;          // shares per (leftover tile, XCD) at most
-  double* partials;  // (kXcds + 1) * (q W + L cmax) partial tiles
+  void* partials;    // (kXcds + 1) * (q W + L cmax) partial tiles of the kernel's type
   double *G0, *gv0, *G1, *gv1;
   int64_t ldg;
 };
 
 __device__ __host__ inline void pers_range(int64_t M, int x, int64_t& r0, int64_t& r1) {
-  r0 = (M * x / kXcds) / kPersRS * kPersRS;
-  r1 = x == kXcds - 1 ? M : (M * (x + 1) / kXcds) / kPersRS * kPersRS;
+  r0 = (M * x / kXcds) / kPersAlign * kPersAlign;
+  r1 = x == kXcds - 1 ? M : (M * (x + 1) / kXcds) / kPersAlign * kPersAlign;
 }
 // Partial-tile block of XCD range x for `part`: the range itself, except the
 // part-1 shares of the one range that holds rows on both sides of p, which
@@ -295,23 +303,36 @@ static __device__ const double g_zero16[16] = {0.0};
 // 15:14; expcnt 6:4 and lgkmcnt 11:8 left at their maxima)
 #define ILS_WAIT_VM(N) __builtin_amdgcn_s_waitcnt(((N) & 0xF) | (((N) >> 4) << 14) | (0x7 << 4) | (0xF << 8))
 
+// Stage geometry per element type: a 16-byte chunk holds RPC rows of a
+// column, a stage RS rows = 8 chunks (16 rows of FP64, 32 of FP32), so a
+// stage of one operand is 8 KB either way.
+template <typename T>
+struct PersGeo {
+  static constexpr int RPC = 16 / (int)sizeof(T);
+  static constexpr int RS = 8 * RPC;
+};
+
 __device__ inline int pers_swz(int s) { return (s >> 1) & 7; }
 
+template <typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPersWpc)))
 void k_gram_pers(GramPJob job) {
-  __shared__ __attribute__((aligned(16))) double L[2][2][64 * kPersRS];  // [stage][operand][slot * 16 + row]
+  typedef typename Mma<T>::acc_t acc_t;
+  constexpr int RPC = PersGeo<T>::RPC, RS = PersGeo<T>::RS;
+  __shared__ __attribute__((aligned(16))) T L[2][2][64 * RS];  // [stage][operand][slot * RS + row]
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
   const int lr = lane & 15;
   const int x = (int)(blockIdx.x % kXcds), j = (int)(blockIdx.x / kXcds);
   int64_t r0, r1;
   pers_range(job.M, x, r0, r1);
-  const int64_t S = (r1 - r0 + kPersRS - 1) / kPersRS;
+  const int64_t S = (r1 - r0 + RS - 1) / RS;
   if (S == 0) return;
   const int64_t LS = (int64_t)job.L * S;
   // main tiles over the whole range, then this workgroup's leftover stages
   const int64_t u0 = (int64_t)j * LS / job.W, u1 = (int64_t)(j + 1) * LS / job.W;
-  const double* A = job.A;
+  const T* A = (const T*)job.A;
+  const T* vb = (const T*)job.vb;
   const int64_t lda = job.lda;
   const int n = job.n;
 
@@ -330,8 +351,8 @@ void k_gram_pers(GramPJob job) {
       const int64_t send = u1 < (int64_t)(lt + 1) * S ? u1 : (int64_t)(lt + 1) * S;
       c = j - pers_first((int64_t)lt * S, LS, job.W);
       tile = job.q * job.W + lt;
-      klo = r0 + (u - (int64_t)lt * S) * kPersRS;
-      khi = r0 + (send - (int64_t)lt * S) * kPersRS < r1 ? r0 + (send - (int64_t)lt * S) * kPersRS : r1;
+      klo = r0 + (u - (int64_t)lt * S) * RS;
+      khi = r0 + (send - (int64_t)lt * S) * RS < r1 ? r0 + (send - (int64_t)lt * S) * RS : r1;
       u = send;
     }
     int ti, tj;
@@ -341,81 +362,78 @@ void k_gram_pers(GramPJob job) {
       const int64_t kbeg = part ? (klo > job.p ? klo : job.p) : klo;
       const int64_t kend = part ? khi : (khi < job.p ? khi : job.p);
       if (kbeg >= kend) continue;
-      v4d acc[2][2];
+      acc_t acc[2][2];
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int cc = 0; cc < 2; ++cc) acc[a][cc] = v4d{};
+        for (int cc = 0; cc < 2; ++cc) acc[a][cc] = acc_t{};
       auto compute = [&](int buf) {
-        const double* La = &L[buf][0][0];
-        const double* Lb = diag ? &L[buf][0][0] : &L[buf][1][0];
+        const T* La = &L[buf][0][0];
+        const T* Lb = diag ? &L[buf][0][0] : &L[buf][1][0];
 #pragma unroll
-        for (int kk = 0; kk < kPersRS; kk += 4) {
+        for (int kk = 0; kk < RS; kk += 4) {
           const int kr = kk + (lane >> 4);
-          double fa[2], fb[2];
+          T fa[2], fb[2];
 #pragma unroll
           for (int a = 0; a < 2; ++a) {
-            const int s = wr + a * 16 + lr;
-            fa[a] = La[s * kPersRS + (((kr >> 1) ^ pers_swz(s)) << 1) + (kr & 1)];
+            const int sl = wr + a * 16 + lr;
+            fa[a] = La[sl * RS + (((kr / RPC) ^ pers_swz(sl)) * RPC) + (kr % RPC)];
           }
 #pragma unroll
           for (int cc = 0; cc < 2; ++cc) {
-            const int s = wc + cc * 16 + lr;
-            fb[cc] = Lb[s * kPersRS + (((kr >> 1) ^ pers_swz(s)) << 1) + (kr & 1)];
+            const int sl = wc + cc * 16 + lr;
+            fb[cc] = Lb[sl * RS + (((kr / RPC) ^ pers_swz(sl)) * RPC) + (kr % RPC)];
           }
 #pragma unroll
           for (int a = 0; a < 2; ++a)
 #pragma unroll
-            for (int cc = 0; cc < 2; ++cc)
-              acc[a][cc] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[cc], acc[a][cc], 0, 0, 0);
+            for (int cc = 0; cc < 2; ++cc) acc[a][cc] = Mma<T>::run(fa[a], fb[cc], acc[a][cc]);
         }
       };
-      // rows [ka, kb) of buffer 0 through registers (ka..kb within one stage), the rest zero
+      // rows [ka, kb) of buffer 0 through registers (within one stage), the rest zero
       auto reg_stage = [&](int64_t ka, int64_t kb) {
         __syncthreads();
-        for (int id = t; id < 2 * 64 * (kPersRS / 2); id += 256) {
-          const int op = id / (64 * (kPersRS / 2)), s = (id / (kPersRS / 2)) % 64, q = id % (kPersRS / 2);
+        for (int id = t; id < 2 * 64 * 8; id += 256) {
+          const int op = id / (64 * 8), sl = (id / 8) % 64, qc = id % 8;
           if (op == 1 && diag) continue;
-          const int col = (op ? tj : ti) * 64 + s;
-          const double* cp = col < n ? A + (int64_t)col * lda : (col == n ? job.vb : nullptr);
-          const int64_t r = ka + 2 * q;
-          double v0 = 0.0, v1 = 0.0;
-          if (cp) {
-            if (r < kb) v0 = cp[r];
-            if (r + 1 < kb) v1 = cp[r + 1];
+          const int col = (op ? tj : ti) * 64 + sl;
+          const T* cp = col < n ? A + (int64_t)col * lda : (col == n ? vb : nullptr);
+          T* d = &L[0][op][sl * RS + ((qc ^ pers_swz(sl)) * RPC)];
+#pragma unroll
+          for (int e = 0; e < RPC; ++e) {
+            const int64_t r = ka + qc * RPC + e;
+            d[e] = (cp && r < kb) ? cp[r] : (T)0;
           }
-          double* d = &L[0][op][s * kPersRS + ((q ^ pers_swz(s)) << 1)];
-          d[0] = v0;
-          d[1] = v1;
         }
         __syncthreads();
         compute(0);
       };
       int64_t ka = kbeg;
-      if (ka & 1) {  // odd first row: one row through registers, then even rows
-        reg_stage(ka, ka + 1);
-        ++ka;
+      if (ka % RPC) {  // first row off a 16-byte boundary: up to it through registers
+        const int64_t kn = (ka / RPC + 1) * RPC < kend ? (ka / RPC + 1) * RPC : kend;
+        reg_stage(ka, kn);
+        ka = kn;
       }
-      const int64_t nfull = (kend - ka) / kPersRS;
+      const int64_t nfull = (kend - ka) / RS;
       if (nfull > 0) {
         // this lane's sources: load i of operand op fills slots (2w + i) * 8 + lane / 8, chunk lane % 8
-        const double* src[2][2];
+        const T* src[2][2];
         int64_t step[2][2];
 #pragma unroll
         for (int op = 0; op < 2; ++op)
 #pragma unroll
           for (int i = 0; i < 2; ++i) {
-            const int s = (2 * w + i) * 8 + (lane >> 3);
-            const int sig = (lane & 7) ^ pers_swz(s);
-            const int col = (op ? tj : ti) * 64 + s;
+            const int sl = (2 * w + i) * 8 + (lane >> 3);
+            const int sig = (lane & 7) ^ pers_swz(sl);
+            const int col = (op ? tj : ti) * 64 + sl;
             if (col < n) {
-              src[op][i] = A + (int64_t)col * lda + ka + 2 * sig;
-              step[op][i] = kPersRS;
-            } else if (col == n && job.vb) {
-              src[op][i] = job.vb + ka + 2 * sig;
-              step[op][i] = kPersRS;
+              src[op][i] = A + (int64_t)col * lda + ka + RPC * sig;
+              step[op][i] = RS;
+            } else if (col == n && vb) {
+              src[op][i] = vb + ka + RPC * sig;
+              step[op][i] = RS;
             } else {
-              src[op][i] = g_zero16 + 2 * sig;
+              src[op][i] = (const T*)g_zero16 + RPC * sig;
               step[op][i] = 0;
             }
           }
@@ -424,13 +442,14 @@ void k_gram_pers(GramPJob job) {
           for (int i = 0; i < 2; ++i)
             __builtin_amdgcn_global_load_lds(
                 (const __attribute__((address_space(1))) void*)(src[0][i] + st * step[0][i]),
-                (__attribute__((address_space(3))) void*)&L[buf][0][(2 * w + i) * 128], 16, 0, 0);
+                (__attribute__((address_space(3))) void*)&L[buf][0][(2 * w + i) * (1024 / (int)sizeof(T))], 16, 0, 0);
           if (!diag) {
 #pragma unroll
             for (int i = 0; i < 2; ++i)
               __builtin_amdgcn_global_load_lds(
                   (const __attribute__((address_space(1))) void*)(src[1][i] + st * step[1][i]),
-                  (__attribute__((address_space(3))) void*)&L[buf][1][(2 * w + i) * 128], 16, 0, 0);
+                  (__attribute__((address_space(3))) void*)&L[buf][1][(2 * w + i) * (1024 / (int)sizeof(T))], 16, 0,
+                  0);
           }
         };
         __syncthreads();  // buffer 0 may still be read by a register stage
@@ -446,19 +465,19 @@ void k_gram_pers(GramPJob job) {
           compute((int)(st & 1));
         }
       }
-      const int64_t kt = ka + nfull * kPersRS;
+      const int64_t kt = ka + nfull * RS;
       if (kt < kend) reg_stage(kt, kend);
       const int vx = pers_vx(x, part, r0, r1, job.p);
-      double* P = job.partials + (main ? pers_slot_main(vx, tile, job.q, job.W)
-                                       : pers_slot_left(vx, tile - job.q * job.W, c, job.q, job.W, job.L, job.cmax)) *
-                                     4096;
+      T* P = (T*)job.partials + (main ? pers_slot_main(vx, tile, job.q, job.W)
+                                      : pers_slot_left(vx, tile - job.q * job.W, c, job.q, job.W, job.L, job.cmax)) *
+                                    4096;
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int cc = 0; cc < 2; ++cc)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int row = wr + a * 16 + Mma<double>::row(lane, v);
+            const int row = wr + a * 16 + Mma<T>::row(lane, v);
             const int col = wc + cc * 16 + lr;
             P[row * 64 + col] = acc[a][cc][v];
           }
@@ -470,7 +489,9 @@ void k_gram_pers(GramPJob job) {
 // Per (tile, part): the shares of XCD 0..7 in row order (share index c within
 // an XCD follows the rows).  Wave 0 lists them, one (XCD, c) pair per lane in
 // that order, compacted by ballot; then every thread adds its element.
+template <typename T>
 __global__ __launch_bounds__(256) void k_gram_pers_fin(GramPJob job) {
+  constexpr int RS = PersGeo<T>::RS;
   __shared__ int slots[kXcds * kPersMaxShares];
   __shared__ int nsl;
   const int part = (int)blockIdx.y / job.T, tile = (int)blockIdx.y % job.T;
@@ -488,7 +509,7 @@ __global__ __launch_bounds__(256) void k_gram_pers_fin(GramPJob job) {
       if (x < kXcds) {
         int64_t r0, r1;
         pers_range(job.M, x, r0, r1);
-        const int64_t S = (r1 - r0 + kPersRS - 1) / kPersRS;
+        const int64_t S = (r1 - r0 + RS - 1) / RS;
         int64_t klo = r0, khi = r1;
         bool ok = S > 0;
         if (ok && !main) {
@@ -500,8 +521,8 @@ __global__ __launch_bounds__(256) void k_gram_pers_fin(GramPJob job) {
             const int64_t a = u0 > (int64_t)lt * S ? u0 : (int64_t)lt * S;
             const int64_t b = u1 < (int64_t)(lt + 1) * S ? u1 : (int64_t)(lt + 1) * S;
             ok = a < b;
-            klo = r0 + (a - (int64_t)lt * S) * kPersRS;
-            khi = r0 + (b - (int64_t)lt * S) * kPersRS;
+            klo = r0 + (a - (int64_t)lt * S) * RS;
+            khi = r0 + (b - (int64_t)lt * S) * RS;
             if (khi > r1) khi = r1;
           }
         }
@@ -530,11 +551,11 @@ __global__ __launch_bounds__(256) void k_gram_pers_fin(GramPJob job) {
   for (; q + 8 <= cnt; q += 8) {
     double v[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) v[k] = job.partials[(size_t)slots[q + k] * 4096 + e];
+    for (int k = 0; k < 8; ++k) v[k] = (double)((const T*)job.partials)[(size_t)slots[q + k] * 4096 + e];
 #pragma unroll
     for (int k = 0; k < 8; ++k) sacc += v[k];
   }
-  for (; q < cnt; ++q) sacc += job.partials[(size_t)slots[q] * 4096 + e];
+  for (; q < cnt; ++q) sacc += (double)((const T*)job.partials)[(size_t)slots[q] * 4096 + e];
   double* G = part ? job.G1 : job.G0;
   double* gv = part ? job.gv1 : job.gv0;
   if (i == job.n) {
@@ -558,13 +579,14 @@ static int device_cus() {
   return cache[dev];
 }
 
-// Largest number of workgroups sharing one leftover tile within one XCD range.
-static int pers_cmax(int64_t M, int L, int W) {
+// Largest number of workgroups sharing one leftover tile within one XCD range
+// (stages of RS rows).
+static int pers_cmax(int64_t M, int L, int W, int RS) {
   int cm = 1;
   for (int x = 0; x < kXcds && L > 0; ++x) {
     int64_t r0, r1;
     pers_range(M, x, r0, r1);
-    const int64_t S = (r1 - r0 + kPersRS - 1) / kPersRS;
+    const int64_t S = (r1 - r0 + RS - 1) / RS;
     const int64_t LS = (int64_t)L * S;
     if (LS == 0) continue;
     for (int j = 0; j < W; ++j) {
@@ -582,9 +604,9 @@ static int pers_cmax(int64_t M, int L, int W) {
 struct PersShape {
   int T, W, q, L, cmax;
 };
-static PersShape pers_shape(int64_t nc, int64_t M) {
+static PersShape pers_shape(int64_t nc, int64_t M, int RS) {
   static std::mutex mu;
-  static std::map<std::tuple<int64_t, int64_t, int>, int> cache;
+  static std::map<std::tuple<int64_t, int64_t, int, int>, int> cache;
   PersShape sh;
   const int nt = (int)((nc + 63) / 64);
   sh.T = nt * (nt + 1) / 2;
@@ -592,23 +614,31 @@ static PersShape pers_shape(int64_t nc, int64_t M) {
   sh.q = sh.T / sh.W;
   sh.L = sh.T - sh.q * sh.W;
   std::lock_guard<std::mutex> lk(mu);
-  auto key = std::make_tuple(nc, M, sh.W);
+  auto key = std::make_tuple(nc, M, sh.W, RS);
   auto it = cache.find(key);
   if (it == cache.end()) {
     if (cache.size() > 256) cache.clear();
-    it = cache.emplace(key, pers_cmax(M, sh.L, sh.W)).first;
+    it = cache.emplace(key, pers_cmax(M, sh.L, sh.W, RS)).first;
   }
   sh.cmax = it->second;
   return sh;
 }
 
+// Partial tiles in doubles (either element type's tiles fit).
 static size_t pers_partials(int64_t nc, int64_t M) {
-  const PersShape sh = pers_shape(nc, M);
-  return ((size_t)(kXcds + 1) * ((size_t)sh.q * sh.W + (size_t)sh.L * sh.cmax)) * 4096;
+  size_t s = 0;
+  for (int RS : {PersGeo<double>::RS, PersGeo<float>::RS}) {
+    const PersShape sh = pers_shape(nc, M, RS);
+    s = std::max(s, ((size_t)(kXcds + 1) * ((size_t)sh.q * sh.W + (size_t)sh.L * sh.cmax)) * 4096);
+  }
+  return s;
 }
 
-static bool pers_aligned(const double* A, int64_t lda, const double* vb) {
-  return ((uintptr_t)A & 15) == 0 && (lda & 1) == 0 && (!vb || ((uintptr_t)vb & 15) == 0);
+// 16-byte aligned columns: the base and the border column on 16 bytes, lda a
+// multiple of 16 / sizeof(T).
+template <typename T>
+static bool pers_aligned(const T* A, int64_t lda, const T* vb) {
+  return ((uintptr_t)A & 15) == 0 && (lda % (16 / (int64_t)sizeof(T))) == 0 && (!vb || ((uintptr_t)vb & 15) == 0);
 }
 
 // Launch configuration: tile edge and the number of workgroups to aim for
@@ -637,11 +667,11 @@ GramCfg gram_default_cfg(int64_t n) {
   return c;
 }
 
-// Without a table entry: the persistent kernel for FP64 products with
-// enough columns and rows to give every resident workgroup several stages,
+// Without a table entry: the persistent kernel (FP32 from a copy of the
+// rows) for products with enough columns and rows to give every resident workgroup several stages,
 // and few enough tiles that splitting the rows per XCD stays cheap.
 static GramCfg auto_cfg(int precision, int64_t n, int64_t K) {
-  if (precision == ILS_PREC_FP64 && n >= 192 && K >= 2048) {
+  if (n >= 192 && K >= 2048) {
     const int nt = (int)((n + 1 + 63) / 64);
     if (nt * (nt + 1) / 2 <= 2 * kPersWpc * (device_cus() / kXcds)) return GramCfg{64, kPersWpc, kGramPersistent};
   }
@@ -777,7 +807,7 @@ static void gram_run(hipStream_t s, int64_t K, int64_t n, const double* A, int64
                      T* partials, double* G, int64_t ldg, double* gv, hipEvent_t mid, GramCfg cfg,
                      int64_t K1 = -1, const double* A1 = nullptr, const double* vb1 = nullptr,
                      double* G1 = nullptr, double* gv1 = nullptr) {
-  if (std::is_same<T, double>::value && cfg.kind == kGramPersistent && pers_aligned(A, lda, vb) &&
+  if (std::is_same<T, double>::value && cfg.kind == kGramPersistent && pers_aligned<double>(A, lda, vb) &&
       (K1 < 0 || (A1 == A + K && (vb ? vb1 == vb + K : vb1 == nullptr)))) {
     GramPJob pj;
     pj.A = A;
@@ -787,7 +817,7 @@ static void gram_run(hipStream_t s, int64_t K, int64_t n, const double* A, int64
     pj.p = K;
     pj.n = (int)n;
     pj.nc = (int)n + (vb ? 1 : 0);
-    const PersShape sh = pers_shape(pj.nc, pj.M);
+    const PersShape sh = pers_shape(pj.nc, pj.M, PersGeo<double>::RS);
     pj.T = sh.T;
     pj.W = sh.W;
     pj.q = sh.q;
@@ -800,9 +830,10 @@ static void gram_run(hipStream_t s, int64_t K, int64_t n, const double* A, int64
       pj.G1 = G1;
       pj.gv1 = gv1;
       pj.ldg = ldg;
-      hipLaunchKernelGGL(k_gram_pers, dim3(kXcds * sh.W), dim3(256), 0, s, pj);
+      hipLaunchKernelGGL(k_gram_pers<double>, dim3(kXcds * sh.W), dim3(256), 0, s, pj);
       if (mid) (void)hipEventRecord(mid, s);
-      hipLaunchKernelGGL(k_gram_pers_fin, dim3(64 * 64 / 256, sh.T * (K1 >= 0 ? 2 : 1)), dim3(256), 0, s, pj);
+      hipLaunchKernelGGL(k_gram_pers_fin<double>, dim3(64 * 64 / 256, sh.T * (K1 >= 0 ? 2 : 1)), dim3(256), 0, s,
+                         pj);
       return;
     }
   }
@@ -831,8 +862,67 @@ static void gram_run(hipStream_t s, int64_t K, int64_t n, const double* A, int64
     gram_launch<T, 64>(s, job, partials, mid);
 }
 
+// A^T A of an FP32 matrix (K x n, column-major, ldaf, 16-byte aligned
+// columns) with the persistent kernel.
+static void gram_f32_pers(hipStream_t s, int64_t K, int64_t n, const float* Af, int64_t ldaf, float* partials,
+                          double* G, int64_t ldg, hipEvent_t mid) {
+  GramPJob pj;
+  pj.A = Af;
+  pj.lda = ldaf;
+  pj.vb = nullptr;
+  pj.M = K;
+  pj.p = K;
+  pj.n = (int)n;
+  pj.nc = (int)n;
+  const PersShape sh = pers_shape(n, K, PersGeo<float>::RS);
+  pj.T = sh.T;
+  pj.W = sh.W;
+  pj.q = sh.q;
+  pj.L = sh.L;
+  pj.cmax = sh.cmax;
+  pj.partials = partials;
+  pj.G0 = G;
+  pj.gv0 = nullptr;
+  pj.G1 = nullptr;
+  pj.gv1 = nullptr;
+  pj.ldg = ldg;
+  hipLaunchKernelGGL(k_gram_pers<float>, dim3(kXcds * sh.W), dim3(256), 0, s, pj);
+  if (mid) (void)hipEventRecord(mid, s);
+  hipLaunchKernelGGL(k_gram_pers_fin<float>, dim3(64 * 64 / 256, sh.T), dim3(256), 0, s, pj);
+}
+
+// Column-major FP32 copy of rows [0, K) of A with leading dimension ldaf.
+__global__ void k_copy_f32(int64_t K, int64_t n, const double* __restrict__ A, int64_t lda, float* __restrict__ Af,
+                           int64_t ldaf) {
+  for (int64_t c = blockIdx.y; c < n; c += gridDim.y)
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < K; i += (int64_t)gridDim.x * 256)
+      Af[i + c * ldaf] = (float)A[i + c * lda];
+}
+
+int64_t gram_f32_copy_ld(int64_t K) { return (K + 3) / 4 * 4; }
+
+// The FP32 product through a copy: the copy must be 16-byte aligned (it is,
+// with the leading dimension above, from any allocation) and the shape within
+// the shares the reduction lists.
+static bool f32_copy_fits(int64_t n, int64_t K, const float* Af) {
+  return Af && ((uintptr_t)Af & 15) == 0 && pers_shape(n, K, PersGeo<float>::RS).cmax <= kPersMaxShares;
+}
+
+static void gram_f32_via_copy(hipStream_t s, int64_t K, int64_t n, const double* A, int64_t lda, float* Af,
+                              float* partials, double* G, int64_t ldg, hipEvent_t mid) {
+  const int64_t ldaf = gram_f32_copy_ld(K);
+  const int64_t bx = std::min<int64_t>(std::max<int64_t>((K + 255) / 256, 1), 64);
+  const int64_t by = std::min<int64_t>(n, 65535);
+  hipLaunchKernelGGL(k_copy_f32, dim3((unsigned)bx, (unsigned)by), dim3(256), 0, s, K, n, A, lda, Af, ldaf);
+  gram_f32_pers(s, K, n, Af, ldaf, partials, G, ldg, mid);
+}
+
 void launch_gram_cfg(hipStream_t s, int precision, int64_t K, int64_t n, const double* A, int64_t lda,
-                     void* partials, double* G, int64_t ldg, GramCfg cfg) {
+                     void* partials, double* G, int64_t ldg, GramCfg cfg, float* a1f) {
+  if (precision == ILS_PREC_MIXED && cfg.kind == kGramPersistent && f32_copy_fits(n, K, a1f)) {
+    gram_f32_via_copy(s, K, n, A, lda, a1f, (float*)partials, G, ldg, nullptr);
+    return;
+  }
   if (precision == ILS_PREC_MIXED)
     gram_run<float>(s, K, n, A, lda, nullptr, (float*)partials, G, ldg, nullptr, nullptr, cfg);
   else
@@ -849,6 +939,17 @@ void launch_gram2_f64(hipStream_t s, int64_t n, int64_t lda, int64_t ldg, double
                       int64_t K1, const double* A1, const double* vb1, double* G1, double* gv1) {
   gram_run<double>(s, K0, n, A0, lda, vb0, partials, G0, ldg, gv0, mid, gram_cfg(ILS_PREC_FP64, n, K0), K1, A1,
                    vb1, G1, gv1);
+}
+
+
+bool gram_f32_uses_copy(int64_t n, int64_t K) { return gram_cfg(ILS_PREC_MIXED, n, K).kind == kGramPersistent; }
+
+void launch_gram_f32_copy(hipStream_t s, int64_t K, int64_t n, const double* A, int64_t lda, float* Af,
+                          float* partials, double* G, int64_t ldg, hipEvent_t mid) {
+  if (f32_copy_fits(n, K, Af))
+    gram_f32_via_copy(s, K, n, A, lda, Af, partials, G, ldg, mid);
+  else
+    launch_gram_f32(s, K, n, A, lda, partials, G, ldg, mid);
 }
 
 void launch_gram_f32(hipStream_t s, int64_t K, int64_t n, const double* A, int64_t lda,

@@ -1,13 +1,15 @@
 #!/usr/bin/env python3
 """Rebuild the committed launch table (gram_mi355x.json) on one MI355X.
 
-Keeps the table's Gram entries (chosen by timing the paper form's whole
+Keeps the table's FP64 Gram entries (chosen by timing the paper form's whole
 two-part launch, which the single-block sweep does not see) and sweeps, on the
-benchmark's own inputs, the residual A^T J (b - A x) of the 20000 x 1000
-problem and the batched solver on the 4096-problem batch (FP64 paper form and
-mixed correction form, stopped at rel.err 1e-6 as in the benchmark).  Writes
-the merged table to the path given (default: this directory's
-gram_mi355x.json) and prints every entry.
+benchmark's own inputs, the mixed-precision Gram A1^T A1 (the mixed
+correction form's only product: split-K tiles and workgroups, and the
+persistent kind on an FP32 copy of A1), the residual A^T J (b - A x) of the
+20000 x 1000 problem and the batched solver on the 4096-problem batch (FP64
+paper form and mixed correction form, stopped at rel.err 1e-6 as in the
+benchmark).  Writes the merged table to the path given (default: this
+directory's gram_mi355x.json) and prints every entry.
 
     python paper_2203_15340_amd/tune/tune_mi355x.py [--out PATH]
 """
@@ -36,12 +38,13 @@ def main():
     ils.tune_clear()
     ils.tune_load(src)
     with open(src) as f:
-        gram_entries = [e for e in json.load(f)["entries"] if e["kernel"] == "gram"]
+        gram_entries = [e for e in json.load(f)["entries"] if e["kernel"] == "gram" and e["precision"] == 0]
 
     P = W.large(ratio=0.5, seed=1)
     A = torch.from_numpy(np.ascontiguousarray(P.A.T)).cuda().t()
     b = torch.from_numpy(P.b).cuda()
     x = torch.from_numpy(np.random.default_rng(0).standard_normal(P.n)).cuda()
+    print("mixed Gram:", ils.tune_gram(A, 0, P.p, precision=ils.PREC_MIXED, reps=10), flush=True)
     print("residual:", ils.tune_residual(A, b, P.p, x, reps=10), flush=True)
     del A, b, x
 
@@ -56,8 +59,8 @@ def main():
     ils.tune_save(args.out)
     with open(args.out) as f:
         saved = json.load(f)["entries"]
-    # the Gram entries are the loaded ones, unchanged
-    assert sorted(json.dumps(e, sort_keys=True) for e in saved if e["kernel"] == "gram") == \
+    # the FP64 Gram entries are the loaded ones, unchanged
+    assert sorted(json.dumps(e, sort_keys=True) for e in saved if e["kernel"] == "gram" and e["precision"] == 0) == \
         sorted(json.dumps(dict(e, kind=e.get("kind", 0)), sort_keys=True) for e in gram_entries)
     for e in saved:
         print(json.dumps(e))

@@ -106,6 +106,25 @@ def test_residual_paths(shape):
     assert_close(host(r), ref, 1e-12)
 
 
+@pytest.mark.parametrize("shape", [(1003, 90, 1000), (45, 3, 70)], ids=["blocks_and_tail", "one_block"])
+def test_residual_padded_lda(shape):
+    """A view into a taller buffer (lda > m, the rows past m holding NaN):
+    the one-pass kernel's rows past m read nothing, so the padding never
+    enters r; with a ragged last 16-row block and n not a multiple of 64."""
+    p, q, n = shape
+    P = W.dense_ils(p, q, n, ratio=0.5, seed=p + q + n + 1)
+    m = p + q
+    buf = torch.full((n, m + 13), float("nan"), dtype=torch.float64, device="cuda")
+    buf[:, :m] = torch.from_numpy(np.ascontiguousarray(P.A.T)).cuda()
+    A = buf.t()[:m]
+    assert A.stride(1) == m + 13
+    x = np.random.default_rng(3).standard_normal(n)
+    r = ils.residual(A, dev(P.b), P.p, dev(x))
+    ref = O.residual(P.A, P.b, P.p, x)
+    assert np.all(np.isfinite(host(r)))
+    assert_close(host(r), ref, 1e-12)
+
+
 def test_spd_solve(prob):
     P, A, b, _ = prob
     G1 = O.gram(P.A, 0, P.p)

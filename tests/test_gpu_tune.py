@@ -28,7 +28,7 @@ def test_tuned_gram_matches_oracle(tmp_path, prec):
         best = ils.tune_gram(A, 0, P.p, precision=prec, reps=3)
         print(f"[gpu-tune] precision {prec}: {best}", flush=True)
         if best["kind"] == ils.GRAM_PERSISTENT:
-            assert prec == ils.PREC_FP64 and best["tile"] == 64 and best["workgroups"] == 4
+            assert best["tile"] == 64 and best["workgroups"] == 4
         else:
             assert best["tile"] in (64, 128) and 256 <= best["workgroups"] <= 8192
         assert best["ms"] > 0

@@ -38,8 +38,7 @@ def test_roundtrip(tmp_path):
     '{"version": 1, "entries": [\n  {"kernel": "gram", "precision": 0, "n_bucket": 10, "k_bucket": 15, "tile": 96, "workgroups": 512}\n]}\n',
     '{"version": 1, "entries": [\n  {"kernel": "gram", "precision": 5, "n_bucket": 10, "k_bucket": 15, "tile": 64, "workgroups": 512}\n]}\n',
     '{"version": 1, "entries": [\n  {"kernel": "gram", "precision": 0}\n]}\n',
-    # the persistent kind is FP64 only, 64-tiles, 4 workgroups per CU
-    '{"version": 1, "entries": [\n  {"kernel": "gram", "precision": 1, "n_bucket": 10, "k_bucket": 15, "tile": 64, "workgroups": 4, "kind": 1}\n]}\n',
+    # the persistent kind: 64-tiles, 4 workgroups per CU
     '{"version": 1, "entries": [\n  {"kernel": "gram", "precision": 0, "n_bucket": 10, "k_bucket": 15, "tile": 64, "workgroups": 8, "kind": 1}\n]}\n',
     '{"version": 1, "entries": [\n  {"kernel": "gram", "precision": 0, "n_bucket": 10, "k_bucket": 15, "tile": 128, "workgroups": 4, "kind": 1}\n]}\n',
     '{"version": 1, "entries": [\n  {"kernel": "gram", "precision": 0, "n_bucket": 10, "k_bucket": 15, "tile": 64, "workgroups": 512, "kind": 2}\n]}\n',
