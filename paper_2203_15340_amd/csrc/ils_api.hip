@@ -281,9 +281,9 @@ int ils::sp_solve_op(ils_handle* h, const MatOp& M, const double* b, const doubl
       (st = h->need(kBufDinv, gj_scratch_bytes(n, n + nrhs), (void**)&dinv)))
     return fail(info, st);
   // mixed precision: scratch for the FP32 copy of A1 when the launch table's
-  // mixed Gram entry reads one
+  // mixed Gram entry reads one (dense A; the paper form is FP64 only)
   float* a1f = nullptr;
-  if (!M.sp && o->precision == ILS_PREC_MIXED && gram_f32_uses_copy(n, p) &&
+  if (!M.sp && !paper && o->precision == ILS_PREC_MIXED && gram_f32_uses_copy(n, p) &&
       (st = h->need(kBufA1f32, sizeof(float) * gram_f32_copy_ld(p) * n, (void**)&a1f)))
     return fail(info, st);
 
@@ -296,15 +296,26 @@ int ils::sp_solve_op(ils_handle* h, const MatOp& M, const double* b, const doubl
   // the device starts on it while the host queues the rest of the solve.
   const bool bordered = paper && !M.sp;
   hipEvent_t mid = h->gram_end_event();
-  h->mark(1);
-  if (bordered)  // A1^T A1, A1^T b1 and A2^T A2, A2^T b2 in one launch pair
-    launch_gram2_f64(s, n, M.lda, ldw, (double*)part, mid, p, M.A, b, W, g, q, M.A + p, b + p, W + n * ldw, rv);
-  else  // A1^T A1 for [A1^T A1 | A2^T A2 | A^T J b] or [A1^T A1 | I]
-    mat_gram(s, M, 0, o->precision, part, W, ldw, mid, a1f);
-  HIPCHK(hipMemsetAsync(h->st, 0, sizeof(LoopState), s));
-  if (!bordered) {
-    mat_colpass(s, M, b, g, nullptr, &ds->bits);
+  if (a1f) {
+    // mixed precision through the FP32 copy: the column pass writes the copy
+    // of A1 while it reads A, then the Gram kernel reads only the copy
+    HIPCHK(hipMemsetAsync(h->st, 0, sizeof(LoopState), s));
+    launch_colpass(s, p, q, n, M.A, M.lda, b, g, nullptr, &ds->bits, a1f, gram_f32_copy_ld(p));
+    h->mark(1);
+    launch_gram_f32_on_copy(s, p, n, a1f, (float*)part, W, ldw, mid);
     if (o->stop_rule == ILS_STOP_RR) launch_norm2(s, n, g, &ds->scal[0]);
+  } else {
+    h->mark(1);
+    if (bordered)  // A1^T A1, A1^T b1 and A2^T A2, A2^T b2 in one launch pair
+      launch_gram2_f64(s, n, M.lda, ldw, (double*)part, mid, p, M.A, b, W, g, q, M.A + p, b + p, W + n * ldw,
+                       rv);
+    else  // A1^T A1 for [A1^T A1 | A2^T A2 | A^T J b] or [A1^T A1 | I]
+      mat_gram(s, M, 0, o->precision, part, W, ldw, mid);
+    HIPCHK(hipMemsetAsync(h->st, 0, sizeof(LoopState), s));
+    if (!bordered) {
+      mat_colpass(s, M, b, g, nullptr, &ds->bits);
+      if (o->stop_rule == ILS_STOP_RR) launch_norm2(s, n, g, &ds->scal[0]);
+    }
   }
   if (o->stop_rule == ILS_STOP_XREF) launch_norm2(s, n, o->x_ref, &ds->scal[1]);
   h->mark(3);
@@ -350,9 +361,10 @@ int ils::sp_solve_op(ils_handle* h, const MatOp& M, const double* b, const doubl
 
   // launch k computes x_{k+1} and decides on x_{k-1}; launch max_outer + 1
   // only decides
+  const int64_t nlaunch = o->max_outer + 2;
   int64_t k = 0, chunk = h->sp_queue;
   while (true) {
-    const int64_t kend = std::min(k + chunk, o->max_outer + 2);
+    const int64_t kend = std::min(k + chunk, nlaunch);
     for (; k < kend; ++k) {
       if (!paper && k == 0 && !x0) {
         // r_0 at x_0 = 0 is A^T J b, which the column pass formed
@@ -361,12 +373,17 @@ int ils::sp_solve_op(ils_handle* h, const MatOp& M, const double* b, const doubl
         launch_sp_step(s, a0, k);
         continue;
       }
-      if (!paper && k <= o->max_outer) mat_residual(s, M, b, k & 1 ? xb1 : xb0, tv, rv, &ds->done);
+      if (!paper && k <= o->max_outer) {
+        // skipped on the device when launch k is going to end the loop on x_{k-1}
+        SpStopCheck chk{spart + ((k - 1) & 1) * nblk, sbad + ((k - 1) & 1) * nblk, nblk, o->stop_rule, o->tol,
+                        k - 1, o->max_outer, ds->scal, &ds->resid_skip};
+        mat_residual(s, M, b, k & 1 ? xb1 : xb0, tv, rv, &ds->done, k >= 1 ? &chk : nullptr);
+      }
       launch_sp_step(s, a, k);
     }
     if (h->timing()) HIPCHK(hipEventRecord(h->ev1, s));
     if ((st = read_state(h))) return fail(info, st);
-    if (h->st_host->done || h->st_host->bits || k > o->max_outer + 1) break;
+    if (h->st_host->done || h->st_host->bits || k >= nlaunch) break;
     chunk = std::min<int64_t>(chunk * 2, 64);
   }
   h->mark(7);

@@ -35,6 +35,7 @@ struct LoopState {
                       // 2 ||inner target||^2, 7 relative error
   int nactive;        // multi-right-hand-side solve: columns still iterating
   unsigned int arrive3;// last-block counter of the blocked RK-RGS steps
+  int resid_skip;     // SP correction form: the last residual pass was skipped
 };
 
 // Pointers loaded from memory or passed to out-of-line functions are generic,
@@ -114,7 +115,7 @@ constexpr uint64_t kTagScd = 0x534344ull;
 // ---------------------------------------------------------------- launchers
 // Dense building blocks (k_dense.hip).
 void launch_colpass(hipStream_t s, int64_t p, int64_t q, int64_t n, const double* A, int64_t lda,
-                    const double* b, double* g, double* cn, int* bits);
+                    const double* b, double* g, double* cn, int* bits, float* a1f = nullptr, int64_t ldaf = 0);
 // r = A^T J (b - A x); t is residual_scratch(m, n) doubles of scratch (t = b - A x
 // in the first m).  Skipped when *done != 0.
 void launch_border_combine(hipStream_t s, int64_t n, double* g, const double* g2, const double* G1,
@@ -133,10 +134,39 @@ struct ResidCfg {
 ResidCfg residual_cfg(int64_t n, int64_t m);
 size_t residual_scratch(int64_t m, int64_t n);
 size_t residual_scratch_cfg(int64_t m, int64_t n, ResidCfg c);
+// SP step geometry: rows per workgroup (one wave each) and threads
+constexpr int kSpRows = 4;
+constexpr int kSpThreads = kSpRows * kWave;
+
+// The SP step's stop quantity from the summed partials: relative error
+// against x_ref, or RR (Sec. 5).  One definition for every kernel that takes
+// the stopping test, so all reach the same decision bit for bit.
+__device__ inline double sp_metric(double tot, int stop_rule, const double* scal) {
+  if (stop_rule == ILS_STOP_XREF) return sqrt(tot) / sqrt(scal[1]);
+  if (stop_rule == ILS_STOP_RR) return tot / scal[0];
+  return 0.0;
+}
+
+// The stopping test on x_kk that an SP step launch will take, repeated by a
+// kernel queued before it (the same partials added in the same order): a
+// correction-form residual for x_{kk+1} that the loop will not use is
+// skipped.  part == null: no test.
+struct SpStopCheck {
+  const double* part;  // metric partials of x_kk (nblk entries)
+  const int* pbad;     // non-finite flags of x_{kk+1} (nblk entries)
+  int nblk;
+  int stop_rule;
+  double tol;
+  int64_t kk, max_outer;
+  const double* scal;  // LoopState::scal
+  int* skip;           // set to whether the test ended the loop (read by the follow-up kernel)
+};
 void launch_residual(hipStream_t s, int64_t p, int64_t q, int64_t n, const double* A, int64_t lda,
-                     const double* b, const double* x, double* t, double* r, const int* done);
+                     const double* b, const double* x, double* t, double* r, const int* done,
+                     const SpStopCheck* chk = nullptr);
 void launch_residual_cfg(hipStream_t s, int64_t p, int64_t q, int64_t n, const double* A, int64_t lda,
-                         const double* b, const double* x, double* t, double* r, const int* done, ResidCfg c);
+                         const double* b, const double* x, double* t, double* r, const int* done, ResidCfg c,
+                         const SpStopCheck* chk = nullptr);
 // Gram of rows [0, K) of A (A already offset to the first row).  `partials`
 // must hold gram_partials_size(n, K) doubles.
 size_t gram_partials_size(int64_t n, int64_t K);
@@ -148,13 +178,17 @@ void launch_gram_f64(hipStream_t s, int64_t K, int64_t n, const double* A, int64
 void launch_gram_f32(hipStream_t s, int64_t K, int64_t n, const double* A, int64_t lda,
                      float* partials, double* G, int64_t ldg, hipEvent_t mid = nullptr);
 // FP32 Gram through an FP32 copy of the K rows (Af: gram_f32_copy_ld(K) x n
-// floats of scratch), formed first; taken when the launch table's mixed entry
-// for (n, K) is the persistent kind (gram_f32_uses_copy), which then reads
-// half the bytes of the FP64 rows.
+// floats of scratch, 16-byte aligned), formed first; taken when the launch
+// table's mixed entry for (n, K) is the persistent kind and the shape suits
+// it (gram_f32_uses_copy), which then reads half the bytes of the FP64 rows.
 int64_t gram_f32_copy_ld(int64_t K);
 bool gram_f32_uses_copy(int64_t n, int64_t K);
 void launch_gram_f32_copy(hipStream_t s, int64_t K, int64_t n, const double* A, int64_t lda, float* Af,
                           float* partials, double* G, int64_t ldg, hipEvent_t mid = nullptr);
+// The same product when Af already holds the copy (written by the column
+// pass): only the persistent kernel and its reduction are queued.
+void launch_gram_f32_on_copy(hipStream_t s, int64_t K, int64_t n, const float* Af, float* partials, double* G,
+                             int64_t ldg, hipEvent_t mid = nullptr);
 // Both bordered products [A0 vb0]^T [A0 vb0] and [A1 vb1]^T [A1 vb1] in one
 // launch pair (FP64, part 0's configuration); `partials` must hold
 // gram2_partials_size(n, K0, K1) doubles.
@@ -235,6 +269,7 @@ struct SpStepArgs {
 };
 int sp_step_blocks(int64_t n);
 void launch_sp_step(hipStream_t s, const SpStepArgs& a, int64_t k);
+
 
 // C = alpha X^T S Y + beta C0 (k_gemm.hip); S = diag(+1 for k < kneg, -1 after).
 struct GemmTnArgs {

@@ -33,15 +33,15 @@ void mat_colpass(hipStream_t s, const MatOp& M, const double* b, double* g, doub
 }
 
 void mat_residual(hipStream_t s, const MatOp& M, const double* b, const double* x, double* t, double* r,
-                  const int* done) {
+                  const int* done, const SpStopCheck* chk) {
   if (!M.sp)
-    launch_residual(s, M.p, M.q, M.n, M.A, M.lda, b, x, t, r, done);
+    launch_residual(s, M.p, M.q, M.n, M.A, M.lda, b, x, t, r, done, chk);
   else
     launch_csr_residual(s, *M.sp, b, x, t, r, done);
 }
 
 void mat_gram(hipStream_t s, const MatOp& M, int second, int precision, void* part, double* G, int64_t ldg,
-              hipEvent_t mid, float* a1f) {
+              hipEvent_t mid) {
   if (M.sp) {
     launch_sparse_gram(s, *M.sp, second, G, ldg);
     if (mid) (void)hipEventRecord(mid, s);
@@ -49,8 +49,6 @@ void mat_gram(hipStream_t s, const MatOp& M, int second, int precision, void* pa
   }
   if (second)
     launch_gram_f64(s, M.q, M.n, M.A + M.p, M.lda, (double*)part, G, ldg, mid);
-  else if (precision == ILS_PREC_MIXED && a1f && gram_f32_uses_copy(M.n, M.p))
-    launch_gram_f32_copy(s, M.p, M.n, M.A, M.lda, a1f, (float*)part, G, ldg, mid);
   else if (precision == ILS_PREC_MIXED)
     launch_gram_f32(s, M.p, M.n, M.A, M.lda, (float*)part, G, ldg, mid);
   else

@@ -114,14 +114,12 @@ struct MatOp {
 int check_op(const MatOp& M, const double* b, const double* x, const ils_opts* o);
 size_t mat_gram_partials(const MatOp& M);  // doubles of split-K scratch for mat_gram
 void mat_colpass(hipStream_t s, const MatOp& M, const double* b, double* g, double* cn, int* bits);
+// chk: the SP step's stopping test to repeat first (dense one-pass path), or null
 void mat_residual(hipStream_t s, const MatOp& M, const double* b, const double* x, double* t, double* r,
-                  const int* done);
+                  const int* done, const SpStopCheck* chk = nullptr);
 // G = A1^T A1 (second == 0) or A2^T A2 (second == 1).
-// a1f: scratch for an FP32 copy of A1 (gram_f32_copy_ld(p) x n floats) or
-// null; with it, and the mixed launch entry of the persistent kind, the FP32
-// product reads the copy.
 void mat_gram(hipStream_t s, const MatOp& M, int second, int precision, void* part, double* G, int64_t ldg,
-              hipEvent_t mid = nullptr, float* a1f = nullptr);
+              hipEvent_t mid = nullptr);
 void mat_rk_inner(hipStream_t st, const MatOp& M, const double* tgt, const double* cn, const int* j1,
                   const int* j2, int64_t count, double* w, double* s, double* z, const int* inner_done,
                   const int* outer_done);

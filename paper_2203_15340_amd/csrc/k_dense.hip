@@ -8,14 +8,17 @@ namespace ils {
 // ------------------------------------------------------------------ column pass
 // One workgroup per column j: g_j = A1_(j)^T b1 - A2_(j)^T b2 (Alg. 1 step 4)
 // and cn_j = ||A1_(j)||^2, the column weights of Alg. 2 steps 8 and 10.
-// Non-finite entries of A or b raise kBitNonfinite.
+// Non-finite entries of A or b raise kBitNonfinite.  With a1f, the pass also
+// writes A1 rounded to FP32 (leading dimension ldaf), the operand of the
+// mixed-precision Gram, while it reads A anyway.
 constexpr int kColThreads = 256;
 
 __global__ __launch_bounds__(kColThreads) void k_colpass(const double* __restrict__ A, int64_t lda,
                                                           int64_t p, int64_t q,
                                                           const double* __restrict__ b,
                                                           double* __restrict__ g,
-                                                          double* __restrict__ cn, int* bits) {
+                                                          double* __restrict__ cn, int* bits,
+                                                          float* __restrict__ a1f, int64_t ldaf) {
   __shared__ double red[3][kColThreads / kWave];
   const int64_t j = blockIdx.x;
   const double* col = A + j * lda;
@@ -35,6 +38,13 @@ __global__ __launch_bounds__(kColThreads) void k_colpass(const double* __restric
       s1 += av[u] * bv[u];
       c += av[u] * av[u];
       ok &= isfinite(av[u]) && isfinite(bv[u]);
+    }
+    if (a1f) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t i = i0 + threadIdx.x + u * kColThreads;
+        if (i < p) a1f[i + j * ldaf] = (float)av[u];
+      }
     }
   }
   for (int64_t i0 = p; i0 < p + q; i0 += U * kColThreads) {
@@ -62,9 +72,9 @@ __global__ __launch_bounds__(kColThreads) void k_colpass(const double* __restric
 }
 
 void launch_colpass(hipStream_t s, int64_t p, int64_t q, int64_t n, const double* A, int64_t lda,
-                    const double* b, double* g, double* cn, int* bits) {
+                    const double* b, double* g, double* cn, int* bits, float* a1f, int64_t ldaf) {
   hipLaunchKernelGGL(k_colpass, dim3((unsigned)n), dim3(kColThreads), 0, s, A, lda, p, q, b, g, cn,
-                     bits);
+                     bits, a1f, ldaf);
 }
 
 // g = g1 - g2 with g1 = A1^T b1 and g2 = A2^T b2 taken from the bordered Gram
@@ -211,19 +221,55 @@ __global__ __launch_bounds__(kR1Threads) void k_resid_1pass(const double* __rest
                                                              int64_t p, int64_t m, int64_t n,
                                                              const double* __restrict__ b,
                                                              const double* __restrict__ x,
-                                                             double* __restrict__ part, const int* done) {
+                                                             double* __restrict__ part, const int* done,
+                                                             SpStopCheck chk) {
   if (done && *done) return;
   __shared__ double red[2][kR1Threads / kWave][kR1Rows];
   __shared__ double xs[kR1MaxN];
+  __shared__ double chk_red[kSpThreads / kWave];
+  __shared__ int chk_bad[kSpThreads / kWave];
   const int tid = threadIdx.x, k = tid & (kR1Rows - 1), g = tid / kR1Rows;
   const int lane = tid & (kWave - 1), w = tid / kWave;
   const int64_t nblk = (m + kR1Rows - 1) / kR1Rows;
   const int64_t G = gridDim.x;
   const uint32_t boff = (uint32_t)((k + (int64_t)g * lda) * 8);
   for (int c = tid; c < kR1MaxN; c += kR1Threads) xs[c] = c < n ? x[c] : 0.0;
+  // the SP step's stopping test on the previous iterate, by the first
+  // kSpThreads threads in the SP step's own order (its loads go out before
+  // the block's, so waiting for them does not wait for the block)
+  const bool check = chk.part != nullptr;
+  double ctot = 0.0;
+  int cbad = 0;
+  if (check && tid < kSpThreads) {
+    for (int bkt = tid; bkt < chk.nblk; bkt += kSpThreads) {
+      ctot += chk.part[bkt];
+      cbad |= chk.pbad[bkt];
+    }
+  }
   R1Block d0, d1;
   r1_load(d0, A, lda, m, n, b, r1_first(blockIdx.x, G), k, boff);
+  if (check && w < kSpThreads / kWave) {
+    ctot = wave_sum(ctot);
+    cbad = __any(cbad);
+    if (lane == 0) {
+      chk_red[w] = ctot;
+      chk_bad[w] = cbad;
+    }
+  }
   lds_barrier();
+  if (check) {
+    double tot = chk_red[0];
+    int anybad = chk_bad[0];
+#pragma unroll
+    for (int q = 1; q < kSpThreads / kWave; ++q) {
+      tot += chk_red[q];
+      anybad |= chk_bad[q];
+    }
+    const double metric = sp_metric(tot, chk.stop_rule, chk.scal);
+    const bool taken = (chk.stop_rule != ILS_STOP_FIXED && metric < chk.tol) || chk.kk == chk.max_outer || anybad;
+    if (blockIdx.x == 0 && tid == 0) *chk.skip = taken ? 1 : 0;
+    if (taken) return;
+  }
   double acc = 0.0;  // column g + 64 k
   // one block: t_k = J_kk (b_k - (A x)_k) through LDS, then the block's
   // column sums t^T A_blk, each reduced over the 16 row lanes by recursive
@@ -275,8 +321,9 @@ __global__ __launch_bounds__(kR1Threads) void k_resid_1pass(const double* __rest
 // r_c = the workgroup partials of column c added by one wave: lane q takes
 // partials q, q + 64, ... in order, then a fixed butterfly.
 __global__ __launch_bounds__(256) void k_resid_1pass_fin(const double* __restrict__ part, int nwg, int64_t n,
-                                                          double* __restrict__ r, const int* done) {
-  if (done && *done) return;
+                                                          double* __restrict__ r, const int* done,
+                                                          const int* skip) {
+  if ((done && *done) || (skip && *skip)) return;
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t c = (int64_t)blockIdx.x * (256 / kWave) + (threadIdx.x >> 6);
   if (c >= n) return;
@@ -370,12 +417,14 @@ __global__ __launch_bounds__(kColThreads) void k_resid_cols(const double* __rest
 }
 
 void launch_residual(hipStream_t s, int64_t p, int64_t q, int64_t n, const double* A, int64_t lda,
-                     const double* b, const double* x, double* t, double* r, const int* done) {
-  launch_residual_cfg(s, p, q, n, A, lda, b, x, t, r, done, residual_cfg(n, p + q));
+                     const double* b, const double* x, double* t, double* r, const int* done,
+                     const SpStopCheck* chk) {
+  launch_residual_cfg(s, p, q, n, A, lda, b, x, t, r, done, residual_cfg(n, p + q), chk);
 }
 
 void launch_residual_cfg(hipStream_t s, int64_t p, int64_t q, int64_t n, const double* A, int64_t lda,
-                         const double* b, const double* x, double* t, double* r, const int* done, ResidCfg c) {
+                         const double* b, const double* x, double* t, double* r, const int* done, ResidCfg c,
+                         const SpStopCheck* chk) {
   const int64_t m = p + q;
   if (m == 0) {  // no rows: r = 0
     launch_fill_vec(s, n, nullptr, r);
@@ -384,10 +433,11 @@ void launch_residual_cfg(hipStream_t s, int64_t p, int64_t q, int64_t n, const d
   if (one_pass(n, c) && one_pass_fits(lda)) {
     const int nwg = r1_wgs(m, c.wgs > 0 ? c.wgs : kR1Wgs);
     double* part = t + (m > 0 ? m : 1);
+    SpStopCheck none{};
     hipLaunchKernelGGL(k_resid_1pass, dim3((unsigned)nwg), dim3(kR1Threads), 0, s, A, lda, p, m, n, b, x, part,
-                       done);
+                       done, chk ? *chk : none);
     hipLaunchKernelGGL(k_resid_1pass_fin, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, (const double*)part, nwg,
-                       n, r, done);
+                       n, r, done, chk ? (const int*)chk->skip : nullptr);
     return;
   }
   const int64_t groups = resid_groups(m, n);

@@ -942,7 +942,15 @@ void launch_gram2_f64(hipStream_t s, int64_t n, int64_t lda, int64_t ldg, double
 }
 
 
-bool gram_f32_uses_copy(int64_t n, int64_t K) { return gram_cfg(ILS_PREC_MIXED, n, K).kind == kGramPersistent; }
+bool gram_f32_uses_copy(int64_t n, int64_t K) {
+  return gram_cfg(ILS_PREC_MIXED, n, K).kind == kGramPersistent &&
+         pers_shape(n, K, PersGeo<float>::RS).cmax <= kPersMaxShares;
+}
+
+void launch_gram_f32_on_copy(hipStream_t s, int64_t K, int64_t n, const float* Af, float* partials, double* G,
+                             int64_t ldg, hipEvent_t mid) {
+  gram_f32_pers(s, K, n, Af, gram_f32_copy_ld(K), partials, G, ldg, mid);
+}
 
 void launch_gram_f32_copy(hipStream_t s, int64_t K, int64_t n, const double* A, int64_t lda, float* Af,
                           float* partials, double* G, int64_t ldg, hipEvent_t mid) {

@@ -11,7 +11,9 @@
 // k + 1: every workgroup adds the partials of launch k in the same fixed
 // order, so all reach the same decision without atomics or fences, and
 // workgroup 0 records it in LoopState; the deciding launch also copies the
-// returned iterate into the caller's x.  The host queues several steps ahead;
+// returned iterate into the caller's x.  (The correction form's residual
+// queued between launches k and k + 1 repeats the same test, so the pass
+// over A for an x_{k+1} the loop will not use is skipped.)  The host queues several steps ahead;
 // a launch that finds the loop finished by an EARLIER launch returns at once.
 // LoopState::done holds the deciding launch's index + 1, so a workgroup of the
 // deciding launch itself that starts after workgroup 0's store is visible
@@ -20,10 +22,8 @@
 
 namespace ils {
 
-// rows per workgroup, one wave each (2 and 8 measured slower at n = 1000:
-// 70-74 us for the 7 steps of a solve against 65-68 us)
-constexpr int kSpRows = 4;
-constexpr int kSpThreads = kSpRows * kWave;
+// kSpRows rows per workgroup, one wave each (2 and 8 measured slower at
+// n = 1000: 70-74 us for the 7 steps of a solve against 65-68 us)
 
 // Dot product of a contiguous row with v by one wave: each lane issues
 // sixteen loads per round before using them (a 1000-long row is one round);
@@ -114,9 +114,7 @@ __global__ __launch_bounds__(kSpThreads) void k_sp_step(SpStepArgs a, int64_t k)
     }
     tot = block_sum<kSpThreads>(tot, tred);
     anybad = __syncthreads_or(anybad);
-    double metric = 0.0;
-    if (a.stop_rule == ILS_STOP_XREF) metric = sqrt(tot) / sqrt(st->scal[1]);
-    else if (a.stop_rule == ILS_STOP_RR) metric = tot / st->scal[0];
+    const double metric = sp_metric(tot, a.stop_rule, st->scal);
     int done = 0, status = ILS_OK;
     int64_t iters = kk;
     if (a.stop_rule != ILS_STOP_FIXED && metric < a.tol) {
