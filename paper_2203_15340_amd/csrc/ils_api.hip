@@ -276,7 +276,7 @@ int ils::sp_solve_op(ils_handle* h, const MatOp& M, const double* b, const doubl
       (st = h->need(kBufX1, sizeof(double) * n, (void**)&xb1)) ||
       (st = h->need(kBufT, sizeof(double) * residual_scratch(m, n), (void**)&tv)) ||
       (st = h->need(kBufR, sizeof(double) * n, (void**)&rv)) ||
-      (st = h->need(kBufSPart, sizeof(double) * 2 * nblk, (void**)&spart)) ||
+      (st = h->need(kBufSPart, sizeof(double) * 4 * nblk, (void**)&spart)) ||
       (st = h->need(kBufSBad, sizeof(int) * 2 * nblk, (void**)&sbad)) ||
       (st = h->need(kBufDinv, gj_scratch_bytes(n, n + nrhs), (void**)&dinv)))
     return fail(info, st);
@@ -353,6 +353,10 @@ int ils::sp_solve_op(ils_handle* h, const MatOp& M, const double* b, const doubl
   a.r = rv;
   a.partials = spart;
   a.nonfinite_part = sbad;
+  // correction form with a test that does not need r_{k+1}: x_{k+1}'s metric
+  // partials as well, for the residual's skip test
+  const bool test_next = !paper && o->stop_rule != ILS_STOP_RR;
+  a.next_partials = (test_next && o->stop_rule == ILS_STOP_XREF) ? spart + 2 * nblk : nullptr;
   a.st = ds;
   a.stop_rule = o->stop_rule;
   a.tol = o->tol;
@@ -374,9 +378,12 @@ int ils::sp_solve_op(ils_handle* h, const MatOp& M, const double* b, const doubl
         continue;
       }
       if (!paper && k <= o->max_outer) {
-        // skipped on the device when launch k is going to end the loop on x_{k-1}
-        SpStopCheck chk{spart + ((k - 1) & 1) * nblk, sbad + ((k - 1) & 1) * nblk, nblk, o->stop_rule, o->tol,
-                        k - 1, o->max_outer, ds->scal, &ds->resid_skip};
+        // skipped on the device when the loop is going to end without r_k:
+        // at x_{k-1} (launch k's test) or, for a test that does not need
+        // r_k, at x_k (launch k + 1's test by the metric or the step limit)
+        SpStopCheck chk{spart + ((k - 1) & 1) * nblk, sbad + ((k - 1) & 1) * nblk, nullptr, nblk, o->stop_rule,
+                        o->tol, k - 1, o->max_outer, ds->scal, &ds->resid_skip};
+        if (test_next) chk.part_next = a.next_partials ? a.next_partials + ((k - 1) & 1) * nblk : spart;
         mat_residual(s, M, b, k & 1 ? xb1 : xb0, tv, rv, &ds->done, k >= 1 ? &chk : nullptr);
       }
       launch_sp_step(s, a, k);

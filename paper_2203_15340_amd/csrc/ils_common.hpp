@@ -147,13 +147,16 @@ __device__ inline double sp_metric(double tot, int stop_rule, const double* scal
   return 0.0;
 }
 
-// The stopping test on x_kk that an SP step launch will take, repeated by a
-// kernel queued before it (the same partials added in the same order): a
-// correction-form residual for x_{kk+1} that the loop will not use is
-// skipped.  part == null: no test.
+// The stopping tests that SP step launches will take, repeated by a kernel
+// queued before them (the same partials added in the same order): a
+// correction-form residual for an iterate the loop will not use is skipped.
+// Test 1 is launch kk + 1's test on x_kk (partials of x_kk's metric, flags of
+// x_{kk+1}); test 2 (part_next non-null) the end of the loop at x_kk + 1 by
+// its metric or the step limit alone.  part == null: no test.
 struct SpStopCheck {
-  const double* part;  // metric partials of x_kk (nblk entries)
-  const int* pbad;     // non-finite flags of x_{kk+1} (nblk entries)
+  const double* part;       // metric partials of x_kk (nblk entries)
+  const int* pbad;          // non-finite flags of x_{kk+1} (nblk entries)
+  const double* part_next;  // metric partials of x_{kk+1}, or null
   int nblk;
   int stop_rule;
   double tol;
@@ -261,6 +264,7 @@ struct SpStepArgs {
   const double* r;      // correction form: residual at x_k (n)
   double* partials;     // per-block metric partials, two sets of sp_step_blocks(n)
   int* nonfinite_part;  // per-block flags, two sets
+  double* next_partials;// XREF: per-block partials of x_{k+1}'s metric (two sets), or null
   LoopState* st;
   int stop_rule;
   double tol;

@@ -226,7 +226,7 @@ __global__ __launch_bounds__(kR1Threads) void k_resid_1pass(const double* __rest
   if (done && *done) return;
   __shared__ double red[2][kR1Threads / kWave][kR1Rows];
   __shared__ double xs[kR1MaxN];
-  __shared__ double chk_red[kSpThreads / kWave];
+  __shared__ double chk_red[2][kSpThreads / kWave];
   __shared__ int chk_bad[kSpThreads / kWave];
   const int tid = threadIdx.x, k = tid & (kR1Rows - 1), g = tid / kR1Rows;
   const int lane = tid & (kWave - 1), w = tid / kWave;
@@ -234,39 +234,47 @@ __global__ __launch_bounds__(kR1Threads) void k_resid_1pass(const double* __rest
   const int64_t G = gridDim.x;
   const uint32_t boff = (uint32_t)((k + (int64_t)g * lda) * 8);
   for (int c = tid; c < kR1MaxN; c += kR1Threads) xs[c] = c < n ? x[c] : 0.0;
-  // the SP step's stopping test on the previous iterate, by the first
-  // kSpThreads threads in the SP step's own order (its loads go out before
-  // the block's, so waiting for them does not wait for the block)
-  const bool check = chk.part != nullptr;
-  double ctot = 0.0;
+  // the SP steps' stopping tests, by the first kSpThreads threads in the SP
+  // step's own order (their loads go out before the block's, so waiting for
+  // them does not wait for the block)
+  const bool check = chk.part != nullptr, check2 = check && chk.part_next != nullptr;
+  double ctot = 0.0, ctot2 = 0.0;
   int cbad = 0;
   if (check && tid < kSpThreads) {
     for (int bkt = tid; bkt < chk.nblk; bkt += kSpThreads) {
       ctot += chk.part[bkt];
       cbad |= chk.pbad[bkt];
+      if (check2) ctot2 += chk.part_next[bkt];
     }
   }
   R1Block d0, d1;
   r1_load(d0, A, lda, m, n, b, r1_first(blockIdx.x, G), k, boff);
   if (check && w < kSpThreads / kWave) {
     ctot = wave_sum(ctot);
+    ctot2 = wave_sum(ctot2);
     cbad = __any(cbad);
     if (lane == 0) {
-      chk_red[w] = ctot;
+      chk_red[0][w] = ctot;
+      chk_red[1][w] = ctot2;
       chk_bad[w] = cbad;
     }
   }
   lds_barrier();
   if (check) {
-    double tot = chk_red[0];
+    double tot = chk_red[0][0], tot2 = chk_red[1][0];
     int anybad = chk_bad[0];
 #pragma unroll
     for (int q = 1; q < kSpThreads / kWave; ++q) {
-      tot += chk_red[q];
+      tot += chk_red[0][q];
+      tot2 += chk_red[1][q];
       anybad |= chk_bad[q];
     }
-    const double metric = sp_metric(tot, chk.stop_rule, chk.scal);
-    const bool taken = (chk.stop_rule != ILS_STOP_FIXED && metric < chk.tol) || chk.kk == chk.max_outer || anybad;
+    const bool conv = chk.stop_rule != ILS_STOP_FIXED && sp_metric(tot, chk.stop_rule, chk.scal) < chk.tol;
+    bool taken = conv || chk.kk == chk.max_outer || anybad;
+    if (check2) {
+      const bool conv2 = chk.stop_rule != ILS_STOP_FIXED && sp_metric(tot2, chk.stop_rule, chk.scal) < chk.tol;
+      taken = taken || conv2 || chk.kk + 1 == chk.max_outer;
+    }
     if (blockIdx.x == 0 && tid == 0) *chk.skip = taken ? 1 : 0;
     if (taken) return;
   }

@@ -12,8 +12,10 @@
 // order, so all reach the same decision without atomics or fences, and
 // workgroup 0 records it in LoopState; the deciding launch also copies the
 // returned iterate into the caller's x.  (The correction form's residual
-// queued between launches k and k + 1 repeats the same test, so the pass
-// over A for an x_{k+1} the loop will not use is skipped.)  The host queues several steps ahead;
+// queued before launch k + 1 repeats the test that ends the loop: on x_{k+1}
+// from the partials launch k also writes for it (relative error, fixed
+// count), or on x_k (RR, which needs that residual), so the pass over A for
+// an iterate the loop will not use is skipped.)  The host queues several steps ahead;
 // a launch that finds the loop finished by an EARLIER launch returns at once.
 // LoopState::done holds the deciding launch's index + 1, so a workgroup of the
 // deciding launch itself that starts after workgroup 0's store is visible
@@ -141,7 +143,7 @@ __global__ __launch_bounds__(kSpThreads) void k_sp_step(SpStepArgs a, int64_t k)
     }
   }
   double* xn = (k & 1) ? a.xbuf0 : a.xbuf1;
-  double mp = 0.0;
+  double mp = 0.0, mpn = 0.0;
   int bad = 0;
   if (i < a.n) {
     const double dot = dot_rest(row, v, a.n, lane, rv0, vv0);
@@ -158,26 +160,34 @@ __global__ __launch_bounds__(kSpThreads) void k_sp_step(SpStepArgs a, int64_t k)
                                                    : a.r[i];
       mp = ri * ri;
     }
+    if (a.next_partials) {
+      // x_{k+1}'s relative-error partial, the same value launch k + 1 forms
+      const double dn = xi - a.x_ref[i];
+      mpn = dn * dn;
+    }
     if (lane == 0) xn[i] = xi;
     bad = !isfinite(xi);
   }
-  __shared__ double red[kSpRows];
+  __shared__ double red[kSpRows], redn[kSpRows];
   __shared__ int redb[kSpRows];
   if (lane == 0) {
     red[w] = mp;
+    redn[w] = mpn;
     redb[w] = bad;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double sum = red[0];
+    double sum = red[0], sumn = redn[0];
     int anyb = redb[0];
 #pragma unroll
     for (int q = 1; q < kSpRows; ++q) {
       sum += red[q];
+      sumn += redn[q];
       anyb |= redb[q];
     }
     a.partials[(k & 1) * nblk + blockIdx.x] = sum;
     a.nonfinite_part[(k & 1) * nblk + blockIdx.x] = anyb;
+    if (a.next_partials) a.next_partials[(k & 1) * nblk + blockIdx.x] = sumn;
   }
 }
 
