@@ -258,13 +258,15 @@ def bench_batched(ils, W, np, torch, count=4096, single_sample=256):
     return out
 
 
-def bench_warm_start(ils, W, np, torch, n_train=50000, n_test=2000, epochs=20, single_sample=20):
+def bench_warm_start(ils, W, np, torch, n_train=50000, n_test=2000, single_sample=20):
     """Learned warm start on a family sharing A (18000 + 2000 x 1000, ratio
     0.5): x = U theta + 1e-3 eps with U a random 1000 x 32 orthonormal basis,
     b = A x.  Training pairs (b, x_SP) come from the multi-right-hand-side SP
     solve at RR < 1e-20 (relative residual 1e-10); the network sees every
-    10th row of b.  Test: n_test fresh right-hand sides solved to rel.err
-    1e-6 from the zero start and from the network's x0 (inference timed)."""
+    10th row of b and trains in 8 stages of 10 epochs with the step size
+    halved each stage.  Test: n_test fresh right-hand sides solved to rel.err
+    1e-6 on the prepared A (Gram products and elimination done once), from
+    the zero start and from the network's x0 (inference timed)."""
     log("warm start: generating the family")
     P, U = W.ws_problem(seed=4)
     A = torch.from_numpy(np.ascontiguousarray(P.A.T)).cuda().t()
@@ -288,12 +290,16 @@ def bench_warm_start(ils, W, np, torch, n_train=50000, n_test=2000, epochs=20, s
     log(f"training targets: {n_train} SP solves in {t_sp:.2f} s, max outer {inf.outer_iters}, "
         f"max rel.err vs planted {sp_err:.1e}")
     del Xtr
-    ws = ils.WarmStart(P.m, P.n, rows, hidden=512, seed=4)
+    hidden = 1024
+    schedule = [(10, 1e-3 * 0.5 ** i) for i in range(8)]
+    ws = ils.WarmStart(P.m, P.n, rows, hidden=hidden, seed=4)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    loss = ws.train(Btr, Xsp, epochs=epochs, batch=256, lr=1e-3)
+    for ep, lr in schedule:
+        loss = ws.train(Btr, Xsp, epochs=ep, batch=256, lr=lr)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
+    epochs = sum(e for e, _ in schedule)
     log(f"training: {epochs} epochs in {t_train:.2f} s, final loss {loss:.3e}")
     del Btr, Xsp
     torch.cuda.empty_cache()
@@ -301,33 +307,56 @@ def bench_warm_start(ils, W, np, torch, n_train=50000, n_test=2000, epochs=20, s
     Xte, Bte = rhs(W.ws_solutions(U, n_test, seed=(4, 3)))
     kw = dict(stop_rule=ils.STOP_XREF, tol=1e-6, x_ref=Xte)
     out = {"family": "A 18000+2000 x 1000 ratio 0.5 (seed 4); x = U theta + 1e-3 eps, U 1000 x 32",
-           "train_pairs": n_train, "test_rhs": n_test, "epochs": epochs, "final_loss": loss,
-           "train_s": t_train, "train_targets": {"sp_solves_per_s": n_train / t_sp,
-                                                 "max_outer": inf.outer_iters, "rr_tol": 1e-20,
-                                                 "max_rel_err_vs_planted": sp_err}}
+           "train_pairs": n_train, "test_rhs": n_test, "hidden": hidden, "epochs": epochs,
+           "schedule": "8 stages of 10 epochs, step 1e-3 halved per stage, batch 256",
+           "final_loss": loss, "train_s": t_train,
+           "train_targets": {"sp_solves_per_s": n_train / t_sp, "max_outer": inf.outer_iters,
+                             "rr_tol": 1e-20, "max_rel_err_vs_planted": sp_err}}
     X0 = ws.infer(Bte)
     e0 = ((X0 - Xte).norm(dim=0) / Xte.norm(dim=0)).cpu().numpy()
     out["warm_start_initial_rel_err"] = {"median": float(np.median(e0)), "max": float(e0.max())}
-    for name in ("zero_start", "warm_start"):
-        reps = 5
-        ils.sp_solve_multi(A, Bte, P.p, **kw)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            x0 = ws.infer(Bte) if name == "warm_start" else None
-            X, inf, it = ils.sp_solve_multi(A, Bte, P.p, X0=x0, **kw)
-        torch.cuda.synchronize()
-        el = (time.perf_counter() - t0) / reps
-        out[name] = {"solves_per_s": n_test / el, "ms_per_batch": el * 1e3, "status": inf.status,
-                     "mean_outer": float(it.mean()), "max_outer": int(it.max()),
-                     "max_rel_err": inf.rel_err}
-        log(f"{name}: {n_test / el:.0f} solves/s, mean outer {it.mean():.2f}")
+
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(3):
-        ws.infer(Bte)
+    prep = ils.SPPrepared(A, P.p)
     torch.cuda.synchronize()
-    out["inference_ms_per_batch"] = (time.perf_counter() - t0) / 3 * 1e3
+    out["prepare_ms"] = (time.perf_counter() - t0) * 1e3
+    reps = 5
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            r = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps, r
+
+    # per-batch work without outer steps: A^T J B, c = P A^T J B, copies
+    el0, _ = timed(lambda: prep.solve_multi(Bte, stop_rule=ils.STOP_FIXED, max_outer=0))
+    out["per_batch_setup_ms"] = el0 * 1e3
+    el_inf, _ = timed(lambda: ws.infer(Bte))
+    out["inference_ms_per_batch"] = el_inf * 1e3
+    for name in ("zero_start", "warm_start"):
+        def run(warm=(name == "warm_start")):
+            x0 = ws.infer(Bte) if warm else None
+            return prep.solve_multi(Bte, X0=x0, **kw)
+        el, (X, inf2, it) = timed(run)
+        steps_ms = el * 1e3 - el0 * 1e3 - (el_inf * 1e3 if name == "warm_start" else 0.0)
+        out[name] = {"solves_per_s": n_test / el, "ms_per_batch": el * 1e3, "status": inf2.status,
+                     "mean_outer": float(it.mean()), "max_outer": int(it.max()),
+                     "outer_steps_ms": steps_ms, "max_rel_err": inf2.rel_err}
+        log(f"{name} (prepared A): {n_test / el:.0f} solves/s, mean outer {it.mean():.2f}, "
+            f"max {int(it.max())}, outer steps {steps_ms:.2f} ms")
+    z, w = out["zero_start"], out["warm_start"]
+    out["ratios"] = {"max_outer_warm_over_zero": w["max_outer"] / max(z["max_outer"], 1),
+                     "outer_steps_ms_warm_over_zero": w["outer_steps_ms"] / max(z["outer_steps_ms"], 1e-9),
+                     "solves_per_s_warm_over_zero": w["solves_per_s"] / z["solves_per_s"]}
+    prep.close()
+    # the unprepared multi-right-hand-side solve (Grams and elimination per call), for context
+    el, (X, inf3, it) = timed(lambda: ils.sp_solve_multi(A, Bte, P.p, **kw))
+    out["unprepared_zero_start"] = {"solves_per_s": n_test / el, "ms_per_batch": el * 1e3,
+                                    "mean_outer": float(it.mean())}
     x = torch.empty(P.n, dtype=torch.float64, device="cuda")
     ils.sp_solve(A, Bte[:, 0], P.p, out=x, stop_rule=ils.STOP_XREF, tol=1e-6, x_ref=Xte[:, 0])
     torch.cuda.synchronize()

@@ -183,6 +183,29 @@ int ils_sp_solve_multi(ils_handle* h, int64_t p, int64_t q, int64_t n, const dou
                        double* X, int64_t ldx, const ils_opts* opts, int64_t* iters /* host */,
                        ils_info* info /* host */);
 
+/* SP on a fixed A, prepared once (Alg. 1 steps 2-5 without b): forms
+ * A1^T A1 and A2^T A2 and eliminates [A1^T A1 | A2^T A2 | I] to [I | B | P]
+ * (B = P A2^T A2, P = (A1^T A1)^{-1}), keeping B, P and A^T J A on the
+ * device (3 n^2 doubles owned by the object).  Each later solve then costs
+ * A^T J b (one product over A for all right-hand sides), c = P A^T J b and
+ * its outer steps x_{k+1} = B x_k + c (Alg. 1 step 6), with the same per-
+ * column stop tests and results as ils_sp_solve_multi (up to rounding in c).
+ * For callers that solve many right-hand sides with one A over time, e.g.
+ * with a learned warm start.  A is not copied: it must stay allocated and
+ * unchanged while the object lives.  The object uses h's device, stream and
+ * workspace; destroy it before h.  Errors: ILS_ERR_ARG (shapes, pointers),
+ * ILS_ERR_NONFINITE (a non-finite entry of A), ILS_ERR_NOT_SPD (A1^T A1 not
+ * positive definite), ILS_ERR_ALLOC; *prep is NULL on error. */
+typedef struct ils_sp_prep ils_sp_prep;
+int ils_sp_prepare(ils_handle* h, int64_t p, int64_t q, int64_t n, const double* A, int64_t lda,
+                   ils_sp_prep** prep /* host out */);
+/* As ils_sp_solve_multi on the prepared A (B m x nrhs, ldb >= m; X0 may be
+ * NULL; X n x nrhs; ILS_FORM_PAPER, ILS_PREC_FP64 only). */
+int ils_sp_prep_solve_multi(ils_sp_prep* prep, int64_t nrhs, const double* B, int64_t ldb, const double* X0,
+                            int64_t ldx0, double* X, int64_t ldx, const ils_opts* opts, int64_t* iters /* host */,
+                            ils_info* info /* host */);
+int ils_sp_prep_destroy(ils_sp_prep* prep);
+
 /* SP-RK-RGS (Algorithm 2) for nrhs right-hand sides B = [b_1 .. b_nrhs] (m x
  * nrhs, ldb >= p + q) with the same A and one index stream: the column draws
  * of Alg. 2 steps 8 and 10 depend only on the column norms of A1, so every

@@ -31,7 +31,8 @@ LIB_PATH = _build.LIB
 EXPORTS = ("ils_create", "ils_destroy", "ils_opts_default", "ils_status_string", "ils_sp_solve",
            "ils_rk_solve", "ils_rgs_solve", "ils_gram", "ils_colpass", "ils_residual", "ils_residual_noalloc",
            "ils_spd_solve", "ils_rk_indices", "ils_scd_subsets", "ils_set_profiling",
-           "ils_get_phase_times", "ils_sp_solve_batched", "ils_sp_solve_multi", "ils_rk_solve_multi", "ils_ws_create",
+           "ils_get_phase_times", "ils_sp_solve_batched", "ils_sp_solve_multi", "ils_rk_solve_multi", "ils_sp_prepare",
+           "ils_sp_prep_solve_multi", "ils_sp_prep_destroy", "ils_ws_create",
            "ils_ws_destroy", "ils_ws_train", "ils_ws_infer", "ils_ws_save", "ils_ws_load",
            "ils_ws_nparams", "ils_ws_get_params", "ils_ws_set_params", "ils_ws_forward", "ils_ws_grad",
            "ils_ws_adam", "ils_csr_create", "ils_csr_destroy", "ils_sp_solve_csr", "ils_rk_solve_csr",
@@ -109,6 +110,9 @@ def load_library(path: str = LIB_PATH):
                                          P, P]),
         "ils_rk_solve_multi": (C.c_int, [P, I64, I64, I64, P, I64, I64, P, I64, P, I64, P, I64, P,
                                          P, P]),
+        "ils_sp_prepare": (C.c_int, [P, I64, I64, I64, P, I64, C.POINTER(P)]),
+        "ils_sp_prep_solve_multi": (C.c_int, [P, I64, P, I64, P, I64, P, I64, P, P, P]),
+        "ils_sp_prep_destroy": (C.c_int, [P]),
         "ils_ws_create": (C.c_int, [P, I64, I64, I64, P, I64, U64, C.POINTER(P)]),
         "ils_ws_destroy": (C.c_int, [P]),
         "ils_ws_train": (C.c_int, [P, I64, P, I64, P, I64, I32, I64, C.c_double, P]),
@@ -298,6 +302,64 @@ def sp_solve_multi(A, B, p, X0=None, out=None, raise_on_error=False, **kw):
     if raise_on_error and rc != OK:
         raise ILSError(f"ils_sp_solve_multi: {status_string(rc)}")
     return X, res, iters
+
+
+class SPPrepared:
+    """SP on a fixed A (ils_sp_prepare): the Gram products and the
+    elimination are done here once; solve_multi then costs A^T J B, one
+    product with P and the outer steps.  A (column-major float64 CUDA
+    tensor) must stay alive and unchanged while this object lives."""
+
+    def __init__(self, A, p):
+        torch = _torch()
+        if A.dim() != 2 or A.dtype != torch.float64 or not A.is_cuda:
+            raise ILSError("A must be a column-major (stride (1, lda)) float64 CUDA tensor")
+        self.A = A
+        self.m, self.n = A.shape
+        self.p = p
+        self._h = handle(A.device)
+        obj = C.c_void_p()
+        _rc(load_library().ils_sp_prepare(self._h, p, self.m - p, self.n, _ptr(A), _ld(A), C.byref(obj)),
+            "ils_sp_prepare")
+        self._obj = obj
+
+    def close(self):
+        if getattr(self, "_obj", None):
+            load_library().ils_sp_prep_destroy(self._obj)
+            self._obj = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve_multi(self, B, X0=None, out=None, raise_on_error=False, **kw):
+        """As sp_solve_multi.  Returns (X, Info, iters)."""
+        import numpy as np
+        torch = _torch()
+        nrhs = B.shape[1]
+        _check_mat(B, self.m, nrhs, "B")
+        _check_mat(X0, self.n, nrhs, "X0")
+        xr = kw.get("x_ref")
+        if xr is not None:
+            _check_mat(xr, self.n, nrhs, "x_ref")
+            if nrhs > 1 and xr.stride(1) != self.n:
+                raise ILSError("x_ref must have leading dimension n")
+        X = out if out is not None else torch.empty((nrhs, self.n), dtype=torch.float64,
+                                                    device=self.A.device).t()
+        _check_mat(X, self.n, nrhs, "out")
+        o = make_opts(**kw)
+        info = _Info()
+        iters = np.zeros(nrhs, dtype=np.int64)
+        rc = load_library().ils_sp_prep_solve_multi(
+            self._obj, nrhs, _ptr(B), _ld(B), _ptr(X0), self.n if X0 is None else _ld(X0), _ptr(X), _ld(X),
+            C.byref(o), iters.ctypes.data, C.byref(info))
+        res = Info(int(rc), int(info.outer_iters), int(info.inner_iters), float(info.rr),
+                   float(info.rel_err), float(info.device_ms))
+        if raise_on_error and rc != OK:
+            raise ILSError(f"ils_sp_prep_solve_multi: {status_string(rc)}")
+        return X, res, iters
 
 
 def rk_solve_multi(A, B, p, X0=None, out=None, raise_on_error=False, **kw):

@@ -230,6 +230,7 @@ void launch_copy_cols(hipStream_t s, int64_t n, int64_t ncol, const double* X, i
                       double* Y, int64_t ldy);
 void launch_fill_vec(hipStream_t s, int64_t n, const double* src, double* dst);
 void launch_eye(hipStream_t s, int64_t n, double* Y, int64_t ldy);
+void launch_diag_screen(hipStream_t s, int64_t n, const double* G1, const double* G2, int64_t ldg, int* bits);
 void launch_sub(hipStream_t s, int64_t n, const double* X, int64_t ldx, const double* Y, int64_t ldy,
                 double* Z, int64_t ldz);
 

@@ -52,6 +52,7 @@ enum BufSlot {
   kBufRmT,      // multi-RHS RK-RGS: inner targets (n x nrhs)
   kBufRmV,      // multi-RHS RK-RGS: w - s of a group (p x kMR), then A1^T of it (n x kMR)
   kBufRmF,      // multi-RHS RK-RGS: frozen flags, target norms
+  kBufMC,       // prepared-A SP: P A^T J B
   kBufCount
 };
 

@@ -103,6 +103,19 @@ void launch_border_combine(hipStream_t s, int64_t n, double* g, const double* g2
                      ldg, gcol, bits);
 }
 
+// A non-finite diagonal entry of G1 or G2 (a non-finite entry of A, or a
+// column whose squares overflow) raises kBitNonfinite.
+__global__ __launch_bounds__(256) void k_diag_screen(int64_t n, const double* __restrict__ G1,
+                                                     const double* __restrict__ G2, int64_t ldg, int* bits) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int bad = j < n && (!isfinite(G1[j + j * ldg]) || !isfinite(G2[j + j * ldg]));
+  if (__syncthreads_or(bad) && threadIdx.x == 0) atomicOr(bits, kBitNonfinite);
+}
+
+void launch_diag_screen(hipStream_t s, int64_t n, const double* G1, const double* G2, int64_t ldg, int* bits) {
+  hipLaunchKernelGGL(k_diag_screen, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, G1, G2, ldg, bits);
+}
+
 // ------------------------------------------------------------------ residual
 // r = A^T J (b - A x); up to n = 1024 in one pass over A (below), otherwise
 // in two.

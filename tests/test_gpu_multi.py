@@ -134,3 +134,73 @@ def test_argument_errors(fam):
                dict(stop_rule=ils.STOP_XREF)):
         _, info, _ = ils.sp_solve_multi(A, Bd, P.p, **kw)
         assert info.status == ils.ERR_ARG
+
+
+# ------------------------------------------------------------------ prepared A
+@pytest.fixture(scope="module")
+def prep(fam):
+    P, Xs, B, A, Bd = fam
+    pr = ils.SPPrepared(A, P.p)
+    yield pr
+    pr.close()
+
+
+@pytest.mark.parametrize("steps", [1, 4])
+def test_prepared_fixed_schedule_iterates(fam, prep, steps):
+    """ils_sp_prep_solve_multi: B and P from one elimination of
+    [A1^T A1 | A2^T A2 | I], c = P A^T J b per column; the iterates follow
+    the oracle's explicit-P SP column by column."""
+    P, Xs, B, A, Bd = fam
+    X0 = np.asfortranarray(np.random.default_rng(10 + steps).standard_normal(Xs.shape))
+    X, info, iters = prep.solve_multi(Bd, X0=devA(X0), stop_rule=ils.STOP_FIXED, max_outer=steps)
+    assert info.status == ils.OK and np.all(iters == steps)
+    ref, _ = oracle_cols(P, B, x0s=X0, stop_rule=O.STOP_FIXED, max_outer=steps)
+    cols_close(host(X), ref, 1e-10)
+
+
+@pytest.mark.parametrize("rule", ["xref", "rr"])
+def test_prepared_converged_columns_match_oracle(fam, prep, rule):
+    P, Xs, B, A, Bd = fam
+    if rule == "xref":
+        X, info, iters = prep.solve_multi(Bd, stop_rule=ils.STOP_XREF, tol=1e-9, x_ref=devA(Xs))
+        ref, rinf = oracle_cols(P, B, stop_rule=O.STOP_XREF, tol=1e-9, x_refs=Xs)
+    else:
+        X, info, iters = prep.solve_multi(Bd, stop_rule=ils.STOP_RR, tol=1e-18)
+        ref, rinf = oracle_cols(P, B, stop_rule=O.STOP_RR, tol=1e-18)
+    assert info.status == ils.OK
+    np.testing.assert_array_equal(iters, [i.outer_iters for i in rinf])
+    cols_close(host(X), ref, 1e-10)
+
+
+def test_prepared_reuse_and_subsets(fam, prep):
+    """Several solves on one prepared A: a column subset, then the full set
+    again; each matches the unprepared multi solve."""
+    P, Xs, B, A, Bd = fam
+    kw = dict(stop_rule=ils.STOP_XREF, tol=1e-9)
+    k = max(1, Xs.shape[1] // 3)
+    for cols in (slice(0, k), slice(0, Xs.shape[1])):
+        Bs = devA(B[:, cols])
+        Xr = devA(Xs[:, cols])
+        Xp, ip, itp = prep.solve_multi(Bs, x_ref=Xr, **kw)
+        Xm, im, itm = ils.sp_solve_multi(A, Bs, P.p, x_ref=Xr, **kw)
+        assert ip.status == im.status == ils.OK
+        np.testing.assert_array_equal(itp, itm)
+        cols_close(host(Xp), host(Xm), 1e-11)
+
+
+def test_prepared_errors():
+    P = W.dense_ils(60, 30, 20, ratio=0.5, seed=3)
+    Az = P.A.copy()
+    Az[:P.p, 4] = 0.0  # A1 rank deficient: A1^T A1 singular
+    with pytest.raises(ils.ILSError, match="positive definite|SPD"):
+        ils.SPPrepared(devA(Az), P.p)
+    An = P.A.copy()
+    An[7, 2] = np.nan
+    with pytest.raises(ils.ILSError, match="finite"):
+        ils.SPPrepared(devA(An), P.p)
+    pr = ils.SPPrepared(devA(P.A), P.p)
+    Bd = devA(P.b[:, None])
+    for kw in (dict(form=ils.FORM_CORRECTION), dict(precision=ils.PREC_MIXED)):
+        _, info, _ = pr.solve_multi(Bd, **kw)
+        assert info.status == ils.ERR_ARG
+    pr.close()
