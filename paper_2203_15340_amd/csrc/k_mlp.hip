@@ -11,7 +11,6 @@
 
 namespace ils {
 
-typedef short v4s __attribute__((ext_vector_type(4)));
 
 __device__ inline float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 // float -> bfloat16, round to nearest even (NaN stays NaN)
@@ -23,7 +22,9 @@ __device__ inline uint16_t f2bf(float f) {
 }
 
 // ------------------------------------------------------------------ GEMM
-// C (M x N) = op(A) op(B), K-sum in FP32 on v_mfma_f32_16x16x16_bf16.
+// C (M x N) = op(A) op(B), K-sum in FP32 on gfx950's v_mfma_f32_16x16x32_bf16
+// (8 bf16 per lane per operand: lanes 16g..16g+15 hold k = 8g..8g+7 of their
+// row or column, so one 16-byte LDS read feeds a whole 32-deep stage).
 //   TA = 0: A is M x K column-major, element (i, k) at A[i + k lda]
 //   TA = 1: A is stored K x M,       element (i, k) at A[k + i lda]
 //   TB = 0: B is K x N column-major, element (k, j) at B[k + j ldb]
@@ -34,7 +35,9 @@ __device__ inline uint16_t f2bf(float f) {
 // move as 16-byte vectors, the others are transposed on the way in.
 constexpr int kBT = 64;       // tile edge
 constexpr int kBK = 32;       // k per stage
-constexpr int kBLd = kBK + 4; // padded LDS row (bf16 elements), keeps 8-byte alignment
+constexpr int kBLd = kBK + 8; // padded LDS row (bf16 elements): 80 bytes, rows stay 16-byte aligned
+
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 // Load this thread's 8 elements of the 64 x 32 panel (operand rows
 // [r0, r0 + 64), k in [k0, k0 + 32)); `rows` bounds the operand's row index
@@ -107,18 +110,18 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(MlpGemmArgs g) {
       panel_fetch<TA == 1>(g.A, g.lda, g.M, g.K, i0, k0 + kBK, t, va);
       panel_fetch<TB == 0>(g.B, g.ldb, g.N, g.K, j0, k0 + kBK, t, vb);
     }
+    static_assert(kBK == 32, "one 16x16x32 step per stage");
+    {
+      v8bf fa[2], fb[2];
 #pragma unroll
-    for (int kk = 0; kk < kBK; kk += 16) {
-      v4s fa[2], fb[2];
+      for (int a = 0; a < 2; ++a) fa[a] = *(const v8bf*)&As[wr + a * 16 + lr][8 * lq];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) fa[a] = *(const v4s*)&As[wr + a * 16 + lr][kk + 4 * lq];
-#pragma unroll
-      for (int c = 0; c < 2; ++c) fb[c] = *(const v4s*)&Bs[wc + c * 16 + lr][kk + 4 * lq];
+      for (int c = 0; c < 2; ++c) fb[c] = *(const v8bf*)&Bs[wc + c * 16 + lr][8 * lq];
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int c = 0; c < 2; ++c)
-          acc[a][c] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fa[a], fb[c], acc[a][c], 0, 0, 0);
+          acc[a][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[a], fb[c], acc[a][c], 0, 0, 0);
     }
     __syncthreads();
   }
