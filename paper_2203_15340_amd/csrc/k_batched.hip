@@ -504,12 +504,23 @@ __device__ void solve_one(const BatchArgs& a, const BatchProblem& P, double* slo
   int status = ILS_OK;
   int64_t k = 0;
   double metric = 0.0;
+  // the test on x_k first when it does not need r_k (relative error, fixed
+  // count), so the iterate that ends the loop costs no pass over A; and
+  // r_0 = A^T J b at x_0 = 0 is the column pass's g
+  const bool r_first = a.stop_rule == ILS_STOP_RR;
   for (;; ++k) {
-    if (need_r) {
+    auto residual = [&]() {
+      if (!need_r) return;
+      if (k == 0 && !P.x0 && !paper) {
+        for (int j = t; j < n; j += NT) r[j] = g[j];
+        __syncthreads();
+        return;
+      }
       for (int j = t; j < n; j += NT) xs[j] = xk[j];
       __syncthreads();
       wg_residual(P.A, lda, p, q, n, P.b, r);
-    }
+    };
+    if (r_first) residual();
     double mp = 0.0;
     for (int j = t; j < n; j += NT) {
       if (a.stop_rule == ILS_STOP_XREF) {
@@ -526,6 +537,7 @@ __device__ void solve_one(const BatchArgs& a, const BatchProblem& P, double* slo
       status = a.stop_rule == ILS_STOP_FIXED ? ILS_OK : ILS_ERR_NO_CONVERGENCE;
       break;
     }
+    if (!r_first) residual();
     bool bad = false;
     {
       const double* v = paper ? xk : r;
