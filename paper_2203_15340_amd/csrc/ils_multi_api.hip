@@ -56,9 +56,20 @@ int multi_bufs(ils_handle* h, int64_t n, int64_t nrhs, bool need_g, bool rr, Mul
   return ILS_OK;
 }
 
+// Rows of A from which A^T J B takes the persistent kernel (long K).
+constexpr int64_t kAtjbPersMinRows = 2048;
+
+// Partial-tile scratch (doubles) atjb may use.
+size_t atjb_partials(int64_t p, int64_t q, int64_t n, int64_t nrhs) {
+  return p + q >= kAtjbPersMinRows ? gemm_tn_pers_partials(p + q, n, nrhs) : 0;
+}
+
 // A^T J B into G (n x nrhs, ldg): rows p.. of B enter negated (J = diag(I_p, -I_q)).
 void atjb(hipStream_t s, int64_t p, int64_t q, int64_t n, const double* A, int64_t lda, int64_t nrhs,
-          const double* B, int64_t ldb, double* G, int64_t ldg) {
+          const double* B, int64_t ldb, double* G, int64_t ldg, double* partials, size_t partial_doubles) {
+  if (p + q >= kAtjbPersMinRows &&
+      launch_gemm_tn_pers(s, p + q, p, n, nrhs, A, lda, B, ldb, partials, partial_doubles, G, ldg))
+    return;
   GemmTnArgs gb = {};
   gb.M = n;
   gb.N = nrhs;
@@ -262,7 +273,9 @@ extern "C" int ils_sp_solve_multi(ils_handle* h, int64_t p, int64_t q, int64_t n
   double *W, *H = nullptr, *Bt, *dinv;
   void* part;
   MultiBufs mb;
-  const size_t part_bytes = std::max(gram_partials_size(n, p), gram_partials_size(n, q)) * sizeof(double);
+  const size_t part_doubles =
+      std::max({gram_partials_size(n, p), gram_partials_size(n, q), atjb_partials(p, q, n, nrhs)});
+  const size_t part_bytes = part_doubles * sizeof(double);
   if ((st = h->need(kBufW, sizeof(double) * ldw * (2 * n + nrhs), (void**)&W)) ||
       (st = multi_bufs(h, n, nrhs, rr, rr, mb)) ||
       (rr && (st = h->need(kBufH, sizeof(double) * n * n, (void**)&H))) ||
@@ -278,10 +291,10 @@ extern "C" int ils_sp_solve_multi(ils_handle* h, int64_t p, int64_t q, int64_t n
   launch_gram_f64(s, q, n, A + p, lda, (double*)part, W + n * ldw, ldw);
   if (rr) launch_sub(s, n, W, ldw, W + n * ldw, ldw, H, n);
   if (rr) {
-    atjb(s, p, q, n, A, lda, nrhs, B, ldb, mb.Gm, n);
+    atjb(s, p, q, n, A, lda, nrhs, B, ldb, mb.Gm, n, (double*)part, part_doubles);
     launch_mat_copy(s, n, nrhs, mb.Gm, n, W + 2 * n * ldw, ldw);
   } else {
-    atjb(s, p, q, n, A, lda, nrhs, B, ldb, W + 2 * n * ldw, ldw);
+    atjb(s, p, q, n, A, lda, nrhs, B, ldb, W + 2 * n * ldw, ldw, (double*)part, part_doubles);
   }
   // [A1^T A1 | A2^T A2 | A^T J B] -> [I | B_sp | C]
   launch_gj(s, n, n + nrhs, W, ldw, dinv, &ds->bits);
@@ -385,13 +398,16 @@ extern "C" int ils_sp_prep_solve_multi(ils_sp_prep* pr, int64_t nrhs, const doub
   hipStream_t s = h->stream;
   const bool rr = o->stop_rule == ILS_STOP_RR;
   double* Cm;
+  void* part = nullptr;
   MultiBufs mb;
+  const size_t part_doubles = atjb_partials(p, q, n, nrhs);
   if ((st = multi_bufs(h, n, nrhs, true, rr, mb)) ||
-      (st = h->need(kBufMC, sizeof(double) * (size_t)n * (size_t)nrhs, (void**)&Cm)))
+      (st = h->need(kBufMC, sizeof(double) * (size_t)n * (size_t)nrhs, (void**)&Cm)) ||
+      (part_doubles && (st = h->need(kBufPart, part_doubles * sizeof(double), &part))))
     return fail_multi(info, st);
   HIPCHK(hipMemsetAsync(h->st, 0, sizeof(LoopState), s));
   if (h->timing()) HIPCHK(hipEventRecord(h->ev0, s));
-  atjb(s, p, q, n, pr->A, pr->lda, nrhs, B, ldb, mb.Gm, n);
+  atjb(s, p, q, n, pr->A, pr->lda, nrhs, B, ldb, mb.Gm, n, (double*)part, part_doubles);
   GemmTnArgs gc = {};  // C = P A^T J B (P symmetric, so P^T Y = P Y)
   gc.M = n;
   gc.N = nrhs;

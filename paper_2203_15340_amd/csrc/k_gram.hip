@@ -271,6 +271,12 @@ struct GramPJob {
   void* partials;    // (kXcds + 1) * (q W + L cmax) partial tiles of the kernel's type
   double *G0, *gv0, *G1, *gv1;
   int64_t ldg;
+  // rectangular product X^T J Y (rect != 0): A is X (n columns), Y has ny
+  // columns, tiles run over mt x nt (tile = ti + mt tj), and the reduction
+  // writes G0 = part 0 - part 1 (rows [0, p) minus rows [p, M))
+  int rect, mt, ny;
+  const void* Y;
+  int64_t ldy;
 };
 
 __device__ __host__ inline void pers_range(int64_t M, int x, int64_t& r0, int64_t& r1) {
@@ -333,8 +339,16 @@ void k_gram_pers(GramPJob job) {
   const int64_t u0 = (int64_t)j * LS / job.W, u1 = (int64_t)(j + 1) * LS / job.W;
   const T* A = (const T*)job.A;
   const T* vb = (const T*)job.vb;
-  const int64_t lda = job.lda;
+  const T* Y = (const T*)job.Y;
+  const int64_t lda = job.lda, ldy = job.ldy;
   const int n = job.n;
+  // column `col` of operand op (0: the tile's rows, 1: its columns), or null
+  // for a zero slot
+  auto opcol = [&](int op, int col) -> const T* {
+    if (job.rect && op == 1) return col < job.ny ? Y + (int64_t)col * ldy : nullptr;
+    if (col < n) return A + (int64_t)col * lda;
+    return (!job.rect && col == n) ? vb : nullptr;
+  };
 
   int mi = 0;
   for (int64_t u = u0; mi < job.q || u < u1;) {
@@ -356,7 +370,12 @@ void k_gram_pers(GramPJob job) {
       u = send;
     }
     int ti, tj;
-    tile_of(tile, ti, tj);
+    if (job.rect) {
+      ti = tile % job.mt;
+      tj = tile / job.mt;
+    } else {
+      tile_of(tile, ti, tj);
+    }
     // a diagonal tile loads its one panel twice, as every other tile loads
     // two: its workgroup then walks the rows in step with the rest instead of
     // running ahead (fetch 545 -> 452 MB per launch at 20000 x 1000)
@@ -397,8 +416,7 @@ void k_gram_pers(GramPJob job) {
         __syncthreads();
         for (int id = t; id < 2 * 64 * 8; id += 256) {
           const int op = id / (64 * 8), sl = (id / 8) % 64, qc = id % 8;
-          const int col = (op ? tj : ti) * 64 + sl;
-          const T* cp = col < n ? A + (int64_t)col * lda : (col == n ? vb : nullptr);
+          const T* cp = opcol(op, (op ? tj : ti) * 64 + sl);
           T* d = &L[0][op][sl * RS + ((qc ^ pers_swz(sl)) * RPC)];
 #pragma unroll
           for (int e = 0; e < RPC; ++e) {
@@ -426,12 +444,9 @@ void k_gram_pers(GramPJob job) {
           for (int i = 0; i < 2; ++i) {
             const int sl = (2 * w + i) * 8 + (lane >> 3);
             const int sig = (lane & 7) ^ pers_swz(sl);
-            const int col = (op ? tj : ti) * 64 + sl;
-            if (col < n) {
-              src[op][i] = A + (int64_t)col * lda + ka + RPC * sig;
-              step[op][i] = RS;
-            } else if (col == n && vb) {
-              src[op][i] = vb + ka + RPC * sig;
+            const T* cp = opcol(op, (op ? tj : ti) * 64 + sl);
+            if (cp) {
+              src[op][i] = cp + ka + RPC * sig;
               step[op][i] = RS;
             } else {
               src[op][i] = (const T*)g_zero16 + RPC * sig;
@@ -491,70 +506,93 @@ void k_gram_pers(GramPJob job) {
 template <typename T>
 __global__ __launch_bounds__(256) void k_gram_pers_fin(GramPJob job) {
   constexpr int RS = PersGeo<T>::RS;
-  __shared__ int slots[kXcds * kPersMaxShares];
-  __shared__ int nsl;
-  const int part = (int)blockIdx.y / job.T, tile = (int)blockIdx.y % job.T;
+  __shared__ int slots[2][kXcds * kPersMaxShares];
+  __shared__ int nsl[2];
+  // rectangular product: one block per tile adds part 0 and subtracts part 1
+  const int part = job.rect ? 0 : (int)blockIdx.y / job.T, tile = (int)blockIdx.y % job.T;
+  const int nlists = job.rect ? 2 : 1;
   if (threadIdx.x < 64) {
     const int lane = threadIdx.x;
-    const int64_t lo = part ? job.p : 0, hi = part ? job.M : job.p;
-    const bool main = tile < job.q * job.W;
-    const int lt = tile - job.q * job.W;
-    const int per = main ? 1 : job.cmax;  // pairs (XCD, share) per XCD
-    int base = 0;
-    for (int p0 = 0; p0 < kXcds * per; p0 += 64) {
-      const int pair = p0 + lane;
-      const int x = pair / per, c = pair % per;
-      int slot = -1;
-      if (x < kXcds) {
-        int64_t r0, r1;
-        pers_range(job.M, x, r0, r1);
-        const int64_t S = (r1 - r0 + RS - 1) / RS;
-        int64_t klo = r0, khi = r1;
-        bool ok = S > 0;
-        if (ok && !main) {
-          const int64_t LS = (int64_t)job.L * S;
-          const int j = pers_first((int64_t)lt * S, LS, job.W) + c;
-          ok = j < job.W;
-          if (ok) {
-            const int64_t u0 = (int64_t)j * LS / job.W, u1 = (int64_t)(j + 1) * LS / job.W;
-            const int64_t a = u0 > (int64_t)lt * S ? u0 : (int64_t)lt * S;
-            const int64_t b = u1 < (int64_t)(lt + 1) * S ? u1 : (int64_t)(lt + 1) * S;
-            ok = a < b;
-            klo = r0 + (a - (int64_t)lt * S) * RS;
-            khi = r0 + (b - (int64_t)lt * S) * RS;
-            if (khi > r1) khi = r1;
+    for (int li = 0; li < nlists; ++li) {
+      const int pt = job.rect ? li : part;
+      const int64_t lo = pt ? job.p : 0, hi = pt ? job.M : job.p;
+      const bool main = tile < job.q * job.W;
+      const int lt = tile - job.q * job.W;
+      const int per = main ? 1 : job.cmax;  // pairs (XCD, share) per XCD
+      int base = 0;
+      for (int p0 = 0; p0 < kXcds * per; p0 += 64) {
+        const int pair = p0 + lane;
+        const int x = pair / per, c = pair % per;
+        int slot = -1;
+        if (x < kXcds) {
+          int64_t r0, r1;
+          pers_range(job.M, x, r0, r1);
+          const int64_t S = (r1 - r0 + RS - 1) / RS;
+          int64_t klo = r0, khi = r1;
+          bool ok = S > 0;
+          if (ok && !main) {
+            const int64_t LS = (int64_t)job.L * S;
+            const int j = pers_first((int64_t)lt * S, LS, job.W) + c;
+            ok = j < job.W;
+            if (ok) {
+              const int64_t u0 = (int64_t)j * LS / job.W, u1 = (int64_t)(j + 1) * LS / job.W;
+              const int64_t a = u0 > (int64_t)lt * S ? u0 : (int64_t)lt * S;
+              const int64_t b = u1 < (int64_t)(lt + 1) * S ? u1 : (int64_t)(lt + 1) * S;
+              ok = a < b;
+              klo = r0 + (a - (int64_t)lt * S) * RS;
+              khi = r0 + (b - (int64_t)lt * S) * RS;
+              if (khi > r1) khi = r1;
+            }
+          }
+          if (ok && (klo > lo ? klo : lo) < (khi < hi ? khi : hi)) {
+            const int vx = pers_vx(x, pt, r0, r1, job.p);
+            slot = (int)(main ? pers_slot_main(vx, tile, job.q, job.W)
+                              : pers_slot_left(vx, lt, c, job.q, job.W, job.L, job.cmax));
           }
         }
-        if (ok && (klo > lo ? klo : lo) < (khi < hi ? khi : hi)) {
-          const int vx = pers_vx(x, part, r0, r1, job.p);
-          slot = (int)(main ? pers_slot_main(vx, tile, job.q, job.W)
-                            : pers_slot_left(vx, lt, c, job.q, job.W, job.L, job.cmax));
-        }
+        const uint64_t m = __ballot(slot >= 0);
+        if (slot >= 0) slots[li][base + __popcll(m & ((1ull << lane) - 1))] = slot;
+        base += __popcll(m);
       }
-      const uint64_t m = __ballot(slot >= 0);
-      if (slot >= 0) slots[base + __popcll(m & ((1ull << lane) - 1))] = slot;
-      base += __popcll(m);
+      if (lane == 0) nsl[li] = base;
     }
-    if (lane == 0) nsl = base;
   }
   __syncthreads();
   int ti, tj;
-  tile_of(tile, ti, tj);
+  if (job.rect) {
+    ti = tile % job.mt;
+    tj = tile / job.mt;
+  } else {
+    tile_of(tile, ti, tj);
+  }
   const int e = blockIdx.x * 256 + threadIdx.x;
   const int row = e / 64, col = e % 64;
   const int i = ti * 64 + row, jj = tj * 64 + col;
-  if (i >= job.nc || jj >= job.nc || (ti == tj && row < col) || (i == job.n && jj == job.n)) return;
-  const int cnt = nsl;
-  double sacc = 0.0;
-  int q = 0;
-  for (; q + 8 <= cnt; q += 8) {
-    double v[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) v[k] = (double)((const T*)job.partials)[(size_t)slots[q + k] * 4096 + e];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) sacc += v[k];
+  if (job.rect) {
+    if (i >= job.n || jj >= job.ny) return;
+  } else if (i >= job.nc || jj >= job.nc || (ti == tj && row < col) || (i == job.n && jj == job.n)) {
+    return;
   }
-  for (; q < cnt; ++q) sacc += (double)((const T*)job.partials)[(size_t)slots[q] * 4096 + e];
+  const T* partials = (const T*)job.partials;
+  auto add_list = [&](int li) {
+    const int cnt = nsl[li];
+    double sacc = 0.0;
+    int q = 0;
+    for (; q + 8 <= cnt; q += 8) {
+      double v[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) v[k] = (double)partials[(size_t)slots[li][q + k] * 4096 + e];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) sacc += v[k];
+    }
+    for (; q < cnt; ++q) sacc += (double)partials[(size_t)slots[li][q] * 4096 + e];
+    return sacc;
+  };
+  if (job.rect) {
+    job.G0[i + (int64_t)jj * job.ldg] = add_list(0) - add_list(1);
+    return;
+  }
+  const double sacc = add_list(0);
   double* G = part ? job.G1 : job.G0;
   double* gv = part ? job.gv1 : job.gv0;
   if (i == job.n) {
@@ -603,17 +641,22 @@ static int pers_cmax(int64_t M, int L, int W, int RS) {
 struct PersShape {
   int T, W, q, L, cmax;
 };
+static PersShape pers_shape_t(int T, int64_t M, int RS);
 static PersShape pers_shape(int64_t nc, int64_t M, int RS) {
+  const int nt = (int)((nc + 63) / 64);
+  return pers_shape_t(nt * (nt + 1) / 2, M, RS);
+}
+// The plan for T tiles over M rows in stages of RS rows.
+static PersShape pers_shape_t(int T, int64_t M, int RS) {
   static std::mutex mu;
   static std::map<std::tuple<int64_t, int64_t, int, int>, int> cache;
   PersShape sh;
-  const int nt = (int)((nc + 63) / 64);
-  sh.T = nt * (nt + 1) / 2;
+  sh.T = T;
   sh.W = kPersWpc * (device_cus() / kXcds);
   sh.q = sh.T / sh.W;
   sh.L = sh.T - sh.q * sh.W;
   std::lock_guard<std::mutex> lk(mu);
-  auto key = std::make_tuple(nc, M, sh.W, RS);
+  auto key = std::make_tuple((int64_t)T, M, sh.W, RS);
   auto it = cache.find(key);
   if (it == cache.end()) {
     if (cache.size() > 256) cache.clear();
@@ -808,7 +851,7 @@ static void gram_run(hipStream_t s, int64_t K, int64_t n, const double* A, int64
                      double* G1 = nullptr, double* gv1 = nullptr) {
   if (std::is_same<T, double>::value && cfg.kind == kGramPersistent && pers_aligned<double>(A, lda, vb) &&
       (K1 < 0 || (A1 == A + K && (vb ? vb1 == vb + K : vb1 == nullptr)))) {
-    GramPJob pj;
+    GramPJob pj = {};
     pj.A = A;
     pj.lda = lda;
     pj.vb = vb;
@@ -865,7 +908,7 @@ static void gram_run(hipStream_t s, int64_t K, int64_t n, const double* A, int64
 // columns) with the persistent kernel.
 static void gram_f32_pers(hipStream_t s, int64_t K, int64_t n, const float* Af, int64_t ldaf, float* partials,
                           double* G, int64_t ldg, hipEvent_t mid) {
-  GramPJob pj;
+  GramPJob pj = {};
   pj.A = Af;
   pj.lda = ldaf;
   pj.vb = nullptr;
@@ -888,6 +931,54 @@ static void gram_f32_pers(hipStream_t s, int64_t K, int64_t n, const float* Af, 
   hipLaunchKernelGGL(k_gram_pers<float>, dim3(kXcds * sh.W), dim3(256), 0, s, pj);
   if (mid) (void)hipEventRecord(mid, s);
   hipLaunchKernelGGL(k_gram_pers_fin<float>, dim3(64 * 64 / 256, sh.T), dim3(256), 0, s, pj);
+}
+
+// C = X^T J Y with J = diag(I_kneg, -I_{K-kneg}) (X: K x M, Y: K x N,
+// column-major, K contiguous) on the persistent kernel: 64 x 64 tiles of C
+// over the same per-XCD row ranges, the two signs as the kernel's two row
+// parts, subtracted in the reduction.  False (nothing queued) when the
+// operands are not 16-byte aligned with even leading dimensions, the plan
+// needs more shares per tile than the reduction lists, or `partials` is
+// smaller than gemm_tn_pers_partials.
+static int rect_tiles(int64_t M, int64_t N) { return (int)(((M + 63) / 64) * ((N + 63) / 64)); }
+
+size_t gemm_tn_pers_partials(int64_t K, int64_t M, int64_t N) {
+  const PersShape sh = pers_shape_t(rect_tiles(M, N), K, PersGeo<double>::RS);
+  return ((size_t)(kXcds + 1) * ((size_t)sh.q * sh.W + (size_t)sh.L * sh.cmax)) * 4096;
+}
+
+bool launch_gemm_tn_pers(hipStream_t s, int64_t K, int64_t kneg, int64_t M, int64_t N, const double* X,
+                         int64_t ldx, const double* Y, int64_t ldy, double* partials, size_t partial_doubles,
+                         double* C, int64_t ldc) {
+  if (K < 1 || M < 1 || N < 1 || !pers_aligned<double>(X, ldx, nullptr) || !pers_aligned<double>(Y, ldy, nullptr))
+    return false;
+  const int T = rect_tiles(M, N);
+  const PersShape sh = pers_shape_t(T, K, PersGeo<double>::RS);
+  if (sh.cmax > kPersMaxShares || gemm_tn_pers_partials(K, M, N) > partial_doubles) return false;
+  GramPJob pj = {};
+  pj.A = X;
+  pj.lda = ldx;
+  pj.vb = nullptr;
+  pj.M = K;
+  pj.p = kneg < K ? kneg : K;
+  pj.n = (int)M;
+  pj.nc = (int)M;
+  pj.T = sh.T;
+  pj.W = sh.W;
+  pj.q = sh.q;
+  pj.L = sh.L;
+  pj.cmax = sh.cmax;
+  pj.partials = partials;
+  pj.G0 = C;
+  pj.ldg = ldc;
+  pj.rect = 1;
+  pj.mt = (int)((M + 63) / 64);
+  pj.ny = (int)N;
+  pj.Y = Y;
+  pj.ldy = ldy;
+  hipLaunchKernelGGL(k_gram_pers<double>, dim3(kXcds * sh.W), dim3(256), 0, s, pj);
+  hipLaunchKernelGGL(k_gram_pers_fin<double>, dim3(64 * 64 / 256, sh.T), dim3(256), 0, s, pj);
+  return true;
 }
 
 // Column-major FP32 copy of rows [0, K) of A with leading dimension ldaf.
