@@ -32,10 +32,11 @@ def banner(msg):
 
 
 # (p, q, n, nrhs): one tile, ragged tiles in both directions, many columns;
-# the last two have m >= 2048, where A^T J B runs on the resident per-XCD
-# kernel (even m: aligned columns) or falls back to the tiled product (odd m)
+# the last three have m >= 2048, where A^T J B runs on the resident per-XCD
+# kernel (even m: aligned columns; q = 0: no negated rows) or falls back to
+# the tiled product (odd m)
 CASES = [(500, 100, 50, 7), (700, 90, 150, 70), (1100, 130, 200, 130), (300, 0, 77, 65),
-         (2600, 300, 130, 33), (2601, 450, 100, 66)]
+         (2600, 300, 130, 33), (2601, 450, 100, 66), (2400, 0, 90, 20)]
 
 
 @pytest.fixture(scope="module", params=CASES, ids=lambda c: "p%d_q%d_n%d_r%d" % c)
