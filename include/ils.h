@@ -353,6 +353,16 @@ int ils_ws_adam(ils_ws* net, const float* grad, double lr);
 int ils_gram(ils_handle* h, int64_t r0, int64_t r1, int64_t n, const double* A, int64_t lda,
              double* G, int64_t ldg, int32_t precision);
 
+/* G = A^T J B = A1^T B1 - A2^T B2 for many right-hand sides at once (the
+ * A^T J b of Alg. 1 step 4 for every column of B; p + q rows, A m x n with
+ * lda >= m, B m x nrhs with ldb >= m, G n x nrhs column-major with
+ * ldg >= n; FP64).  For m >= 2048 with 16-byte aligned A and B and even lda,
+ * ldb it runs on the resident per-XCD kernel of the Gram products
+ * (rectangular 64 x 64 tiles, the two signs as two row parts subtracted in
+ * the reduction), otherwise on the tiled product.  Waits for the result. */
+int ils_atjb(ils_handle* h, int64_t p, int64_t q, int64_t n, const double* A, int64_t lda, int64_t nrhs,
+             const double* B, int64_t ldb, double* G, int64_t ldg);
+
 /* g = A^T J b = A1^T b1 - A2^T b2 and c_j = ||A1_(j)||^2 (Alg. 1 step 4,
  * Alg. 2 steps 3, 8, 10). */
 int ils_colpass(ils_handle* h, int64_t p, int64_t q, int64_t n, const double* A, int64_t lda,

@@ -32,7 +32,7 @@ EXPORTS = ("ils_create", "ils_destroy", "ils_opts_default", "ils_status_string",
            "ils_rk_solve", "ils_rgs_solve", "ils_gram", "ils_colpass", "ils_residual", "ils_residual_noalloc",
            "ils_spd_solve", "ils_rk_indices", "ils_scd_subsets", "ils_set_profiling",
            "ils_get_phase_times", "ils_sp_solve_batched", "ils_sp_solve_multi", "ils_rk_solve_multi", "ils_sp_prepare",
-           "ils_sp_prep_solve_multi", "ils_sp_prep_destroy", "ils_ws_create",
+           "ils_sp_prep_solve_multi", "ils_sp_prep_destroy", "ils_atjb", "ils_ws_create",
            "ils_ws_destroy", "ils_ws_train", "ils_ws_infer", "ils_ws_save", "ils_ws_load",
            "ils_ws_nparams", "ils_ws_get_params", "ils_ws_set_params", "ils_ws_forward", "ils_ws_grad",
            "ils_ws_adam", "ils_csr_create", "ils_csr_destroy", "ils_sp_solve_csr", "ils_rk_solve_csr",
@@ -113,6 +113,7 @@ def load_library(path: str = LIB_PATH):
         "ils_sp_prepare": (C.c_int, [P, I64, I64, I64, P, I64, C.POINTER(P)]),
         "ils_sp_prep_solve_multi": (C.c_int, [P, I64, P, I64, P, I64, P, I64, P, P, P]),
         "ils_sp_prep_destroy": (C.c_int, [P]),
+        "ils_atjb": (C.c_int, [P, I64, I64, I64, P, I64, I64, P, I64, P, I64]),
         "ils_ws_create": (C.c_int, [P, I64, I64, I64, P, I64, U64, C.POINTER(P)]),
         "ils_ws_destroy": (C.c_int, [P]),
         "ils_ws_train": (C.c_int, [P, I64, P, I64, P, I64, I32, I64, C.c_double, P]),
@@ -417,6 +418,17 @@ def gram(A, r0, r1, precision=PREC_FP64):
     G = torch.empty(n, n, dtype=torch.float64, device=A.device).t()
     _rc(load_library().ils_gram(handle(A.device), r0, r1, n, _ptr(A), _ld(A), _ptr(G), n,
                                 precision), "ils_gram")
+    return G
+
+
+def atjb(A, B, p):
+    """A^T J B (n x nrhs, column-major float64) for the columns of B."""
+    torch = _torch()
+    m, n = A.shape
+    nrhs = B.shape[1]
+    G = torch.empty((nrhs, n), dtype=torch.float64, device=A.device).t()
+    _rc(load_library().ils_atjb(handle(A.device), p, m - p, n, _ptr(A), _ld(A), nrhs, _ptr(B), _ld(B),
+                                _ptr(G), n), "ils_atjb")
     return G
 
 

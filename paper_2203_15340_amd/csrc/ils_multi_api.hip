@@ -257,6 +257,22 @@ int check_multi(int64_t m, int64_t n, int64_t nrhs, int64_t ldb, int64_t ldx, co
 
 }  // namespace
 
+extern "C" int ils_atjb(ils_handle* h, int64_t p, int64_t q, int64_t n, const double* A, int64_t lda,
+                        int64_t nrhs, const double* B, int64_t ldb, double* G, int64_t ldg) {
+  const int64_t m = p + q;
+  if (!h || !A || !B || !G || n < 1 || p < 0 || q < 0 || m < 1 || nrhs < 1 || lda < m || ldb < m || ldg < n)
+    return ILS_ERR_ARG;
+  HIPCHK(hipSetDevice(h->device));
+  const size_t part_doubles = atjb_partials(p, q, n, nrhs);
+  void* part = nullptr;
+  int st;
+  if (part_doubles && (st = h->need(kBufPart, part_doubles * sizeof(double), &part))) return st;
+  atjb(h->stream, p, q, n, A, lda, nrhs, B, ldb, G, ldg, (double*)part, part_doubles);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return ILS_OK;
+}
+
 extern "C" int ils_sp_solve_multi(ils_handle* h, int64_t p, int64_t q, int64_t n, const double* A,
                                   int64_t lda, int64_t nrhs, const double* B, int64_t ldb,
                                   const double* X0, int64_t ldx0, double* X, int64_t ldx,

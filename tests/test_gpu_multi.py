@@ -208,3 +208,26 @@ def test_prepared_errors():
         _, info, _ = pr.solve_multi(Bd, **kw)
         assert info.status == ils.ERR_ARG
     pr.close()
+
+
+# ------------------------------------------------------------------ A^T J B
+ATJB = [(2600, 300, 130, 33), (2601, 450, 100, 66), (3000, 0, 200, 70), (100, 3000, 64, 64),
+        (1500, 200, 50, 7), (18000, 2000, 1000, 130)]
+
+
+@pytest.mark.parametrize("shape", ATJB, ids=lambda c: "p%d_q%d_n%d_r%d" % c)
+def test_atjb_matches_oracle(shape):
+    """ils_atjb on the resident kernel (even m >= 2048, including q = 0 and a
+    mostly negated A), its fallback (odd m) and the tiled path (m < 2048),
+    each column against the oracle's A^T J (b - A 0) with a componentwise
+    bound: a length-m sum in any order, |err| <= m u (|A|^T |B|)."""
+    p, q, n, r = shape
+    banner(f"atjb p={p} q={q} n={n} nrhs={r}")
+    rng = np.random.default_rng(p + q + n + r)
+    A = np.asfortranarray(rng.standard_normal((p + q, n)))
+    B = np.asfortranarray(rng.standard_normal((p + q, r)))
+    G = host(ils.atjb(devA(A), devA(B), p))
+    zero = np.zeros(n)
+    ref = np.stack([O.residual(A, B[:, j], p, zero) for j in range(r)], axis=1)
+    bound = (p + q) * 2.0 ** -52 * (np.abs(A).T @ np.abs(B)) + 1e-300
+    assert np.all(np.abs(G - ref) <= bound), np.max(np.abs(G - ref) / bound)
