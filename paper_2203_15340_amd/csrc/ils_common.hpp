@@ -188,14 +188,6 @@ int64_t gram_f32_copy_ld(int64_t K);
 bool gram_f32_uses_copy(int64_t n, int64_t K);
 void launch_gram_f32_copy(hipStream_t s, int64_t K, int64_t n, const double* A, int64_t lda, float* Af,
                           float* partials, double* G, int64_t ldg, hipEvent_t mid = nullptr);
-// C = X^T J Y (J = diag(I_kneg, -I_{K-kneg}); X K x M, Y K x N, column-major)
-// on the persistent Gram kernel's plan, for long K; false (nothing queued)
-// when it does not apply (alignment, plan, or partials smaller than
-// gemm_tn_pers_partials(K, M, N) doubles).
-size_t gemm_tn_pers_partials(int64_t K, int64_t M, int64_t N);
-bool launch_gemm_tn_pers(hipStream_t s, int64_t K, int64_t kneg, int64_t M, int64_t N, const double* X,
-                         int64_t ldx, const double* Y, int64_t ldy, double* partials, size_t partial_doubles,
-                         double* C, int64_t ldc);
 // The same product when Af already holds the copy (written by the column
 // pass): only the persistent kernel and its reduction are queued.
 void launch_gram_f32_on_copy(hipStream_t s, int64_t K, int64_t n, const float* Af, float* partials, double* G,
@@ -302,6 +294,12 @@ struct GemmTnArgs {
   int64_t ldkeep;
 };
 void launch_gemm_tn(hipStream_t s, const GemmTnArgs& g);
+// The same product on the persistent Gram kernel's plan (per-XCD row ranges,
+// partial tiles reduced with the epilogue; k_gram.hip); false (nothing
+// queued) when it does not apply (alignment, plan, or partials smaller than
+// gemm_tn_pers_partials(K, M, N) doubles).
+size_t gemm_tn_pers_partials(int64_t K, int64_t M, int64_t N);
+bool launch_gemm_tn_pers(hipStream_t s, const GemmTnArgs& g, double* partials, size_t partial_doubles);
 
 // Multi-right-hand-side helpers (k_multi.hip).
 void launch_mat_copy(hipStream_t s, int64_t rows, int64_t cols, const double* X, int64_t ldx,

@@ -56,20 +56,33 @@ int multi_bufs(ils_handle* h, int64_t n, int64_t nrhs, bool need_g, bool rr, Mul
   return ILS_OK;
 }
 
-// Rows of A from which A^T J B takes the persistent kernel (long K).
+// Products that take the persistent kernel: long contractions (A^T J B over
+// the rows of A), and the n x n products of the outer steps once there are
+// enough tiles to fill the grid.
 constexpr int64_t kAtjbPersMinRows = 2048;
+constexpr int64_t kStepPersMinK = 512;
+constexpr int64_t kStepPersMinTiles = 64;
 
-// Partial-tile scratch (doubles) atjb may use.
+bool step_pers(int64_t n, int64_t nrhs) {
+  return n >= kStepPersMinK && ((n + 63) / 64) * ((nrhs + 63) / 64) >= kStepPersMinTiles;
+}
+
+// Partial-tile scratch (doubles) the products of a solve may use.
 size_t atjb_partials(int64_t p, int64_t q, int64_t n, int64_t nrhs) {
   return p + q >= kAtjbPersMinRows ? gemm_tn_pers_partials(p + q, n, nrhs) : 0;
+}
+size_t step_partials(int64_t n, int64_t nrhs) { return step_pers(n, nrhs) ? gemm_tn_pers_partials(n, n, nrhs) : 0; }
+
+// C = alpha X^T S Y + beta C0 on the persistent kernel where `pers` holds and
+// it applies, else on the tiled product.
+void gemm(hipStream_t s, const GemmTnArgs& g, bool pers, double* partials, size_t partial_doubles) {
+  if (pers && partials && launch_gemm_tn_pers(s, g, partials, partial_doubles)) return;
+  launch_gemm_tn(s, g);
 }
 
 // A^T J B into G (n x nrhs, ldg): rows p.. of B enter negated (J = diag(I_p, -I_q)).
 void atjb(hipStream_t s, int64_t p, int64_t q, int64_t n, const double* A, int64_t lda, int64_t nrhs,
           const double* B, int64_t ldb, double* G, int64_t ldg, double* partials, size_t partial_doubles) {
-  if (p + q >= kAtjbPersMinRows &&
-      launch_gemm_tn_pers(s, p + q, p, n, nrhs, A, lda, B, ldb, partials, partial_doubles, G, ldg))
-    return;
   GemmTnArgs gb = {};
   gb.M = n;
   gb.N = nrhs;
@@ -83,7 +96,7 @@ void atjb(hipStream_t s, int64_t p, int64_t q, int64_t n, const double* A, int64
   gb.beta = 0.0;
   gb.C = G;
   gb.ldc = ldg;
-  launch_gemm_tn(s, gb);
+  gemm(s, gb, p + q >= kAtjbPersMinRows, partials, partial_doubles);
 }
 
 // Alg. 1 step 6 for every column: X_{k+1} = B X_k + C (Bt = B^T, n x n;
@@ -93,7 +106,9 @@ void atjb(hipStream_t s, int64_t p, int64_t q, int64_t n, const double* A, int64
 // reset by the caller, which also holds h->ev0 when timing.
 int multi_iterate(ils_handle* h, int64_t n, int64_t nrhs, const double* Bt, const double* Cm, int64_t ldc,
                   const double* H, const MultiBufs& mb, const double* X0, int64_t ldx0, double* X, int64_t ldx,
-                  const ils_opts* o, int64_t* iters_out, ils_info* info) {
+                  const ils_opts* o, int64_t* iters_out, ils_info* info, double* partials,
+                  size_t partial_doubles) {
+  const bool pers = step_pers(n, nrhs);
   hipStream_t s = h->stream;
   LoopState* ds = h->st;
   const bool rr = o->stop_rule == ILS_STOP_RR;
@@ -162,7 +177,7 @@ int multi_iterate(ils_handle* h, int64_t n, int64_t nrhs, const double* Bt, cons
     if (!fixed) {
       if (rr) {
         gr.Y = cur;
-        launch_gemm_tn(s, gr);
+        gemm(s, gr, pers, partials, partial_doubles);
       }
       ma.V = rr ? mb.R : cur;
       HIPCHK(hipMemsetAsync(&ds->nactive, 0, sizeof(int), s));
@@ -187,7 +202,7 @@ int multi_iterate(ils_handle* h, int64_t n, int64_t nrhs, const double* Bt, cons
     gu.Y = cur;
     gu.C = nxt;
     gu.keep = cur;
-    launch_gemm_tn(s, gu);
+    gemm(s, gu, pers, partials, partial_doubles);
     std::swap(cur, nxt);
   }
   launch_mat_copy(s, n, nrhs, cur, n, X, ldx);
@@ -289,8 +304,8 @@ extern "C" int ils_sp_solve_multi(ils_handle* h, int64_t p, int64_t q, int64_t n
   double *W, *H = nullptr, *Bt, *dinv;
   void* part;
   MultiBufs mb;
-  const size_t part_doubles =
-      std::max({gram_partials_size(n, p), gram_partials_size(n, q), atjb_partials(p, q, n, nrhs)});
+  const size_t part_doubles = std::max({gram_partials_size(n, p), gram_partials_size(n, q),
+                                        atjb_partials(p, q, n, nrhs), step_partials(n, nrhs)});
   const size_t part_bytes = part_doubles * sizeof(double);
   if ((st = h->need(kBufW, sizeof(double) * ldw * (2 * n + nrhs), (void**)&W)) ||
       (st = multi_bufs(h, n, nrhs, rr, rr, mb)) ||
@@ -315,7 +330,8 @@ extern "C" int ils_sp_solve_multi(ils_handle* h, int64_t p, int64_t q, int64_t n
   // [A1^T A1 | A2^T A2 | A^T J B] -> [I | B_sp | C]
   launch_gj(s, n, n + nrhs, W, ldw, dinv, &ds->bits);
   launch_transpose(s, n, n, W + n * ldw, ldw, Bt, n);
-  return multi_iterate(h, n, nrhs, Bt, W + 2 * n * ldw, ldw, H, mb, X0, ldx0, X, ldx, o, iters_out, info);
+  return multi_iterate(h, n, nrhs, Bt, W + 2 * n * ldw, ldw, H, mb, X0, ldx0, X, ldx, o, iters_out, info,
+                       (double*)part, part_doubles);
 }
 
 // ------------------------------------------------------------------ prepared A
@@ -416,7 +432,8 @@ extern "C" int ils_sp_prep_solve_multi(ils_sp_prep* pr, int64_t nrhs, const doub
   double* Cm;
   void* part = nullptr;
   MultiBufs mb;
-  const size_t part_doubles = atjb_partials(p, q, n, nrhs);
+  const size_t part_doubles = std::max({atjb_partials(p, q, n, nrhs), step_partials(n, nrhs),
+                                        step_pers(n, nrhs) ? gemm_tn_pers_partials(n, n, nrhs) : (size_t)0});
   if ((st = multi_bufs(h, n, nrhs, true, rr, mb)) ||
       (st = h->need(kBufMC, sizeof(double) * (size_t)n * (size_t)nrhs, (void**)&Cm)) ||
       (part_doubles && (st = h->need(kBufPart, part_doubles * sizeof(double), &part))))
@@ -437,6 +454,7 @@ extern "C" int ils_sp_prep_solve_multi(ils_sp_prep* pr, int64_t nrhs, const doub
   gc.beta = 0.0;
   gc.C = Cm;
   gc.ldc = n;
-  launch_gemm_tn(s, gc);
-  return multi_iterate(h, n, nrhs, pr->Bt(), Cm, n, pr->H(), mb, X0, ldx0, X, ldx, o, iters_out, info);
+  gemm(s, gc, step_pers(n, nrhs), (double*)part, part_doubles);
+  return multi_iterate(h, n, nrhs, pr->Bt(), Cm, n, pr->H(), mb, X0, ldx0, X, ldx, o, iters_out, info,
+                       (double*)part, part_doubles);
 }

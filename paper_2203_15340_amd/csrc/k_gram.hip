@@ -259,6 +259,8 @@ constexpr int kPersWpc = kGramPersistentWpc;  // resident workgroups per CU (32 
 constexpr int kPersAlign = 16;  // row ranges start on multiples of 16 rows
 constexpr int kPersMaxShares = 64;  // shares per (leftover tile, XCD) the reduction lists
 
+enum { kGramTri = 0, kGramRect = 1, kGramWhole = 2 };  // products of the persistent kernel
+
 struct GramPJob {
   const void* A;     // row 0 of the rows [0, M) (double, or float for the FP32 kind)
   int64_t lda;
@@ -271,12 +273,22 @@ struct GramPJob {
   void* partials;    // (kXcds + 1) * (q W + L cmax) partial tiles of the kernel's type
   double *G0, *gv0, *G1, *gv1;
   int64_t ldg;
-  // rectangular product X^T J Y (rect != 0): A is X (n columns), Y has ny
-  // columns, tiles run over mt x nt (tile = ti + mt tj), and the reduction
-  // writes G0 = part 0 - part 1 (rows [0, p) minus rows [p, M))
-  int rect, mt, ny;
+  // rectangular products X^T J Y: A is X (n columns), Y has ny columns,
+  // tiles run over mt x nt (tile = ti + mt tj), and the reduction writes
+  // G0 = part 0 - part 1 (rows [0, p) minus rows [p, M))
+  int mt, ny;
   const void* Y;
   int64_t ldy;
+  // rectangular epilogue: C = alpha (part 0 - part 1) + beta C0 on columns j
+  // with active[j] (or all when active is null); other columns get keep[:, j]
+  // (or are left as they are when keep is null), and a tile whose columns are
+  // all inactive is not computed
+  double alpha, beta;
+  const double* C0;
+  int64_t ldc0;
+  const int* active;
+  const double* keep;
+  int64_t ldkeep;
 };
 
 __device__ __host__ inline void pers_range(int64_t M, int x, int64_t& r0, int64_t& r1) {
@@ -320,18 +332,26 @@ struct PersGeo {
 
 __device__ inline int pers_swz(int s) { return (s >> 1) & 7; }
 
-template <typename T>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kPersWpc)))
+// (the whole-range launch runs up to one workgroup per tile, 2 per CU at the
+// shapes it takes, so it may use the registers of 2 waves per SIMD)
+template <typename T, int R>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(R == kGramWhole ? 2 : kPersWpc)))
 void k_gram_pers(GramPJob job) {
+  // R: kind of product, fixed at compile time so each instance carries only
+  // its own code (kGramTri: lower tiles of A^T A with an optional border
+  // column, partial tiles; kGramRect: X^T J Y, partial tiles; kGramWhole:
+  // X^T Y, one workgroup per tile over all rows, C written directly)
+  constexpr bool rect = R != kGramTri, whole = R == kGramWhole;
   typedef typename Mma<T>::acc_t acc_t;
   constexpr int RPC = PersGeo<T>::RPC, RS = PersGeo<T>::RS;
   __shared__ __attribute__((aligned(16))) T L[2][2][64 * RS];  // [stage][operand][slot * RS + row]
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
   const int lr = lane & 15;
-  const int x = (int)(blockIdx.x % kXcds), j = (int)(blockIdx.x / kXcds);
-  int64_t r0, r1;
-  pers_range(job.M, x, r0, r1);
+  // whole-range launch: one workgroup per tile over all rows, no partials
+  const int x = whole ? 0 : (int)(blockIdx.x % kXcds), j = whole ? (int)blockIdx.x : (int)(blockIdx.x / kXcds);
+  int64_t r0 = 0, r1 = job.M;
+  if (!whole) pers_range(job.M, x, r0, r1);
   const int64_t S = (r1 - r0 + RS - 1) / RS;
   if (S == 0) return;
   const int64_t LS = (int64_t)job.L * S;
@@ -345,9 +365,9 @@ void k_gram_pers(GramPJob job) {
   // column `col` of operand op (0: the tile's rows, 1: its columns), or null
   // for a zero slot
   auto opcol = [&](int op, int col) -> const T* {
-    if (job.rect && op == 1) return col < job.ny ? Y + (int64_t)col * ldy : nullptr;
+    if (rect && op == 1) return col < job.ny ? Y + (int64_t)col * ldy : nullptr;
     if (col < n) return A + (int64_t)col * lda;
-    return (!job.rect && col == n) ? vb : nullptr;
+    return (!rect && col == n) ? vb : nullptr;
   };
 
   int mi = 0;
@@ -370,9 +390,13 @@ void k_gram_pers(GramPJob job) {
       u = send;
     }
     int ti, tj;
-    if (job.rect) {
+    if (rect) {
       ti = tile % job.mt;
       tj = tile / job.mt;
+      if (job.active) {
+        const int col = tj * 64 + (t & 63);
+        if (!__syncthreads_or(t < 64 && col < job.ny && job.active[col])) continue;
+      }
     } else {
       tile_of(tile, ti, tj);
     }
@@ -481,20 +505,47 @@ void k_gram_pers(GramPJob job) {
       }
       const int64_t kt = ka + nfull * RS;
       if (kt < kend) reg_stage(kt, kend);
-      const int vx = pers_vx(x, part, r0, r1, job.p);
-      T* P = (T*)job.partials + (main ? pers_slot_main(vx, tile, job.q, job.W)
-                                      : pers_slot_left(vx, tile - job.q * job.W, c, job.q, job.W, job.L, job.cmax)) *
-                                    4096;
+      if (whole) {
+        // the tile's final value with the rectangular epilogue
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+        for (int cc = 0; cc < 2; ++cc) {
+          const int jj = tj * 64 + wc + cc * 16 + lr;
+          if (jj >= job.ny) continue;
+          const bool live = !job.active || job.active[jj];
+          if (!live && !job.keep) continue;
 #pragma unroll
-        for (int cc = 0; cc < 2; ++cc)
+          for (int a = 0; a < 2; ++a)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int row = wr + a * 16 + Mma<T>::row(lane, v);
-            const int col = wc + cc * 16 + lr;
-            P[row * 64 + col] = acc[a][cc][v];
-          }
+            for (int v = 0; v < 4; ++v) {
+              const int i = ti * 64 + wr + a * 16 + Mma<T>::row(lane, v);
+              if (i >= n) continue;
+              double val;
+              if (live) {
+                val = job.alpha * (double)acc[a][cc][v];
+                if (job.beta != 0.0) val += job.beta * job.C0[i + (int64_t)jj * job.ldc0];
+              } else {
+                val = job.keep[i + (int64_t)jj * job.ldkeep];
+              }
+              job.G0[i + (int64_t)jj * job.ldg] = val;
+            }
+        }
+      } else {
+        const int vx = pers_vx(x, part, r0, r1, job.p);
+        T* P = (T*)job.partials + (main ? pers_slot_main(vx, tile, job.q, job.W)
+                                        : pers_slot_left(vx, tile - job.q * job.W, c, job.q, job.W, job.L,
+                                                         job.cmax)) *
+                                      4096;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int cc = 0; cc < 2; ++cc)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int row = wr + a * 16 + Mma<T>::row(lane, v);
+              const int col = wc + cc * 16 + lr;
+              P[row * 64 + col] = acc[a][cc][v];
+            }
+      }
       __syncthreads();  // LDS free for the next share
     }
   }
@@ -503,18 +554,19 @@ void k_gram_pers(GramPJob job) {
 // Per (tile, part): the shares of XCD 0..7 in row order (share index c within
 // an XCD follows the rows).  Wave 0 lists them, one (XCD, c) pair per lane in
 // that order, compacted by ballot; then every thread adds its element.
-template <typename T>
+template <typename T, int R>
 __global__ __launch_bounds__(256) void k_gram_pers_fin(GramPJob job) {
+  constexpr bool rect = R == kGramRect;
   constexpr int RS = PersGeo<T>::RS;
   __shared__ int slots[2][kXcds * kPersMaxShares];
   __shared__ int nsl[2];
   // rectangular product: one block per tile adds part 0 and subtracts part 1
-  const int part = job.rect ? 0 : (int)blockIdx.y / job.T, tile = (int)blockIdx.y % job.T;
-  const int nlists = job.rect ? 2 : 1;
+  const int part = rect ? 0 : (int)blockIdx.y / job.T, tile = (int)blockIdx.y % job.T;
+  const int nlists = rect ? 2 : 1;
   if (threadIdx.x < 64) {
     const int lane = threadIdx.x;
     for (int li = 0; li < nlists; ++li) {
-      const int pt = job.rect ? li : part;
+      const int pt = rect ? li : part;
       const int64_t lo = pt ? job.p : 0, hi = pt ? job.M : job.p;
       const bool main = tile < job.q * job.W;
       const int lt = tile - job.q * job.W;
@@ -559,7 +611,7 @@ __global__ __launch_bounds__(256) void k_gram_pers_fin(GramPJob job) {
   }
   __syncthreads();
   int ti, tj;
-  if (job.rect) {
+  if (rect) {
     ti = tile % job.mt;
     tj = tile / job.mt;
   } else {
@@ -568,8 +620,12 @@ __global__ __launch_bounds__(256) void k_gram_pers_fin(GramPJob job) {
   const int e = blockIdx.x * 256 + threadIdx.x;
   const int row = e / 64, col = e % 64;
   const int i = ti * 64 + row, jj = tj * 64 + col;
-  if (job.rect) {
+  if (rect) {
     if (i >= job.n || jj >= job.ny) return;
+    if (job.active && !job.active[jj]) {
+      if (job.keep) job.G0[i + (int64_t)jj * job.ldg] = job.keep[i + (int64_t)jj * job.ldkeep];
+      return;
+    }
   } else if (i >= job.nc || jj >= job.nc || (ti == tj && row < col) || (i == job.n && jj == job.n)) {
     return;
   }
@@ -588,8 +644,10 @@ __global__ __launch_bounds__(256) void k_gram_pers_fin(GramPJob job) {
     for (; q < cnt; ++q) sacc += (double)partials[(size_t)slots[li][q] * 4096 + e];
     return sacc;
   };
-  if (job.rect) {
-    job.G0[i + (int64_t)jj * job.ldg] = add_list(0) - add_list(1);
+  if (rect) {
+    double v = job.alpha * (add_list(0) - add_list(1));
+    if (job.beta != 0.0) v += job.beta * job.C0[i + (int64_t)jj * job.ldc0];
+    job.G0[i + (int64_t)jj * job.ldg] = v;
     return;
   }
   const double sacc = add_list(0);
@@ -872,9 +930,9 @@ static void gram_run(hipStream_t s, int64_t K, int64_t n, const double* A, int64
       pj.G1 = G1;
       pj.gv1 = gv1;
       pj.ldg = ldg;
-      hipLaunchKernelGGL(k_gram_pers<double>, dim3(kXcds * sh.W), dim3(256), 0, s, pj);
+      hipLaunchKernelGGL((k_gram_pers<double, kGramTri>), dim3(kXcds * sh.W), dim3(256), 0, s, pj);
       if (mid) (void)hipEventRecord(mid, s);
-      hipLaunchKernelGGL(k_gram_pers_fin<double>, dim3(64 * 64 / 256, sh.T * (K1 >= 0 ? 2 : 1)), dim3(256), 0, s,
+      hipLaunchKernelGGL((k_gram_pers_fin<double, kGramTri>), dim3(64 * 64 / 256, sh.T * (K1 >= 0 ? 2 : 1)), dim3(256), 0, s,
                          pj);
       return;
     }
@@ -928,39 +986,74 @@ static void gram_f32_pers(hipStream_t s, int64_t K, int64_t n, const float* Af, 
   pj.G1 = nullptr;
   pj.gv1 = nullptr;
   pj.ldg = ldg;
-  hipLaunchKernelGGL(k_gram_pers<float>, dim3(kXcds * sh.W), dim3(256), 0, s, pj);
+  hipLaunchKernelGGL((k_gram_pers<float, kGramTri>), dim3(kXcds * sh.W), dim3(256), 0, s, pj);
   if (mid) (void)hipEventRecord(mid, s);
-  hipLaunchKernelGGL(k_gram_pers_fin<float>, dim3(64 * 64 / 256, sh.T), dim3(256), 0, s, pj);
+  hipLaunchKernelGGL((k_gram_pers_fin<float, kGramTri>), dim3(64 * 64 / 256, sh.T), dim3(256), 0, s, pj);
 }
 
-// C = X^T J Y with J = diag(I_kneg, -I_{K-kneg}) (X: K x M, Y: K x N,
-// column-major, K contiguous) on the persistent kernel: 64 x 64 tiles of C
-// over the same per-XCD row ranges, the two signs as the kernel's two row
-// parts, subtracted in the reduction.  False (nothing queued) when the
-// operands are not 16-byte aligned with even leading dimensions, the plan
-// needs more shares per tile than the reduction lists, or `partials` is
-// smaller than gemm_tn_pers_partials.
+// The product of GemmTnArgs, C = alpha X^T S Y + beta C0 (S = diag(I_kneg,
+// -I_{K-kneg}); X: K x M, Y: K x N, column-major, K contiguous; optional
+// column mask and keep) on the persistent kernel: 64 x 64 tiles of C over
+// the same per-XCD row ranges, the two signs as the kernel's two row parts,
+// subtracted in the reduction, which also applies the epilogue.  False
+// (nothing queued) when the operands are not 16-byte aligned with even
+// leading dimensions, the plan needs more shares per tile than the reduction
+// lists, or `partials` is smaller than gemm_tn_pers_partials.
 static int rect_tiles(int64_t M, int64_t N) { return (int)(((M + 63) / 64) * ((N + 63) / 64)); }
+// longest contraction the whole-range launch takes (above it, the row split
+// over XCDs keeps each tile's stages shared in one L2)
+constexpr int64_t kWholeMaxK = 4096;
 
 size_t gemm_tn_pers_partials(int64_t K, int64_t M, int64_t N) {
   const PersShape sh = pers_shape_t(rect_tiles(M, N), K, PersGeo<double>::RS);
   return ((size_t)(kXcds + 1) * ((size_t)sh.q * sh.W + (size_t)sh.L * sh.cmax)) * 4096;
 }
 
-bool launch_gemm_tn_pers(hipStream_t s, int64_t K, int64_t kneg, int64_t M, int64_t N, const double* X,
-                         int64_t ldx, const double* Y, int64_t ldy, double* partials, size_t partial_doubles,
-                         double* C, int64_t ldc) {
-  if (K < 1 || M < 1 || N < 1 || !pers_aligned<double>(X, ldx, nullptr) || !pers_aligned<double>(Y, ldy, nullptr))
+bool launch_gemm_tn_pers(hipStream_t s, const GemmTnArgs& g, double* partials, size_t partial_doubles) {
+  const int64_t K = g.K, M = g.M, N = g.N;
+  if (K < 1 || M < 1 || N < 1 || !pers_aligned<double>(g.X, g.ldx, nullptr) ||
+      !pers_aligned<double>(g.Y, g.ldy, nullptr))
     return false;
   const int T = rect_tiles(M, N);
+  if (g.kneg >= K && K <= kWholeMaxK && T <= kPersWpc * device_cus()) {
+    // short contraction, one sign: a workgroup per tile walks all K rows and
+    // writes its tile of C (no row split over XCDs, no partials)
+    GramPJob pj = {};
+    pj.A = g.X;
+    pj.lda = g.ldx;
+    pj.M = K;
+    pj.p = K;
+    pj.n = (int)M;
+    pj.nc = (int)M;
+    pj.T = T;
+    pj.W = T;
+    pj.q = 1;
+    pj.L = 0;
+    pj.cmax = 1;
+    pj.G0 = g.C;
+    pj.ldg = g.ldc;
+    pj.mt = (int)((M + 63) / 64);
+    pj.ny = (int)N;
+    pj.Y = g.Y;
+    pj.ldy = g.ldy;
+    pj.alpha = g.alpha;
+    pj.beta = g.beta;
+    pj.C0 = g.C0;
+    pj.ldc0 = g.ldc0;
+    pj.active = g.active;
+    pj.keep = g.keep;
+    pj.ldkeep = g.ldkeep;
+    hipLaunchKernelGGL((k_gram_pers<double, kGramWhole>), dim3(T), dim3(256), 0, s, pj);
+    return true;
+  }
   const PersShape sh = pers_shape_t(T, K, PersGeo<double>::RS);
   if (sh.cmax > kPersMaxShares || gemm_tn_pers_partials(K, M, N) > partial_doubles) return false;
   GramPJob pj = {};
-  pj.A = X;
-  pj.lda = ldx;
+  pj.A = g.X;
+  pj.lda = g.ldx;
   pj.vb = nullptr;
   pj.M = K;
-  pj.p = kneg < K ? kneg : K;
+  pj.p = g.kneg < K ? g.kneg : K;
   pj.n = (int)M;
   pj.nc = (int)M;
   pj.T = sh.T;
@@ -969,15 +1062,21 @@ bool launch_gemm_tn_pers(hipStream_t s, int64_t K, int64_t kneg, int64_t M, int6
   pj.L = sh.L;
   pj.cmax = sh.cmax;
   pj.partials = partials;
-  pj.G0 = C;
-  pj.ldg = ldc;
-  pj.rect = 1;
+  pj.G0 = g.C;
+  pj.ldg = g.ldc;
   pj.mt = (int)((M + 63) / 64);
   pj.ny = (int)N;
-  pj.Y = Y;
-  pj.ldy = ldy;
-  hipLaunchKernelGGL(k_gram_pers<double>, dim3(kXcds * sh.W), dim3(256), 0, s, pj);
-  hipLaunchKernelGGL(k_gram_pers_fin<double>, dim3(64 * 64 / 256, sh.T), dim3(256), 0, s, pj);
+  pj.Y = g.Y;
+  pj.ldy = g.ldy;
+  pj.alpha = g.alpha;
+  pj.beta = g.beta;
+  pj.C0 = g.C0;
+  pj.ldc0 = g.ldc0;
+  pj.active = g.active;
+  pj.keep = g.keep;
+  pj.ldkeep = g.ldkeep;
+  hipLaunchKernelGGL((k_gram_pers<double, kGramRect>), dim3(kXcds * sh.W), dim3(256), 0, s, pj);
+  hipLaunchKernelGGL((k_gram_pers_fin<double, kGramRect>), dim3(64 * 64 / 256, sh.T), dim3(256), 0, s, pj);
   return true;
 }
 

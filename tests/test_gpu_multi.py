@@ -231,3 +231,61 @@ def test_atjb_matches_oracle(shape):
     ref = np.stack([O.residual(A, B[:, j], p, zero) for j in range(r)], axis=1)
     bound = (p + q) * 2.0 ** -52 * (np.abs(A).T @ np.abs(B)) + 1e-300
     assert np.all(np.abs(G - ref) <= bound), np.max(np.abs(G - ref) / bound)
+
+
+# ------------------------------------------------------------------ outer steps on the resident kernel
+@pytest.fixture(scope="module")
+def wide():
+    """n = 520 (9 tile rows) and 460 right-hand sides (8 tile columns): the
+    outer-step products B X_k (and P A^T J B on a prepared A) run on the
+    resident per-XCD kernel with its masked epilogue."""
+    p, q, n, r = 2600, 300, 520, 460
+    banner(f"wide family p={p} q={q} n={n} nrhs={r}")
+    P = W.dense_ils(p, q, n, ratio=0.5, seed=77)
+    Xs = W.planted_columns(n, r, seed=(p, n, r))
+    B = np.asfortranarray(P.A @ Xs)
+    return P, Xs, B, devA(P.A), devA(B)
+
+
+SAMPLE = [0, 229, 459]
+
+
+@pytest.mark.parametrize("prepared", [False, True], ids=["multi", "prepared"])
+def test_wide_fixed_schedule_sampled_columns(wide, prepared):
+    P, Xs, B, A, Bd = wide
+    X0 = np.asfortranarray(np.random.default_rng(5).standard_normal(Xs.shape))
+    kw = dict(X0=devA(X0), stop_rule=ils.STOP_FIXED, max_outer=3)
+    if prepared:
+        pr = ils.SPPrepared(A, P.p)
+        X, info, iters = pr.solve_multi(Bd, **kw)
+        pr.close()
+    else:
+        X, info, iters = ils.sp_solve_multi(A, Bd, P.p, **kw)
+    assert info.status == ils.OK and np.all(iters == 3)
+    Xh = host(X)
+    for j in SAMPLE:
+        ref, _ = O.sp_solve(P.A, B[:, j], P.p, variant=O.SP_EXPLICIT, x0=X0[:, j], stop_rule=O.STOP_FIXED,
+                            max_outer=3)
+        assert_close(Xh[:, j], ref, 1e-10, what=f"column {j}")
+
+
+def test_wide_converged_matches_tiled_path(wide):
+    """Per-column stop tests with frozen columns (relative error to 1e-9):
+    the prepared solve on the resident kernel gives the outer counts and
+    iterates of the multi solve on the same kernel and of the single-right-
+    hand-side solver for sampled columns."""
+    P, Xs, B, A, Bd = wide
+    kw = dict(stop_rule=ils.STOP_XREF, tol=1e-9, x_ref=devA(Xs))
+    Xm, im, itm = ils.sp_solve_multi(A, Bd, P.p, **kw)
+    pr = ils.SPPrepared(A, P.p)
+    Xp, ip, itp = pr.solve_multi(Bd, **kw)
+    pr.close()
+    assert im.status == ip.status == ils.OK
+    np.testing.assert_array_equal(itm, itp)
+    cols_close(host(Xp), host(Xm), 1e-10)
+    for j in SAMPLE:
+        b = torch.from_numpy(np.ascontiguousarray(B[:, j])).to(DEV)
+        xr = torch.from_numpy(np.ascontiguousarray(Xs[:, j])).to(DEV)
+        x1, i1 = ils.sp_solve(A, b, P.p, stop_rule=ils.STOP_XREF, x_ref=xr, tol=1e-9)
+        assert i1.outer_iters == itm[j]
+        assert_close(host(Xm)[:, j], host(x1), 1e-10, what=f"column {j}")
