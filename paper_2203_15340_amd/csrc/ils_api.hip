@@ -296,10 +296,11 @@ int ils::sp_solve_op(ils_handle* h, const MatOp& M, const double* b, const doubl
   // the device starts on it while the host queues the rest of the solve.
   const bool bordered = paper && !M.sp;
   hipEvent_t mid = h->gram_end_event();
+  const double* xr = o->stop_rule == ILS_STOP_XREF ? o->x_ref : nullptr;
   if (a1f) {
     // mixed precision through the FP32 copy: the column pass writes the copy
     // of A1 while it reads A, then the Gram kernel reads only the copy
-    HIPCHK(hipMemsetAsync(h->st, 0, sizeof(LoopState), s));
+    launch_state_reset(s, ds, n, xr);
     launch_colpass(s, p, q, n, M.A, M.lda, b, g, nullptr, &ds->bits, a1f, gram_f32_copy_ld(p));
     h->mark(1);
     launch_gram_f32_on_copy(s, p, n, a1f, (float*)part, W, ldw, mid);
@@ -311,13 +312,12 @@ int ils::sp_solve_op(ils_handle* h, const MatOp& M, const double* b, const doubl
                        rv);
     else  // A1^T A1 for [A1^T A1 | A2^T A2 | A^T J b] or [A1^T A1 | I]
       mat_gram(s, M, 0, o->precision, part, W, ldw, mid);
-    HIPCHK(hipMemsetAsync(h->st, 0, sizeof(LoopState), s));
+    launch_state_reset(s, ds, n, xr);
     if (!bordered) {
       mat_colpass(s, M, b, g, nullptr, &ds->bits);
       if (o->stop_rule == ILS_STOP_RR) launch_norm2(s, n, g, &ds->scal[0]);
     }
   }
-  if (o->stop_rule == ILS_STOP_XREF) launch_norm2(s, n, o->x_ref, &ds->scal[1]);
   h->mark(3);
   GjCombine pre{g, rv, W + 2 * n * ldw};  // bordered: A^T J b formed by the elimination's first kernel
   if (bordered) {

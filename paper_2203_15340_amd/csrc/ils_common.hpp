@@ -224,6 +224,8 @@ size_t gram_partials_size_cfg(int64_t n, int64_t K, GramCfg c);
 void launch_gram_cfg(hipStream_t s, int precision, int64_t K, int64_t n, const double* A, int64_t lda,
                      void* partials, double* G, int64_t ldg, GramCfg cfg, float* a1f = nullptr);
 void launch_norm2(hipStream_t s, int64_t n, const double* v, double* out);
+// LoopState zeroed, and ||x_ref||^2 into its scal[1] when x_ref is given.
+void launch_state_reset(hipStream_t s, LoopState* st, int64_t n, const double* x_ref);
 void launch_transpose(hipStream_t s, int64_t n, int64_t ncol, const double* X, int64_t ldx,
                       double* Y, int64_t ldy);
 void launch_copy_cols(hipStream_t s, int64_t n, int64_t ncol, const double* X, int64_t ldx,

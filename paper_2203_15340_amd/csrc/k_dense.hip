@@ -486,6 +486,26 @@ void launch_norm2(hipStream_t s, int64_t n, const double* v, double* out) {
   hipLaunchKernelGGL(k_norm2, dim3(1), dim3(1024), 0, s, n, v, out);
 }
 
+// The loop state cleared and, with x_ref, ||x_ref||^2 into scal[1] (the
+// relative-error denominator): one launch instead of a fill and k_norm2.
+__global__ __launch_bounds__(1024) void k_state_reset(LoopState* __restrict__ st, int64_t n,
+                                                      const double* __restrict__ x_ref) {
+  __shared__ double red[1024 / kWave];
+  constexpr int kWords = (int)(sizeof(LoopState) / sizeof(int));
+  static_assert(sizeof(LoopState) % sizeof(int) == 0, "LoopState is a whole number of words");
+  int* w = (int*)st;
+  for (int e = threadIdx.x; e < kWords; e += 1024) w[e] = 0;
+  if (!x_ref) return;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) s += x_ref[i] * x_ref[i];
+  s = block_sum<1024>(s, red);  // its barrier also orders the zeroing before the store below
+  if (threadIdx.x == 0) st->scal[1] = s;
+}
+
+void launch_state_reset(hipStream_t s, LoopState* st, int64_t n, const double* x_ref) {
+  hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(1024), 0, s, st, n, x_ref);
+}
+
 // Y (ncol x n, ldy) = X^T for X n x ncol (ldx), through 32x32 LDS tiles.
 __global__ __launch_bounds__(256) void k_transpose(int64_t n, int64_t ncol, const double* __restrict__ X,
                                                    int64_t ldx, double* __restrict__ Y, int64_t ldy) {
