@@ -278,19 +278,23 @@ __global__ __launch_bounds__(256) void k_rkb_close(const T* __restrict__ part, i
   }
   red[g][le] = acc;
   __syncthreads();
+  // C is handed to the last workgroup through device-scope stores and loads
+  // (past the per-XCD caches): the writing wave waits until its stores are
+  // acknowledged and then counts, so no cache write-back or invalidation
+  // (a device-scope fence in every workgroup) is needed
   if (threadIdx.x < kRedE && e < kRBX * kRBY) {
     double tot = red[0][le];
 #pragma unroll
     for (int u = 1; u < kRedG; ++u) tot += red[u][le];
-    C[e] = tot;
+    __hip_atomic_store(C + e, tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
+  __asm__ __volatile__("" ::: "memory");
   if (threadIdx.x == 0) {
-    __threadfence();
-    is_last = atomicAdd(arrive, 1u) == gridDim.x - 1;
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): wave 0's stores of C have completed
+    is_last = __hip_atomic_fetch_add(arrive, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1;
   }
   __syncthreads();
   if (!is_last) return;
-  __threadfence();
   if (threadIdx.x >= 64) return;
   rkb_recur_wave(C, bt, j1, j2, tgt, cn, z, coef);
   if (lane == 0) *arrive = 0;

@@ -261,19 +261,22 @@ __global__ __launch_bounds__(256) void k_rkbm_close(RkmClose a) {
   }
   red[g][le] = acc;
   __syncthreads();
+  // C goes to the last workgroup through device-scope stores and loads, as
+  // in the single-right-hand-side close: the writing wave waits for its
+  // stores, then counts (no device-scope fence per workgroup)
   if (threadIdx.x < kMRedE && e < kMRX * kMRY) {
     double tot = red[0][le];
 #pragma unroll
     for (int u = 1; u < kMRedG; ++u) tot += red[u][le];
-    a.C[e] = tot;
+    __hip_atomic_store(a.C + e, tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
+  __asm__ __volatile__("" ::: "memory");
   if (threadIdx.x == 0) {
-    __threadfence();
-    is_last = atomicAdd(a.arrive, 1u) == gridDim.x - 1;
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): wave 0's stores of C have completed
+    is_last = __hip_atomic_fetch_add(a.arrive, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1;
   }
   __syncthreads();
   if (!is_last) return;
-  __threadfence();
   const int w = threadIdx.x >> 6;
   for (int r = w; r < a.R; r += 4) {
     const bool frozen = *(volatile const int*)(a.frozen + r) != 0;
