@@ -317,6 +317,22 @@ __device__ __host__ inline size_t pers_slot_left(int vx, int lt, int c, int q, i
 
 static __device__ const double g_zero16[16] = {0.0};
 
+// Issue-priority balancing of the resident workgroups.  A SIMD's arbiter
+// favours its older waves, so the workgroups of one XCD, left alone, drift
+// apart as they walk the range (at 20000 x 1000, 48 stages in, the earliest
+// workgroup was 60 us into the launch and the latest 208 us): the L2 then
+// serves each stage to fewer of the tiles that read it (reads 3.2x A) and
+// the launch ends on a tail of the late workgroups.  Every ep_len stages each
+// wave counts its arrival on the counter of its (XCD, wave slot, epoch) and
+// takes its rank among the XCD's W workgroups as its issue priority (the
+// first quarter lowest, the last quarter highest).  Nothing waits on the
+// counters: they reorder issue only, so the arithmetic and its order are
+// unchanged.  The reduction kernel clears them for the next launch (they
+// start at zero); a launch that finds them not cleared only loses the
+// balancing.
+constexpr int kPersEpochs = 64;
+static __device__ unsigned g_pers_rank[kXcds * 4 * kPersEpochs];
+
 // s_waitcnt with a vector-memory limit only (vmcnt low bits 3:0, high bits
 // 15:14; expcnt 6:4 and lgkmcnt 11:8 left at their maxima)
 #define ILS_WAIT_VM(N) __builtin_amdgcn_s_waitcnt(((N) & 0xF) | (((N) >> 4) << 14) | (0x7 << 4) | (0xF << 8))
@@ -368,6 +384,36 @@ void k_gram_pers(GramPJob job) {
     if (rect && op == 1) return col < job.ny ? Y + (int64_t)col * ldy : nullptr;
     if (col < n) return A + (int64_t)col * lda;
     return (!rect && col == n) ? vb : nullptr;
+  };
+
+  // issue-priority balancing (see g_pers_rank): epochs of ep_len stages,
+  // the same length for every workgroup of the XCD
+  const int64_t ep_len = whole ? 0 : ((int64_t)job.q * S + LS / job.W) / kPersEpochs + 8;
+  int64_t done = 0, mark = ep_len;
+  int ep = 0;
+  unsigned rank = 0;
+  bool rank_pend = false;
+  auto balance = [&]() {
+    if (whole) return;
+    if (rank_pend) {
+      // the count issued one stage ago has returned (the stage wait covers it)
+      const int pr = __builtin_amdgcn_readfirstlane((int)rank) * 4 / job.W;
+      if (pr <= 0) __builtin_amdgcn_s_setprio(0);
+      else if (pr == 1) __builtin_amdgcn_s_setprio(1);
+      else if (pr == 2) __builtin_amdgcn_s_setprio(2);
+      else __builtin_amdgcn_s_setprio(3);
+      rank_pend = false;
+    }
+    if (++done == mark) {
+      mark += ep_len;
+      if (ep < kPersEpochs) {
+        if (lane == 0)
+          rank = __hip_atomic_fetch_add(&g_pers_rank[(x * 4 + w) * kPersEpochs + ep], 1u, __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT);
+        rank_pend = true;
+        ++ep;
+      }
+    }
   };
 
   int mi = 0;
@@ -500,6 +546,7 @@ void k_gram_pers(GramPJob job) {
           __builtin_amdgcn_s_barrier();
           __asm__ __volatile__("" ::: "memory");
           if (st + 1 < nfull) issue(st + 1, (int)((st + 1) & 1));
+          balance();
           compute((int)(st & 1));
         }
       }
@@ -556,6 +603,8 @@ void k_gram_pers(GramPJob job) {
 // that order, compacted by ballot; then every thread adds its element.
 template <typename T, int R>
 __global__ __launch_bounds__(256) void k_gram_pers_fin(GramPJob job) {
+  if (blockIdx.x == 0 && blockIdx.y == 0)
+    for (int e = threadIdx.x; e < kXcds * 4 * kPersEpochs; e += blockDim.x) g_pers_rank[e] = 0u;
   constexpr bool rect = R == kGramRect;
   constexpr int RS = PersGeo<T>::RS;
   __shared__ int slots[2][kXcds * kPersMaxShares];

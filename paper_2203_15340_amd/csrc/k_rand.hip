@@ -257,13 +257,14 @@ __global__ __launch_bounds__(256) void k_rk_check(const double* __restrict__ A1,
   sacc = block_sum<256>(sacc, red);
   if (threadIdx.x == 0) {
     const double rj = tgt[j] - sacc;
-    res2[j] = rj * rj;
-    __threadfence();
-    is_last = atomicAdd(arrive, 1u) == gridDim.x - 1;
+    // device-scope store, then wait for it before counting the arrival: the
+    // last workgroup reads every entry with device-scope loads (no fence)
+    __hip_atomic_store(res2 + j, rj * rj, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    is_last = __hip_atomic_fetch_add(arrive, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1;
   }
   __syncthreads();
   if (!is_last) return;
-  __threadfence();
   double tot = 0.0;
   for (int64_t jj = threadIdx.x; jj < n; jj += 256)
     tot += __hip_atomic_load(res2 + jj, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
