@@ -30,6 +30,7 @@ PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 (vector = matrix)
 PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gram_fp64_20000x1000_traffic.json")
+GRAM_SAMPLE = 8  # timed solves per HIP-event sample of the Gram launch
 TUNE_FILE = os.path.join(ROOT, "paper_2203_15340_amd", "tune", "gram_mi355x.json")
 GRAM_SRC = os.path.join(ROOT, "paper_2203_15340_amd", "csrc", "k_gram.hip")
 
@@ -583,10 +584,10 @@ def main():
         ils.tune_load(TUNE_FILE)
         tuned = tuned_entry(TUNE_FILE, ils.PREC_FP64, P.n, P.p)
         log(f"Gram launch table {TUNE_FILE}: A1 {tuned}")
-    # timed solves carry only the two events around the Gram launch (each
-    # event costs device time); the full phase breakdown comes from extra
-    # solves after the timed region
-    ils.set_profiling(ils.PROFILE_GRAM)
+    # every GRAM_SAMPLE-th timed solve carries the two HIP events around the
+    # Gram launch (each event costs device time and its read-back host time);
+    # the full phase breakdown comes from extra solves after the timed region
+    ils.set_profiling(ils.PROFILE_OFF)
     log(f"warmup {args.warmup}")
     for _ in range(args.warmup):
         _, info = ils.sp_solve(A, b, P.p, out=x, **kw)
@@ -595,10 +596,15 @@ def main():
     log(f"timing {args.steps} solves")
     gram_ms, infos = [], []
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for i in range(args.steps):
+        sample = i % GRAM_SAMPLE == 0
+        if sample:
+            ils.set_profiling(ils.PROFILE_GRAM)
         _, info = ils.sp_solve(A, b, P.p, out=x, **kw)
         infos.append(info)
-        gram_ms.append(ils.phase_times()["gram"])
+        if sample:
+            gram_ms.append(ils.phase_times()["gram"])
+            ils.set_profiling(ils.PROFILE_OFF)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     assert all(i.status == ils.OK for i in infos)
@@ -694,7 +700,8 @@ def main():
                      "kernel": gram_kernel_name(tuned),
                      "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
-                     "flops_per_launch": gram_flops, "avg_launch_ms": gram_avg},
+                     "flops_per_launch": gram_flops, "avg_launch_ms": gram_avg,
+                     "launch_samples": len(gram_ms)},
         "phases_ms": ph,
         "forms": forms,
         "ratio_0_9": ratio09,

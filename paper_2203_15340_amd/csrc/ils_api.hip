@@ -312,7 +312,9 @@ int ils::sp_solve_op(ils_handle* h, const MatOp& M, const double* b, const doubl
                        rv);
     else  // A1^T A1 for [A1^T A1 | A2^T A2 | A^T J b] or [A1^T A1 | I]
       mat_gram(s, M, 0, o->precision, part, W, ldw, mid);
-    launch_state_reset(s, ds, n, xr);
+    // the bordered form's one-launch elimination clears the loop state in its
+    // first kernel (nothing before it reads or raises the state's bits)
+    if (!(bordered && gj_one_launch(n, nrhs))) launch_state_reset(s, ds, n, xr);
     if (!bordered) {
       mat_colpass(s, M, b, g, nullptr, &ds->bits);
       if (o->stop_rule == ILS_STOP_RR) launch_norm2(s, n, g, &ds->scal[0]);
@@ -330,10 +332,13 @@ int ils::sp_solve_op(ils_handle* h, const MatOp& M, const double* b, const doubl
     launch_eye(s, n, W + n * ldw, ldw);
   }
   h->mark(4);
-  launch_gj(s, n, nrhs, W, ldw, dinv, &ds->bits, bordered ? &pre : nullptr);
+  // the one-launch elimination also writes B (or P) row-major for the steps
+  const bool one = gj_one_launch(n, nrhs);
+  const GjExtras ex{bordered ? ds : nullptr, xr, Mrow, n, n, n};
+  launch_gj(s, n, nrhs, W, ldw, dinv, &ds->bits, bordered ? &pre : nullptr, one ? &ex : nullptr);
   if (bordered && o->stop_rule == ILS_STOP_RR) launch_norm2(s, n, g, &ds->scal[0]);
   h->mark(5);
-  launch_transpose(s, n, n, W + n * ldw, ldw, Mrow, n);
+  if (!one) launch_transpose(s, n, n, W + n * ldw, ldw, Mrow, n);
   if (!paper) launch_fill_vec(s, n, x0, xb0);  // the paper form's step 0 reads x0 itself
   h->mark(6);
 

@@ -246,9 +246,21 @@ struct GjCombine {
   const double* g2;  // A2^T b2 (n)
   double* gcol;      // the column of W that receives A^T J b
 };
+// Extra work of the one-launch form (n <= 2048 with right-hand sides,
+// gj_one_launch): the loop state cleared first (and ||reset_xr||^2 into its
+// scal[1] when reset_xr is given), as launch_state_reset, and columns
+// [bcol0, bcol0 + nbt) of the result written row-major as well:
+// bt[(c - bcol0) + r ldbt] = W[r, c].
+struct GjExtras {
+  LoopState* reset;
+  const double* reset_xr;
+  double* bt;
+  int64_t ldbt, bcol0, nbt;
+};
 size_t gj_scratch_bytes(int64_t n, int64_t ncols);
+bool gj_one_launch(int64_t n, int64_t nrhs);
 void launch_gj(hipStream_t s, int64_t n, int64_t nrhs, double* W, int64_t ldw, void* scratch, int* bits,
-               const GjCombine* pre = nullptr);
+               const GjCombine* pre = nullptr, const GjExtras* ex = nullptr);
 
 // SP outer step kernels (k_sp.hip).
 struct SpStepArgs {

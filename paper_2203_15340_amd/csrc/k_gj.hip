@@ -317,6 +317,7 @@ struct GjFlow {
   unsigned* ticket;
   int* bits;
   GjCombine pre;  // optional right-hand-side column formed first (see launch_gj)
+  GjExtras ex;    // optional loop-state reset and row-major copy (see launch_gj)
 };
 
 struct FlowStep {
@@ -422,6 +423,25 @@ __global__ __launch_bounds__(kGjThreads, kFlowOcc) void k_gj_flow(GjFlow a) {
           const int64_t r = r0 + i, c = c0 + j;
           if (r < rmax && c >= cmin && c < cmax) ast(W + r + c * ldw, v[(x * 2 + y) * 4 + u]);
         }
+  };
+  // the last step's final tiles also go row-major into ex.bt (columns
+  // [bcol0, bcol0 + nbt)), through As: every wave is past its product
+  auto store_bt = [&](const double (&v)[16], int64_t r0, int64_t c0) {
+    if (c0 + kNB <= a.ex.bcol0 || c0 >= a.ex.bcol0 + a.ex.nbt) return;
+    __syncthreads();
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) As[ic + y * 16 + lr][jr + x * 16 + (lane >> 4) + 4 * u] = v[(x * 2 + y) * 4 + u];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int e = t + q * kGjThreads, i = e >> 6, j = e & (kNB - 1);
+      const int64_t r = r0 + i, c = c0 + j;
+      if (r < n && c >= a.ex.bcol0 && c < a.ex.bcol0 + a.ex.nbt) a.ex.bt[(c - a.ex.bcol0) + r * a.ex.ldbt] = As[i][j];
+    }
   };
   // tile (A operand) As[i][k] = v(i, k); (B operand) Bs[j][k] = v(k, j)
   auto stash_a = [&](const double (&v)[16]) {
@@ -639,6 +659,7 @@ __global__ __launch_bounds__(kGjThreads, kFlowOcc) void k_gj_flow(GjFlow a) {
       store_out(acc, k0, cj, k0 + f.nb, f.c0, ncols);
       flow_signal(a.pdone + k * a.S + j);
       if (t == 0) __hip_atomic_fetch_add(a.cnt + k * a.S + j, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (a.ex.bt && k == R - 1) store_bt(acc, k0, cj);
       continue;
     }
     u -= f.nP;
@@ -679,6 +700,7 @@ __global__ __launch_bounds__(kGjThreads, kFlowOcc) void k_gj_flow(GjFlow a) {
     for (int q = 0; q < 16; ++q) cv[q] -= acc[q];
     store_out(cv, ri, cj, n, f.c0, ncols);
     flow_signal(a.cnt + k * a.S + j);
+    if (a.ex.bt && k == R - 1) store_bt(cv, ri, cj);
   }
 }
 
@@ -688,6 +710,7 @@ __global__ __launch_bounds__(kGjThreads) void k_gj_flow_init(GjFlow a) {
   __shared__ double Ds[kNB][kLds];
   __shared__ double Es[kNB][kLds];
   __shared__ InvBlk inv;
+  __shared__ double rsum[kGjThreads / kWave];
   const int t = threadIdx.x;
   // the first pivot block's loads go out first (columns 0..63: untouched by
   // the right-hand-side column written below)
@@ -700,6 +723,20 @@ __global__ __launch_bounds__(kGjThreads) void k_gj_flow_init(GjFlow a) {
   }
   const int64_t nint = 2 * (int64_t)a.R * a.S + 2 * a.R + 1;  // cnt, pdone, dflag, lflag, ticket
   for (int64_t e = t; e < nint; e += kGjThreads) a.cnt[e] = 0;
+  if (a.ex.reset) {
+    // the loop state cleared (its bits included) before anything below can
+    // raise a bit, and ||x_ref||^2 for the relative error
+    constexpr int kWords = (int)(sizeof(LoopState) / sizeof(int));
+    int* lw = (int*)a.ex.reset;
+    for (int e = t; e < kWords; e += kGjThreads) lw[e] = 0;
+    if (a.ex.reset_xr) {
+      double sq = 0.0;
+      for (int64_t i = t; i < a.n; i += kGjThreads) sq += a.ex.reset_xr[i] * a.ex.reset_xr[i];
+      sq = block_sum<kGjThreads>(sq, rsum);  // its barrier also orders the zeroing before the store
+      if (t == 0) a.ex.reset->scal[1] = sq;
+    }
+    __syncthreads();
+  }
   if (a.pre.g) {
     // the right-hand-side column g = g1 - g2 and the screen of g and of the
     // diagonals of the two Gram blocks (columns 0..n-1 and n..2n-1 of W); the
@@ -753,6 +790,7 @@ __global__ __launch_bounds__(kGjThreads) void k_gj_flow_init(GjFlow a) {
 }
 
 static bool flow_fits(int64_t n) { return (n + kNB - 1) / kNB <= kFlowMaxRows; }
+bool gj_one_launch(int64_t n, int64_t nrhs) { return flow_fits(n) && nrhs > 0; }
 
 size_t gj_scratch_bytes(int64_t n, int64_t ncols) {
   size_t b = sizeof(double) * 2 * kNB * kNB;  // the step-by-step form
@@ -766,10 +804,10 @@ size_t gj_scratch_bytes(int64_t n, int64_t ncols) {
 
 
 void launch_gj(hipStream_t s, int64_t n, int64_t nrhs, double* W, int64_t ldw, void* scratch, int* bits,
-               const GjCombine* pre) {
+               const GjCombine* pre, const GjExtras* ex) {
   const int64_t ncols = n + nrhs;
   const int row_tiles = (int)((n + kNB - 1) / kNB);
-  if (flow_fits(n) && ncols > n) {
+  if (gj_one_launch(n, nrhs)) {
     GjFlow a;
     a.W = W;
     a.ldw = ldw;
@@ -785,6 +823,7 @@ void launch_gj(hipStream_t s, int64_t n, int64_t nrhs, double* W, int64_t ldw, v
     a.ticket = (unsigned*)(a.lflag + a.R);
     a.bits = bits;
     a.pre = pre ? *pre : GjCombine{nullptr, nullptr, nullptr};
+    a.ex = ex ? *ex : GjExtras{nullptr, nullptr, nullptr, 0, 0, 0};
     hipLaunchKernelGGL(k_gj_flow_init, dim3(1), dim3(kGjThreads), 0, s, a);
     hipLaunchKernelGGL(k_gj_flow, dim3(kFlowWgs), dim3(kGjThreads), 0, s, a);
     return;
