@@ -5,6 +5,8 @@
 //   * the inner loops themselves, one workgroup per problem, which are a
 //     chain of dependent reductions and cannot be spread across the chip;
 //   * the per-outer-step helpers (right-hand side, stop test, update).
+#include <type_traits>
+
 #include "ils_common.hpp"
 #include "k_rand.hpp"
 
@@ -73,7 +75,9 @@ void launch_rk_draw(hipStream_t s, uint64_t seed, uint64_t outer, int64_t t0, in
 // weights (word 1).  Otherwise tau_t holds the alpha_t indices with the
 // smallest keys (SplitMix64 stream seeded with word 2, low index bits
 // replaced by the index); the alpha_t-th smallest key is found by an 8-pass
-// radix select over LDS histograms, and tau_t is written as a bitmask.
+// radix select over LDS histograms (each pass: histogram of the next byte of
+// the keys that share the selected prefix, a parallel prefix over the 256
+// bins), and tau_t is written as a bitmask, one wave ballot per 64 indices.
 __global__ __launch_bounds__(256) void k_scd_draw(uint64_t seed, uint64_t outer, int64_t t0,
                                                   int64_t n, int64_t alpha_opt, int norm_mode,
                                                   const double* __restrict__ prefix,
@@ -81,6 +85,7 @@ __global__ __launch_bounds__(256) void k_scd_draw(uint64_t seed, uint64_t outer,
                                                   uint32_t* __restrict__ mask, int64_t mask_words) {
   __shared__ uint64_t keys[kScdMaxN];
   __shared__ unsigned hist[256];
+  __shared__ unsigned wsum[4];
   __shared__ uint64_t sel_prefix;
   __shared__ int64_t sel_rank;
   const int64_t t = blockIdx.x;
@@ -110,38 +115,47 @@ __global__ __launch_bounds__(256) void k_scd_draw(uint64_t seed, uint64_t outer,
     sel_prefix = 0;
     sel_rank = alpha - 1;
   }
-  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int pass = 0; pass < 8; ++pass) {
     const int shift = 56 - 8 * pass;
     const uint64_t hmask = pass == 0 ? 0ull : (~0ull << (shift + 8));
-    for (int i = threadIdx.x; i < 256; i += 256) hist[i] = 0;
+    hist[threadIdx.x] = 0;
     __syncthreads();
     const uint64_t pre = sel_prefix;
+    const int64_t rank = sel_rank;
     for (int64_t s = threadIdx.x; s < n; s += 256) {
       const uint64_t k = keys[s];
       if ((k & hmask) == pre) atomicAdd(&hist[(k >> shift) & 255u], 1u);
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-      int64_t rank = sel_rank, cum = 0;
-      int d = 0;
-      for (; d < 255; ++d) {
-        if (cum + (int64_t)hist[d] > rank) break;
-        cum += hist[d];
-      }
-      sel_rank = rank - cum;
-      sel_prefix = pre | ((uint64_t)d << shift);
+    // inclusive prefix over the 256 bins (one per thread): within each wave
+    // by shifts, then the totals of the lower waves; the one bin whose range
+    // [before, before + count) holds the rank continues the selection
+    const unsigned h = hist[threadIdx.x];
+    unsigned incl = h;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const unsigned o = __shfl_up(incl, off, 64);
+      if (lane >= off) incl += o;
+    }
+    if (lane == 63) wsum[wv] = incl;
+    __syncthreads();
+    for (int q = 0; q < wv; ++q) incl += wsum[q];
+    const int64_t before = (int64_t)incl - h;
+    if (h > 0 && before <= rank && rank < (int64_t)incl) {
+      sel_rank = rank - before;
+      sel_prefix = pre | ((uint64_t)threadIdx.x << shift);
     }
     __syncthreads();
   }
   const uint64_t thr = sel_prefix;  // exact key of rank alpha - 1
-  for (int64_t wd = threadIdx.x; wd < mask_words; wd += 256) {
-    uint32_t bits = 0;
-    for (int e = 0; e < 32; ++e) {
-      const int64_t s = wd * 32 + e;
-      if (s < n && keys[s] <= thr) bits |= 1u << e;
-    }
-    mrow[wd] = bits;
+  // bit s of tau_t: keys[s] <= thr, 64 bits per wave ballot
+  for (int64_t base = 0; base < n; base += 256) {
+    const int64_t s = base + threadIdx.x;
+    const uint64_t bal = __ballot(s < n && keys[s] <= thr);
+    const int64_t w0 = (base + wv * 64) / 32;
+    if (lane == 0 && w0 < mask_words) mrow[w0] = (uint32_t)bal;
+    if (lane == 1 && w0 + 1 < mask_words) mrow[w0 + 1] = (uint32_t)(bal >> 32);
   }
 }
 
@@ -304,6 +318,10 @@ void launch_rk_check_f32(hipStream_t st, const double* A1, int64_t lda, int64_t 
 __device__ inline bool better(double v, int i, double bv, int bi) {
   return v > bv || (v == bv && i < bi);
 }
+// The same test with both comparisons evaluated (no branch).
+__device__ inline bool better_nb(double v, int i, double bv, int bi) {
+  return (v > bv) | ((v == bv) & (i < bi));
+}
 
 // Global-memory form for n > kScdMaxN (greedy or norm-weighted choice only):
 // one workgroup, r in global memory.
@@ -452,28 +470,37 @@ __global__ __launch_bounds__(kScdRegThreads) void k_scd_inner_reg(
     for (int e = 0; e < E; ++e) {
       nrm += rr[e] * rr[e];
       const bool member = t < count && s0 + e < n && (norm_mode ? s0 + e == jn : ((bits >> e) & 1u));
-      if (member) {
-        const double av = norm_mode ? 0.0 : fabs((double)rr[e]);
-        if (better(av, (int)(s0 + e), bv, bi)) {
-          bv = av;
-          br = rr[e];
-          bi = (int)(s0 + e);
-        }
-      }
+      const double av = norm_mode ? 0.0 : fabs((double)rr[e]);
+      const bool take = member & better_nb(av, (int)(s0 + e), bv, bi);
+      bv = take ? av : bv;
+      br = take ? rr[e] : br;
+      bi = take ? (int)(s0 + e) : bi;
     }
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-      nrm += __shfl_xor(nrm, off, kWave);
-      const double ov = __shfl_xor(bv, off, kWave);
-      const T orr = __shfl_xor(br, off, kWave);
-      const int oi = __shfl_xor(bi, off, kWave);
-      if (better(ov, oi, bv, bi)) {
-        bv = ov;
-        br = orr;
-        bi = oi;
-      }
-    }
-    if (lane == 0) {
+    // the wave's sum and best (|r|, index) by DPP moves, selects instead of
+    // branches: within each row of 16 lanes the partner lanes are lane ^ 1,
+    // lane ^ 2, then the mirror within 8 and within 16 lanes (every lane
+    // ends with its row's result); then lane 15 of rows 0 and 2 goes to rows
+    // 1 and 3, and lane 31 to rows 2 and 3, so lane 63 holds the wave's
+    // result.  Lanes a move does not write get the identity (0, -1, max).
+    auto level = [&](auto ctrl, auto rows) {
+      constexpr int C = decltype(ctrl)::value, RM = decltype(rows)::value;
+      const T on = __builtin_amdgcn_update_dpp((T)0, nrm, C, RM, 0xF, false);
+      const double ov = __builtin_amdgcn_update_dpp(-1.0, bv, C, RM, 0xF, false);
+      const T orr = __builtin_amdgcn_update_dpp((T)0, br, C, RM, 0xF, false);
+      const int oi = __builtin_amdgcn_update_dpp(0x7FFFFFFF, bi, C, RM, 0xF, false);
+      nrm += on;
+      const bool take = better_nb(ov, oi, bv, bi);
+      bv = take ? ov : bv;
+      br = take ? orr : br;
+      bi = take ? oi : bi;
+    };
+    level(std::integral_constant<int, 0xB1>{}, std::integral_constant<int, 0xF>{});   // quad_perm 1,0,3,2
+    level(std::integral_constant<int, 0x4E>{}, std::integral_constant<int, 0xF>{});   // quad_perm 2,3,0,1
+    level(std::integral_constant<int, 0x141>{}, std::integral_constant<int, 0xF>{});  // row_half_mirror
+    level(std::integral_constant<int, 0x140>{}, std::integral_constant<int, 0xF>{});  // row_mirror
+    level(std::integral_constant<int, 0x142>{}, std::integral_constant<int, 0xA>{});  // row_bcast:15
+    level(std::integral_constant<int, 0x143>{}, std::integral_constant<int, 0xC>{});  // row_bcast:31
+    if (lane == 63) {
       red_n[par][wv] = nrm;
       red_v[par][wv] = bv;
       red_r[par][wv] = br;
@@ -487,11 +514,10 @@ __global__ __launch_bounds__(kScdRegThreads) void k_scd_inner_reg(
 #pragma unroll
     for (int q = 1; q < kScdRegWaves; ++q) {
       nrm += red_n[par][q];
-      if (better(red_v[par][q], red_i[par][q], bv, bi)) {
-        bv = red_v[par][q];
-        br = red_r[par][q];
-        bi = red_i[par][q];
-      }
+      const bool take = better_nb(red_v[par][q], red_i[par][q], bv, bi);
+      bv = take ? red_v[par][q] : bv;
+      br = take ? red_r[par][q] : br;
+      bi = take ? red_i[par][q] : bi;
     }
     if (check && (double)nrm <= stop2) {
       if (tid == 0) *inner_done = 1;
