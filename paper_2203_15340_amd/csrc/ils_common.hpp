@@ -49,17 +49,34 @@ __device__ inline __attribute__((address_space(1))) T* glb(T* p) {
 }
 
 // ---------------------------------------------------------------- reductions
-// Butterfly sum over the 64 lanes of a wavefront.  The pairing order is
-// fixed, so results are reproducible run to run.
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+// Sum over the 64 lanes of a wavefront, every lane of which must be active;
+// every lane gets the same bits.  DPP moves pair the lanes: within each row
+// of 16, lane ^ 1, lane ^ 2, then the mirrors within 8 and within 16 lanes
+// (each pair adds the same two values, so a row's lanes agree); then lane
+// 15 of rows 0 and 2 is added into rows 1 and 3, and lane 31 into rows 2
+// and 3, so lane 63 holds the total, which is read back to all lanes.  The
+// order is fixed, so results are reproducible run to run; a row of 64-bit
+// moves and adds costs a small part of the six LDS permutes of a shuffle
+// butterfly.
+template <typename T>
+__device__ inline T wave_sum_dpp(T v) {
+  v += __builtin_amdgcn_update_dpp((T)0, v, 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
+  v += __builtin_amdgcn_update_dpp((T)0, v, 0x4E, 0xF, 0xF, false);   // quad_perm 2,3,0,1
+  v += __builtin_amdgcn_update_dpp((T)0, v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+  v += __builtin_amdgcn_update_dpp((T)0, v, 0x140, 0xF, 0xF, false);  // row_mirror
+  v += __builtin_amdgcn_update_dpp((T)0, v, 0x142, 0xA, 0xF, false);  // row_bcast:15 into rows 1, 3
+  v += __builtin_amdgcn_update_dpp((T)0, v, 0x143, 0xC, 0xF, false);  // row_bcast:31 into rows 2, 3
   return v;
 }
+__device__ inline double wave_sum(double v) {
+  v = wave_sum_dpp(v);
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), kWave - 1);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), kWave - 1);
+  return __hiloint2double(hi, lo);
+}
 __device__ inline float wave_sum(float v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
-  return v;
+  v = wave_sum_dpp(v);
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), kWave - 1));
 }
 
 // Sum over a workgroup of NT threads; every thread gets the result.  `red`
