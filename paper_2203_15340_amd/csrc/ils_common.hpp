@@ -58,12 +58,18 @@ __device__ inline __attribute__((address_space(1))) T* glb(T* p) {
 // order is fixed, so results are reproducible run to run; a row of 64-bit
 // moves and adds costs a small part of the six LDS permutes of a shuffle
 // butterfly.
+// Sum over each row of 16 lanes, every lane of the row getting the same bits.
 template <typename T>
-__device__ inline T wave_sum_dpp(T v) {
+__device__ inline T row16_sum(T v) {
   v += __builtin_amdgcn_update_dpp((T)0, v, 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
   v += __builtin_amdgcn_update_dpp((T)0, v, 0x4E, 0xF, 0xF, false);   // quad_perm 2,3,0,1
   v += __builtin_amdgcn_update_dpp((T)0, v, 0x141, 0xF, 0xF, false);  // row_half_mirror
   v += __builtin_amdgcn_update_dpp((T)0, v, 0x140, 0xF, 0xF, false);  // row_mirror
+  return v;
+}
+template <typename T>
+__device__ inline T wave_sum_dpp(T v) {
+  v = row16_sum(v);
   v += __builtin_amdgcn_update_dpp((T)0, v, 0x142, 0xA, 0xF, false);  // row_bcast:15 into rows 1, 3
   v += __builtin_amdgcn_update_dpp((T)0, v, 0x143, 0xC, 0xF, false);  // row_bcast:31 into rows 2, 3
   return v;

@@ -388,11 +388,7 @@ __device__ __attribute__((noinline)) void wg_residual(const double* A_, int64_t 
   }
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
-    double v = acc[u];
-    v += __shfl_xor(v, 1);
-    v += __shfl_xor(v, 2);
-    v += __shfl_xor(v, 4);
-    v += __shfl_xor(v, 8);
+    const double v = row16_sum(acc[u]);
     const int c = g + G * u;
     if (k == 0 && c < n) r[c] = v;
   }

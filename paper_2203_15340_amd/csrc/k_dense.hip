@@ -149,6 +149,20 @@ static int64_t resid_groups(int64_t m, int64_t n) {
 // runs or giving each workgroup a contiguous range of blocks moved it by
 // under 1 us).  Each workgroup's column sums go to a partial vector; a
 // second kernel adds the partials in workgroup order.
+// Partner value for the recursive halving over the 16 row lanes of a DPP
+// row at level o (8, 4, 2, 1): a lane whose bit o differs and whose earlier
+// levels agree.  The mirror within 16 lanes (level 8) and within 8 lanes
+// (level 4) pair such lanes as well as lane ^ o does, and move by DPP
+// instead of an LDS permute; levels 2 and 1 are lane ^ 2 and lane ^ 1.
+__device__ inline double row_partner(double v, int o) {
+  switch (o) {
+    case 8: return __builtin_amdgcn_update_dpp(0.0, v, 0x140, 0xF, 0xF, false);  // row_mirror
+    case 4: return __builtin_amdgcn_update_dpp(0.0, v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+    case 2: return __builtin_amdgcn_update_dpp(0.0, v, 0x4E, 0xF, 0xF, false);   // quad_perm 2,3,0,1
+    default: return __builtin_amdgcn_update_dpp(0.0, v, 0xB1, 0xF, 0xF, false);  // quad_perm 1,0,3,2
+  }
+}
+
 constexpr int kR1Threads = 1024;
 constexpr int kR1Rows = 16;
 constexpr int kR1Groups = kR1Threads / kR1Rows;  // 64 column groups
@@ -320,7 +334,7 @@ __global__ __launch_bounds__(kR1Threads) void k_resid_1pass(const double* __rest
 #pragma unroll
       for (int j = 0; j < len / 2; ++j) {
         const double lo = d.a[j], hi = d.a[j + len / 2];
-        const double got = __shfl_xor(up ? lo : hi, o);
+        const double got = row_partner(up ? lo : hi, o);
         d.a[j] = (up ? hi : lo) + got;
       }
     }

@@ -255,8 +255,7 @@ __global__ __launch_bounds__(256) void k_csr_resid(int64_t m, int64_t p, const i
   double a = 0.0;
   if (row < m)
     for (int64_t e = rowptr[row] + sub; e < rowptr[row + 1]; e += 16) a += val[e] * x[colidx[e]];
-#pragma unroll
-  for (int off = 8; off >= 1; off >>= 1) a += __shfl_xor(a, off, kWave);
+  a = row16_sum(a);
   if (row < m && sub == 0) {
     const double d = b[row] - a;
     t[row] = row < p ? d : -d;
