@@ -67,6 +67,26 @@ __device__ inline T row16_sum(T v) {
   v += __builtin_amdgcn_update_dpp((T)0, v, 0x140, 0xF, 0xF, false);  // row_mirror
   return v;
 }
+// The value of lane l ^ 16 and of lane l ^ 32 (all lanes active), by the
+// gfx950 permlane swaps instead of an LDS permute: with both operands the
+// same register, the swap of rows 1, 3 with rows 0, 2 (of lanes 32-63 with
+// lanes 0-31) leaves the partner's value in the first result on odd rows
+// (upper lanes) and in the second on even rows (lower lanes).
+__device__ inline double lane_xor16(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  const auto b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  const bool odd = (threadIdx.x >> 4) & 1;
+  return __hiloint2double(odd ? b[0] : b[1], odd ? a[0] : a[1]);
+}
+__device__ inline double lane_xor32(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const auto a = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto b = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  const bool upper = (threadIdx.x >> 5) & 1;
+  return __hiloint2double(upper ? b[0] : b[1], upper ? a[0] : a[1]);
+}
+
 template <typename T>
 __device__ inline T wave_sum_dpp(T v) {
   v = row16_sum(v);

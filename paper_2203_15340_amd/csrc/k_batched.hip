@@ -368,8 +368,8 @@ __device__ __attribute__((noinline)) void wg_residual(const double* A_, int64_t 
     double sdot = 0.0;
 #pragma unroll
     for (int u = 0; u < PER; ++u) sdot = fma(av[u], (g + G * u < n) ? xs[g + G * u] : 0.0, sdot);
-    sdot += __shfl_xor(sdot, 16);
-    sdot += __shfl_xor(sdot, 32);
+    sdot += lane_xor16(sdot);
+    sdot += lane_xor32(sdot);
     if (lane < R) red[w * R + k] = sdot;
     __syncthreads();
     if (t < R) {

@@ -313,8 +313,8 @@ __global__ __launch_bounds__(kR1Threads) void k_resid_1pass(const double* __rest
     double sx = 0.0;
 #pragma unroll
     for (int u = 0; u < kR1Per; ++u) sx = fma(d.a[u], xs[g + kR1Groups * u], sx);
-    sx += __shfl_xor(sx, 16);
-    sx += __shfl_xor(sx, 32);
+    sx += lane_xor16(sx);
+    sx += lane_xor32(sx);
     if (lane < kR1Rows) red[par][w][k] = sx;
     lds_barrier();
     double tot = 0.0;
