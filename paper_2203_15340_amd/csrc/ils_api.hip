@@ -19,6 +19,7 @@ ils_handle::~ils_handle() {
   for (auto& b : bufs) if (b.p) (void)hipFree(b.p);
   if (st) (void)hipFree(st);
   if (st_host) (void)hipHostFree(st_host);
+  if (st_map) (void)hipHostFree(st_map);
   if (ev0) (void)hipEventDestroy(ev0);
   if (ev1) (void)hipEventDestroy(ev1);
   for (auto& e : pev)
@@ -97,6 +98,9 @@ extern "C" int ils_create(ils_handle** out, int device_ordinal, void* hip_stream
   }
   if (hipMalloc((void**)&h->st, sizeof(LoopState)) != hipSuccess ||
       hipHostMalloc((void**)&h->st_host, sizeof(LoopState), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&h->st_map, sizeof(LoopState), hipHostMallocMapped | hipHostMallocCoherent) !=
+          hipSuccess ||
+      hipHostGetDevicePointer((void**)&h->st_map_dev, h->st_map, 0) != hipSuccess ||
       hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess) {
     delete h;
     return ILS_ERR_ALLOC;
@@ -367,6 +371,8 @@ int ils::sp_solve_op(ils_handle* h, const MatOp& M, const double* b, const doubl
   a.tol = o->tol;
   a.max_outer = o->max_outer;
   a.form = o->form;
+  a.mirror = h->st_map_dev;
+  *(volatile int*)&h->st_map->done = 0;  // the previous solve's work has drained
 
   // launch k computes x_{k+1} and decides on x_{k-1}; launch max_outer + 1
   // only decides
@@ -394,6 +400,18 @@ int ils::sp_solve_op(ils_handle* h, const MatOp& M, const double* b, const doubl
       launch_sp_step(s, a, k);
     }
     if (h->timing()) HIPCHK(hipEventRecord(h->ev1, s));
+    // the deciding launch wrote its outcome to the mapped mirror: once the
+    // stream has drained it is read there, with no copy; otherwise (a setup
+    // kernel raised a bit, or more launches are needed) the state is copied
+    if ((st = stream_wait(s))) return fail(info, st);
+    if (*(volatile int*)&h->st_map->done) {
+      h->st_host->done = h->st_map->done;
+      h->st_host->status = h->st_map->status;
+      h->st_host->iters = h->st_map->iters;
+      h->st_host->metric = h->st_map->metric;
+      h->st_host->bits = 0;
+      break;
+    }
     if ((st = read_state(h))) return fail(info, st);
     if (h->st_host->done || h->st_host->bits || k >= nlaunch) break;
     chunk = std::min<int64_t>(chunk * 2, 64);

@@ -328,6 +328,9 @@ struct SpStepArgs {
   double tol;
   int64_t max_outer;
   int form;
+  // mapped pinned host memory (device address) that the deciding launch also
+  // writes done, status, iters and metric to, or null
+  LoopState* mirror = nullptr;
 };
 int sp_step_blocks(int64_t n);
 void launch_sp_step(hipStream_t s, const SpStepArgs& a, int64_t k);

@@ -70,6 +70,11 @@ struct ils_handle {
   ils::Buf bufs[ils::kBufCount];
   ils::LoopState* st = nullptr;       // device
   ils::LoopState* st_host = nullptr;  // pinned host mirror
+  // mapped pinned host memory the SP step's deciding launch writes its
+  // outcome to (host address, device address), so the SP solve reads it
+  // without a device-to-host copy
+  ils::LoopState* st_map = nullptr;
+  ils::LoopState* st_map_dev = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   static constexpr int kPhases = 7;
   int profile = ILS_PROFILE_OFF;  // ILS_PROFILE_*

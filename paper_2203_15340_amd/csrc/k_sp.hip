@@ -101,7 +101,9 @@ __global__ __launch_bounds__(kSpThreads) void k_sp_step(SpStepArgs a, int64_t k)
   // this step's row loads go out first; their latency overlaps the stopping
   // test of the previous step
   double rv0[kDotDepth], vv0[kDotDepth];
-  if (i < a.n) dot_first(row, v, a.n, lane, rv0, vv0);
+  // x_0 = 0 in the paper form: x_1 = c, the rows of B are not read
+  const bool zero_v = first && !a.x0;
+  if (i < a.n && !zero_v) dot_first(row, v, a.n, lane, rv0, vv0);
   if (k >= 1) {
     // stopping test for x_{k-1} from the partials of launch k - 1: strided
     // per thread, then the block tree (the same order in every workgroup)
@@ -134,10 +136,18 @@ __global__ __launch_bounds__(kSpThreads) void k_sp_step(SpStepArgs a, int64_t k)
       const double* xs = (iters & 1) ? a.xbuf1 : a.xbuf0;
       if ((threadIdx.x & 63) == 0 && i < a.n) a.x_out[i] = xs[i];
       if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const int dv = (int)(k < INT_MAX - 1 ? k + 1 : INT_MAX);
         st->metric = metric;
         st->status = status;
         st->iters = iters;
-        st->done = (int)(k < INT_MAX - 1 ? k + 1 : INT_MAX);
+        st->done = dv;
+        if (a.mirror) {
+          // the host reads these once the stream has drained
+          a.mirror->metric = metric;
+          a.mirror->status = status;
+          a.mirror->iters = iters;
+          __hip_atomic_store(&a.mirror->done, dv, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
       }
       return;
     }
@@ -146,7 +156,7 @@ __global__ __launch_bounds__(kSpThreads) void k_sp_step(SpStepArgs a, int64_t k)
   double mp = 0.0, mpn = 0.0;
   int bad = 0;
   if (i < a.n) {
-    const double dot = dot_rest(row, v, a.n, lane, rv0, vv0);
+    const double dot = zero_v ? 0.0 : dot_rest(row, v, a.n, lane, rv0, vv0);
     const double xki = xk ? xk[i] : 0.0;
     if (first && lane == 0) a.xbuf0[i] = xki;
     const double xi = (a.form == ILS_FORM_PAPER) ? dot + a.c[i] : xki + dot;
