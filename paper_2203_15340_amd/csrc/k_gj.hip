@@ -721,6 +721,28 @@ __global__ __launch_bounds__(kGjThreads) void k_gj_flow_init(GjFlow a) {
     const int e = t + q * kGjThreads, r = e & (kNB - 1), c = e >> 6;
     dv[q] = (r < nb && c < nb) ? a.W[r + (int64_t)c * a.ldw] : (r == c ? 1.0 : 0.0);
   }
+  // every other load goes out before any store: the one-launch form has
+  // n <= kFlowMaxRows * 64, so each thread's entries are one batch
+  constexpr int kPer = kFlowMaxRows * kNB / kGjThreads;
+  double g1[kPer], g2[kPer], d1[kPer], d2[kPer], xr[kPer];
+  if (a.pre.g) {
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int64_t j = t + (int64_t)u * kGjThreads;
+      const bool in = j < a.n;
+      g1[u] = in ? a.pre.g[j] : 0.0;
+      g2[u] = in ? a.pre.g2[j] : 0.0;
+      d1[u] = in ? a.W[j + j * a.ldw] : 0.0;
+      d2[u] = in ? a.W[j + (a.n + j) * a.ldw] : 0.0;
+    }
+  }
+  if (a.ex.reset && a.ex.reset_xr) {
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int64_t j = t + (int64_t)u * kGjThreads;
+      xr[u] = j < a.n ? a.ex.reset_xr[j] : 0.0;
+    }
+  }
   const int64_t nint = 2 * (int64_t)a.R * a.S + 2 * a.R + 1;  // cnt, pdone, dflag, lflag, ticket
   for (int64_t e = t; e < nint; e += kGjThreads) a.cnt[e] = 0;
   if (a.ex.reset) {
@@ -731,7 +753,8 @@ __global__ __launch_bounds__(kGjThreads) void k_gj_flow_init(GjFlow a) {
     for (int e = t; e < kWords; e += kGjThreads) lw[e] = 0;
     if (a.ex.reset_xr) {
       double sq = 0.0;
-      for (int64_t i = t; i < a.n; i += kGjThreads) sq += a.ex.reset_xr[i] * a.ex.reset_xr[i];
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) sq += xr[u] * xr[u];
       sq = block_sum<kGjThreads>(sq, rsum);  // its barrier also orders the zeroing before the store
       if (t == 0) a.ex.reset->scal[1] = sq;
     }
@@ -739,20 +762,7 @@ __global__ __launch_bounds__(kGjThreads) void k_gj_flow_init(GjFlow a) {
   }
   if (a.pre.g) {
     // the right-hand-side column g = g1 - g2 and the screen of g and of the
-    // diagonals of the two Gram blocks (columns 0..n-1 and n..2n-1 of W); the
-    // one-launch form has n <= kFlowMaxRows * 64, so each thread's entries
-    // are loaded in one batch
-    constexpr int kPer = kFlowMaxRows * kNB / kGjThreads;
-    double g1[kPer], g2[kPer], d1[kPer], d2[kPer];
-#pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-      const int64_t j = t + (int64_t)u * kGjThreads;
-      const bool in = j < a.n;
-      g1[u] = in ? a.pre.g[j] : 0.0;
-      g2[u] = in ? a.pre.g2[j] : 0.0;
-      d1[u] = in ? a.W[j + j * a.ldw] : 0.0;
-      d2[u] = in ? a.W[j + (a.n + j) * a.ldw] : 0.0;
-    }
+    // diagonals of the two Gram blocks (columns 0..n-1 and n..2n-1 of W)
     int bad = 0;
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
