@@ -594,7 +594,7 @@ static double gs_line_min(const double* a, const double* v, double a_nrm2, int64
  * work counted in the cost remark after Alg. 2).  INCREMENTAL carries
  * s = w - A1 z instead: s gains the Kaczmarz move gamma a1 and loses the
  * Gauss-Seidel move delta a2; the iterates are the same in exact arithmetic.
- * Reading (inner "until convergence"): every inner_check steps, starting at
+ * Reading (the inner loops run to convergence): every inner_check steps, starting at
  * t = 0, stop if ||bhat - A1^T A1 z|| <= inner_tol * ||bhat|| (INCREMENTAL uses
  * A1 z = w - s); always stop after max_inner steps.  ORA_STOP_FIXED runs
  * exactly max_inner inner steps and max_outer outer steps. */
