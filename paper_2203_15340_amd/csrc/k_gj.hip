@@ -286,8 +286,10 @@ __global__ __launch_bounds__(kGjThreads) void k_gj_update(double* __restrict__ W
 // waits, by polling counters in device memory, only for the items whose
 // output it reads.  Items of step k (pivot block K = block row k):
 //   L_k        (k + 1 < R) update the next pivot block (k+1, k+1) with step
-//              k's pivot rows, formed here from D_k^{-1}, and invert it;
-//              the chain L_0 -> L_1 -> ... is the critical path;
+//              k's pivot rows, formed here from D_k^{-1} (the block is
+//              C - X^T D_k^{-1} X with X = W[K, k+1], C = W[k+1, k+1]: a
+//              symmetric Schur complement), and invert it; the chain
+//              L_0 -> L_1 -> ... is the critical path;
 //   P(k, j)    R_j = D_k^{-1} W[K, j] in place, for every trailing strip j;
 //   U(k, i, j) W[i, j] -= W[i, K] R_j for every row block i != k.
 // Strips are the 64-column blocks of W (the last pivot block may be short,
@@ -521,15 +523,13 @@ __global__ __launch_bounds__(kGjThreads, kFlowOcc) void k_gj_flow(GjFlow a) {
       // ---- L_k: D_{k+1} = W[k+1, k+1] - W[k+1, K] D_k^{-1} W[K, k+1], inverted
       const int64_t k1 = k0 + kNB;
       const int nbn = (int)(n - k1 < kNB ? n - k1 : kNB);
+      // the Schur complement is symmetric, so M = W[k+1, K] is taken as X^T:
+      // both tiles read here lie in strip k + 1
       bool ok = true;
-      if (t == 0 && k >= 1) {
-        ok = flow_wait(a.cnt + (k - 1) * a.S + k, flow_target(a, k - 1, k), a.bits) &&
-             flow_wait(a.cnt + (k - 1) * a.S + k + 1, flow_target(a, k - 1, k + 1), a.bits);
-      }
+      if (t == 0 && k >= 1) ok = flow_wait(a.cnt + (k - 1) * a.S + k + 1, flow_target(a, k - 1, k + 1), a.bits);
       if (!finish_wait(ok)) continue;
-      double xv[16], mv[16], cv[16];
+      double xv[16], cv[16];
       load_tile(xv, k0, k1, k0 + kNB, k1, ncols);  // X = W[K, k+1]
-      load_tile(mv, k1, k0, n, k0, k0 + kNB);      // M = W[k+1, K]
       load_out(cv, k1, k1, n, k1, ncols);          // C = W[k+1, k+1]
       stash_b(xv);                                 // X has been read
       __syncthreads();
@@ -543,7 +543,12 @@ __global__ __launch_bounds__(kGjThreads, kFlowOcc) void k_gj_flow(GjFlow a) {
       double acc[16];
       product(acc);  // R = D_k^{-1} X
       __syncthreads();
-      stash_a(mv);
+      // As[i][k] = M(i, k) = X(k, i)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int e = t + q * kGjThreads;
+        As[e >> 6][e & (kNB - 1)] = xv[q];
+      }
 #pragma unroll
       for (int x = 0; x < 2; ++x)
 #pragma unroll
