@@ -77,7 +77,8 @@ void launch_rk_draw(hipStream_t s, uint64_t seed, uint64_t outer, int64_t t0, in
 // replaced by the index); the alpha_t-th smallest key is found by an 8-pass
 // radix select over LDS histograms (each pass: histogram of the next byte of
 // the keys that share the selected prefix, a parallel prefix over the 256
-// bins), and tau_t is written as a bitmask, one wave ballot per 64 indices.
+// bins; the passes end once the selected byte holds a single key), and
+// tau_t is written as a bitmask, one wave ballot per 64 indices.
 __global__ __launch_bounds__(256) void k_scd_draw(uint64_t seed, uint64_t outer, int64_t t0,
                                                   int64_t n, int64_t alpha_opt, int norm_mode,
                                                   const double* __restrict__ prefix,
@@ -88,6 +89,8 @@ __global__ __launch_bounds__(256) void k_scd_draw(uint64_t seed, uint64_t outer,
   __shared__ unsigned wsum[4];
   __shared__ uint64_t sel_prefix;
   __shared__ int64_t sel_rank;
+  __shared__ int sel_one;
+  __shared__ uint64_t sel_key;
   const int64_t t = blockIdx.x;
   uint64_t out[4];
   philox4x64_10((uint64_t)(t0 + t), outer, 0, 0, seed, kTagScd, out);
@@ -114,6 +117,7 @@ __global__ __launch_bounds__(256) void k_scd_draw(uint64_t seed, uint64_t outer,
   if (threadIdx.x == 0) {
     sel_prefix = 0;
     sel_rank = alpha - 1;
+    sel_one = 0;
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int pass = 0; pass < 8; ++pass) {
@@ -145,10 +149,19 @@ __global__ __launch_bounds__(256) void k_scd_draw(uint64_t seed, uint64_t outer,
     if (h > 0 && before <= rank && rank < (int64_t)incl) {
       sel_rank = rank - before;
       sel_prefix = pre | ((uint64_t)threadIdx.x << shift);
+      sel_one = h == 1;
     }
     __syncthreads();
+    if (sel_one) {
+      // the selected byte holds one key: it is the key of rank alpha - 1
+      const uint64_t pm = ~0ull << shift, sp = sel_prefix;
+      for (int64_t s = threadIdx.x; s < n; s += 256)
+        if ((keys[s] & pm) == sp) sel_key = keys[s];
+      __syncthreads();
+      break;
+    }
   }
-  const uint64_t thr = sel_prefix;  // exact key of rank alpha - 1
+  const uint64_t thr = sel_one ? sel_key : sel_prefix;  // exact key of rank alpha - 1
   // bit s of tau_t: keys[s] <= thr, 64 bits per wave ballot
   for (int64_t base = 0; base < n; base += 256) {
     const int64_t s = base + threadIdx.x;
@@ -267,7 +280,20 @@ __global__ __launch_bounds__(256) void k_rk_check(const double* __restrict__ A1,
   const int64_t j = blockIdx.x;
   const double* col = A1 + j * lda;
   double sacc = 0.0;
-  for (int64_t i = threadIdx.x; i < p; i += 256) sacc += col[i] * v[i];
+  // eight loads of each operand in flight per thread per round; the sum
+  // runs over the rows in the same order as one row at a time
+  constexpr int U = 8;
+  for (int64_t i0 = 0; i0 < p; i0 += U * 256) {
+    double av[U], vv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = i0 + threadIdx.x + u * 256;
+      av[u] = i < p ? col[i] : 0.0;
+      vv[u] = i < p ? v[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) sacc += av[u] * vv[u];
+  }
   sacc = block_sum<256>(sacc, red);
   if (threadIdx.x == 0) {
     const double rj = tgt[j] - sacc;
