@@ -162,3 +162,28 @@ def test_unaligned_rows_fall_back():
     Ad = devA(A)
     G = ils.gram(Ad, 1, 6001).cpu().numpy()
     check_gram(G, A, 1, 6001)
+
+
+def test_resident_gram_is_reproducible(tmp_path):
+    # the resident launch reorders wave issue by arrival rank (counters that
+    # the reduction clears after each launch): the products and their order
+    # of summation are fixed, so repeated launches, here with a resident
+    # launch of the FP32 kind in between, give the same bits
+    K, n = 20000, 1000
+    A = np.random.default_rng(45).standard_normal((K, n))
+    f = tmp_path / "t.json"
+    entries = [{"kernel": "gram", "precision": prec, "n_bucket": bucket(n), "k_bucket": bucket(K), "tile": 64,
+                "workgroups": 4, "kind": ils.GRAM_PERSISTENT} for prec in (ils.PREC_FP64, ils.PREC_MIXED)]
+    f.write_text('{"version": 1, "entries": [\n  ' + ",\n  ".join(json.dumps(e) for e in entries) + "\n]}\n")
+    ils.tune_clear()
+    try:
+        ils.tune_load(f)
+        dA = devA(A)
+        G0 = ils.gram(dA, 0, K).cpu().numpy()
+        ils.gram(dA, 0, K, precision=ils.PREC_MIXED)
+        G1 = ils.gram(dA, 0, K).cpu().numpy()
+        G2 = ils.gram(dA, 0, K).cpu().numpy()
+        assert np.array_equal(G0, G1) and np.array_equal(G0, G2)
+        check_gram(G0, A, 0, K)
+    finally:
+        ils.tune_clear()
