@@ -531,11 +531,14 @@ __global__ __launch_bounds__(kGjThreads, kFlowOcc) void k_gj_flow(GjFlow a) {
       double xv[16], cv[16];
       load_tile(xv, k0, k1, k0 + kNB, k1, ncols);  // X = W[K, k+1]
       load_out(cv, k1, k1, n, k1, ncols);          // C = W[k+1, k+1]
+      // the first look at D_k^{-1}'s flag goes out with the tile loads
+      int dseen = 0;
+      if (t == 0) dseen = __hip_atomic_load(a.dflag + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       stash_b(xv);                                 // X has been read
       __syncthreads();
       if (t == 0) {
         __hip_atomic_fetch_add(a.lflag + k, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        ok = flow_wait(a.dflag + k, 1, a.bits);
+        ok = dseen >= 1 || flow_wait(a.dflag + k, 1, a.bits);
       }
       if (!finish_wait(ok)) continue;
       stash_dinv(a.dinv + (int64_t)k * kNB * kNB);
