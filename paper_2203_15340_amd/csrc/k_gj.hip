@@ -289,19 +289,37 @@ __global__ __launch_bounds__(kGjThreads) void k_gj_update(double* __restrict__ W
 //              k's pivot rows, formed here from D_k^{-1} (the block is
 //              C - X^T D_k^{-1} X with X = W[K, k+1], C = W[k+1, k+1]: a
 //              symmetric Schur complement), and invert it; the chain
-//              L_0 -> L_1 -> ... is the critical path;
+//              L_0 -> L_1 -> ... is the critical path, run in turn by the
+//              workgroup holding L_0's ticket, each inverse kept in its LDS;
 //   P(k, j)    R_j = D_k^{-1} W[K, j] in place, for every trailing strip j;
-//   U(k, i, j) W[i, j] -= W[i, K] R_j for every row block i != k.
+//   U(k, i, j) W[i, j] -= W[i, K] R_j for every row block i != k;
+//   PC(k)      when strip k+2 is a whole block of the matrix part, P(k, k+2)
+//              together with U(k, k+1, k+2) and U(k, k+2, k+2): the two tiles
+//              L_{k+1} reads, formed as soon as D_k^{-1} is out (their
+//              multipliers W[k+1, K] and W[k+2, K] taken, by the symmetry of
+//              the Schur complement, as the transposes of W[K, k+1] and
+//              W[K, k+2]), so the chain need not wait for the rest of the
+//              strip; the two U items then have nothing to do.
 // Strips are the 64-column blocks of W (the last pivot block may be short,
 // then its strip also holds right-hand-side columns).  Counters:
-//   cnt[k][j]   items of step k that have written strip j (R of them, R - 1
-//               for strip k+1, whose row k+1 belongs to L_k),
+//   tcnt[i][j]  steps that have updated tile (i, j) (block row i, strip j):
+//               every step k < j writes every tile of strip j once, except
+//               the pivot block (k+1, k+1) of L_k, so an item that needs the
+//               tile as of step k - 1 waits for tcnt >= k,
+//   cnt[k][j]   items of step k done with strip j (R of them, R - 1 for strip
+//               k+1, whose row k+1 belongs to L_k): U(k, k-1, j) overwrites the
+//               previous pivot row's tile, which every item of step k - 1 in
+//               strip j reads, so it waits for all of them,
 //   pdone[k][j] P(k, j) done,  dflag[k] D_k^{-1} published,
-//   lflag[k]    L_k has read W[K, k+1], which P(k, k+1) then overwrites.
-// Tickets are issued in step order (within a step: L_k, the P items, then the
-// U items strip by strip), and an item only waits for items with smaller
-// tickets, which are held by running workgroups; so every wait ends.  A
-// bounded spin still raises kBitStall rather than hanging if one did not.
+//   lflag[k]    L_k (and PC(k)) have read W[K, k+1], which P(k, k+1) then
+//               overwrites.
+// Tickets are issued in step order (within a step: L_k, PC(k), the P items,
+// then the U items strip by strip; in a strip, the rows below the pivot
+// first).  An item only waits for items with smaller tickets, which are held
+// by running workgroups, or for the chain's inverses and flags; the chain's
+// link k waits only for items of step k - 1, which need nothing from it
+// beyond D_{k-1}^{-1}; so every wait ends.  A bounded spin still raises
+// kBitStall rather than hanging if one did not.
 constexpr int kFlowMaxRows = 32;
 constexpr int kFlowOcc = 1;  // workgroups per CU
 constexpr int kFlowWgs = 256 * kFlowOcc;
@@ -312,6 +330,7 @@ struct GjFlow {
   int64_t ldw, n, ncols;
   int R, S;
   double* dinv;  // R blocks of 64 x 64, row-major
+  int* tcnt;     // R x S
   int* cnt;      // R x S
   int* pdone;    // R x S
   int* dflag;    // R
@@ -341,9 +360,32 @@ __device__ inline FlowStep flow_step(const GjFlow& a, int k) {
   return f;
 }
 
-// writers of strip j at step k (see above)
+// whether step k has a PC item (see above)
+__device__ inline bool flow_pc(const GjFlow& a, int k) { return (int64_t)(k + 3) * kNB <= a.n; }
+
+// the value of tcnt[i][j] once tile (i, j) is as of step k - 1 (the pivot
+// block (j, j) is not written at step j - 1)
+__device__ inline int tile_need(int i, int j, int k) { return (i == j && k >= j) ? j - 1 : k; }
+__device__ inline int* tile_cnt(const GjFlow& a, int i, int j) { return a.tcnt + i * a.S + j; }
+
+// items of step k that finish with strip j (see above)
 __device__ inline int flow_target(const GjFlow& a, int k, int j) {
   return (k + 1 < a.R && j == k + 1) ? a.R - 1 : a.R;
+}
+
+// Thread 0 polls until *p >= tp and *q >= tq (both read in one round trip).
+__device__ inline bool flow_wait2(const int* p, int tp, const int* q, int tq, int* bits) {
+  for (int spin = 0;; ++spin) {
+    const int vp = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int vq = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (vp >= tp && vq >= tq) return true;
+    if (__hip_atomic_load(bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+    if (spin >= kSpinLimit) {
+      atomicOr(bits, kBitStall);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
 }
 
 // Thread 0 polls until *p >= target; false if the bits were raised meanwhile.
@@ -470,8 +512,9 @@ __global__ __launch_bounds__(kGjThreads, kFlowOcc) void k_gj_flow(GjFlow a) {
       As[e >> 6][e & (kNB - 1)] = v[q];
     }
   };
-  // acc (output layout) = A B over the full 64-deep contraction
-  auto product = [&](double (&acc)[16]) {
+  // acc (output layout) = A B over the full 64-deep contraction, A from Ao
+  // (Ao[i][k] = A(i, k)), B from Bs
+  auto product_a = [&](double (&acc)[16], const double (*Ao)[kNB + 1]) {
     v4d c4[2][2];
 #pragma unroll
     for (int x = 0; x < 2; ++x)
@@ -481,7 +524,7 @@ __global__ __launch_bounds__(kGjThreads, kFlowOcc) void k_gj_flow(GjFlow a) {
     for (int kk = 0; kk < kNB; kk += 4) {
       const int kr = kk + (lane >> 4);
       const double b0 = Bs[jr + lr][kr], b1 = Bs[jr + 16 + lr][kr];
-      const double a0 = As[ic + lr][kr], a1 = As[ic + 16 + lr][kr];
+      const double a0 = Ao[ic + lr][kr], a1 = Ao[ic + 16 + lr][kr];
       c4[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, a0, c4[0][0], 0, 0, 0);
       c4[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, a1, c4[0][1], 0, 0, 0);
       c4[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1, a0, c4[1][0], 0, 0, 0);
@@ -494,6 +537,7 @@ __global__ __launch_bounds__(kGjThreads, kFlowOcc) void k_gj_flow(GjFlow a) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) acc[(x * 2 + y) * 4 + u] = c4[x][y][u];
   };
+  auto product = [&](double (&acc)[16]) { product_a(acc, As); };
   // thread 0 runs the waits; every thread learns the outcome
   auto finish_wait = [&](bool ok) {
     if (t == 0) s_ok = ok;
@@ -520,22 +564,169 @@ __global__ __launch_bounds__(kGjThreads, kFlowOcc) void k_gj_flow(GjFlow a) {
     const int64_t k0 = (int64_t)k * kNB;
     const int R = a.R;
     if (f.hasL && u == 0) {
-      // ---- L_k: D_{k+1} = W[k+1, k+1] - W[k+1, K] D_k^{-1} W[K, k+1], inverted
-      const int64_t k1 = k0 + kNB;
-      const int nbn = (int)(n - k1 < kNB ? n - k1 : kNB);
-      // the Schur complement is symmetric, so M = W[k+1, K] is taken as X^T:
-      // both tiles read here lie in strip k + 1
+      // ---- the chain: L_0, L_1, ... in this one workgroup, each inverse kept in
+      // LDS for the next link (the later L_k tickets have nothing to do)
+      if (k > 0) continue;
+      for (int kc = 0; kc + 1 < R; ++kc) {
+        // L_k: D_{k+1} = W[k+1, k+1] - W[k+1, K] D_k^{-1} W[K, k+1], inverted
+        const int k = kc;
+        const int64_t k0 = (int64_t)k * kNB, k1 = k0 + kNB;
+        const int nbn = (int)(n - k1 < kNB ? n - k1 : kNB);
+        // the Schur complement is symmetric, so M = W[k+1, K] is taken as X^T:
+        // both tiles read here lie in strip k + 1
+        bool ok = true;
+        if (t == 0 && k >= 1)
+          ok = flow_wait2(tile_cnt(a, k, k + 1), k, tile_cnt(a, k + 1, k + 1), k, a.bits);
+        if (!finish_wait(ok)) break;
+        double xv[16], cv[16];
+        load_tile(xv, k0, k1, k0 + kNB, k1, ncols);  // X = W[K, k+1]
+        load_out(cv, k1, k1, n, k1, ncols);          // C = W[k+1, k+1]
+        // the first look at D_k^{-1}'s flag goes out with the tile loads
+        int dseen = 0;
+        if (t == 0 && k == 0) dseen = __hip_atomic_load(a.dflag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        stash_b(xv);                                 // X has been read
+        __syncthreads();
+        if (t == 0) {
+          __hip_atomic_fetch_add(a.lflag + k, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (k == 0) ok = dseen >= 1 || flow_wait(a.dflag, 1, a.bits);
+        }
+        if (!finish_wait(ok)) break;
+        double acc[16];
+        if (k == 0) {
+          stash_dinv(a.dinv);
+          __syncthreads();
+          product(acc);  // R = D_0^{-1} X
+        } else {
+          product_a(acc, Ds);  // R = D_k^{-1} X, D_k^{-1} left in Ds by the previous link
+        }
+        __syncthreads();
+        // As[i][k] = M(i, k) = X(k, i)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const int e = t + q * kGjThreads;
+          As[e >> 6][e & (kNB - 1)] = xv[q];
+        }
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int j = jr + x * 16 + (lane >> 4) + 4 * q, i = ic + y * 16 + lr;
+              Bs[j][i] = acc[(x * 2 + y) * 4 + q];
+              Ds[i][j] = cv[(x * 2 + y) * 4 + q];  // C, row-major
+            }
+        __syncthreads();
+        bool inv_ok;
+        double(*Dinv)[kNB + 1];
+        if (nbn == kNB) {
+          // D = C - M R is symmetric: its lower 16 x 16 blocks are formed and
+          // mirrored, and wave 0 takes block (0, 0) alone and inverts it while
+          // waves 1-3 form the other nine
+          const int li = lane & 15, lg = lane >> 4;
+          auto block_d = [&](int bi, int bj) {
+            v4d d = ld16(&Ds[16 * bi][16 * bj], kLds, lane);
+#pragma unroll
+            for (int kk = 0; kk < kNB; kk += 4) {
+              const int kr = kk + lg;
+              d = __builtin_amdgcn_mfma_f64_16x16x4f64(-As[16 * bi + li][kr], Bs[16 * bj + li][kr], d, 0, 0, 0);
+            }
+            return d;
+          };
+          if (w == 0) {
+            st16(&Ds[0][0], kLds, block_d(0, 0), lane);
+            __threadfence_block();
+            double av[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) av[c] = Ds[li][4 * lg + c];
+            const bool okl = leaf_inv16(av, lane);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) inv.x[li][4 * lg + c] = av[c];
+            if (lane == 0) inv.bad = okl ? 0 : 1;
+          } else {
+            // (1,0) (1,1) (2,0) | (2,1) (2,2) (3,0) | (3,1) (3,2) (3,3)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+              const int e = 3 * (w - 1) + q;
+              const int bi = e < 2 ? 1 : (e < 5 ? 2 : 3);
+              const int bj = e - (bi == 1 ? 0 : (bi == 2 ? 2 : 5));
+              const v4d d = block_d(bi, bj);
+              st16(&Ds[16 * bi][16 * bj], kLds, d, lane);
+              if (bi != bj) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) Ds[16 * bj + li][16 * bi + lg + 4 * u] = d[u];
+              }
+            }
+          }
+          __syncthreads();
+          if (w == 0) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) Bs[li][4 * lg + c] = inv.x[li][4 * lg + c];
+          }
+          __syncthreads();
+          inv_ok = invert64_steps(&Ds[0][0], &Bs[0][0], inv);
+          Dinv = Ds;
+        } else {
+          product(acc);  // M R
+#pragma unroll
+          for (int q = 0; q < 16; ++q) cv[q] -= acc[q];
+          // right-hand-side columns sharing the short last block's strip
+          store_out(cv, k1, k1, n, k1 + nbn, ncols);
+          __syncthreads();
+#pragma unroll
+          for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int y = 0; y < 2; ++y)
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                const int j = jr + x * 16 + (lane >> 4) + 4 * q, i = ic + y * 16 + lr;
+                As[i][j] = (i < nbn && j < nbn) ? cv[(x * 2 + y) * 4 + q] : (i == j ? 1.0 : 0.0);
+              }
+          __syncthreads();
+          inv_ok = invert64_blk(&As[0][0], &Bs[0][0], inv);
+          Dinv = As;
+        }
+        if (!inv_ok) {
+          if (t == 0) atomicOr(a.bits, kBitNotSpd);
+          break;
+        }
+        double* dn = a.dinv + (int64_t)(k + 1) * kNB * kNB;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const int e = t + q * kGjThreads;
+          ast(dn + e, Dinv[e >> 6][e & (kNB - 1)]);
+        }
+        flow_signal(a.dflag + k + 1);  // also: every wave has read Dinv
+      }
+      continue;
+    }
+    if (f.hasL) --u;
+    const bool pc = flow_pc(a, k);
+    if (pc && u == 0) {
+      // ---- PC(k): R = D_k^{-1} W[K, k+2] in place, then
+      // W[k+1, k+2] -= X^T R and W[k+2, k+2] -= W[K, k+2]^T R (X = W[K, k+1])
+      const int64_t k1 = k0 + kNB, k2 = k1 + kNB;
       bool ok = true;
-      if (t == 0 && k >= 1) ok = flow_wait(a.cnt + (k - 1) * a.S + k + 1, flow_target(a, k - 1, k + 1), a.bits);
+      if (t == 0 && k >= 1) {
+        ok = flow_wait(tile_cnt(a, k, k + 1), k, a.bits) && flow_wait(tile_cnt(a, k, k + 2), k, a.bits) &&
+             flow_wait(tile_cnt(a, k + 1, k + 2), k, a.bits) && flow_wait(tile_cnt(a, k + 2, k + 2), k, a.bits);
+      }
       if (!finish_wait(ok)) continue;
-      double xv[16], cv[16];
+      double xv[16], pv[16], c1[16], c2[16];
       load_tile(xv, k0, k1, k0 + kNB, k1, ncols);  // X = W[K, k+1]
-      load_out(cv, k1, k1, n, k1, ncols);          // C = W[k+1, k+1]
-      // the first look at D_k^{-1}'s flag goes out with the tile loads
+      load_tile(pv, k0, k2, k0 + kNB, k2, ncols);  // W[K, k+2]
+      load_out(c1, k1, k2, n, k2, ncols);          // W[k+1, k+2]
+      load_out(c2, k2, k2, n, k2, ncols);          // W[k+2, k+2]
       int dseen = 0;
       if (t == 0) dseen = __hip_atomic_load(a.dflag + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      stash_b(xv);                                 // X has been read
-      __syncthreads();
+      // Ds[i][k] = X(k, i): the multiplier W[k+1, K]
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int e = t + q * kGjThreads;
+        Ds[e >> 6][e & (kNB - 1)] = xv[q];
+      }
+      stash_b(pv);
+      __syncthreads();  // X has been read
       if (t == 0) {
         __hip_atomic_fetch_add(a.lflag + k, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         ok = dseen >= 1 || flow_wait(a.dflag + k, 1, a.bits);
@@ -544,14 +735,11 @@ __global__ __launch_bounds__(kGjThreads, kFlowOcc) void k_gj_flow(GjFlow a) {
       stash_dinv(a.dinv + (int64_t)k * kNB * kNB);
       __syncthreads();
       double acc[16];
-      product(acc);  // R = D_k^{-1} X
-      __syncthreads();
-      // As[i][k] = M(i, k) = X(k, i)
-#pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const int e = t + q * kGjThreads;
-        As[e >> 6][e & (kNB - 1)] = xv[q];
-      }
+      product(acc);  // R
+      store_out(acc, k0, k2, k0 + kNB, k2, ncols);
+      flow_signal(a.pdone + k * a.S + k + 2);  // every wave is past the product
+      if (t == 0) __hip_atomic_fetch_add(tile_cnt(a, k, k + 2), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      // Bs[j][k] = R(k, j); As[i][k] = W[K, k+2](k, i): the multiplier W[k+2, K]
 #pragma unroll
       for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -560,101 +748,39 @@ __global__ __launch_bounds__(kGjThreads, kFlowOcc) void k_gj_flow(GjFlow a) {
           for (int q = 0; q < 4; ++q) {
             const int j = jr + x * 16 + (lane >> 4) + 4 * q, i = ic + y * 16 + lr;
             Bs[j][i] = acc[(x * 2 + y) * 4 + q];
-            Ds[i][j] = cv[(x * 2 + y) * 4 + q];  // C, row-major
           }
-      __syncthreads();
-      bool inv_ok;
-      double(*Dinv)[kNB + 1];
-      if (nbn == kNB) {
-        // D = C - M R is symmetric: its lower 16 x 16 blocks are formed and
-        // mirrored, and wave 0 takes block (0, 0) alone and inverts it while
-        // waves 1-3 form the other nine
-        const int li = lane & 15, lg = lane >> 4;
-        auto block_d = [&](int bi, int bj) {
-          v4d d = ld16(&Ds[16 * bi][16 * bj], kLds, lane);
-#pragma unroll
-          for (int kk = 0; kk < kNB; kk += 4) {
-            const int kr = kk + lg;
-            d = __builtin_amdgcn_mfma_f64_16x16x4f64(-As[16 * bi + li][kr], Bs[16 * bj + li][kr], d, 0, 0, 0);
-          }
-          return d;
-        };
-        if (w == 0) {
-          st16(&Ds[0][0], kLds, block_d(0, 0), lane);
-          __threadfence_block();
-          double av[4];
-#pragma unroll
-          for (int c = 0; c < 4; ++c) av[c] = Ds[li][4 * lg + c];
-          const bool okl = leaf_inv16(av, lane);
-#pragma unroll
-          for (int c = 0; c < 4; ++c) inv.x[li][4 * lg + c] = av[c];
-          if (lane == 0) inv.bad = okl ? 0 : 1;
-        } else {
-          // (1,0) (1,1) (2,0) | (2,1) (2,2) (3,0) | (3,1) (3,2) (3,3)
-#pragma unroll
-          for (int q = 0; q < 3; ++q) {
-            const int e = 3 * (w - 1) + q;
-            const int bi = e < 2 ? 1 : (e < 5 ? 2 : 3);
-            const int bj = e - (bi == 1 ? 0 : (bi == 2 ? 2 : 5));
-            const v4d d = block_d(bi, bj);
-            st16(&Ds[16 * bi][16 * bj], kLds, d, lane);
-            if (bi != bj) {
-#pragma unroll
-              for (int u = 0; u < 4; ++u) Ds[16 * bj + li][16 * bi + lg + 4 * u] = d[u];
-            }
-          }
-        }
-        __syncthreads();
-        if (w == 0) {
-#pragma unroll
-          for (int c = 0; c < 4; ++c) Bs[li][4 * lg + c] = inv.x[li][4 * lg + c];
-        }
-        __syncthreads();
-        inv_ok = invert64_steps(&Ds[0][0], &Bs[0][0], inv);
-        Dinv = Ds;
-      } else {
-        product(acc);  // M R
-#pragma unroll
-        for (int q = 0; q < 16; ++q) cv[q] -= acc[q];
-        // right-hand-side columns sharing the short last block's strip
-        store_out(cv, k1, k1, n, k1 + nbn, ncols);
-        __syncthreads();
-#pragma unroll
-        for (int x = 0; x < 2; ++x)
-#pragma unroll
-          for (int y = 0; y < 2; ++y)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              const int j = jr + x * 16 + (lane >> 4) + 4 * q, i = ic + y * 16 + lr;
-              As[i][j] = (i < nbn && j < nbn) ? cv[(x * 2 + y) * 4 + q] : (i == j ? 1.0 : 0.0);
-            }
-        __syncthreads();
-        inv_ok = invert64_blk(&As[0][0], &Bs[0][0], inv);
-        Dinv = As;
-      }
-      if (!inv_ok) {
-        if (t == 0) atomicOr(a.bits, kBitNotSpd);
-        continue;
-      }
-      double* dn = a.dinv + (int64_t)(k + 1) * kNB * kNB;
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         const int e = t + q * kGjThreads;
-        ast(dn + e, Dinv[e >> 6][e & (kNB - 1)]);
+        As[e >> 6][e & (kNB - 1)] = pv[q];
       }
-      flow_signal(a.dflag + k + 1);
+      __syncthreads();
+      product(acc);  // W[k+2, K] R
+#pragma unroll
+      for (int q = 0; q < 16; ++q) c2[q] -= acc[q];
+      product_a(acc, Ds);  // W[k+1, K] R
+#pragma unroll
+      for (int q = 0; q < 16; ++q) c1[q] -= acc[q];
+      store_out(c1, k1, k2, n, k2, ncols);
+      store_out(c2, k2, k2, n, k2, ncols);
+      wait_stores();
+      __syncthreads();
+      if (t == 0) {
+        __hip_atomic_fetch_add(tile_cnt(a, k + 1, k + 2), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(tile_cnt(a, k + 2, k + 2), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(a.cnt + k * a.S + k + 2, 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
       continue;
     }
-    if (f.hasL) --u;
     if (u < f.nP) {
       // ---- P(k, j): R_j = D_k^{-1} W[K, j]
-      const int j = f.j0 + u;
+      const int j = pc ? (u == 1 ? k + 1 : f.j0 + u) : f.j0 + u;
       const int64_t cj = (int64_t)j * kNB;
       bool ok = true;
       if (t == 0) {
         ok = flow_wait(a.dflag + k, 1, a.bits);
-        if (ok && k >= 1) ok = flow_wait(a.cnt + (k - 1) * a.S + j, flow_target(a, k - 1, j), a.bits);
-        if (ok && f.hasL && j == k + 1) ok = flow_wait(a.lflag + k, 1, a.bits);
+        if (ok && k >= 1) ok = flow_wait(tile_cnt(a, k, j), tile_need(k, j, k), a.bits);
+        if (ok && f.hasL && j == k + 1) ok = flow_wait(a.lflag + k, pc ? 2 : 1, a.bits);
       }
       if (!finish_wait(ok)) continue;
       double xv[16];
@@ -666,33 +792,38 @@ __global__ __launch_bounds__(kGjThreads, kFlowOcc) void k_gj_flow(GjFlow a) {
       product(acc);
       store_out(acc, k0, cj, k0 + f.nb, f.c0, ncols);
       flow_signal(a.pdone + k * a.S + j);
-      if (t == 0) __hip_atomic_fetch_add(a.cnt + k * a.S + j, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (t == 0) {
+        __hip_atomic_fetch_add(tile_cnt(a, k, j), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(a.cnt + k * a.S + j, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
       if (a.ex.bt && k == R - 1) store_bt(acc, k0, cj);
       continue;
     }
     u -= f.nP;
     // ---- U(k, i, j): W[i, j] -= W[i, K] R_j
+    // (rows in each strip from the one below the pivot down, then from the top:
+    // the tiles the next pivot steps read first)
     int i, j;
     if (f.hasL) {
       if (u < R - 2) {
         j = k + 1;
-        i = u < k ? u : u + 2;
+        i = (k + 2 + u) % R;
       } else {
         u -= R - 2;
         j = k + 2 + u / (R - 1);
-        const int r = u % (R - 1);
-        i = r < k ? r : r + 1;
+        i = (k + 1 + u % (R - 1)) % R;
       }
     } else {
       j = f.j0 + u / (R - 1);
-      const int r = u % (R - 1);
-      i = r < k ? r : r + 1;
+      i = (k + 1 + u % (R - 1)) % R;
     }
+    if (pc && j == k + 2 && (i == k + 1 || i == k + 2)) continue;  // formed by PC(k)
     const int64_t ri = (int64_t)i * kNB, cj = (int64_t)j * kNB;
     bool ok = true;
     if (t == 0) {
       ok = flow_wait(a.pdone + k * a.S + j, 1, a.bits);
-      if (ok && k >= 1) ok = flow_wait(a.cnt + (k - 1) * a.S + k, flow_target(a, k - 1, k), a.bits);
+      if (ok && k >= 1) ok = flow_wait(tile_cnt(a, i, k), k, a.bits) && flow_wait(tile_cnt(a, i, j), tile_need(i, j, k), a.bits);
+      if (ok && i == k - 1) ok = flow_wait(a.cnt + (k - 1) * a.S + j, flow_target(a, k - 1, j), a.bits);
     }
     if (!finish_wait(ok)) continue;
     double mv[16], rv[16], cv[16];
@@ -707,7 +838,8 @@ __global__ __launch_bounds__(kGjThreads, kFlowOcc) void k_gj_flow(GjFlow a) {
 #pragma unroll
     for (int q = 0; q < 16; ++q) cv[q] -= acc[q];
     store_out(cv, ri, cj, n, f.c0, ncols);
-    flow_signal(a.cnt + k * a.S + j);
+    flow_signal(tile_cnt(a, i, j));
+    if (t == 0) __hip_atomic_fetch_add(a.cnt + k * a.S + j, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (a.ex.bt && k == R - 1) store_bt(cv, ri, cj);
   }
 }
@@ -751,8 +883,8 @@ __global__ __launch_bounds__(kGjThreads) void k_gj_flow_init(GjFlow a) {
       xr[u] = j < a.n ? a.ex.reset_xr[j] : 0.0;
     }
   }
-  const int64_t nint = 2 * (int64_t)a.R * a.S + 2 * a.R + 1;  // cnt, pdone, dflag, lflag, ticket
-  for (int64_t e = t; e < nint; e += kGjThreads) a.cnt[e] = 0;
+  const int64_t nint = 3 * (int64_t)a.R * a.S + 2 * a.R + 1;  // tcnt, cnt, pdone, dflag, lflag, ticket
+  for (int64_t e = t; e < nint; e += kGjThreads) a.tcnt[e] = 0;
   if (a.ex.reset) {
     // the loop state cleared (its bits included) before anything below can
     // raise a bit, and ||x_ref||^2 for the relative error
@@ -814,7 +946,7 @@ size_t gj_scratch_bytes(int64_t n, int64_t ncols) {
   size_t b = sizeof(double) * 2 * kNB * kNB;  // the step-by-step form
   if (flow_fits(n)) {
     const int64_t R = (n + kNB - 1) / kNB, S = (ncols + kNB - 1) / kNB;
-    const size_t f = sizeof(double) * R * kNB * kNB + sizeof(int) * (2 * R * S + 2 * R + 1);
+    const size_t f = sizeof(double) * R * kNB * kNB + sizeof(int) * (3 * R * S + 2 * R + 1);
     if (f > b) b = f;
   }
   return b;
@@ -834,7 +966,8 @@ void launch_gj(hipStream_t s, int64_t n, int64_t nrhs, double* W, int64_t ldw, v
     a.R = row_tiles;
     a.S = (int)((ncols + kNB - 1) / kNB);
     a.dinv = (double*)scratch;
-    a.cnt = (int*)(a.dinv + (int64_t)a.R * kNB * kNB);
+    a.tcnt = (int*)(a.dinv + (int64_t)a.R * kNB * kNB);
+    a.cnt = a.tcnt + a.R * a.S;
     a.pdone = a.cnt + a.R * a.S;
     a.dflag = a.pdone + a.R * a.S;
     a.lflag = a.dflag + a.R;

@@ -134,11 +134,14 @@ def test_spd_solve(prob):
     assert_close(host(X), np.linalg.solve(G1, R), 1e-12)
 
 
-@pytest.mark.parametrize("n,nrhs", [(1, 1), (63, 2), (64, 64), (65, 1), (128, 129), (129, 64), (300, 301),
+@pytest.mark.parametrize("n,nrhs", [(1, 1), (63, 2), (64, 64), (65, 1), (128, 129), (129, 64), (192, 3), (300, 301),
+                                    (320, 1),
                                     (960, 1), (1000, 1001), (2047, 3), (2048, 2049), (2049, 2),
                                     (2112, 5), (2148, 7), (4096, 3), (4097, 2)])
 def test_spd_solve_block_edges(n, nrhs):
-    # block edges of the 64-wide Gauss-Jordan: one block, exact multiples, ragged tails;
+    # block edges of the 64-wide Gauss-Jordan: one block, exact multiples, ragged tails
+    # (192 and 320: the last pivot block whole, formed ahead of the chain with its
+    # row; 300: the ragged block after such steps);
     # up to 32 block rows the elimination is one dataflow launch, above it one
     # launch pair per block step (2048 / 2049, and 2112 / 2148 ending on a
     # full and a ragged block); 4096 and 4097 are the large step-by-step cases
