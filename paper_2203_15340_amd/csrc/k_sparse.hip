@@ -347,8 +347,20 @@ void launch_sparse_gram(hipStream_t s, const ils_csr& A, int second, double* G, 
 // The incremental inner step of Alg. 2 (s = w - A1 z) with the A1 part of
 // columns j1, j2 read from the CSC copy.  Rows of the two columns overlap in
 // general, so the s update of the Kaczmarz half is made visible to the whole
-// workgroup (barrier) before the Gauss-Seidel half reads it.
+// workgroup (barrier) before the Gauss-Seidel half reads it.  The column
+// draws do not depend on the iterate, so the next step's column data (its
+// indices, offsets, lengths, targets, norms, and the row indices and values
+// of both columns) are loaded during the current step; a step then waits only
+// on its gathers of w and s and its two block sums.  Columns longer than
+// kRkSpQ entries per thread take the loop form.
 constexpr int kRkSpThreads = 1024;
+constexpr int kRkSpQ = 2;
+
+struct RkSpMeta {
+  int j1, j2;
+  int64_t b1, l1, b2, l2;
+  double tg, c1, c2;
+};
 
 __global__ __launch_bounds__(kRkSpThreads) void k_rk_inner_csc(
     const int64_t* __restrict__ colptr, const int32_t* __restrict__ rowidx, const double* __restrict__ cval,
@@ -358,27 +370,112 @@ __global__ __launch_bounds__(kRkSpThreads) void k_rk_inner_csc(
   if (*(volatile const int*)inner_done || *(volatile const int*)outer_done) return;
   __shared__ double red[2][kRkSpThreads / kWave];
   const int tid = threadIdx.x;
-  for (int64_t t = 0; t < count; ++t) {
-    const int j1 = j1s[t], j2 = j2s[t];
-    const int64_t b1 = colptr[j1], l1 = a1len[j1], b2 = colptr[j2], l2 = a1len[j2];
-    double d = 0.0;
-    for (int64_t e = tid; e < l1; e += kRkSpThreads) d += cval[b1 + e] * w[rowidx[b1 + e]];
-    d = block_sum<kRkSpThreads>(d, red[0]);
-    const double gam = (tgt[j1] - d) / cn[j1];
-    for (int64_t e = tid; e < l1; e += kRkSpThreads) {
-      const int64_t r = rowidx[b1 + e];
-      const double av = cval[b1 + e];
-      w[r] += gam * av;
-      s[r] += gam * av;
+  auto meta_of = [&](int64_t t) {
+    RkSpMeta m;
+    m.j1 = j1s[t];
+    m.j2 = j2s[t];
+    m.b1 = colptr[m.j1];
+    m.l1 = a1len[m.j1];
+    m.b2 = colptr[m.j2];
+    m.l2 = a1len[m.j2];
+    m.tg = tgt[m.j1];
+    m.c1 = cn[m.j1];
+    m.c2 = cn[m.j2];
+    return m;
+  };
+  auto fits = [&](const RkSpMeta& m) { return m.l1 <= kRkSpQ * kRkSpThreads && m.l2 <= kRkSpQ * kRkSpThreads; };
+  // this thread's entries e = tid + q T of both columns (row -1: none)
+  int32_t r1[kRkSpQ], r2[kRkSpQ], n1[kRkSpQ], n2[kRkSpQ];
+  double v1[kRkSpQ], v2[kRkSpQ], u1[kRkSpQ], u2[kRkSpQ];
+  auto cols_of = [&](const RkSpMeta& m, int32_t (&ra)[kRkSpQ], double (&va)[kRkSpQ], int32_t (&rb)[kRkSpQ],
+                     double (&vb)[kRkSpQ]) {
+#pragma unroll
+    for (int q = 0; q < kRkSpQ; ++q) {
+      const int64_t e = tid + (int64_t)q * kRkSpThreads;
+      const bool in1 = e < m.l1, in2 = e < m.l2;
+      ra[q] = in1 ? rowidx[m.b1 + e] : -1;
+      va[q] = in1 ? cval[m.b1 + e] : 0.0;
+      rb[q] = in2 ? rowidx[m.b2 + e] : -1;
+      vb[q] = in2 ? cval[m.b2 + e] : 0.0;
     }
-    __syncthreads();
-    double d2 = 0.0;
-    for (int64_t e = tid; e < l2; e += kRkSpThreads) d2 += cval[b2 + e] * s[rowidx[b2 + e]];
-    d2 = block_sum<kRkSpThreads>(d2, red[1]);
-    const double del = d2 / cn[j2];
-    if (tid == 0) z[j2] += del;
-    for (int64_t e = tid; e < l2; e += kRkSpThreads) s[rowidx[b2 + e]] -= del * cval[b2 + e];
-    __syncthreads();
+  };
+  if (count <= 0) return;
+#pragma unroll
+  for (int q = 0; q < kRkSpQ; ++q) {
+    n1[q] = n2[q] = -1;
+    u1[q] = u2[q] = 0.0;
+  }
+  RkSpMeta m = meta_of(0);
+  if (fits(m)) cols_of(m, r1, v1, r2, v2);
+  for (int64_t t = 0; t < count; ++t) {
+    const bool has_next = t + 1 < count;
+    RkSpMeta mn = m;
+    if (has_next) mn = meta_of(t + 1);
+    if (fits(m)) {
+      double wv[kRkSpQ], sv[kRkSpQ];
+#pragma unroll
+      for (int q = 0; q < kRkSpQ; ++q) {
+        wv[q] = r1[q] >= 0 ? w[r1[q]] : 0.0;
+        sv[q] = r1[q] >= 0 ? s[r1[q]] : 0.0;
+      }
+      double d = 0.0;
+#pragma unroll
+      for (int q = 0; q < kRkSpQ; ++q)
+        if (r1[q] >= 0) d += v1[q] * wv[q];
+      d = block_sum<kRkSpThreads>(d, red[0]);
+      const double gam = (m.tg - d) / m.c1;
+#pragma unroll
+      for (int q = 0; q < kRkSpQ; ++q)
+        if (r1[q] >= 0) {
+          w[r1[q]] = wv[q] + gam * v1[q];
+          s[r1[q]] = sv[q] + gam * v1[q];
+        }
+      // the next step's columns go out while this one finishes
+      if (has_next && fits(mn)) cols_of(mn, n1, u1, n2, u2);
+      __syncthreads();
+      double s2[kRkSpQ];
+#pragma unroll
+      for (int q = 0; q < kRkSpQ; ++q) s2[q] = r2[q] >= 0 ? s[r2[q]] : 0.0;
+      double d2 = 0.0;
+#pragma unroll
+      for (int q = 0; q < kRkSpQ; ++q)
+        if (r2[q] >= 0) d2 += v2[q] * s2[q];
+      d2 = block_sum<kRkSpThreads>(d2, red[1]);
+      const double del = d2 / m.c2;
+      if (tid == 0) z[m.j2] += del;
+#pragma unroll
+      for (int q = 0; q < kRkSpQ; ++q)
+        if (r2[q] >= 0) s[r2[q]] = s2[q] - del * v2[q];
+      __syncthreads();
+    } else {
+      double d = 0.0;
+      for (int64_t e = tid; e < m.l1; e += kRkSpThreads) d += cval[m.b1 + e] * w[rowidx[m.b1 + e]];
+      d = block_sum<kRkSpThreads>(d, red[0]);
+      const double gam = (m.tg - d) / m.c1;
+      for (int64_t e = tid; e < m.l1; e += kRkSpThreads) {
+        const int64_t r = rowidx[m.b1 + e];
+        const double av = cval[m.b1 + e];
+        w[r] += gam * av;
+        s[r] += gam * av;
+      }
+      __syncthreads();
+      double d2 = 0.0;
+      for (int64_t e = tid; e < m.l2; e += kRkSpThreads) d2 += cval[m.b2 + e] * s[rowidx[m.b2 + e]];
+      d2 = block_sum<kRkSpThreads>(d2, red[1]);
+      const double del = d2 / m.c2;
+      if (tid == 0) z[m.j2] += del;
+      for (int64_t e = tid; e < m.l2; e += kRkSpThreads) s[rowidx[m.b2 + e]] -= del * cval[m.b2 + e];
+      __syncthreads();
+      if (has_next && fits(mn)) cols_of(mn, n1, u1, n2, u2);
+    }
+    m = mn;
+#pragma unroll
+    for (int q = 0; q < kRkSpQ; ++q) {
+      r1[q] = n1[q];
+      v1[q] = u1[q];
+      r2[q] = n2[q];
+      v2[q] = u2[q];
+    }
   }
 }
 
