@@ -125,6 +125,30 @@ def test_rk_fixed_schedule(sp, form):
     assert_close(host(x), ref, 1e-10)
 
 
+def test_rk_mixed_column_lengths():
+    # A1 columns above and below the sparse inner step's register capacity
+    # (2048 entries) in one schedule: the step alternates between its register
+    # form and its loop form and loads the next step's columns in either
+    p, q, n = 5000, 500, 40
+    banner(f"sparse RK-RGS, mixed column lengths p={p} q={q} n={n}")
+    P = W.sparse_ils(p, q, n, density=0.05, ratio=0.7, seed=11)
+    A = P.A.toarray(order="F")
+    rng = np.random.default_rng(5)
+    for c in (3, 17, 18, 30):
+        A[:p, c] += rng.standard_normal(p)
+    S = ils.SparseA.from_scipy(sps.csr_matrix(A), p)
+    try:
+        b = dev(P.b)
+        for f in (ils.FORM_PAPER, ils.FORM_CORRECTION):
+            kw = dict(stop_rule=ils.STOP_FIXED, max_outer=2, max_inner=300, seed=7, form=f)
+            x, inf = S.rk_solve(b, **kw)
+            assert inf.status == ils.OK
+            ref, _ = O.rk_solve(A, P.b, P.p, **kw)
+            assert_close(host(x), ref, 1e-10)
+    finally:
+        S.close()
+
+
 @pytest.mark.parametrize("alpha", [0, 1])
 def test_scd_fixed_schedule(sp, alpha):
     P, A, S, b, _ = sp
