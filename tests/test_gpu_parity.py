@@ -158,6 +158,24 @@ def test_spd_solve_block_edges(n, nrhs):
     assert_close(host(Y), np.linalg.solve(G, R), 1e-11)
 
 
+@pytest.mark.parametrize("n,nrhs", [(1000, 1001), (2048, 65)])
+def test_spd_solve_is_reproducible(n, nrhs):
+    # the dataflow elimination fixes every tile's update order (one writer per
+    # tile and step, steps in order), so repeated calls give the same bits; a
+    # tile read before its producer finished, or overwritten while still read,
+    # would show as a difference between calls
+    rng = np.random.default_rng(n + 3)
+    X = rng.standard_normal((2 * n + 9, n))
+    G, R = devA(X.T @ X), devA(rng.standard_normal((n, nrhs)))
+    rc, Y0 = ils.spd_solve(G, R)
+    assert rc == ils.OK
+    y0 = host(Y0).copy()
+    for _ in range(12):
+        rc, Y = ils.spd_solve(G, R)
+        assert rc == ils.OK
+        assert np.array_equal(host(Y).view(np.uint64), y0.view(np.uint64))
+
+
 def test_spd_solve_repeated_sizes():
     # the dataflow elimination clears its counters on every call; alternate sizes
     # so that a stale counter or a short scratch buffer would show
